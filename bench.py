@@ -1,0 +1,341 @@
+#!/usr/bin/env python3
+"""Benchmark of the splatting renderer's training step on one MI355X.
+
+Headline: forward + L1 loss + backward (all Gaussian parameters and the se(3)
+pose) of 300k Gaussians at 1200x680 in a room-shaped synthetic scene,
+reported as Mpixel/s.  One step = one launch of the HIP graph that holds the
+whole fused step (projection, depth sort, pair emission, tile sort, ranges,
+persistent forward/L1/backward rasteriser, chain to parameters and pose),
+plus zeroing the gradient buffers.  Also reported: per-stage times and the
+roofline of the dominant kernel (from an eager, event-timed loop of the same
+step), the batched 16-keyframe launch against 16 per-frame launches, and the
+CPU oracle timed on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd Mpixel/s at 1200×680, 300k Gaussians; batched vs per-frame speedup"
+
+# Algorithmic FP32 operations per unit of rasteriser work (counted from the
+# formulas; an FMA counts 2, exp2 / rcp count 1):
+#   forward evaluation of one list entry at one pixel: offset (2), quadratic
+#     form (7), exp2 (1), opacity product (1), clamp (1), alpha test (1)   = 13
+#   blending an accepted entry: 1 - alpha, T update, T test, weight, 4 FMAs = 12
+#   backward re-evaluation of an entry (same as forward)                   = 13
+#   backward contribution of an accepted entry: T recovery (2), weight (1),
+#     colour/depth grads (4), dL/dalpha (17), running sums (12), clamp test
+#     and scale (2), centre and conic grads (14), opacity grad (1), block
+#     reduction adds for the 10 gradient fields (10)                      = 63
+FLOP_FWD_EVAL, FLOP_BLEND, FLOP_BWD_EVAL, FLOP_BWD_CONTRIB = 13, 12, 13, 63
+# MI355X FP32 vector peak without packed FP32: 256 CUs x 4 SIMDs x 16 lanes
+# x 2 (FMA) x 2.4 GHz.
+PEAK_FP32_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def build_c2(gsr, torch, W, O=None):
+    scene = W.room_scene(300_000, seed=0)
+    cam = W.camera_replica()
+    return scene, cam
+
+
+def make_targets(gsr, torch, W, r, g, cams_d, sizes, seed=1):
+    """Targets rendered from the scene itself plus 5% noise (depth noise is
+    multiplicative; depth 0 where the accumulated opacity is below 0.5)."""
+    out = r.render_forward(g, cams_d, gsr.Config())
+    torch.cuda.synchronize()
+    rgb = out["rgb"].cpu().numpy()
+    dep = out["depth"].cpu().numpy()
+    alpha = 1.0 - out["T_final"].cpu().numpy()
+    t_rgb, t_d = W.noisy_targets(rgb, dep, seed=seed, sigma=0.05, min_alpha=0.5, alpha=alpha)
+    return (torch.as_tensor(t_rgb).cuda(), torch.as_tensor(t_d).cuda()), r.pair_count()
+
+
+def time_graph(torch, r, grads, loss, steps, warmup, stream):
+    def step():
+        for t in grads.values():
+            t.zero_()
+        loss.zero_()
+        r.graph_launch(stream=stream)
+
+    with torch.cuda.stream(stream):
+        for _ in range(warmup):
+            step()
+        stream.synchronize()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        e0.record(stream)
+        for _ in range(steps):
+            step()
+        e1.record(stream)
+        e1.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3 / steps
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps, wall
+
+
+def run_headline(args, gsr, torch, W):
+    scene, cam = build_c2(gsr, torch, W)
+    sizes = [(cam.width, cam.height)]
+    g = gsr.Gaussians.from_arrays(*scene.arrays())
+    cams_d = gsr.pack_cameras([cam])
+    r = gsr.Renderer(0)
+    r.plan(scene.n, sizes)
+    (t_rgb, t_d), pairs = make_targets(gsr, torch, W, r, g, cams_d, sizes)
+    r.plan(scene.n, sizes, pair_capacity=int(pairs * 1.25) + 4096)
+    cfg = gsr.Config()
+    tuning = r.get_tuning()
+    if not args.no_autotune:
+        tuning = r.autotune(g, cams_d, cfg, t_rgb, t_d, None, 1.0, 0.1, reps=2)
+        log("autotune:", tuning)
+    grads = r.new_grads(scene.n)
+    loss = torch.zeros(1, device="cuda")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        r.graph_capture(g, cams_d, cfg, t_rgb, t_d, None, 1.0, 0.1, grads=grads, loss=loss, stream=stream)
+    stream.synchronize()
+    ms, wall = time_graph(torch, r, grads, loss, args.steps, args.warmup, stream)
+    r.check_overflow(stream=stream)
+    log(f"graph step: {ms:.3f} ms (wall {wall:.3f} ms), loss {loss.item():.2f}")
+
+    # Eager, event-timed loop of the same step for per-stage times.
+    r.set_profiling(True)
+    for _ in range(3):
+        r.render_l1_fused(g, cams_d, cfg, t_rgb, t_d, None, 1.0, 0.1, grads=grads, loss=loss)
+    r.stage_times()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        r.render_l1_fused(g, cams_d, cfg, t_rgb, t_d, None, 1.0, 0.1, grads=grads, loss=loss)
+    e1.record()
+    e1.synchronize()
+    eager_ms = e0.elapsed_time(e1) / args.steps
+    st = r.stage_times()
+    r.set_profiling(False)
+    calls = max(1, st.pop("calls"))
+    stages = {k: v / calls for k, v in st.items()}
+    work = r.work_counts()
+    raster_ms = stages["raster"]
+    flops = (work["fwd_evals"] * FLOP_FWD_EVAL + work["blended"] * FLOP_BLEND +
+             work["bwd_evals"] * FLOP_BWD_EVAL + work["blended"] * FLOP_BWD_CONTRIB)
+    achieved = flops / (raster_ms * 1e-3) / 1e12
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_FP32_TFLOPS, 1),
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
+            "kernel": "k_render_fused", "kernel_ms": round(raster_ms, 4), "flop_per_launch": int(flops)}
+    px = cam.width * cam.height
+    return dict(ms=ms, wall=wall, eager_ms=eager_ms, stages=stages, work=work, roof=roof, tuning=tuning,
+                mpx=px / (ms * 1e-3) / 1e6, pairs=pairs)
+
+
+def run_batched(args, gsr, torch, W):
+    """16 keyframes of mixed resolution over 1M Gaussians: one graph launch
+    of the batched fused step vs 16 per-frame fused calls on the same stream
+    (gradients accumulated into the same buffers)."""
+    scene = W.room_scene(1_000_000, seed=0)
+    cams = W.mapping_views(seed=2)
+    sizes = [(c.width, c.height) for c in cams]
+    g = gsr.Gaussians.from_arrays(*scene.arrays())
+    cams_d = gsr.pack_cameras(cams)
+    rb = gsr.Renderer(0)
+    rb.plan(scene.n, sizes)
+    (t_rgb, t_d), pairs = make_targets(gsr, torch, W, rb, g, cams_d, sizes)
+    rb.plan(scene.n, sizes, pair_capacity=int(pairs * 1.25) + 4096)
+    cfg = gsr.Config()
+    if not args.no_autotune:
+        rb.autotune(g, cams_d, cfg, t_rgb, t_d, None, 1.0, 0.1, reps=1)
+    grads = rb.new_grads(scene.n)
+    loss = torch.zeros(1, device="cuda")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        rb.graph_capture(g, cams_d, cfg, t_rgb, t_d, None, 1.0, 0.1, grads=grads, loss=loss, stream=stream)
+    stream.synchronize()
+    steps = max(3, args.steps // 4)
+    b_ms, _ = time_graph(torch, rb, grads, loss, steps, 2, stream)
+    rb.check_overflow(stream=stream)
+    del rb
+    torch.cuda.empty_cache()
+
+    # Per-frame: one renderer per view (planned once), 16 calls per step.
+    offs, po = [], 0
+    for w, h in sizes:
+        offs.append(po)
+        po += w * h
+    per = []
+    for v, c in enumerate(cams):
+        r = gsr.Renderer(0)
+        w, h = sizes[v]
+        r.plan(scene.n, [sizes[v]])
+        tr = t_rgb[3 * offs[v]:3 * offs[v] + 3 * w * h]
+        td = t_d[offs[v]:offs[v] + w * h]
+        per.append((r, gsr.pack_cameras([c]), tr, td))
+    pose = torch.zeros(1, 6, device="cuda")
+    gr1 = dict(grads)
+
+    def step():
+        for t in grads.values():
+            t.zero_()
+        loss.zero_()
+        for v, (r, cd, tr, td) in enumerate(per):
+            gr1["d_pose"] = grads["d_pose"][v:v + 1]
+            r.render_l1_fused(g, cd, cfg, tr, td, None, 1.0, 0.1, grads=gr1, loss=loss)
+
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        step()
+    e1.record()
+    e1.synchronize()
+    p_ms = e0.elapsed_time(e1) / steps
+    del per, pose
+    torch.cuda.empty_cache()
+    total_px = sum(w * h for w, h in sizes)
+    return {"workload": "1M Gaussians, 16 keyframes (4x320x240, 8x640x480, 4x1200x680), fwd+L1+bwd",
+            "batched_ms": round(b_ms, 3), "per_frame_ms": round(p_ms, 3),
+            "speedup": round(p_ms / b_ms, 3), "batched_mpx_s": round(total_px / (b_ms * 1e-3) / 1e6, 1),
+            "per_frame_mpx_s": round(total_px / (p_ms * 1e-3) / 1e6, 1), "pairs": int(pairs)}
+
+
+def cpu_baseline(args, W, n_tiles=None):
+    """The FP64 oracle on a bounded sample of the headline workload: projection
+    and binning of all 300k Gaussians (charged pro rata to the sampled tiles)
+    and forward + L1 + backward of a spread of sampled tiles, one thread."""
+    import numpy as np
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:  # pragma: no cover
+        threadpool_limits = None
+    import oracle as O
+    ctx = threadpool_limits(1) if threadpool_limits else None
+    try:
+        scene, cam = W.room_scene(300_000, seed=0), W.camera_replica()
+        cfg = O.Config().as_f32()
+        t0 = time.perf_counter()
+        proj = O.project(scene, cam, cfg)
+        starts, gauss = O.tile_lists(proj)
+        t_geo = time.perf_counter() - t0
+        TX, TY = proj["TX"], proj["TY"]
+        T = TX * TY
+        rng = np.random.default_rng(0)
+        order = rng.permutation(T)
+        t_rgb, t_d, _ = W.random_targets([(cam.width, cam.height)], seed=1)
+        t_rgb = t_rgb.reshape(3, cam.height, cam.width)
+        t_d = t_d.reshape(cam.height, cam.width)
+        t1 = time.perf_counter()
+        px = 0
+        done_tiles = 0
+        budget = args.cpu_seconds
+        for tile in order[: (n_tiles or T)]:
+            pxs, pys = O.splat._tile_pixels(tile, TX, cam.width, cam.height)
+            lst = gauss[starts[tile]:starts[tile + 1]]
+            rr = O.splat._blend_tile(proj, lst, pxs, pys, cfg)
+            C = rr["C"].T
+            e = C - t_rgb[:, pys, pxs]
+            ed = rr["D"] - t_d[pys, pxs]
+            gC = np.sign(e).T
+            gD = 0.1 * np.sign(ed) * (t_d[pys, pxs] > 0)
+            O.splat._blend_tile_backward(proj, lst, pxs, pys, cfg, rr, gC, gD, np.zeros_like(gD))
+            px += pxs.size
+            done_tiles += 1
+            if time.perf_counter() - t1 > budget:
+                break
+        t_tiles = time.perf_counter() - t1
+        # Per-Gaussian chain for the whole frame, charged pro rata as well.
+        t2 = time.perf_counter()
+        O.backward_params(proj, np.zeros((proj["n"], 10)), cfg)
+        t_chain = time.perf_counter() - t2
+        frac = done_tiles / T
+        total = t_tiles + (t_geo + t_chain) * frac
+        return {"value": round(px / total / 1e6, 6), "unit": "Mpixel/s", "cores": 1, "kind": "oracle",
+                "sample": (f"{done_tiles} of {T} tiles ({px} px) of the 300k-Gaussian 1200x680 workload, "
+                           f"forward + L1 + backward in FP64; projection/binning ({t_geo:.1f} s) and the "
+                           f"per-Gaussian chain ({t_chain:.1f} s) of the full frame charged pro rata"),
+                "cpu": platform.processor() or platform.machine(), "host_cpus": os.cpu_count(),
+                "seconds": round(total, 2)}
+    finally:
+        if ctx is not None:
+            ctx.__exit__(None, None, None)
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); the renderer has no "
+              "multi-GPU path to time", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2311_11700_amd as gsr
+    import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    log("headline: 300k Gaussians, 1200x680")
+    h = run_headline(args, gsr, torch, W)
+    batched = None
+    if not args.no_batched:
+        log("batched: 1M Gaussians, 16 keyframes")
+        batched = run_batched(args, gsr, torch, W)
+        log("batched:", batched)
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle sample)")
+        cpu = cpu_baseline(args, W)
+        log("cpu:", cpu)
+    line = {
+        "metric": METRIC,
+        "value": round(h["mpx"], 2),
+        "unit": "Mpixel/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(h["ms"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "fwd+L1+bwd, 300k Gaussians (room scene, 70% on walls/floor), 1200x680, f=600; "
+                               "grads to all Gaussian parameters and the se(3) pose; HIP graph of the fused step",
+                   "gaussians": 300000, "width": 1200, "height": 680, "loss": "L1 rgb + 0.1 L1 depth"},
+        "roofline": h["roof"],
+        "cpu_baseline": cpu,
+        "batched": batched,
+        "eager_ms_per_step": round(h["eager_ms"], 4),
+        "stages_ms": {k: round(v, 4) for k, v in h["stages"].items()},
+        "work": h["work"],
+        "tuning": h["tuning"],
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

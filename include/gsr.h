@@ -1,0 +1,261 @@
+/*
+ * gsr.h -- C ABI of the MI355X (gfx950) differentiable tile-based Gaussian
+ * splatting renderer: the rendering hot path of GS-SLAM's tracking and
+ * mapping loops (Yan et al., "GS-SLAM: Dense Visual SLAM with 3D Gaussian
+ * Splatting", arXiv 2311.11700).
+ *
+ * Method (paper references):
+ *   - Scene: Gaussians with mean, covariance R S S^T R^T (Eq. 1-2, rotation
+ *     from a real-first quaternion, supplement eq. q2R), opacity, RGB colour.
+ *   - Projection: Sigma' = J W Sigma W^T J^T (Eq. 3) plus a low-pass term;
+ *     centre m = K X_c / z, depth d = z (Sec. 3.1, Sec. 3.3).
+ *   - Binning: 16x16 tiles; a Gaussian covers the tiles of the bounding box of
+ *     its cutoff_sigma ellipse; tile lists sorted by (tile, float32 depth bits,
+ *     Gaussian index).
+ *   - Compositing: front-to-back alpha blending of colour (Eq. 4) and depth
+ *     (Eq. 5), final transmittance T_final = 1 - cumulative opacity (Sec. 3.2).
+ *   - Backward: gradients of the blend (supplement eq. grad_depth and its
+ *     colour analogue), chained through the projection to every Gaussian
+ *     parameter and to the camera pose (Eq. 11 and supplement Sec. A; the
+ *     Sigma' path of the pose gradient is kept unless GSR_PAPER_POSE_APPROX).
+ *   - Loss: weighted L1 on colour and depth (Eq. 6, Eq. 10).
+ *
+ * Conventions
+ *   - All arrays are caller-owned DEVICE memory unless marked HOST.
+ *   - Pixel (x, y) has its centre at integer coordinates (x, y).
+ *   - Views are concatenated: view v's pixels start at pixel offset
+ *     P_v = sum_{u<v} W_u H_u.  Colour images are planar per view:
+ *     rgb[3 * P_v + c * H_v * W_v + y * W_v + x].  depth, T_final, last and the
+ *     per-pixel upstream gradients use [P_v + y * W_v + x].
+ *   - Gradient outputs ACCUMULATE (+=): the caller zeroes them before the
+ *     first call; batched views and repeated calls sum.
+ *   - Functions return a gsr_status and never throw.  Calls on one context
+ *     are not thread-safe; use one context per host thread.
+ *   - Nothing on the render path allocates device memory: scratch lives in the
+ *     caller's workspace, sized by gsr_plan().
+ */
+#ifndef GSR_H
+#define GSR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gsr_ctx gsr_ctx;
+/* A hipStream_t passed as an opaque pointer (NULL = the null stream). */
+typedef void *gsr_stream;
+
+typedef enum {
+  GSR_OK = 0,
+  GSR_E_INVALID = -1,     /* bad argument: null pointer, size mismatch with the plan, ... */
+  GSR_E_CAPACITY = -2,    /* the tile-pair buffer was too small: see gsr_required_pairs() */
+  GSR_E_HIP = -3,         /* a HIP runtime call failed: see gsr_last_error() */
+  GSR_E_UNSUPPORTED = -4, /* configuration not supported (e.g. a view wider than 65535 px) */
+  GSR_E_STATE = -5        /* call out of order (no plan, workspace not filled by a forward) */
+} gsr_status;
+
+/* One camera (80 bytes, DEVICE array [n_views]).  Pinhole intrinsics in
+ * pixels; world->camera pose X_c = R X + t (R row-major).  width/height must
+ * equal the sizes given to gsr_plan() for this view. */
+typedef struct {
+  float fx, fy, cx, cy;
+  float R[9];
+  float t[3];
+  int32_t width, height;
+  int32_t _pad[2];
+} gsr_camera;
+
+/* The Gaussian set (Eq. 1-2), structure of arrays, float32, DEVICE:
+ *   mean [n][3], log_scale [n][3] (scale = exp), quat [n][4] (w, x, y, z;
+ *   normalised inside), opacity_logit [n] (opacity = sigmoid), rgb [n][3].
+ *   mask [n] (nullable, uint8): 0 excludes a Gaussian (coarse-to-fine
+ *   selection of reliable Gaussians, Eq. 12).
+ * Non-finite parameters and zero quaternions cull the Gaussian. */
+typedef struct {
+  int64_t n;
+  const float *mean, *log_scale, *quat, *opacity_logit, *rgb;
+  const uint8_t *mask;
+} gsr_gaussians;
+
+enum {
+  /* Every Gaussian covers every tile of every view (finite-difference mode:
+   * together with alpha_min = T_min = 0 and alpha_max = 1 the image is a
+   * smooth function of the parameters). */
+  GSR_FULL_RECT = 1u << 0,
+  /* Backward: produce gradients for the Gaussian parameters. */
+  GSR_GAUSS_GRAD = 1u << 1,
+  /* Backward: produce the se(3) pose gradient of every view. */
+  GSR_POSE_GRAD = 1u << 2,
+  /* Pose gradient through the projected centre and depth only, dropping
+   * the Sigma' term as the paper does for speed (Sec. 3.3, supplement). */
+  GSR_PAPER_POSE_APPROX = 1u << 3
+};
+
+/* Renderer constants.  The paper is silent on them; gsr_default_config()
+ * returns the values of the 3DGS rasteriser the paper extends:
+ * alpha_min 1/255, alpha_max 0.99, T_min 1e-4, cutoff_sigma 3, z_near 0.2 m,
+ * lowpass 0.3 px^2, bg 0, flags GSR_GAUSS_GRAD | GSR_POSE_GRAD. */
+typedef struct {
+  float alpha_min, alpha_max, T_min, cutoff_sigma, z_near, lowpass;
+  float bg[3];
+  uint32_t flags;
+} gsr_config;
+
+/* Forward outputs, DEVICE (any pointer may be NULL to skip that output):
+ * rgb [3 * sum HW] float, depth / T_final [sum HW] float, last [sum HW] int32
+ * (1 + position in the tile list of the pixel's last blended Gaussian). */
+typedef struct {
+  float *rgb, *depth, *T_final;
+  int32_t *last;
+} gsr_images;
+
+/* Gradient outputs, DEVICE, accumulated (+=).  d_* match the Gaussian
+ * arrays; d_pose [n_views][6] = (rho_x, rho_y, rho_z, phi_x, phi_y, phi_z):
+ * the derivative w.r.t. a left perturbation T_cw <- Exp(xi) T_cw at xi = 0.
+ * Pointers may be NULL when the matching flag is off. */
+typedef struct {
+  float *d_mean, *d_log_scale, *d_quat, *d_opacity_logit, *d_rgb;
+  float *d_pose;
+} gsr_grads;
+
+/* Tuning parameters (picked by gsr_autotune, or set by hand). */
+typedef struct {
+  int32_t blocks_per_cu;   /* persistent rasteriser: resident blocks per CU (1..8) */
+  int32_t tiles_per_pop;   /* tiles a block takes from the work queue at a time (1..8) */
+  int32_t lpt_order;       /* 1: process tiles longest-list first */
+  int32_t _reserved;
+} gsr_tuning;
+
+gsr_config gsr_default_config(void);
+const char *gsr_status_string(gsr_status s);
+/* Text of the last error on this context (never NULL). */
+const char *gsr_last_error(const gsr_ctx *ctx);
+
+/* Create a context on HIP device `device` (owns a few KB of device memory for
+ * the view table and a pinned host word; no other state).  */
+gsr_status gsr_create(int device, gsr_ctx **out);
+void gsr_destroy(gsr_ctx *ctx);
+
+/* Plan a workload: n Gaussians rendered into n_views views of sizes
+ * wh_host[v] = (width, height) (HOST array [n_views][2]), with room for
+ * pair_capacity (tile, Gaussian) pairs.  Writes the workspace size in bytes
+ * the render calls need.  Synchronous; not on the hot path. */
+gsr_status gsr_plan(gsr_ctx *ctx, int64_t n, int n_views, const int32_t *wh_host,
+                    int64_t pair_capacity, size_t *workspace_bytes);
+
+/* Forward render (Eq. 3-5) of every planned view.  `workspace` (DEVICE,
+ * >= workspace_bytes, 256-byte aligned) keeps the projected Gaussians, the
+ * sorted tile lists and per-pixel state for gsr_render_backward.
+ * Synchronises the stream once at the end to check the pair capacity:
+ * on GSR_E_CAPACITY the outputs are undefined and gsr_required_pairs()
+ * tells the capacity to plan for. */
+gsr_status gsr_render_forward(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams,
+                              int n_views, const gsr_config *cfg, void *workspace,
+                              size_t workspace_bytes, const gsr_images *out, gsr_stream stream);
+
+/* Backward of the last forward on this workspace: upstream gradients g_rgb
+ * [3 * sum HW], g_depth [sum HW], g_T (nullable) [sum HW] w.r.t. the colour,
+ * depth and final-transmittance outputs.  Accumulates into `grads`
+ * according to cfg->flags.  Asynchronous. */
+gsr_status gsr_render_backward(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams,
+                               int n_views, const gsr_config *cfg, void *workspace,
+                               size_t workspace_bytes, const float *g_rgb, const float *g_depth,
+                               const float *g_T, const gsr_grads *grads, gsr_stream stream);
+
+/* Weighted L1 loss (Eq. 6 / Eq. 10) and its gradient w.r.t. the rendered
+ * images: loss = w_rgb sum m |C - C*| + w_depth sum m [D* > 0] |D - D*| over
+ * all views' pixels with pixel_mask (nullable uint8, 0 = ignore) != 0;
+ * sign(0) = 0.  Writes (overwrites) g_rgb / g_depth; ADDS the loss into
+ * *loss (DEVICE float).  Asynchronous. */
+gsr_status gsr_l1_loss_grad(gsr_ctx *ctx, const float *rgb, const float *depth,
+                            const float *target_rgb, const float *target_depth,
+                            const uint8_t *pixel_mask, float w_rgb, float w_depth, float *g_rgb,
+                            float *g_depth, float *loss, gsr_stream stream);
+
+/* One training step of the renderer in a single call: forward, L1 loss and
+ * its gradient, and backward, with the per-tile forward, loss gradient and
+ * backward fused in one persistent kernel.  Images in `out` are optional
+ * (NULL struct or NULL members skip them).  ADDS the loss into *loss.
+ * Asynchronous: a pair-capacity overflow is recorded on the device and
+ * reported by gsr_check_overflow(). */
+gsr_status gsr_render_l1_fused(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams,
+                               int n_views, const gsr_config *cfg, const float *target_rgb,
+                               const float *target_depth, const uint8_t *pixel_mask, float w_rgb,
+                               float w_depth, void *workspace, size_t workspace_bytes,
+                               const gsr_images *out, const gsr_grads *grads, float *loss,
+                               gsr_stream stream);
+
+/* Capture gsr_render_l1_fused with these exact arguments (pointers and
+ * scalar values are baked in; buffer CONTENTS may change between launches)
+ * into a HIP graph owned by the context, replacing any earlier capture. */
+gsr_status gsr_graph_capture(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams,
+                             int n_views, const gsr_config *cfg, const float *target_rgb,
+                             const float *target_depth, const uint8_t *pixel_mask, float w_rgb,
+                             float w_depth, void *workspace, size_t workspace_bytes,
+                             const gsr_images *out, const gsr_grads *grads, float *loss,
+                             gsr_stream stream);
+/* Launch the captured graph on `stream` (asynchronous). */
+gsr_status gsr_graph_launch(gsr_ctx *ctx, gsr_stream stream);
+
+/* Synchronise `stream`, then report GSR_E_CAPACITY if any call since the
+ * last check overflowed the pair buffer of this workspace. */
+gsr_status gsr_check_overflow(gsr_ctx *ctx, void *workspace, gsr_stream stream);
+/* Pair count of the last overflowing call (0 if none). */
+int64_t gsr_required_pairs(const gsr_ctx *ctx);
+/* Synchronise `stream` and return the number of (tile, Gaussian) pairs the
+ * last forward on `workspace` produced. */
+int64_t gsr_pair_count(gsr_ctx *ctx, void *workspace, gsr_stream stream);
+
+/* DEVICE pointers into the workspace, for inspection after a forward:
+ * tile_ranges [total_tiles][2] int32 (start, end) into the sorted lists,
+ * sorted_ids [pairs] uint32 = view * n + gaussian index.  Tiles are numbered
+ * view after view, row-major within a view. */
+gsr_status gsr_debug_tiles(gsr_ctx *ctx, void *workspace, const int32_t **tile_ranges,
+                           const uint32_t **sorted_ids, int64_t *total_tiles);
+
+/* Tuning of the fused rasteriser. */
+gsr_status gsr_get_tuning(const gsr_ctx *ctx, gsr_tuning *out);
+gsr_status gsr_set_tuning(gsr_ctx *ctx, const gsr_tuning *t);
+/* Time every candidate tuning on this workload (same arguments as
+ * gsr_render_l1_fused; gradients and loss are written by the trial runs, so
+ * the caller re-zeroes them afterwards), keep the fastest in the context and
+ * return it.  `reps` timed launches per candidate. */
+gsr_status gsr_autotune(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams, int n_views,
+                        const gsr_config *cfg, const float *target_rgb, const float *target_depth,
+                        const uint8_t *pixel_mask, float w_rgb, float w_depth, void *workspace,
+                        size_t workspace_bytes, const gsr_grads *grads, float *loss, int reps,
+                        gsr_tuning *best, gsr_stream stream);
+
+/* Per-stage timing of calls on this context (HIP events recorded on the
+ * call's stream around each stage; HIP-graph launches are not split). */
+enum {
+  GSR_STAGE_PREPROCESS = 0, /* projection, binning data, depth keys */
+  GSR_STAGE_DEPTH_SORT,     /* radix sort of the projected Gaussians by depth */
+  GSR_STAGE_EMIT,           /* scan of tile counts and pair emission */
+  GSR_STAGE_PAIR_SORT,      /* radix sort of the pairs by tile */
+  GSR_STAGE_RANGES,         /* per-tile ranges and work order */
+  GSR_STAGE_RASTER,         /* forward compositing, or the fused forward + L1 + backward */
+  GSR_STAGE_RASTER_BWD,     /* backward compositing (unfused backward only) */
+  GSR_STAGE_PREGRAD,        /* chain to parameters and pose */
+  GSR_NSTAGES
+};
+/* Enable (1) or disable (0) stage timing for later calls. */
+gsr_status gsr_set_profiling(gsr_ctx *ctx, int enable);
+/* Synchronise, then return the summed milliseconds per stage (ms[GSR_NSTAGES])
+ * and the number of timed calls since the last query; resets the sums. */
+gsr_status gsr_stage_times(gsr_ctx *ctx, double *ms, int64_t *calls);
+
+/* Work done by the last forward or fused call on `workspace` (synchronises
+ * `stream`): out[0] = (tile, Gaussian) pairs, out[1] = pixel-Gaussian
+ * evaluations of the forward walk (every list entry a pixel examined, up to
+ * and including the one that stopped it), out[2] = entries blended,
+ * out[3] = list entries the backward walk examines (sum of `last`). */
+gsr_status gsr_work_counts(gsr_ctx *ctx, void *workspace, gsr_stream stream, int64_t *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GSR_H */

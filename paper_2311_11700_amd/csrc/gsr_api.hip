@@ -1,0 +1,644 @@
+// C ABI of the renderer: context, plan and workspace layout, the render
+// entry points, HIP-graph capture of the fused step, and the autotuner.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "gsr_internal.h"
+
+using namespace gsr;
+
+struct gsr_ctx {
+  int device = 0;
+  int num_cus = 256;
+  Plan plan;
+  bool planned = false;
+  std::vector<ViewInfo> views_host;
+  ViewInfo *views_dev = nullptr;
+  int32_t *tile_view_dev = nullptr;
+  unsigned long long *pinned = nullptr;  // 4 pinned host words
+  std::string last_error;
+  int64_t required = 0;
+  Tuning tuning;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  const void *last_forward_ws = nullptr;
+  int sort_grid = 2048;
+  // stage timing
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool;   // (GSR_NSTAGES + 1) events per timed call
+  size_t ev_used = 0;                // event sets recorded and not yet summed
+  double stage_ms[GSR_NSTAGES] = {};
+  int64_t timed_calls = 0;
+  hipEvent_t *cur_events = nullptr;  // events of the call being enqueued
+};
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+
+size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+gsr_status fail(gsr_ctx *ctx, gsr_status st, const std::string &msg) {
+  if (ctx) ctx->last_error = msg;
+  return st;
+}
+
+gsr_status hip_check(gsr_ctx *ctx, hipError_t e, const char *what) {
+  if (e == hipSuccess) return GSR_OK;
+  return fail(ctx, GSR_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+gsr_status last_launch(gsr_ctx *ctx, const char *what) {
+  return hip_check(ctx, hipGetLastError(), what);
+}
+
+int passes_for(int bits) { return (bits + RADIX_BITS - 1) / RADIX_BITS; }
+
+Workspace make_ws(const Plan &p, void *base_v) {
+  char *base = static_cast<char *>(base_v);
+  Workspace w{};
+  w.hdr = reinterpret_cast<uint32_t *>(base + p.off_hdr);
+  w.recA = reinterpret_cast<float4 *>(base + p.off_recA);
+  w.recB = reinterpret_cast<float4 *>(base + p.off_recB);
+  w.recZ = reinterpret_cast<float *>(base + p.off_recZ);
+  w.rect = reinterpret_cast<ushort4 *>(base + p.off_rect);
+  w.count = reinterpret_cast<uint32_t *>(base + p.off_count);
+  for (int k = 0; k < 2; ++k) {
+    w.dkeys[k] = reinterpret_cast<uint32_t *>(base + p.off_dkeys[k]);
+    w.dvals[k] = reinterpret_cast<uint32_t *>(base + p.off_dvals[k]);
+    w.pkeys[k] = reinterpret_cast<uint32_t *>(base + p.off_pkeys[k]);
+    w.pvals[k] = reinterpret_cast<uint32_t *>(base + p.off_pvals[k]);
+  }
+  w.scan_part = reinterpret_cast<unsigned long long *>(base + p.off_scan);
+  w.hist = reinterpret_cast<uint32_t *>(base + p.off_hist);
+  w.digit_total = reinterpret_cast<uint32_t *>(base + p.off_digit);
+  w.ranges = reinterpret_cast<int2 *>(base + p.off_ranges);
+  w.T_final = reinterpret_cast<float *>(base + p.off_T);
+  w.last = reinterpret_cast<int32_t *>(base + p.off_last);
+  w.nevals = reinterpret_cast<int32_t *>(base + p.off_nevals);
+  w.nblend = reinterpret_cast<int32_t *>(base + p.off_nblend);
+  w.counts = reinterpret_cast<unsigned long long *>(base + p.off_counts);
+  w.grad2d = reinterpret_cast<float *>(base + p.off_grad2d);
+  w.pose_part = reinterpret_cast<float *>(base + p.off_pose);
+  w.queue = reinterpret_cast<uint32_t *>(base + p.off_queue);
+  w.loss_part = reinterpret_cast<float *>(base + p.off_loss);
+  w.dsorted = passes_for(32) & 1;
+  w.psorted = passes_for(p.tile_bits) & 1;
+  return w;
+}
+
+gsr_status validate(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams, int n_views,
+                    const gsr_config *cfg, void *ws, size_t ws_bytes) {
+  if (!ctx) return GSR_E_INVALID;
+  if (!ctx->planned) return fail(ctx, GSR_E_STATE, "gsr_plan() has not been called");
+  if (!g || !cams || !cfg || !ws) return fail(ctx, GSR_E_INVALID, "null argument");
+  if (g->n != ctx->plan.n) return fail(ctx, GSR_E_INVALID, "Gaussian count differs from the plan");
+  if (n_views != ctx->plan.n_views) return fail(ctx, GSR_E_INVALID, "view count differs from the plan");
+  if (ws_bytes < ctx->plan.bytes) return fail(ctx, GSR_E_INVALID, "workspace smaller than gsr_plan() requires");
+  if (reinterpret_cast<uintptr_t>(ws) % ALIGN) return fail(ctx, GSR_E_INVALID, "workspace not 256-byte aligned");
+  if (g->n > 0 && (!g->mean || !g->log_scale || !g->quat || !g->opacity_logit || !g->rgb))
+    return fail(ctx, GSR_E_INVALID, "null Gaussian parameter array");
+  if (reinterpret_cast<uintptr_t>(g->quat) % 16) return fail(ctx, GSR_E_INVALID, "quat must be 16-byte aligned");
+  if (!(cfg->alpha_max > 0.f && cfg->alpha_max <= 1.f) || cfg->alpha_min < 0.f || cfg->T_min < 0.f ||
+      !(cfg->cutoff_sigma > 0.f))
+    return fail(ctx, GSR_E_INVALID, "renderer constants out of range");
+  return GSR_OK;
+}
+
+RenderConsts consts(const gsr_config &c) {
+  RenderConsts rc;
+  rc.alpha_min = c.alpha_min;
+  rc.alpha_max = c.alpha_max;
+  rc.T_min = c.T_min;
+  rc.bg[0] = c.bg[0];
+  rc.bg[1] = c.bg[1];
+  rc.bg[2] = c.bg[2];
+  return rc;
+}
+
+constexpr int NEV = GSR_NSTAGES + 1;
+
+// Sum the recorded event sets into stage_ms (synchronises on the events).
+gsr_status drain_events(gsr_ctx *ctx) {
+  for (size_t k = 0; k < ctx->ev_used; ++k) {
+    hipEvent_t *e = &ctx->ev_pool[k * NEV];
+    gsr_status st = hip_check(ctx, hipEventSynchronize(e[NEV - 1]), "hipEventSynchronize");
+    if (st != GSR_OK) return st;
+    for (int j = 0; j < GSR_NSTAGES; ++j) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, e[j], e[j + 1]) == hipSuccess) ctx->stage_ms[j] += ms;
+    }
+    ++ctx->timed_calls;
+  }
+  ctx->ev_used = 0;
+  return GSR_OK;
+}
+
+// Start timing one call: take an event set (draining the pool when full).
+void prof_begin(gsr_ctx *ctx, hipStream_t s) {
+  ctx->cur_events = nullptr;
+  if (!ctx->profiling) return;
+  const size_t sets = ctx->ev_pool.size() / NEV;
+  if (ctx->ev_used == sets) (void)drain_events(ctx);
+  ctx->cur_events = &ctx->ev_pool[ctx->ev_used * NEV];
+  ++ctx->ev_used;
+  (void)hipEventRecord(ctx->cur_events[0], s);
+}
+
+// Mark the end of `stage` (stages run in enum order; skipped stages time ~0).
+void prof_mark(gsr_ctx *ctx, hipStream_t s, int stage) {
+  if (ctx->cur_events) (void)hipEventRecord(ctx->cur_events[stage + 1], s);
+}
+
+// Mark the end of every stage from `first_unmarked` on (the work enqueued
+// since the last mark belongs to `first_unmarked`; later stages time ~0).
+void prof_end(gsr_ctx *ctx, hipStream_t s, int first_unmarked) {
+  if (!ctx->cur_events) return;
+  for (int j = first_unmarked; j < GSR_NSTAGES; ++j) (void)hipEventRecord(ctx->cur_events[j + 1], s);
+  ctx->cur_events = nullptr;
+}
+
+// Projection, depth sort, pair emission, tile sort and ranges.
+void enqueue_lists(gsr_ctx *ctx, const gsr_gaussians &g, const gsr_camera *cams, const gsr_config &cfg,
+                   Workspace &ws, hipStream_t s) {
+  const Plan &p = ctx->plan;
+  launch_reset_header(ws, s);
+  launch_preprocess(g, cams, ctx->views_dev, p.n_views, cfg, ws, s);
+  prof_mark(ctx, s, GSR_STAGE_PREPROCESS);
+  launch_depth_sort(p, ws, s, ctx->sort_grid);
+  prof_mark(ctx, s, GSR_STAGE_DEPTH_SORT);
+  launch_emit_pairs(p, ws, ctx->views_dev, s);
+  prof_mark(ctx, s, GSR_STAGE_EMIT);
+  launch_pair_sort(p, ws, s, ctx->sort_grid);
+  prof_mark(ctx, s, GSR_STAGE_PAIR_SORT);
+  launch_tile_ranges(p, ws, s);
+}
+
+void enqueue_fused(gsr_ctx *ctx, const gsr_gaussians &g, const gsr_camera *cams, const gsr_config &cfg,
+                   const float *t_rgb, const float *t_depth, const uint8_t *pmask, float w_rgb, float w_depth,
+                   Workspace &ws, const gsr_images *out, const gsr_grads &gr, float *loss, hipStream_t s) {
+  const Plan &p = ctx->plan;
+  prof_begin(ctx, s);
+  enqueue_lists(ctx, g, cams, cfg, ws, s);
+  launch_queue_order(p, ws, ctx->tuning.lpt_order, s);
+  launch_fill_f32(ws.grad2d, 0.f, p.n_rec * NGRAD2D, s);
+  prof_mark(ctx, s, GSR_STAGE_RANGES);
+  launch_render_fused(p, ws, ctx->views_dev, ctx->tile_view_dev, g, consts(cfg), t_rgb, t_depth, pmask, w_rgb,
+                      w_depth, out, loss, ctx->tuning, ctx->num_cus, s);
+  prof_mark(ctx, s, GSR_STAGE_RASTER);
+  prof_mark(ctx, s, GSR_STAGE_RASTER_BWD);
+  launch_preprocess_backward(p, g, cams, cfg, ws, gr, s);
+  prof_end(ctx, s, GSR_STAGE_PREGRAD);
+}
+
+}  // namespace
+
+extern "C" {
+
+gsr_config gsr_default_config(void) {
+  gsr_config c;
+  c.alpha_min = 1.0f / 255.0f;
+  c.alpha_max = 0.99f;
+  c.T_min = 1e-4f;
+  c.cutoff_sigma = 3.0f;
+  c.z_near = 0.2f;
+  c.lowpass = 0.3f;
+  c.bg[0] = c.bg[1] = c.bg[2] = 0.f;
+  c.flags = GSR_GAUSS_GRAD | GSR_POSE_GRAD;
+  return c;
+}
+
+const char *gsr_status_string(gsr_status s) {
+  switch (s) {
+    case GSR_OK: return "GSR_OK";
+    case GSR_E_INVALID: return "GSR_E_INVALID: invalid argument";
+    case GSR_E_CAPACITY: return "GSR_E_CAPACITY: tile-pair buffer too small";
+    case GSR_E_HIP: return "GSR_E_HIP: HIP runtime error";
+    case GSR_E_UNSUPPORTED: return "GSR_E_UNSUPPORTED: unsupported configuration";
+    case GSR_E_STATE: return "GSR_E_STATE: call out of order";
+  }
+  return "unknown gsr_status";
+}
+
+const char *gsr_last_error(const gsr_ctx *ctx) { return ctx ? ctx->last_error.c_str() : "null context"; }
+
+gsr_status gsr_create(int device, gsr_ctx **out) {
+  if (!out) return GSR_E_INVALID;
+  *out = nullptr;
+  gsr_ctx *ctx = new gsr_ctx();
+  ctx->device = device;
+  gsr_status st = hip_check(ctx, hipSetDevice(device), "hipSetDevice");
+  if (st == GSR_OK) st = hip_check(ctx, hipDeviceGetAttribute(&ctx->num_cus, hipDeviceAttributeMultiprocessorCount, device), "hipDeviceGetAttribute");
+  if (st == GSR_OK) st = hip_check(ctx, hipHostMalloc(reinterpret_cast<void **>(&ctx->pinned), 4 * sizeof(unsigned long long), hipHostMallocDefault), "hipHostMalloc");
+  if (st != GSR_OK) {
+    std::fprintf(stderr, "gsr_create: %s\n", ctx->last_error.c_str());
+    gsr_destroy(ctx);
+    return st;
+  }
+  *out = ctx;
+  return GSR_OK;
+}
+
+void gsr_destroy(gsr_ctx *ctx) {
+  if (!ctx) return;
+  if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+  if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+  if (ctx->views_dev) (void)hipFree(ctx->views_dev);
+  if (ctx->tile_view_dev) (void)hipFree(ctx->tile_view_dev);
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  delete ctx;
+}
+
+gsr_status gsr_plan(gsr_ctx *ctx, int64_t n, int n_views, const int32_t *wh_host, int64_t pair_capacity,
+                    size_t *workspace_bytes) {
+  if (!ctx) return GSR_E_INVALID;
+  if (n < 0 || n_views < 1 || !wh_host || pair_capacity < 1 || !workspace_bytes)
+    return fail(ctx, GSR_E_INVALID, "gsr_plan: invalid argument");
+  if (n_views > 256) return fail(ctx, GSR_E_UNSUPPORTED, "gsr_plan: at most 256 views per call");
+  if (pair_capacity >= (int64_t)0xFFFFFFFFll) return fail(ctx, GSR_E_UNSUPPORTED, "gsr_plan: pair capacity must be < 2^32 - 1");
+  if (n * (int64_t)n_views >= (int64_t)0xFFFFFFFFll) return fail(ctx, GSR_E_UNSUPPORTED, "gsr_plan: n * n_views must be < 2^32 - 1");
+  Plan p;
+  p.n = n;
+  p.n_views = n_views;
+  p.n_rec = n * n_views;
+  p.capacity = pair_capacity;
+  std::vector<ViewInfo> views(n_views);
+  int64_t tiles = 0, pixels = 0;
+  for (int v = 0; v < n_views; ++v) {
+    const int W = wh_host[2 * v], H = wh_host[2 * v + 1];
+    if (W < 1 || H < 1) return fail(ctx, GSR_E_INVALID, "gsr_plan: view size must be positive");
+    if (W > 65535 || H > 65535) return fail(ctx, GSR_E_UNSUPPORTED, "gsr_plan: view larger than 65535 px");
+    ViewInfo &vi = views[v];
+    vi.W = W;
+    vi.H = H;
+    vi.TX = (W + TILE - 1) / TILE;
+    vi.TY = (H + TILE - 1) / TILE;
+    vi.tile_off = (int32_t)tiles;
+    vi._pad = 0;
+    vi.pix_off = pixels;
+    tiles += (int64_t)vi.TX * vi.TY;
+    pixels += (int64_t)W * H;
+  }
+  if (tiles >= (1ll << 31)) return fail(ctx, GSR_E_UNSUPPORTED, "gsr_plan: too many tiles");
+  p.total_tiles = (int)tiles;
+  p.total_pixels = pixels;
+  int bits = 0;
+  while ((1ll << bits) < tiles) ++bits;
+  p.tile_bits = bits;
+  const int64_t sort_elems = std::max<int64_t>(p.capacity, p.n_rec);
+  p.max_sort_tiles = (int)((sort_elems + SORT_TILE - 1) / SORT_TILE);
+  p.n_scan_blocks = (int)std::max<int64_t>(1, (p.n_rec + SCAN_CHUNK - 1) / SCAN_CHUNK);
+  p.n_pose_blocks = (int)std::max<int64_t>(1, (n + BLOCK - 1) / BLOCK);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + std::max<size_t>(bytes, 1));
+    return o;
+  };
+  const size_t nr = (size_t)p.n_rec, cap = (size_t)p.capacity;
+  p.off_hdr = take(HDR_WORDS * 4);
+  p.off_recA = take(16 * nr);
+  p.off_recB = take(16 * nr);
+  p.off_recZ = take(4 * nr);
+  p.off_rect = take(8 * nr);
+  p.off_count = take(4 * nr);
+  for (int k = 0; k < 2; ++k) p.off_dkeys[k] = take(4 * nr);
+  for (int k = 0; k < 2; ++k) p.off_dvals[k] = take(4 * nr);
+  p.off_scan = take(8 * ((size_t)p.n_scan_blocks + 1));
+  for (int k = 0; k < 2; ++k) p.off_pkeys[k] = take(4 * cap);
+  for (int k = 0; k < 2; ++k) p.off_pvals[k] = take(4 * cap);
+  p.off_hist = take(4 * (size_t)RADIX * p.max_sort_tiles);
+  p.off_digit = take(4 * RADIX);
+  p.off_ranges = take(8 * (size_t)p.total_tiles);
+  p.off_T = take(4 * (size_t)pixels);
+  p.off_last = take(4 * (size_t)pixels);
+  p.off_nevals = take(4 * (size_t)pixels);
+  p.off_nblend = take(4 * (size_t)pixels);
+  p.off_counts = take(64);
+  p.off_grad2d = take(4 * NGRAD2D * nr);
+  p.off_pose = take(4 * 6 * (size_t)n_views * p.n_pose_blocks);
+  p.off_queue = take(4 * (size_t)p.total_tiles);
+  p.off_loss = take(4);
+  p.bytes = off;
+
+  gsr_status st = hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice");
+  if (st != GSR_OK) return st;
+  if (ctx->views_dev) (void)hipFree(ctx->views_dev);
+  if (ctx->tile_view_dev) (void)hipFree(ctx->tile_view_dev);
+  ctx->views_dev = nullptr;
+  ctx->tile_view_dev = nullptr;
+  ctx->planned = false;
+  std::vector<int32_t> tv(tiles);
+  for (int v = 0; v < n_views; ++v)
+    for (int64_t t = 0; t < (int64_t)views[v].TX * views[v].TY; ++t) tv[views[v].tile_off + t] = v;
+  st = hip_check(ctx, hipMalloc(reinterpret_cast<void **>(&ctx->views_dev), sizeof(ViewInfo) * n_views), "hipMalloc(views)");
+  if (st == GSR_OK) st = hip_check(ctx, hipMalloc(reinterpret_cast<void **>(&ctx->tile_view_dev), sizeof(int32_t) * tiles), "hipMalloc(tile_view)");
+  if (st == GSR_OK) st = hip_check(ctx, hipMemcpy(ctx->views_dev, views.data(), sizeof(ViewInfo) * n_views, hipMemcpyHostToDevice), "hipMemcpy(views)");
+  if (st == GSR_OK) st = hip_check(ctx, hipMemcpy(ctx->tile_view_dev, tv.data(), sizeof(int32_t) * tiles, hipMemcpyHostToDevice), "hipMemcpy(tile_view)");
+  if (st != GSR_OK) return st;
+  ctx->plan = p;
+  ctx->views_host = views;
+  ctx->planned = true;
+  ctx->last_forward_ws = nullptr;
+  *workspace_bytes = p.bytes;
+  return GSR_OK;
+}
+
+gsr_status gsr_render_forward(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams, int n_views,
+                              const gsr_config *cfg, void *workspace, size_t workspace_bytes,
+                              const gsr_images *out, gsr_stream stream) {
+  gsr_status st = validate(ctx, g, cams, n_views, cfg, workspace, workspace_bytes);
+  if (st != GSR_OK) return st;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Workspace ws = make_ws(ctx->plan, workspace);
+  prof_begin(ctx, s);
+  enqueue_lists(ctx, *g, cams, *cfg, ws, s);
+  prof_mark(ctx, s, GSR_STAGE_RANGES);
+  launch_render_forward(ctx->plan, ws, ctx->views_dev, ctx->tile_view_dev, *g, consts(*cfg), out, s);
+  prof_end(ctx, s, GSR_STAGE_RASTER);
+  if ((st = last_launch(ctx, "gsr_render_forward launch")) != GSR_OK) return st;
+  st = hip_check(ctx, hipMemcpyAsync(ctx->pinned, ws.hdr + HDR_NPAIRS, 8, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+  if (st == GSR_OK) st = hip_check(ctx, hipStreamSynchronize(s), "hipStreamSynchronize");
+  if (st != GSR_OK) return st;
+  ctx->last_forward_ws = workspace;
+  const int64_t pairs = (int64_t)ctx->pinned[0];
+  if (pairs > ctx->plan.capacity) {
+    ctx->required = pairs;
+    return fail(ctx, GSR_E_CAPACITY, "pair buffer too small: need " + std::to_string(pairs));
+  }
+  return GSR_OK;
+}
+
+gsr_status gsr_render_backward(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams, int n_views,
+                               const gsr_config *cfg, void *workspace, size_t workspace_bytes,
+                               const float *g_rgb, const float *g_depth, const float *g_T,
+                               const gsr_grads *grads, gsr_stream stream) {
+  gsr_status st = validate(ctx, g, cams, n_views, cfg, workspace, workspace_bytes);
+  if (st != GSR_OK) return st;
+  if (!g_rgb || !grads) return fail(ctx, GSR_E_INVALID, "gsr_render_backward: null gradient argument");
+  if (ctx->last_forward_ws != workspace)
+    return fail(ctx, GSR_E_STATE, "gsr_render_backward: workspace was not filled by the last forward");
+  if ((cfg->flags & GSR_GAUSS_GRAD) && (!grads->d_mean || !grads->d_log_scale || !grads->d_quat ||
+                                        !grads->d_opacity_logit || !grads->d_rgb))
+    return fail(ctx, GSR_E_INVALID, "GSR_GAUSS_GRAD needs every d_* pointer");
+  if ((cfg->flags & GSR_POSE_GRAD) && !grads->d_pose) return fail(ctx, GSR_E_INVALID, "GSR_POSE_GRAD needs d_pose");
+  if (grads->d_quat && reinterpret_cast<uintptr_t>(grads->d_quat) % 16)
+    return fail(ctx, GSR_E_INVALID, "d_quat must be 16-byte aligned");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Workspace ws = make_ws(ctx->plan, workspace);
+  const Plan &p = ctx->plan;
+  prof_begin(ctx, s);
+  for (int j = 0; j <= GSR_STAGE_RASTER; ++j) prof_mark(ctx, s, j);
+  launch_fill_f32(ws.grad2d, 0.f, p.n_rec * NGRAD2D, s);
+  launch_render_backward(p, ws, ctx->views_dev, ctx->tile_view_dev, *g, consts(*cfg), g_rgb, g_depth, g_T, s);
+  prof_mark(ctx, s, GSR_STAGE_RASTER_BWD);
+  launch_preprocess_backward(p, *g, cams, *cfg, ws, *grads, s);
+  prof_end(ctx, s, GSR_STAGE_PREGRAD);
+  return last_launch(ctx, "gsr_render_backward launch");
+}
+
+gsr_status gsr_l1_loss_grad(gsr_ctx *ctx, const float *rgb, const float *depth, const float *target_rgb,
+                            const float *target_depth, const uint8_t *pixel_mask, float w_rgb, float w_depth,
+                            float *g_rgb, float *g_depth, float *loss, gsr_stream stream) {
+  if (!ctx) return GSR_E_INVALID;
+  if (!ctx->planned) return fail(ctx, GSR_E_STATE, "gsr_plan() has not been called");
+  if (!rgb || !depth || !target_rgb || !target_depth || !g_rgb || !g_depth)
+    return fail(ctx, GSR_E_INVALID, "gsr_l1_loss_grad: null argument");
+  launch_l1(ctx->plan, ctx->views_dev, rgb, depth, target_rgb, target_depth, pixel_mask, w_rgb, w_depth, g_rgb,
+            g_depth, loss, static_cast<hipStream_t>(stream));
+  return last_launch(ctx, "gsr_l1_loss_grad launch");
+}
+
+static gsr_status fused_checks(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams, int n_views,
+                               const gsr_config *cfg, const float *t_rgb, const float *t_depth, void *ws,
+                               size_t ws_bytes, const gsr_grads *grads) {
+  gsr_status st = validate(ctx, g, cams, n_views, cfg, ws, ws_bytes);
+  if (st != GSR_OK) return st;
+  if (!t_rgb || !t_depth || !grads) return fail(ctx, GSR_E_INVALID, "fused step: null target or gradient argument");
+  if ((cfg->flags & GSR_GAUSS_GRAD) && (!grads->d_mean || !grads->d_log_scale || !grads->d_quat ||
+                                        !grads->d_opacity_logit || !grads->d_rgb))
+    return fail(ctx, GSR_E_INVALID, "GSR_GAUSS_GRAD needs every d_* pointer");
+  if ((cfg->flags & GSR_POSE_GRAD) && !grads->d_pose) return fail(ctx, GSR_E_INVALID, "GSR_POSE_GRAD needs d_pose");
+  if (grads->d_quat && reinterpret_cast<uintptr_t>(grads->d_quat) % 16)
+    return fail(ctx, GSR_E_INVALID, "d_quat must be 16-byte aligned");
+  return GSR_OK;
+}
+
+gsr_status gsr_render_l1_fused(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams, int n_views,
+                               const gsr_config *cfg, const float *target_rgb, const float *target_depth,
+                               const uint8_t *pixel_mask, float w_rgb, float w_depth, void *workspace,
+                               size_t workspace_bytes, const gsr_images *out, const gsr_grads *grads,
+                               float *loss, gsr_stream stream) {
+  gsr_status st = fused_checks(ctx, g, cams, n_views, cfg, target_rgb, target_depth, workspace, workspace_bytes, grads);
+  if (st != GSR_OK) return st;
+  Workspace ws = make_ws(ctx->plan, workspace);
+  enqueue_fused(ctx, *g, cams, *cfg, target_rgb, target_depth, pixel_mask, w_rgb, w_depth, ws, out, *grads, loss,
+                static_cast<hipStream_t>(stream));
+  ctx->last_forward_ws = nullptr;
+  return last_launch(ctx, "gsr_render_l1_fused launch");
+}
+
+gsr_status gsr_graph_capture(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams, int n_views,
+                             const gsr_config *cfg, const float *target_rgb, const float *target_depth,
+                             const uint8_t *pixel_mask, float w_rgb, float w_depth, void *workspace,
+                             size_t workspace_bytes, const gsr_images *out, const gsr_grads *grads, float *loss,
+                             gsr_stream stream) {
+  gsr_status st = fused_checks(ctx, g, cams, n_views, cfg, target_rgb, target_depth, workspace, workspace_bytes, grads);
+  if (st != GSR_OK) return st;
+  if (!stream) return fail(ctx, GSR_E_INVALID, "gsr_graph_capture needs a non-null stream");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (ctx->gexec) (void)hipGraphExecDestroy(ctx->gexec);
+  if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+  ctx->gexec = nullptr;
+  ctx->graph = nullptr;
+  st = hip_check(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+  if (st != GSR_OK) return st;
+  Workspace ws = make_ws(ctx->plan, workspace);
+  const bool prof = ctx->profiling;
+  ctx->profiling = false;  // no event records inside a captured graph
+  enqueue_fused(ctx, *g, cams, *cfg, target_rgb, target_depth, pixel_mask, w_rgb, w_depth, ws, out, *grads, loss, s);
+  ctx->profiling = prof;
+  hipGraph_t graph = nullptr;
+  st = hip_check(ctx, hipStreamEndCapture(s, &graph), "hipStreamEndCapture");
+  if (st != GSR_OK) return st;
+  hipGraphExec_t exec = nullptr;
+  st = hip_check(ctx, hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+  if (st != GSR_OK) {
+    (void)hipGraphDestroy(graph);
+    return st;
+  }
+  ctx->graph = graph;
+  ctx->gexec = exec;
+  ctx->last_forward_ws = nullptr;
+  return GSR_OK;
+}
+
+gsr_status gsr_graph_launch(gsr_ctx *ctx, gsr_stream stream) {
+  if (!ctx) return GSR_E_INVALID;
+  if (!ctx->gexec) return fail(ctx, GSR_E_STATE, "no captured graph");
+  return hip_check(ctx, hipGraphLaunch(ctx->gexec, static_cast<hipStream_t>(stream)), "hipGraphLaunch");
+}
+
+gsr_status gsr_check_overflow(gsr_ctx *ctx, void *workspace, gsr_stream stream) {
+  if (!ctx) return GSR_E_INVALID;
+  if (!ctx->planned || !workspace) return fail(ctx, GSR_E_STATE, "gsr_check_overflow: no plan or workspace");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Workspace ws = make_ws(ctx->plan, workspace);
+  gsr_status st = hip_check(ctx, hipMemcpyAsync(ctx->pinned, ws.hdr, 24, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+  if (st == GSR_OK) st = hip_check(ctx, hipStreamSynchronize(s), "hipStreamSynchronize");
+  if (st != GSR_OK) return st;
+  const uint32_t flag = static_cast<uint32_t>(ctx->pinned[2] & 0xFFFFFFFFull);
+  if (flag) {
+    ctx->required = (int64_t)ctx->pinned[1];
+    launch_fill_u32(ws.hdr + HDR_REQUIRED, 0u, 3, s);
+    st = hip_check(ctx, hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (st != GSR_OK) return st;
+    return fail(ctx, GSR_E_CAPACITY, "pair buffer too small: need " + std::to_string(ctx->required));
+  }
+  return GSR_OK;
+}
+
+int64_t gsr_required_pairs(const gsr_ctx *ctx) { return ctx ? ctx->required : 0; }
+
+int64_t gsr_pair_count(gsr_ctx *ctx, void *workspace, gsr_stream stream) {
+  if (!ctx || !ctx->planned || !workspace) return -1;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Workspace ws = make_ws(ctx->plan, workspace);
+  if (hipMemcpyAsync(ctx->pinned, ws.hdr + HDR_NPAIRS, 8, hipMemcpyDeviceToHost, s) != hipSuccess) return -1;
+  if (hipStreamSynchronize(s) != hipSuccess) return -1;
+  return (int64_t)ctx->pinned[0];
+}
+
+gsr_status gsr_debug_tiles(gsr_ctx *ctx, void *workspace, const int32_t **tile_ranges, const uint32_t **sorted_ids,
+                           int64_t *total_tiles) {
+  if (!ctx) return GSR_E_INVALID;
+  if (!ctx->planned || !workspace) return fail(ctx, GSR_E_STATE, "gsr_debug_tiles: no plan or workspace");
+  Workspace ws = make_ws(ctx->plan, workspace);
+  if (tile_ranges) *tile_ranges = reinterpret_cast<const int32_t *>(ws.ranges);
+  if (sorted_ids) *sorted_ids = ws.pvals[ws.psorted];
+  if (total_tiles) *total_tiles = ctx->plan.total_tiles;
+  return GSR_OK;
+}
+
+gsr_status gsr_get_tuning(const gsr_ctx *ctx, gsr_tuning *out) {
+  if (!ctx || !out) return GSR_E_INVALID;
+  out->blocks_per_cu = ctx->tuning.blocks_per_cu;
+  out->tiles_per_pop = ctx->tuning.tiles_per_pop;
+  out->lpt_order = ctx->tuning.lpt_order;
+  out->_reserved = 0;
+  return GSR_OK;
+}
+
+gsr_status gsr_set_tuning(gsr_ctx *ctx, const gsr_tuning *t) {
+  if (!ctx || !t) return GSR_E_INVALID;
+  if (t->blocks_per_cu < 1 || t->blocks_per_cu > 8 || t->tiles_per_pop < 1 || t->tiles_per_pop > 8)
+    return fail(ctx, GSR_E_INVALID, "tuning out of range");
+  ctx->tuning.blocks_per_cu = t->blocks_per_cu;
+  ctx->tuning.tiles_per_pop = t->tiles_per_pop;
+  ctx->tuning.lpt_order = t->lpt_order ? 1 : 0;
+  return GSR_OK;
+}
+
+gsr_status gsr_autotune(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams, int n_views,
+                        const gsr_config *cfg, const float *target_rgb, const float *target_depth,
+                        const uint8_t *pixel_mask, float w_rgb, float w_depth, void *workspace,
+                        size_t workspace_bytes, const gsr_grads *grads, float *loss, int reps, gsr_tuning *best,
+                        gsr_stream stream) {
+  gsr_status st = fused_checks(ctx, g, cams, n_views, cfg, target_rgb, target_depth, workspace, workspace_bytes, grads);
+  if (st != GSR_OK) return st;
+  if (reps < 1) reps = 1;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Workspace ws = make_ws(ctx->plan, workspace);
+  const Plan &p = ctx->plan;
+  enqueue_lists(ctx, *g, cams, *cfg, ws, s);
+  hipEvent_t e0, e1;
+  if ((st = hip_check(ctx, hipEventCreate(&e0), "hipEventCreate")) != GSR_OK) return st;
+  if ((st = hip_check(ctx, hipEventCreate(&e1), "hipEventCreate")) != GSR_OK) {
+    (void)hipEventDestroy(e0);
+    return st;
+  }
+  const Tuning saved = ctx->tuning;
+  Tuning best_t = saved;
+  float best_ms = 1e30f;
+  const int bpcs[] = {1, 2, 3, 4, 6, 8};
+  const int pops[] = {1, 2, 4};
+  for (int lpt = 0; lpt <= 1 && st == GSR_OK; ++lpt)
+    for (int bpc : bpcs)
+      for (int pop : pops) {
+        Tuning t;
+        t.blocks_per_cu = bpc;
+        t.tiles_per_pop = pop;
+        t.lpt_order = lpt;
+        float total = 0.f;
+        for (int r = 0; r <= reps && st == GSR_OK; ++r) {
+          launch_fill_u32(ws.hdr + HDR_QUEUE, 0u, 1, s);
+          launch_queue_order(p, ws, lpt, s);
+          launch_fill_f32(ws.grad2d, 0.f, p.n_rec * NGRAD2D, s);
+          (void)hipEventRecord(e0, s);
+          launch_render_fused(p, ws, ctx->views_dev, ctx->tile_view_dev, *g, consts(*cfg), target_rgb, target_depth,
+                              pixel_mask, w_rgb, w_depth, nullptr, loss, t, ctx->num_cus, s);
+          (void)hipEventRecord(e1, s);
+          st = hip_check(ctx, hipEventSynchronize(e1), "hipEventSynchronize");
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          if (r > 0) total += ms;  // first run is a warm-up
+        }
+        if (st == GSR_OK && total / reps < best_ms) {
+          best_ms = total / reps;
+          best_t = t;
+        }
+      }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != GSR_OK) return st;
+  ctx->tuning = best_t;
+  if (best) (void)gsr_get_tuning(ctx, best);
+  ctx->last_forward_ws = nullptr;
+  return last_launch(ctx, "gsr_autotune");
+}
+
+gsr_status gsr_set_profiling(gsr_ctx *ctx, int enable) {
+  if (!ctx) return GSR_E_INVALID;
+  if (enable && ctx->ev_pool.empty()) {
+    ctx->ev_pool.resize((size_t)NEV * 64);
+    for (auto &e : ctx->ev_pool) {
+      gsr_status st = hip_check(ctx, hipEventCreate(&e), "hipEventCreate");
+      if (st != GSR_OK) return st;
+    }
+  }
+  ctx->profiling = enable != 0;
+  return GSR_OK;
+}
+
+gsr_status gsr_stage_times(gsr_ctx *ctx, double *ms, int64_t *calls) {
+  if (!ctx || !ms) return GSR_E_INVALID;
+  gsr_status st = drain_events(ctx);
+  if (st != GSR_OK) return st;
+  for (int j = 0; j < GSR_NSTAGES; ++j) {
+    ms[j] = ctx->stage_ms[j];
+    ctx->stage_ms[j] = 0.0;
+  }
+  if (calls) *calls = ctx->timed_calls;
+  ctx->timed_calls = 0;
+  return GSR_OK;
+}
+
+gsr_status gsr_work_counts(gsr_ctx *ctx, void *workspace, gsr_stream stream, int64_t *out) {
+  if (!ctx || !out) return GSR_E_INVALID;
+  if (!ctx->planned || !workspace) return fail(ctx, GSR_E_STATE, "gsr_work_counts: no plan or workspace");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Workspace ws = make_ws(ctx->plan, workspace);
+  launch_work_counts(ctx->plan, ws, s);
+  unsigned long long host[4];
+  gsr_status st = hip_check(ctx, hipMemcpyAsync(host, ws.counts, sizeof(host), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+  if (st == GSR_OK) st = hip_check(ctx, hipStreamSynchronize(s), "hipStreamSynchronize");
+  if (st != GSR_OK) return st;
+  for (int k = 0; k < 4; ++k) out[k] = (int64_t)host[k];
+  return GSR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,158 @@
+// Internal declarations of the gfx950 splatting renderer: the view table,
+// the workspace layout, device helpers shared by the kernels, and the kernel
+// launchers the C ABI calls.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gsr.h"
+
+namespace gsr {
+
+constexpr int TILE = 16;          // tile edge in pixels
+constexpr int BLOCK = 256;        // one thread per pixel of a tile
+constexpr int NGRAD2D = 10;       // u, v, conic a, b, c, opacity, r, g, b, depth
+constexpr int SORT_ITEMS = 8;     // keys per thread per sort tile
+constexpr int SORT_TILE = BLOCK * SORT_ITEMS;
+constexpr int RADIX_BITS = 8;
+constexpr int RADIX = 1 << RADIX_BITS;
+constexpr int SCAN_ITEMS = 8;
+constexpr int SCAN_CHUNK = BLOCK * SCAN_ITEMS;
+
+// Per-view geometry of the concatenated output (device copy lives in the
+// context, written at plan time).
+struct ViewInfo {
+  int32_t W, H, TX, TY;
+  int32_t tile_off;   // first global tile id of the view
+  int32_t _pad;
+  int64_t pix_off;    // first pixel of the view in the concatenated images
+};
+
+// Header words at the start of the workspace.
+enum HeaderWord {
+  HDR_NPAIRS = 0,      // u64 (words 0-1): pairs produced by the last forward
+  HDR_REQUIRED = 2,    // u64 (words 2-3): largest pair count seen that overflowed
+  HDR_OVERFLOW = 4,    // u32: set when a forward overflowed the pair buffer
+  HDR_QUEUE = 5,       // u32: persistent rasteriser work counter
+  HDR_FWD_DONE = 6,    // u32: marker that a forward filled this workspace
+  HDR_WORDS = 64
+};
+
+// Device pointers into the caller's workspace (computed on the host).
+struct Workspace {
+  uint32_t *hdr;
+  float4 *recA;            // [n_rec] (u_hi, u_lo, v_hi, v_lo)
+  float4 *recB;            // [n_rec] (conic a, b, c, opacity)
+  float *recZ;             // [n_rec] camera-frame depth
+  ushort4 *rect;           // [n_rec] (tx0, tx1, ty0, ty1), local tile coordinates
+  uint32_t *count;         // [n_rec] tiles touched (0 = culled)
+  uint32_t *dkeys[2];      // [n_rec] depth keys (float32 bits), ping-pong
+  uint32_t *dvals[2];      // [n_rec] record ids, ping-pong
+  unsigned long long *scan_part;  // [n_scan_blocks + 1]
+  uint32_t *pkeys[2];      // [capacity] global tile ids, ping-pong
+  uint32_t *pvals[2];      // [capacity] record ids, ping-pong
+  uint32_t *hist;          // [RADIX][max_sort_tiles]
+  uint32_t *digit_total;   // [RADIX]
+  int2 *ranges;            // [total_tiles]
+  float *T_final;          // [total_pixels]
+  int32_t *last;           // [total_pixels]
+  int32_t *nevals;         // [total_pixels] entries the forward walk examined
+  int32_t *nblend;         // [total_pixels] entries blended
+  unsigned long long *counts;  // [4] work totals (gsr_work_counts)
+  float *grad2d;           // [n_rec][NGRAD2D]
+  float *pose_part;        // [n_pose_blocks][n_views][6]
+  uint32_t *queue;         // [total_tiles] work order of the persistent rasteriser
+  float *loss_part;        // [1] (unused slot kept for alignment)
+  int dsorted;             // which depth buffer holds the sorted result
+  int psorted;             // which pair buffer holds the sorted result
+};
+
+struct Plan {
+  int64_t n = 0;
+  int n_views = 0;
+  int64_t n_rec = 0;
+  int total_tiles = 0;
+  int64_t total_pixels = 0;
+  int64_t capacity = 0;
+  int tile_bits = 0;
+  int max_sort_tiles = 0;
+  int n_scan_blocks = 0;
+  int n_pose_blocks = 0;
+  size_t bytes = 0;
+  // byte offsets inside the workspace
+  size_t off_hdr, off_recA, off_recB, off_recZ, off_rect, off_count, off_dkeys[2], off_dvals[2],
+      off_scan, off_pkeys[2], off_pvals[2], off_hist, off_digit, off_ranges, off_T, off_last,
+      off_grad2d, off_pose, off_queue, off_loss, off_nevals, off_nblend, off_counts;
+};
+
+struct Tuning {
+  int blocks_per_cu = 2;
+  int tiles_per_pop = 1;
+  int lpt_order = 1;
+};
+
+// Scalar renderer constants passed by value to kernels.
+struct RenderConsts {
+  float alpha_min, alpha_max, T_min;
+  float bg[3];
+};
+
+// ---------------------------------------------------------------- device helpers
+
+__device__ __forceinline__ float wave_sum(float v) {
+  // Butterfly over the 64 lanes of a wavefront.
+  v += __shfl_xor(v, 32);
+  v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 8);
+  v += __shfl_xor(v, 4);
+  v += __shfl_xor(v, 2);
+  v += __shfl_xor(v, 1);
+  return v;
+}
+
+__device__ __forceinline__ unsigned long long lanemask_lt() {
+  const unsigned lane = __lane_id();
+  return lane == 0 ? 0ull : (~0ull >> (64 - lane));
+}
+
+// --------------------------------------------------------------- launchers (host)
+
+// Preprocess (projection, binning data, depth keys) for every (view, Gaussian).
+void launch_preprocess(const gsr_gaussians &g, const gsr_camera *cams, const ViewInfo *views,
+                       int n_views, const gsr_config &cfg, const Workspace &ws, hipStream_t s);
+
+// Sorting and list construction.
+int launch_depth_sort(const Plan &p, Workspace &ws, hipStream_t s, int sort_grid);
+void launch_emit_pairs(const Plan &p, const Workspace &ws, const ViewInfo *views, hipStream_t s);
+int launch_pair_sort(const Plan &p, Workspace &ws, hipStream_t s, int sort_grid);
+void launch_tile_ranges(const Plan &p, const Workspace &ws, hipStream_t s);
+void launch_fill_u32(uint32_t *ptr, uint32_t value, int64_t count, hipStream_t s);
+void launch_fill_f32(float *ptr, float value, int64_t count, hipStream_t s);
+void launch_reset_header(const Workspace &ws, hipStream_t s);
+void launch_queue_order(const Plan &p, const Workspace &ws, int lpt, hipStream_t s);
+
+// Rasterisation.
+void launch_render_forward(const Plan &p, const Workspace &ws, const ViewInfo *views,
+                           const int32_t *tile_view, const gsr_gaussians &g, const RenderConsts &rc,
+                           const gsr_images *out, hipStream_t s);
+void launch_render_backward(const Plan &p, const Workspace &ws, const ViewInfo *views,
+                            const int32_t *tile_view, const gsr_gaussians &g, const RenderConsts &rc,
+                            const float *g_rgb, const float *g_depth, const float *g_T,
+                            hipStream_t s);
+void launch_render_fused(const Plan &p, const Workspace &ws, const ViewInfo *views,
+                         const int32_t *tile_view, const gsr_gaussians &g, const RenderConsts &rc,
+                         const float *t_rgb, const float *t_depth, const uint8_t *pmask,
+                         float w_rgb, float w_depth, const gsr_images *out, float *loss,
+                         const Tuning &tun, int num_cus, hipStream_t s);
+void launch_work_counts(const Plan &p, const Workspace &ws, hipStream_t s);
+void launch_l1(const Plan &p, const ViewInfo *views, const float *rgb, const float *depth,
+               const float *t_rgb, const float *t_depth, const uint8_t *pmask, float w_rgb,
+               float w_depth, float *g_rgb, float *g_depth, float *loss, hipStream_t s);
+
+// Backward preprocess (chain to parameters and pose).
+void launch_preprocess_backward(const Plan &p, const gsr_gaussians &g, const gsr_camera *cams,
+                                const gsr_config &cfg, const Workspace &ws, const gsr_grads &gr,
+                                hipStream_t s);
+
+}  // namespace gsr

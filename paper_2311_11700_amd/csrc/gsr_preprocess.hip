@@ -1,0 +1,153 @@
+// Per-(view, Gaussian) projection: camera-frame centre, EWA screen-space
+// covariance and its conic, opacity, tile rectangle and depth sort key
+// (GS-SLAM Eq. 2-3, supplement eq. q2R).
+//
+// Forward geometry runs in FP64: gfx950 executes FP64 vector arithmetic at
+// the FP32 non-packed rate, and computing the binning quantities (depth sort
+// key, tile rectangle) in FP64 with contraction disabled makes them agree bit
+// for bit with an FP64 reference evaluated in the same order.  The values the
+// rasteriser consumes are rounded to FP32 once, at the end.
+#pragma clang fp contract(off)
+
+#include <math.h>
+
+#include "gsr_internal.h"
+
+namespace gsr {
+
+struct PreConsts {
+  float z_near, lowpass, cutoff;
+  uint32_t flags;
+};
+
+// Rotation matrix of a unit quaternion (w, x, y, z) (GS-SLAM supplement,
+// eq. q2R), row-major.
+template <typename T>
+__device__ __forceinline__ void quat_rot(T w, T x, T y, T z, T R[9]) {
+  R[0] = T(1) - T(2) * (y * y + z * z);
+  R[1] = T(2) * (x * y - w * z);
+  R[2] = T(2) * (x * z + w * y);
+  R[3] = T(2) * (x * y + w * z);
+  R[4] = T(1) - T(2) * (x * x + z * z);
+  R[5] = T(2) * (y * z - w * x);
+  R[6] = T(2) * (x * z - w * y);
+  R[7] = T(2) * (y * z + w * x);
+  R[8] = T(1) - T(2) * (x * x + y * y);
+}
+
+__global__ __launch_bounds__(BLOCK) void k_preprocess(gsr_gaussians g,
+                                                      const gsr_camera *__restrict__ cams,
+                                                      const ViewInfo *__restrict__ views,
+                                                      PreConsts pc, Workspace ws) {
+  const int view = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= g.n) return;
+  const int64_t rec = (int64_t)view * g.n + i;
+  const ViewInfo vi = views[view];
+  const gsr_camera &cam = cams[view];
+
+  const float fm0 = g.mean[3 * i], fm1 = g.mean[3 * i + 1], fm2 = g.mean[3 * i + 2];
+  const float fl0 = g.log_scale[3 * i], fl1 = g.log_scale[3 * i + 1], fl2 = g.log_scale[3 * i + 2];
+  const float4 fq = reinterpret_cast<const float4 *>(g.quat)[i];
+  const float fop = g.opacity_logit[i];
+  const float fc0 = g.rgb[3 * i], fc1 = g.rgb[3 * i + 1], fc2 = g.rgb[3 * i + 2];
+
+  bool ok = isfinite(fm0) && isfinite(fm1) && isfinite(fm2) && isfinite(fl0) && isfinite(fl1) &&
+            isfinite(fl2) && isfinite(fq.x) && isfinite(fq.y) && isfinite(fq.z) && isfinite(fq.w) &&
+            isfinite(fop) && isfinite(fc0) && isfinite(fc1) && isfinite(fc2);
+  if (g.mask) ok = ok && g.mask[i] != 0;
+
+  // Camera-frame centre, each row summed left to right (this is the exact
+  // sequence behind the float32 depth key).
+  const double mx = fm0, my = fm1, mz = fm2;
+  const double W0 = cam.R[0], W1 = cam.R[1], W2 = cam.R[2], W3 = cam.R[3], W4 = cam.R[4],
+               W5 = cam.R[5], W6 = cam.R[6], W7 = cam.R[7], W8 = cam.R[8];
+  const double x = ((W0 * mx + W1 * my) + W2 * mz) + (double)cam.t[0];
+  const double y = ((W3 * mx + W4 * my) + W5 * mz) + (double)cam.t[1];
+  const double z = ((W6 * mx + W7 * my) + W8 * mz) + (double)cam.t[2];
+  ok = ok && (z > (double)pc.z_near);
+
+  // Covariance (Eq. 2).
+  double qw = fq.x, qx = fq.y, qy = fq.z, qz = fq.w;
+  const double qn = sqrt(((qw * qw + qx * qx) + qy * qy) + qz * qz);
+  ok = ok && (qn > 0.0);
+  double Rq[9];
+  {
+    const double inv = ok ? qn : 1.0;
+    qw /= inv; qx /= inv; qy /= inv; qz /= inv;
+    quat_rot<double>(qw, qx, qy, qz, Rq);
+  }
+  const double s0 = exp((double)fl0), s1 = exp((double)fl1), s2 = exp((double)fl2);
+  const double q0 = s0 * s0, q1 = s1 * s1, q2 = s2 * s2;
+  double S[9];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c)
+      S[3 * r + c] = (Rq[3 * r] * q0 * Rq[3 * c] + Rq[3 * r + 1] * q1 * Rq[3 * c + 1]) +
+                     Rq[3 * r + 2] * q2 * Rq[3 * c + 2];
+  // Camera-frame covariance W S W^T.
+  const double Wm[9] = {W0, W1, W2, W3, W4, W5, W6, W7, W8};
+  double M[9], Sc[9];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c)
+      M[3 * r + c] = (Wm[3 * r] * S[c] + Wm[3 * r + 1] * S[3 + c]) + Wm[3 * r + 2] * S[6 + c];
+  for (int r = 0; r < 3; ++r)
+    for (int c = 0; c < 3; ++c)
+      Sc[3 * r + c] = (M[3 * r] * Wm[3 * c] + M[3 * r + 1] * Wm[3 * c + 1]) + M[3 * r + 2] * Wm[3 * c + 2];
+  // EWA projection (Eq. 3): J = [[fx/z, 0, -fx x/z^2], [0, fy/z, -fy y/z^2]].
+  const double fx = cam.fx, fy = cam.fy;
+  const double zz = ok ? z : 1.0;
+  const double J00 = fx / zz, J02 = -(fx * x) / (zz * zz);
+  const double J11 = fy / zz, J12 = -(fy * y) / (zz * zz);
+  const double T00 = J00 * Sc[0] + J02 * Sc[6], T01 = J00 * Sc[1] + J02 * Sc[7],
+               T02 = J00 * Sc[2] + J02 * Sc[8];
+  const double T11 = J11 * Sc[4] + J12 * Sc[7], T12 = J11 * Sc[5] + J12 * Sc[8];
+  const double A = (T00 * J00 + T02 * J02) + (double)pc.lowpass;
+  const double B = T01 * J11 + T02 * J12;
+  const double C = (T11 * J11 + T12 * J12) + (double)pc.lowpass;
+  const double det = A * C - B * B;
+  ok = ok && (det > 0.0);
+
+  const double u = (fx * x) / zz + (double)cam.cx;
+  const double v = (fy * y) / zz + (double)cam.cy;
+
+  int tx0 = 0, tx1 = vi.TX - 1, ty0 = 0, ty1 = vi.TY - 1;
+  if (!(pc.flags & GSR_FULL_RECT) && ok) {
+    const double rx = (double)pc.cutoff * sqrt(A), ry = (double)pc.cutoff * sqrt(C);
+    const double bx0 = floor((u - rx) / (double)TILE), bx1 = floor((u + rx) / (double)TILE);
+    const double by0 = floor((v - ry) / (double)TILE), by1 = floor((v + ry) / (double)TILE);
+    const double cx0 = fmax(0.0, bx0), cx1 = fmin((double)(vi.TX - 1), bx1);
+    const double cy0 = fmax(0.0, by0), cy1 = fmin((double)(vi.TY - 1), by1);
+    ok = ok && (cx0 <= cx1) && (cy0 <= cy1);
+    if (ok) {
+      tx0 = (int)cx0; tx1 = (int)cx1; ty0 = (int)cy0; ty1 = (int)cy1;
+    }
+  }
+
+  if (!ok) {
+    ws.count[rec] = 0u;
+    ws.dkeys[0][rec] = 0xFFFFFFFFu;
+    ws.dvals[0][rec] = (uint32_t)rec;
+    ws.rect[rec] = make_ushort4(1, 0, 1, 0);
+    return;
+  }
+  const float zf = (float)z;
+  const float uh = (float)u, vh = (float)v;
+  const float op = (float)(1.0 / (1.0 + exp(-(double)fop)));
+  ws.recA[rec] = make_float4(uh, (float)(u - (double)uh), vh, (float)(v - (double)vh));
+  ws.recB[rec] = make_float4((float)(C / det), (float)(-B / det), (float)(A / det), op);
+  ws.recZ[rec] = zf;
+  ws.rect[rec] = make_ushort4((unsigned short)tx0, (unsigned short)tx1, (unsigned short)ty0,
+                              (unsigned short)ty1);
+  ws.count[rec] = (uint32_t)(tx1 - tx0 + 1) * (uint32_t)(ty1 - ty0 + 1);
+  ws.dkeys[0][rec] = __float_as_uint(zf);
+  ws.dvals[0][rec] = (uint32_t)rec;
+}
+
+void launch_preprocess(const gsr_gaussians &g, const gsr_camera *cams, const ViewInfo *views,
+                       int n_views, const gsr_config &cfg, const Workspace &ws, hipStream_t s) {
+  PreConsts pc{cfg.z_near, cfg.lowpass, cfg.cutoff_sigma, cfg.flags};
+  dim3 grid((unsigned)((g.n + BLOCK - 1) / BLOCK), (unsigned)n_views);
+  if (g.n > 0) hipLaunchKernelGGL(k_preprocess, grid, dim3(BLOCK), 0, s, g, cams, views, pc, ws);
+}
+
+}  // namespace gsr

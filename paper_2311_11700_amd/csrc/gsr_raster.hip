@@ -1,0 +1,537 @@
+// Per-tile compositing: front-to-back alpha blending of colour and depth
+// (GS-SLAM Eq. 4-5), its backward pass (supplement eq. grad_depth and the
+// colour analogue), and the weighted L1 loss gradient (Eq. 6 / Eq. 10).
+//
+// One 256-thread block (four wave64) renders one 16x16 tile, one thread per
+// pixel.  The tile's Gaussians are staged through LDS in batches: each
+// thread loads one record, converts its centre to tile-relative FP32
+// coordinates (the record keeps the centre as a float pair, so the offset to
+// a pixel keeps full precision even at x ~ 1000 px), and pre-scales the
+// conic so that alpha = min(alpha_max, o * 2^P) with
+// P = a'' dx^2 + 2 b'' dx dy + c'' dy^2 and (a'', b'', c'') = -log2(e)/2 * conic.
+// The forward and the backward evaluate alpha with the same inlined
+// function and contraction disabled, so both take every threshold decision
+// identically.
+#pragma clang fp contract(off)
+
+#include "gsr_internal.h"
+
+namespace gsr {
+
+constexpr int BATCH = 256;
+constexpr float NEG_HALF_LOG2E = -0.72134752044448170368f;  // -log2(e) / 2
+constexpr float LN2 = 0.69314718055994530942f;
+
+struct Staged {
+  float4 geo;  // (u_rel, v_rel, opacity, depth)
+  float4 con;  // (a'', b'', c'', unused)
+  float4 col;  // (r, g, b, unused)
+};
+
+struct TileInfo {
+  int view;
+  int tx, ty;
+  int W, H;
+  int64_t pix;     // global pixel index of this thread (valid if inside)
+  int64_t HW;      // pixels of the view
+  int64_t pix_off; // first pixel of the view
+  bool inside;
+  int2 range;
+  float x0, y0;
+};
+
+__device__ __forceinline__ TileInfo tile_info(int tile, const ViewInfo *__restrict__ views,
+                                              const int32_t *__restrict__ tile_view,
+                                              const int2 *__restrict__ ranges) {
+  TileInfo ti;
+  ti.view = tile_view[tile];
+  const ViewInfo vi = views[ti.view];
+  const int local = tile - vi.tile_off;
+  ti.ty = local / vi.TX;
+  ti.tx = local - ti.ty * vi.TX;
+  ti.W = vi.W;
+  ti.H = vi.H;
+  const int px = ti.tx * TILE + (threadIdx.x & (TILE - 1));
+  const int py = ti.ty * TILE + (threadIdx.x >> 4);
+  ti.inside = px < vi.W && py < vi.H;
+  ti.HW = (int64_t)vi.W * vi.H;
+  ti.pix_off = vi.pix_off;
+  ti.pix = vi.pix_off + (int64_t)py * vi.W + px;
+  ti.range = ranges[tile];
+  ti.x0 = (float)(ti.tx * TILE);
+  ti.y0 = (float)(ti.ty * TILE);
+  return ti;
+}
+
+// Load the record of list position `pos` into this thread's staging slot.
+__device__ __forceinline__ Staged stage_record(uint32_t id, int view, int64_t n, float x0, float y0,
+                                               const float4 *__restrict__ recA,
+                                               const float4 *__restrict__ recB,
+                                               const float *__restrict__ recZ,
+                                               const float *__restrict__ rgb) {
+  const float4 A = recA[id];
+  const float4 Bc = recB[id];
+  const int64_t gi = (int64_t)id - (int64_t)view * n;
+  Staged s;
+  // (u_hi - x0) is exact for |u_hi| < 2^24 and integer x0; the low word adds
+  // the remaining bits.
+  s.geo = make_float4((A.x - x0) + A.y, (A.z - y0) + A.w, Bc.w, recZ[id]);
+  s.con = make_float4(NEG_HALF_LOG2E * Bc.x, NEG_HALF_LOG2E * Bc.y, NEG_HALF_LOG2E * Bc.z, 0.f);
+  s.col = make_float4(rgb[3 * gi], rgb[3 * gi + 1], rgb[3 * gi + 2], 0.f);
+  return s;
+}
+
+// alpha of a staged Gaussian at pixel offset (dx, dy) = centre - pixel.
+__device__ __forceinline__ float splat_alpha(const float4 &geo, const float4 &con, float dx, float dy,
+                                             float alpha_max, float &G, float &oG) {
+  const float t = __fmaf_rn(con.x, dx, 2.f * con.y * dy);
+  const float P = __fmaf_rn(con.z * dy, dy, dx * t);
+  G = __builtin_amdgcn_exp2f(P);
+  oG = geo.z * G;
+  return fminf(alpha_max, oG);
+}
+
+// ------------------------------------------------------------------ forward
+
+struct FwdState {
+  float T, C0, C1, C2, D;
+  int last;
+  int nev;   // list entries examined (including the one that stopped the pixel)
+  int nbl;   // entries blended
+  bool done;
+};
+
+__device__ __forceinline__ void tile_forward(const TileInfo &ti, int64_t n, const float4 *__restrict__ recA,
+                                             const float4 *__restrict__ recB,
+                                             const float *__restrict__ recZ,
+                                             const float *__restrict__ rgb,
+                                             const uint32_t *__restrict__ ids, const RenderConsts &rc,
+                                             Staged *s_rec, FwdState &st) {
+  st.T = 1.f;
+  st.C0 = st.C1 = st.C2 = st.D = 0.f;
+  st.last = 0;
+  st.nev = 0;
+  st.nbl = 0;
+  st.done = !ti.inside;
+  const float lx = (float)(threadIdx.x & (TILE - 1));
+  const float ly = (float)(threadIdx.x >> 4);
+  for (int base = ti.range.x; base < ti.range.y; base += BATCH) {
+    if (__syncthreads_and(st.done)) break;
+    const int pos = base + threadIdx.x;
+    if (pos < ti.range.y)
+      s_rec[threadIdx.x] = stage_record(ids[pos], ti.view, n, ti.x0, ti.y0, recA, recB, recZ, rgb);
+    __syncthreads();
+    if (!st.done) {
+      const int cnt = min(BATCH, ti.range.y - base);
+      for (int k = 0; k < cnt; ++k) {
+        const float4 geo = s_rec[k].geo;
+        const float4 con = s_rec[k].con;
+        const float dx = geo.x - lx, dy = geo.y - ly;
+        float G, oG;
+        const float alpha = splat_alpha(geo, con, dx, dy, rc.alpha_max, G, oG);
+        ++st.nev;
+        if (alpha < rc.alpha_min) continue;
+        const float Tn = st.T * (1.f - alpha);
+        if (Tn < rc.T_min) {
+          st.done = true;
+          break;
+        }
+        ++st.nbl;
+        const float w = alpha * st.T;
+        const float4 col = s_rec[k].col;
+        st.C0 = __fmaf_rn(w, col.x, st.C0);
+        st.C1 = __fmaf_rn(w, col.y, st.C1);
+        st.C2 = __fmaf_rn(w, col.z, st.C2);
+        st.D = __fmaf_rn(w, geo.w, st.D);
+        st.T = Tn;
+        st.last = base - ti.range.x + k + 1;
+      }
+    }
+  }
+  st.C0 = __fmaf_rn(st.T, rc.bg[0], st.C0);
+  st.C1 = __fmaf_rn(st.T, rc.bg[1], st.C1);
+  st.C2 = __fmaf_rn(st.T, rc.bg[2], st.C2);
+}
+
+// ----------------------------------------------------------------- backward
+
+struct BwdIn {
+  float T;         // final transmittance
+  int last;        // list positions [0, last) to walk
+  float gC0, gC1, gC2, gD, gT;
+};
+
+// Walk the tile's list back to front.  Per-Gaussian gradients are reduced
+// over the block (wavefront butterflies, then LDS) and added to grad2d with
+// one FP32 atomic per field.  grad2d fields: (u, v, conic a, b, c, opacity,
+// r, g, b, depth).
+__device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, const float4 *__restrict__ recA,
+                                              const float4 *__restrict__ recB,
+                                              const float *__restrict__ recZ,
+                                              const float *__restrict__ rgb,
+                                              const uint32_t *__restrict__ ids, const RenderConsts &rc,
+                                              const BwdIn &in, float *__restrict__ grad2d,
+                                              Staged *s_rec, float *s_grad, uint32_t *s_id, int *s_max) {
+  const float lx = (float)(threadIdx.x & (TILE - 1));
+  const float ly = (float)(threadIdx.x >> 4);
+  const int lane = threadIdx.x & 63;
+  if (threadIdx.x == 0) *s_max = 0;
+  for (int k = threadIdx.x; k < BATCH * NGRAD2D; k += BLOCK) s_grad[k] = 0.f;
+  __syncthreads();
+  if (in.last > 0) atomicMax(s_max, in.last);
+  __syncthreads();
+  const int maxlast = *s_max;
+
+  float T = in.T;
+  const float Tf = in.T;
+  float aC0 = rc.bg[0], aC1 = rc.bg[1], aC2 = rc.bg[2], aD = 0.f;
+
+  for (int hi = maxlast; hi > 0; hi -= BATCH) {
+    const int lo = hi > BATCH ? hi - BATCH : 0;
+    const int cnt = hi - lo;
+    if ((int)threadIdx.x < cnt) {
+      const uint32_t id = ids[ti.range.x + lo + threadIdx.x];
+      s_id[threadIdx.x] = id;
+      s_rec[threadIdx.x] = stage_record(id, ti.view, n, ti.x0, ti.y0, recA, recB, recZ, rgb);
+    }
+    __syncthreads();
+    for (int k = hi - 1; k >= lo; --k) {
+      const int j = k - lo;
+      float g[NGRAD2D];
+#pragma unroll
+      for (int f = 0; f < NGRAD2D; ++f) g[f] = 0.f;
+      bool has = false;
+      if (k < in.last) {
+        const float4 geo = s_rec[j].geo;
+        const float4 con = s_rec[j].con;
+        const float dx = geo.x - lx, dy = geo.y - ly;
+        float G, oG;
+        const float alpha = splat_alpha(geo, con, dx, dy, rc.alpha_max, G, oG);
+        if (alpha >= rc.alpha_min) {
+          has = true;
+          const float4 col = s_rec[j].col;
+          const float om = 1.f - alpha;
+          const float rinv = __builtin_amdgcn_rcpf(om);
+          T = T * rinv;  // transmittance in front of this Gaussian
+          const float w = alpha * T;
+          g[6] = in.gC0 * w;
+          g[7] = in.gC1 * w;
+          g[8] = in.gC2 * w;
+          g[9] = in.gD * w;
+          const float dLda = T * (in.gC0 * (col.x - aC0) + in.gC1 * (col.y - aC1) +
+                                  in.gC2 * (col.z - aC2) + in.gD * (geo.w - aD)) -
+                             in.gT * Tf * rinv;
+          aC0 = __fmaf_rn(alpha, col.x - aC0, aC0);
+          aC1 = __fmaf_rn(alpha, col.y - aC1, aC1);
+          aC2 = __fmaf_rn(alpha, col.z - aC2, aC2);
+          aD = __fmaf_rn(alpha, geo.w - aD, aD);
+          if (oG <= rc.alpha_max) {
+            const float dLdP = dLda * oG;
+            g[0] = dLdP * __fmaf_rn(con.x, dx, con.y * dy);
+            g[1] = dLdP * __fmaf_rn(con.y, dx, con.z * dy);
+            g[2] = dLdP * dx * dx;
+            g[3] = dLdP * dx * dy;
+            g[4] = dLdP * dy * dy;
+            g[5] = dLda * G;
+          }
+        }
+      }
+      if (__any(has)) {
+#pragma unroll
+        for (int f = 0; f < NGRAD2D; ++f) g[f] = wave_sum(g[f]);
+        if (lane == 0) {
+#pragma unroll
+          for (int f = 0; f < NGRAD2D; ++f) atomicAdd(&s_grad[j * NGRAD2D + f], g[f]);
+        }
+      }
+    }
+    __syncthreads();
+    // Flush: one thread per Gaussian of the batch; constant factors of the
+    // pre-scaled conic applied here.
+    if ((int)threadIdx.x < cnt) {
+      float *src = s_grad + threadIdx.x * NGRAD2D;
+      float v[NGRAD2D];
+      bool nz = false;
+#pragma unroll
+      for (int f = 0; f < NGRAD2D; ++f) {
+        v[f] = src[f];
+        src[f] = 0.f;
+        nz = nz || v[f] != 0.f;
+      }
+      if (nz) {
+        float *dst = grad2d + (size_t)s_id[threadIdx.x] * NGRAD2D;
+        atomicAdd(dst + 0, 2.f * LN2 * v[0]);
+        atomicAdd(dst + 1, 2.f * LN2 * v[1]);
+        atomicAdd(dst + 2, -0.5f * v[2]);
+        atomicAdd(dst + 3, -v[3]);
+        atomicAdd(dst + 4, -0.5f * v[4]);
+        atomicAdd(dst + 5, v[5]);
+        atomicAdd(dst + 6, v[6]);
+        atomicAdd(dst + 7, v[7]);
+        atomicAdd(dst + 8, v[8]);
+        atomicAdd(dst + 9, v[9]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ kernels
+
+struct RasterArgs {
+  const float4 *recA;
+  const float4 *recB;
+  const float *recZ;
+  const float *rgb;
+  const uint32_t *ids;
+  const int2 *ranges;
+  const ViewInfo *views;
+  const int32_t *tile_view;
+  int64_t n;
+  RenderConsts rc;
+};
+
+struct PixelState {
+  float *T;
+  int32_t *last, *nevals, *nblend;
+};
+
+__device__ __forceinline__ void save_state(const PixelState &ps, int64_t pix, const FwdState &st) {
+  ps.T[pix] = st.T;
+  ps.last[pix] = st.last;
+  ps.nevals[pix] = st.nev;
+  ps.nblend[pix] = st.nbl;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, PixelState ps, gsr_images out) {
+  __shared__ Staged s_rec[BATCH];
+  const TileInfo ti = tile_info(blockIdx.x, a.views, a.tile_view, a.ranges);
+  FwdState st;
+  tile_forward(ti, a.n, a.recA, a.recB, a.recZ, a.rgb, a.ids, a.rc, s_rec, st);
+  if (!ti.inside) return;
+  save_state(ps, ti.pix, st);
+  const int64_t loc = ti.pix - ti.pix_off;
+  if (out.rgb) {
+    float *o = out.rgb + 3 * ti.pix_off + loc;
+    o[0] = st.C0;
+    o[ti.HW] = st.C1;
+    o[2 * ti.HW] = st.C2;
+  }
+  if (out.depth) out.depth[ti.pix] = st.D;
+  if (out.T_final) out.T_final[ti.pix] = st.T;
+  if (out.last) out.last[ti.pix] = st.last;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_render_bwd(RasterArgs a, const float *__restrict__ T_ws,
+                                                      const int32_t *__restrict__ last_ws,
+                                                      const float *__restrict__ g_rgb,
+                                                      const float *__restrict__ g_depth,
+                                                      const float *__restrict__ g_T,
+                                                      float *__restrict__ grad2d) {
+  __shared__ Staged s_rec[BATCH];
+  __shared__ float s_grad[BATCH * NGRAD2D];
+  __shared__ uint32_t s_id[BATCH];
+  __shared__ int s_max;
+  const TileInfo ti = tile_info(blockIdx.x, a.views, a.tile_view, a.ranges);
+  BwdIn in{1.f, 0, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (ti.inside) {
+    const int64_t loc = ti.pix - ti.pix_off;
+    in.T = T_ws[ti.pix];
+    in.last = last_ws[ti.pix];
+    const float *gc = g_rgb + 3 * ti.pix_off + loc;
+    in.gC0 = gc[0];
+    in.gC1 = gc[ti.HW];
+    in.gC2 = gc[2 * ti.HW];
+    in.gD = g_depth ? g_depth[ti.pix] : 0.f;
+    in.gT = g_T ? g_T[ti.pix] : 0.f;
+  }
+  tile_backward(ti, a.n, a.recA, a.recB, a.recZ, a.rgb, a.ids, a.rc, in, grad2d, s_rec, s_grad, s_id, &s_max);
+}
+
+__device__ __forceinline__ float sgnf(float x) { return (float)((x > 0.f) - (x < 0.f)); }
+
+// Persistent fused step: pop tiles from the work queue; per tile run the
+// forward blend, the L1 loss gradient of every pixel, and the backward walk
+// without leaving the block (per-pixel state stays in registers).
+__global__ __launch_bounds__(BLOCK) void k_render_fused(RasterArgs a, uint32_t *__restrict__ hdr,
+                                                        const uint32_t *__restrict__ queue, int total_tiles,
+                                                        int tiles_per_pop, const float *__restrict__ t_rgb,
+                                                        const float *__restrict__ t_depth,
+                                                        const uint8_t *__restrict__ pmask, float w_rgb,
+                                                        float w_depth, gsr_images out, float *__restrict__ loss,
+                                                        float *__restrict__ grad2d, PixelState ps) {
+  __shared__ Staged s_rec[BATCH];
+  __shared__ float s_grad[BATCH * NGRAD2D];
+  __shared__ uint32_t s_id[BATCH];
+  __shared__ int s_max;
+  __shared__ int s_q;
+  __shared__ float s_loss[4];
+  for (;;) {
+    if (threadIdx.x == 0) s_q = (int)atomicAdd(hdr + HDR_QUEUE, (uint32_t)tiles_per_pop);
+    __syncthreads();
+    const int q0 = s_q;
+    __syncthreads();
+    if (q0 >= total_tiles) break;
+    const int q1 = min(q0 + tiles_per_pop, total_tiles);
+    for (int q = q0; q < q1; ++q) {
+      const int tile = (int)queue[q];
+      const TileInfo ti = tile_info(tile, a.views, a.tile_view, a.ranges);
+      FwdState st;
+      tile_forward(ti, a.n, a.recA, a.recB, a.recZ, a.rgb, a.ids, a.rc, s_rec, st);
+      BwdIn in{st.T, ti.inside ? st.last : 0, 0.f, 0.f, 0.f, 0.f, 0.f};
+      float lpx = 0.f;
+      if (ti.inside) {
+        const int64_t loc = ti.pix - ti.pix_off;
+        const bool m = pmask ? pmask[ti.pix] != 0 : true;
+        const float *tc = t_rgb + 3 * ti.pix_off + loc;
+        const float e0 = st.C0 - tc[0], e1 = st.C1 - tc[ti.HW], e2 = st.C2 - tc[2 * ti.HW];
+        const float td = t_depth[ti.pix];
+        const bool md = m && td > 0.f;
+        const float ed = st.D - td;
+        if (m) {
+          in.gC0 = w_rgb * sgnf(e0);
+          in.gC1 = w_rgb * sgnf(e1);
+          in.gC2 = w_rgb * sgnf(e2);
+          lpx = w_rgb * (fabsf(e0) + fabsf(e1) + fabsf(e2));
+        }
+        if (md) {
+          in.gD = w_depth * sgnf(ed);
+          lpx += w_depth * fabsf(ed);
+        }
+        save_state(ps, ti.pix, st);
+        if (out.rgb) {
+          float *o = out.rgb + 3 * ti.pix_off + loc;
+          o[0] = st.C0;
+          o[ti.HW] = st.C1;
+          o[2 * ti.HW] = st.C2;
+        }
+        if (out.depth) out.depth[ti.pix] = st.D;
+        if (out.T_final) out.T_final[ti.pix] = st.T;
+        if (out.last) out.last[ti.pix] = st.last;
+      }
+      const float ls = wave_sum(lpx);
+      if ((threadIdx.x & 63) == 0) s_loss[threadIdx.x >> 6] = ls;
+      tile_backward(ti, a.n, a.recA, a.recB, a.recZ, a.rgb, a.ids, a.rc, in, grad2d, s_rec, s_grad, s_id, &s_max);
+      if (threadIdx.x == 0 && loss) atomicAdd(loss, (s_loss[0] + s_loss[1]) + (s_loss[2] + s_loss[3]));
+      // The next tile may have an empty list (no barrier in its forward):
+      // keep its shared-memory writes behind this tile's reads.
+      __syncthreads();
+    }
+  }
+}
+
+// Standalone L1 loss gradient for the autograd path (grid.y = view).
+__global__ __launch_bounds__(BLOCK) void k_l1(const ViewInfo *__restrict__ views, const float *__restrict__ rgb,
+                                              const float *__restrict__ depth,
+                                              const float *__restrict__ t_rgb,
+                                              const float *__restrict__ t_depth,
+                                              const uint8_t *__restrict__ pmask, float w_rgb, float w_depth,
+                                              float *__restrict__ g_rgb, float *__restrict__ g_depth,
+                                              float *__restrict__ loss) {
+  __shared__ float s_w[4];
+  const ViewInfo vi = views[blockIdx.y];
+  const int64_t HW = (int64_t)vi.W * vi.H;
+  float l = 0.f;
+  for (int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x; q < HW; q += (int64_t)gridDim.x * BLOCK) {
+    const int64_t pix = vi.pix_off + q;
+    const int64_t c0 = 3 * vi.pix_off + q;
+    const bool m = pmask ? pmask[pix] != 0 : true;
+    const float td = t_depth[pix];
+    const bool md = m && td > 0.f;
+    const float ed = depth[pix] - td;
+    float lp = 0.f;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      const float e = rgb[c0 + ch * HW] - t_rgb[c0 + ch * HW];
+      g_rgb[c0 + ch * HW] = m ? w_rgb * sgnf(e) : 0.f;
+      lp += m ? fabsf(e) : 0.f;
+    }
+    g_depth[pix] = md ? w_depth * sgnf(ed) : 0.f;
+    l += w_rgb * lp + (md ? w_depth * fabsf(ed) : 0.f);
+  }
+  l = wave_sum(l);
+  if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = l;
+  __syncthreads();
+  if (threadIdx.x == 0 && loss) atomicAdd(loss, (s_w[0] + s_w[1]) + (s_w[2] + s_w[3]));
+}
+
+void launch_l1(const Plan &p, const ViewInfo *views, const float *rgb, const float *depth,
+               const float *t_rgb, const float *t_depth, const uint8_t *pmask, float w_rgb,
+               float w_depth, float *g_rgb, float *g_depth, float *loss, hipStream_t s) {
+  int64_t maxhw = 0;
+  (void)maxhw;
+  const unsigned gx = (unsigned)((p.total_pixels / p.n_views + BLOCK - 1) / BLOCK);
+  dim3 grid(gx < 1024 ? (gx < 1 ? 1 : gx) : 1024, (unsigned)p.n_views);
+  hipLaunchKernelGGL(k_l1, grid, dim3(BLOCK), 0, s, views, rgb, depth, t_rgb, t_depth, pmask, w_rgb, w_depth,
+                     g_rgb, g_depth, loss);
+}
+
+void launch_render_forward(const Plan &p, const Workspace &ws, const ViewInfo *views,
+                           const int32_t *tile_view, const gsr_gaussians &g, const RenderConsts &rc,
+                           const gsr_images *out, hipStream_t s) {
+  RasterArgs a{ws.recA, ws.recB, ws.recZ, g.rgb, ws.pvals[ws.psorted], ws.ranges, views, tile_view, g.n, rc};
+  gsr_images o{nullptr, nullptr, nullptr, nullptr};
+  if (out) o = *out;
+  PixelState ps{ws.T_final, ws.last, ws.nevals, ws.nblend};
+  hipLaunchKernelGGL(k_render_fwd, dim3(p.total_tiles), dim3(BLOCK), 0, s, a, ps, o);
+}
+
+void launch_render_backward(const Plan &p, const Workspace &ws, const ViewInfo *views,
+                            const int32_t *tile_view, const gsr_gaussians &g, const RenderConsts &rc,
+                            const float *g_rgb, const float *g_depth, const float *g_T, hipStream_t s) {
+  RasterArgs a{ws.recA, ws.recB, ws.recZ, g.rgb, ws.pvals[ws.psorted], ws.ranges, views, tile_view, g.n, rc};
+  hipLaunchKernelGGL(k_render_bwd, dim3(p.total_tiles), dim3(BLOCK), 0, s, a, ws.T_final, ws.last, g_rgb,
+                     g_depth, g_T, ws.grad2d);
+}
+
+void launch_render_fused(const Plan &p, const Workspace &ws, const ViewInfo *views,
+                         const int32_t *tile_view, const gsr_gaussians &g, const RenderConsts &rc,
+                         const float *t_rgb, const float *t_depth, const uint8_t *pmask, float w_rgb,
+                         float w_depth, const gsr_images *out, float *loss, const Tuning &tun, int num_cus,
+                         hipStream_t s) {
+  RasterArgs a{ws.recA, ws.recB, ws.recZ, g.rgb, ws.pvals[ws.psorted], ws.ranges, views, tile_view, g.n, rc};
+  gsr_images o{nullptr, nullptr, nullptr, nullptr};
+  if (out) o = *out;
+  int grid = tun.blocks_per_cu * num_cus;
+  const int need = (p.total_tiles + tun.tiles_per_pop - 1) / tun.tiles_per_pop;
+  if (grid > need) grid = need;
+  if (grid < 1) grid = 1;
+  PixelState ps{ws.T_final, ws.last, ws.nevals, ws.nblend};
+  hipLaunchKernelGGL(k_render_fused, dim3(grid), dim3(BLOCK), 0, s, a, ws.hdr, ws.queue, p.total_tiles,
+                     tun.tiles_per_pop, t_rgb, t_depth, pmask, w_rgb, w_depth, o, loss, ws.grad2d, ps);
+}
+
+// Totals of the per-pixel work counters: counts[0] pairs, [1] entries the
+// forward examined, [2] entries blended, [3] sum of last.
+__global__ __launch_bounds__(BLOCK) void k_work_counts(const int32_t *__restrict__ nevals,
+                                                       const int32_t *__restrict__ nblend,
+                                                       const int32_t *__restrict__ last, int64_t total,
+                                                       const uint32_t *__restrict__ hdr,
+                                                       unsigned long long *__restrict__ counts) {
+  unsigned long long a = 0, b = 0, c = 0;
+  for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < total; p += (int64_t)gridDim.x * BLOCK) {
+    a += (unsigned long long)nevals[p];
+    b += (unsigned long long)nblend[p];
+    c += (unsigned long long)last[p];
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o);
+    b += __shfl_xor(b, o);
+    c += __shfl_xor(c, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(counts + 1, a);
+    atomicAdd(counts + 2, b);
+    atomicAdd(counts + 3, c);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    counts[0] = *reinterpret_cast<const unsigned long long *>(hdr + HDR_NPAIRS);
+}
+
+void launch_work_counts(const Plan &p, const Workspace &ws, hipStream_t s) {
+  launch_fill_u32(reinterpret_cast<uint32_t *>(ws.counts), 0u, 8, s);
+  hipLaunchKernelGGL(k_work_counts, dim3(256), dim3(BLOCK), 0, s, ws.nevals, ws.nblend, ws.last, p.total_pixels,
+                     ws.hdr, ws.counts);
+}
+
+}  // namespace gsr

@@ -1,0 +1,413 @@
+// Tile lists: depth sort of the projected Gaussians, emission of
+// (tile, Gaussian) pairs in depth order, a stable radix sort of the pairs by
+// tile id, and per-tile [start, end) ranges.
+//
+// The blending order is the lexicographic (tile, float32 depth bits, index)
+// order.  A least-significant-digit radix sort of the 64-bit key
+// (tile << 32 | depth bits) would make four passes over every pair for the
+// depth digits.  All pairs of one Gaussian share its depth, so those four
+// passes are run once per Gaussian instead (stable sort of the records by
+// depth, ties by record id); the pairs are then emitted in that order and
+// only the tile digits are sorted per pair.  The result is identical to the
+// 64-bit sort; the pair traffic drops from ceil((32 + tile_bits) / 8) passes
+// to ceil(tile_bits / 8).
+//
+// Every kernel reads its element count from device memory and uses a fixed
+// grid, so the whole sequence can be captured in a HIP graph.
+#include "gsr_internal.h"
+
+namespace gsr {
+
+__global__ void k_fill_u32(uint32_t *__restrict__ p, uint32_t v, int64_t n) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x)
+    p[k] = v;
+}
+
+__global__ void k_fill_f32(float *__restrict__ p, float v, int64_t n) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x)
+    p[k] = v;
+}
+
+static unsigned fill_grid(int64_t n) {
+  int64_t b = (n + BLOCK - 1) / BLOCK;
+  if (b > 4096) b = 4096;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+void launch_fill_u32(uint32_t *ptr, uint32_t value, int64_t count, hipStream_t s) {
+  if (count > 0) hipLaunchKernelGGL(k_fill_u32, dim3(fill_grid(count)), dim3(BLOCK), 0, s, ptr, value, count);
+}
+
+void launch_fill_f32(float *ptr, float value, int64_t count, hipStream_t s) {
+  if (count > 0) hipLaunchKernelGGL(k_fill_f32, dim3(fill_grid(count)), dim3(BLOCK), 0, s, ptr, value, count);
+}
+
+// Clear the per-call header words (pair count, queue counter).  The overflow
+// flag and required count are sticky until gsr_check_overflow reads them.
+__global__ void k_reset_header(uint32_t *hdr) {
+  if (threadIdx.x == 0) {
+    hdr[HDR_NPAIRS] = 0u;
+    hdr[HDR_NPAIRS + 1] = 0u;
+    hdr[HDR_QUEUE] = 0u;
+    hdr[HDR_FWD_DONE] = 1u;
+  }
+}
+
+void launch_reset_header(const Workspace &ws, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset_header, dim3(1), dim3(64), 0, s, ws.hdr);
+}
+
+// ----------------------------------------------------------------- block scan
+
+template <typename T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T *s_w, T &total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  T x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const T y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) s_w[wave] = x;
+  __syncthreads();
+  T pre = 0;
+  for (int w = 0; w < wave; ++w) pre += s_w[w];
+  total = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+  __syncthreads();
+  return pre + x - v;
+}
+
+// ----------------------------------------------------------------- radix sort
+
+// Lanes of the wavefront whose digit equals this lane's digit (and valid).
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, int nbits, uint64_t valid) {
+  uint64_t m = valid;
+  for (int b = 0; b < nbits; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t bb = __ballot(bit);
+    m &= bit ? bb : ~bb;
+  }
+  return m;
+}
+
+__device__ __forceinline__ uint32_t sort_count(const unsigned long long *n_dev, uint32_t n_static,
+                                               uint32_t cap) {
+  if (!n_dev) return n_static;
+  const unsigned long long n = *n_dev;
+  return n < cap ? (uint32_t)n : cap;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_radix_hist(const uint32_t *__restrict__ keys,
+                                                      const unsigned long long *n_dev,
+                                                      uint32_t n_static, uint32_t cap, int shift,
+                                                      int nbits, uint32_t *__restrict__ hist,
+                                                      int max_tiles) {
+  __shared__ uint32_t cnt[RADIX];
+  const uint32_t n = sort_count(n_dev, n_static, cap);
+  const uint32_t ntiles = (n + SORT_TILE - 1) / SORT_TILE;
+  const uint32_t mask = (1u << nbits) - 1u;
+  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    cnt[threadIdx.x] = 0u;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < SORT_ITEMS; ++r) {
+      const uint32_t idx = t * SORT_TILE + r * BLOCK + threadIdx.x;
+      const bool valid = idx < n;
+      const uint32_t d = valid ? (keys[idx] >> shift) & mask : 0u;
+      const uint64_t peers = match_digit(d, nbits, __ballot(valid));
+      if (valid && (peers & lanemask_lt()) == 0ull) atomicAdd(&cnt[d], (uint32_t)__popcll(peers));
+    }
+    __syncthreads();
+    hist[(size_t)threadIdx.x * max_tiles + t] = cnt[threadIdx.x];
+    __syncthreads();
+  }
+}
+
+// One block per digit: exclusive scan over the tiles of that digit's column.
+__global__ __launch_bounds__(BLOCK) void k_radix_scan(uint32_t *__restrict__ hist,
+                                                      const unsigned long long *n_dev,
+                                                      uint32_t n_static, uint32_t cap, int max_tiles,
+                                                      uint32_t *__restrict__ digit_total) {
+  __shared__ uint32_t s_w[4];
+  const uint32_t n = sort_count(n_dev, n_static, cap);
+  const uint32_t ntiles = (n + SORT_TILE - 1) / SORT_TILE;
+  uint32_t *col = hist + (size_t)blockIdx.x * max_tiles;
+  uint32_t carry = 0u;
+  for (uint32_t base = 0; base < ntiles; base += BLOCK * SCAN_ITEMS) {
+    uint32_t v[SCAN_ITEMS];
+    uint32_t sum = 0u;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+      const uint32_t idx = base + threadIdx.x * SCAN_ITEMS + k;
+      v[k] = idx < ntiles ? col[idx] : 0u;
+      sum += v[k];
+    }
+    uint32_t total;
+    uint32_t pre = block_exclusive_scan<uint32_t>(sum, s_w, total) + carry;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+      const uint32_t idx = base + threadIdx.x * SCAN_ITEMS + k;
+      if (idx < ntiles) col[idx] = pre;
+      pre += v[k];
+    }
+    carry += total;
+  }
+  if (threadIdx.x == 0) digit_total[blockIdx.x] = carry;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_radix_scatter(
+    const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in,
+    uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out,
+    const unsigned long long *n_dev, uint32_t n_static, uint32_t cap, int shift, int nbits,
+    const uint32_t *__restrict__ hist, int max_tiles, const uint32_t *__restrict__ digit_total) {
+  __shared__ uint32_t s_base[RADIX];
+  __shared__ uint32_t s_run[RADIX];
+  __shared__ uint32_t s_wcnt[4][RADIX];
+  __shared__ uint32_t s_w[4];
+  const uint32_t n = sort_count(n_dev, n_static, cap);
+  const uint32_t ntiles = (n + SORT_TILE - 1) / SORT_TILE;
+  const uint32_t mask = (1u << nbits) - 1u;
+  const int wave = threadIdx.x >> 6;
+  {
+    uint32_t total;
+    s_base[threadIdx.x] = block_exclusive_scan<uint32_t>(digit_total[threadIdx.x], s_w, total);
+    s_wcnt[0][threadIdx.x] = s_wcnt[1][threadIdx.x] = s_wcnt[2][threadIdx.x] = s_wcnt[3][threadIdx.x] = 0u;
+  }
+  __syncthreads();
+  for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    s_run[threadIdx.x] = s_base[threadIdx.x] + hist[(size_t)threadIdx.x * max_tiles + t];
+    __syncthreads();
+#pragma unroll 1
+    for (int r = 0; r < SORT_ITEMS; ++r) {
+      const uint32_t idx = t * SORT_TILE + r * BLOCK + threadIdx.x;
+      const bool valid = idx < n;
+      const uint32_t key = valid ? keys_in[idx] : 0u;
+      const uint32_t val = valid ? vals_in[idx] : 0u;
+      const uint32_t d = (key >> shift) & mask;
+      const uint64_t peers = match_digit(d, nbits, __ballot(valid));
+      const uint64_t below = peers & lanemask_lt();
+      if (valid && below == 0ull) s_wcnt[wave][d] = (uint32_t)__popcll(peers);
+      __syncthreads();
+      if (valid) {
+        uint32_t pos = s_run[d] + (uint32_t)__popcll(below);
+        for (int w = 0; w < wave; ++w) pos += s_wcnt[w][d];
+        keys_out[pos] = key;
+        vals_out[pos] = val;
+      }
+      __syncthreads();
+      const int dd = threadIdx.x;
+      s_run[dd] += s_wcnt[0][dd] + s_wcnt[1][dd] + s_wcnt[2][dd] + s_wcnt[3][dd];
+      s_wcnt[0][dd] = s_wcnt[1][dd] = s_wcnt[2][dd] = s_wcnt[3][dd] = 0u;
+      __syncthreads();
+    }
+  }
+}
+
+// Stable LSD radix sort of (key, value) over bits [0, key_bits); returns the
+// index of the buffer holding the result.
+static int radix_sort(uint32_t *keys[2], uint32_t *vals[2], const unsigned long long *n_dev,
+                      uint32_t n_static, uint32_t cap, int key_bits, uint32_t *hist, int max_tiles,
+                      uint32_t *digit_total, int grid, hipStream_t s) {
+  int cur = 0;
+  for (int shift = 0; shift < key_bits; shift += RADIX_BITS) {
+    const int nbits = key_bits - shift < RADIX_BITS ? key_bits - shift : RADIX_BITS;
+    hipLaunchKernelGGL(k_radix_hist, dim3(grid), dim3(BLOCK), 0, s, keys[cur], n_dev, n_static, cap,
+                       shift, nbits, hist, max_tiles);
+    hipLaunchKernelGGL(k_radix_scan, dim3(RADIX), dim3(BLOCK), 0, s, hist, n_dev, n_static, cap,
+                       max_tiles, digit_total);
+    hipLaunchKernelGGL(k_radix_scatter, dim3(grid), dim3(BLOCK), 0, s, keys[cur], vals[cur],
+                       keys[cur ^ 1], vals[cur ^ 1], n_dev, n_static, cap, shift, nbits, hist,
+                       max_tiles, digit_total);
+    cur ^= 1;
+  }
+  return cur;
+}
+
+static int sort_grid_for(int64_t n, int cap_grid) {
+  int64_t t = (n + SORT_TILE - 1) / SORT_TILE;
+  if (t > cap_grid) t = cap_grid;
+  return t < 1 ? 1 : (int)t;
+}
+
+int launch_depth_sort(const Plan &p, Workspace &ws, hipStream_t s, int sort_grid) {
+  ws.dsorted = radix_sort(ws.dkeys, ws.dvals, nullptr, (uint32_t)p.n_rec, (uint32_t)p.n_rec, 32,
+                          ws.hist, p.max_sort_tiles, ws.digit_total, sort_grid_for(p.n_rec, sort_grid), s);
+  return ws.dsorted;
+}
+
+int launch_pair_sort(const Plan &p, Workspace &ws, hipStream_t s, int sort_grid) {
+  const unsigned long long *n_dev = reinterpret_cast<const unsigned long long *>(ws.hdr + HDR_NPAIRS);
+  ws.psorted = radix_sort(ws.pkeys, ws.pvals, n_dev, 0u, (uint32_t)p.capacity, p.tile_bits, ws.hist,
+                          p.max_sort_tiles, ws.digit_total, sort_grid_for(p.capacity, sort_grid), s);
+  return ws.psorted;
+}
+
+// ----------------------------------------------------------- scan + emit pairs
+
+__global__ __launch_bounds__(BLOCK) void k_scan_reduce(const uint32_t *__restrict__ order,
+                                                       const uint32_t *__restrict__ count,
+                                                       int64_t n_rec,
+                                                       unsigned long long *__restrict__ part) {
+  __shared__ unsigned long long s_w[4];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK;
+  unsigned long long sum = 0ull;
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    const int64_t idx = base + k * BLOCK + threadIdx.x;
+    if (idx < n_rec) sum += count[order[idx]];
+  }
+  unsigned long long total;
+  (void)block_exclusive_scan<unsigned long long>(sum, s_w, total);
+  if (threadIdx.x == 0) part[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(BLOCK) void k_scan_top(unsigned long long *__restrict__ part, int nblocks,
+                                                    uint32_t *__restrict__ hdr, uint64_t capacity) {
+  __shared__ unsigned long long s_w[4];
+  unsigned long long carry = 0ull;
+  for (int base = 0; base < nblocks; base += BLOCK * SCAN_ITEMS) {
+    unsigned long long v[SCAN_ITEMS], sum = 0ull;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+      const int idx = base + threadIdx.x * SCAN_ITEMS + k;
+      v[k] = idx < nblocks ? part[idx] : 0ull;
+      sum += v[k];
+    }
+    unsigned long long total;
+    unsigned long long pre = block_exclusive_scan<unsigned long long>(sum, s_w, total) + carry;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+      const int idx = base + threadIdx.x * SCAN_ITEMS + k;
+      if (idx < nblocks) part[idx] = pre;
+      pre += v[k];
+    }
+    carry += total;
+  }
+  if (threadIdx.x == 0) {
+    unsigned long long *np = reinterpret_cast<unsigned long long *>(hdr + HDR_NPAIRS);
+    *np = carry;
+    if (carry > capacity) {
+      atomicOr(hdr + HDR_OVERFLOW, 1u);
+      atomicMax(reinterpret_cast<unsigned long long *>(hdr + HDR_REQUIRED), carry);
+    }
+  }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_scan_emit(
+    const uint32_t *__restrict__ order, const uint32_t *__restrict__ count,
+    const ushort4 *__restrict__ rect, int64_t n_rec, int64_t n,
+    const unsigned long long *__restrict__ part, const ViewInfo *__restrict__ views,
+    uint64_t capacity, uint32_t *__restrict__ pkeys, uint32_t *__restrict__ pvals) {
+  __shared__ unsigned long long s_w[4];
+  const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + threadIdx.x * SCAN_ITEMS;
+  uint32_t c[SCAN_ITEMS], rid[SCAN_ITEMS];
+  unsigned long long sum = 0ull;
+#pragma unroll
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    const int64_t idx = base + k;
+    rid[k] = idx < n_rec ? order[idx] : 0u;
+    c[k] = idx < n_rec ? count[rid[k]] : 0u;
+    sum += c[k];
+  }
+  unsigned long long total;
+  unsigned long long off = block_exclusive_scan<unsigned long long>(sum, s_w, total) + part[blockIdx.x];
+  for (int k = 0; k < SCAN_ITEMS; ++k) {
+    if (c[k] != 0u) {
+      const uint32_t r = rid[k];
+      const int view = (int)(r / (uint64_t)n);
+      const ViewInfo vi = views[view];
+      const ushort4 rc = rect[r];
+      unsigned long long pos = off;
+      for (int ty = rc.z; ty <= rc.w; ++ty) {
+        const uint32_t row = (uint32_t)(vi.tile_off + ty * vi.TX);
+        for (int tx = rc.x; tx <= rc.y; ++tx) {
+          if (pos < capacity) {
+            pkeys[pos] = row + (uint32_t)tx;
+            pvals[pos] = r;
+          }
+          ++pos;
+        }
+      }
+    }
+    off += c[k];
+  }
+}
+
+void launch_emit_pairs(const Plan &p, const Workspace &ws, const ViewInfo *views, hipStream_t s) {
+  const uint32_t *order = ws.dvals[ws.dsorted];
+  hipLaunchKernelGGL(k_scan_reduce, dim3(p.n_scan_blocks), dim3(BLOCK), 0, s, order, ws.count,
+                     p.n_rec, ws.scan_part);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(BLOCK), 0, s, ws.scan_part, p.n_scan_blocks, ws.hdr,
+                     (uint64_t)p.capacity);
+  hipLaunchKernelGGL(k_scan_emit, dim3(p.n_scan_blocks), dim3(BLOCK), 0, s, order, ws.count, ws.rect,
+                     p.n_rec, p.n, ws.scan_part, views, (uint64_t)p.capacity, ws.pkeys[0], ws.pvals[0]);
+}
+
+// ---------------------------------------------------------------- tile ranges
+
+__global__ __launch_bounds__(BLOCK) void k_tile_ranges(const uint32_t *__restrict__ keys,
+                                                       const unsigned long long *n_dev, uint32_t cap,
+                                                       int2 *__restrict__ ranges) {
+  const uint32_t n = sort_count(n_dev, 0u, cap);
+  for (uint32_t i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) {
+    const uint32_t t = keys[i];
+    if (i == 0 || keys[i - 1] != t) ranges[t].x = (int)i;
+    if (i + 1 == n || keys[i + 1] != t) ranges[t].y = (int)(i + 1);
+  }
+}
+
+void launch_tile_ranges(const Plan &p, const Workspace &ws, hipStream_t s) {
+  launch_fill_u32(reinterpret_cast<uint32_t *>(ws.ranges), 0u, 2 * (int64_t)p.total_tiles, s);
+  const unsigned long long *n_dev = reinterpret_cast<const unsigned long long *>(ws.hdr + HDR_NPAIRS);
+  int64_t blocks = (p.capacity + BLOCK - 1) / BLOCK;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)blocks), dim3(BLOCK), 0, s, ws.pkeys[ws.psorted],
+                     n_dev, (uint32_t)p.capacity, ws.ranges);
+}
+
+// ------------------------------------------------------- work order (LPT)
+
+// One block: bucket the tiles by the bit length of their list length and
+// lay them out longest bucket first.  Order inside a bucket is arbitrary.
+__global__ __launch_bounds__(1024) void k_queue_order(const int2 *__restrict__ ranges, int total,
+                                                      int lpt, uint32_t *__restrict__ queue) {
+  __shared__ uint32_t s_cnt[33];
+  __shared__ uint32_t s_cur[33];
+  if (!lpt) {
+    for (int t = threadIdx.x; t < total; t += blockDim.x) queue[t] = (uint32_t)t;
+    return;
+  }
+  if (threadIdx.x < 33) s_cnt[threadIdx.x] = 0u;
+  __syncthreads();
+  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+    const int2 r = ranges[t];
+    const uint32_t len = (uint32_t)(r.y - r.x);
+    const int b = len ? 32 - __clz(len) : 0;
+    atomicAdd(&s_cnt[b], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t acc = 0u;
+    for (int b = 32; b >= 0; --b) {
+      s_cur[b] = acc;
+      acc += s_cnt[b];
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+    const int2 r = ranges[t];
+    const uint32_t len = (uint32_t)(r.y - r.x);
+    const int b = len ? 32 - __clz(len) : 0;
+    queue[atomicAdd(&s_cur[b], 1u)] = (uint32_t)t;
+  }
+}
+
+void launch_queue_order(const Plan &p, const Workspace &ws, int lpt, hipStream_t s) {
+  hipLaunchKernelGGL(k_queue_order, dim3(1), dim3(1024), 0, s, ws.ranges, p.total_tiles, lpt, ws.queue);
+}
+
+}  // namespace gsr

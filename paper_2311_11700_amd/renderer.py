@@ -1,0 +1,389 @@
+"""Thin Python binding of the C ABI (include/gsr.h) over torch device memory.
+
+Every step of the rendering path runs in libgsr.so; this module only builds
+the C structs from torch tensors, passes torch's current HIP stream, and maps
+status codes to exceptions.  Method names follow the C entry points without
+the ``gsr_`` prefix (``Renderer.render_forward`` calls ``gsr_render_forward``).
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import Optional, Sequence
+
+import torch
+
+from . import _abi as A
+
+
+class GsrError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{message} (status {status})")
+        self.status = status
+
+
+@dataclasses.dataclass
+class Config:
+    """Mirror of gsr_config (renderer constants and flags)."""
+    alpha_min: float = 1.0 / 255.0
+    alpha_max: float = 0.99
+    T_min: float = 1e-4
+    cutoff_sigma: float = 3.0
+    z_near: float = 0.2
+    lowpass: float = 0.3
+    bg: Sequence[float] = (0.0, 0.0, 0.0)
+    flags: int = A.GSR_GAUSS_GRAD | A.GSR_POSE_GRAD
+
+    def to_c(self) -> A.gsr_config:
+        c = A.gsr_config()
+        c.alpha_min, c.alpha_max, c.T_min = self.alpha_min, self.alpha_max, self.T_min
+        c.cutoff_sigma, c.z_near, c.lowpass = self.cutoff_sigma, self.z_near, self.lowpass
+        for k in range(3):
+            c.bg[k] = float(self.bg[k])
+        c.flags = int(self.flags)
+        return c
+
+    @staticmethod
+    def smooth(bg=(0.0, 0.0, 0.0), flags=A.GSR_GAUSS_GRAD | A.GSR_POSE_GRAD) -> "Config":
+        """Finite-difference mode: no thresholds, every tile in every list."""
+        return Config(alpha_min=0.0, alpha_max=1.0, T_min=0.0, bg=bg, flags=flags | A.GSR_FULL_RECT)
+
+
+@dataclasses.dataclass
+class Gaussians:
+    """Gaussian parameters on the device (float32, contiguous)."""
+    mean: torch.Tensor
+    log_scale: torch.Tensor
+    quat: torch.Tensor
+    opacity_logit: torch.Tensor
+    rgb: torch.Tensor
+    mask: Optional[torch.Tensor] = None
+
+    @property
+    def n(self) -> int:
+        return int(self.mean.shape[0])
+
+    @staticmethod
+    def from_arrays(mean, log_scale, quat, opacity_logit, rgb, mask=None, device="cuda") -> "Gaussians":
+        def t(a, dt=torch.float32):
+            return torch.as_tensor(a).to(device=device, dtype=dt).contiguous()
+        return Gaussians(t(mean).reshape(-1, 3), t(log_scale).reshape(-1, 3), t(quat).reshape(-1, 4),
+                         t(opacity_logit).reshape(-1), t(rgb).reshape(-1, 3),
+                         None if mask is None else t(mask, torch.uint8).reshape(-1))
+
+    def c(self) -> A.gsr_gaussians:
+        for name in ("mean", "log_scale", "quat", "opacity_logit", "rgb"):
+            x = getattr(self, name)
+            if x.dtype != torch.float32 or not x.is_contiguous() or not x.is_cuda:
+                raise ValueError(f"Gaussians.{name} must be a contiguous float32 device tensor")
+        g = A.gsr_gaussians()
+        g.n = self.n
+        g.mean, g.log_scale, g.quat = self.mean.data_ptr(), self.log_scale.data_ptr(), self.quat.data_ptr()
+        g.opacity_logit, g.rgb = self.opacity_logit.data_ptr(), self.rgb.data_ptr()
+        g.mask = self.mask.data_ptr() if self.mask is not None else None
+        return g
+
+
+def pack_cameras(cams, device="cuda") -> torch.Tensor:
+    """gsr_camera array on the device, [n_views, 20] 32-bit words.  `cams`
+    are objects with fx, fy, cx, cy, R (3x3), t (3), width, height."""
+    words = torch.zeros((len(cams), 20), dtype=torch.float32)
+    iw = words.view(torch.int32)
+    for v, c in enumerate(cams):
+        words[v, 0:4] = torch.tensor([c.fx, c.fy, c.cx, c.cy], dtype=torch.float32)
+        words[v, 4:13] = torch.as_tensor(c.R, dtype=torch.float32).reshape(9)
+        words[v, 13:16] = torch.as_tensor(c.t, dtype=torch.float32).reshape(3)
+        iw[v, 16] = int(c.width)
+        iw[v, 17] = int(c.height)
+    return words.to(device)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else t.data_ptr()
+
+
+def _stream_ptr(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+class Renderer:
+    """One gsr_ctx (device context + plan) and the workspace tensor of its plan."""
+
+    def __init__(self, device: int = 0):
+        self.lib = A.load()
+        self.device = torch.device("cuda", device)
+        ctx = ctypes.c_void_p()
+        self._check(self.lib.gsr_create(device, ctypes.byref(ctx)), None)
+        self.ctx = ctx
+        self.workspace: Optional[torch.Tensor] = None
+        self.n = -1
+        self.sizes: list = []
+        self.capacity = 0
+
+    def __del__(self):
+        try:
+            if getattr(self, "ctx", None):
+                self.lib.gsr_destroy(self.ctx)
+                self.ctx = None
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ helpers
+    def _check(self, status, ctx=True):
+        if status != A.GSR_OK:
+            msg = self.lib.gsr_last_error(self.ctx).decode() if ctx is not None and getattr(self, "ctx", None) else ""
+            base = self.lib.gsr_status_string(status).decode()
+            raise GsrError(status, f"{base}: {msg}")
+
+    @property
+    def n_views(self) -> int:
+        return len(self.sizes)
+
+    @property
+    def total_pixels(self) -> int:
+        return sum(w * h for w, h in self.sizes)
+
+    def pixel_offsets(self):
+        offs, acc = [], 0
+        for w, h in self.sizes:
+            offs.append(acc)
+            acc += w * h
+        return offs
+
+    def plan(self, n: int, sizes, pair_capacity: Optional[int] = None) -> int:
+        """Plan n Gaussians over views of (width, height) `sizes`; allocates the
+        workspace.  Default capacity: 64 pairs per pixel (at least 1M)."""
+        sizes = [(int(w), int(h)) for w, h in sizes]
+        if pair_capacity is None:
+            pair_capacity = max(1 << 20, 64 * sum(w * h for w, h in sizes))
+        wh = (ctypes.c_int32 * (2 * len(sizes)))(*[v for s in sizes for v in s])
+        nbytes = ctypes.c_size_t()
+        self._check(self.lib.gsr_plan(self.ctx, int(n), len(sizes), wh, int(pair_capacity), ctypes.byref(nbytes)))
+        self.workspace = None
+        self.workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=self.device)
+        self.n, self.sizes, self.capacity = int(n), sizes, int(pair_capacity)
+        return int(nbytes.value)
+
+    def _ws(self):
+        base = self.workspace.data_ptr()
+        aligned = (base + 255) // 256 * 256
+        return aligned, self.workspace.numel() - (aligned - base)
+
+    def ensure_plan(self, n: int, sizes, pair_capacity: Optional[int] = None):
+        sizes = [(int(w), int(h)) for w, h in sizes]
+        if self.workspace is None or n != self.n or sizes != self.sizes or (
+                pair_capacity is not None and pair_capacity > self.capacity):
+            self.plan(n, sizes, pair_capacity if pair_capacity is not None else
+                      (self.capacity if sizes == self.sizes and self.capacity else None))
+
+    def new_images(self, last=True):
+        P = self.total_pixels
+        return dict(rgb=torch.empty(3 * P, device=self.device), depth=torch.empty(P, device=self.device),
+                    T_final=torch.empty(P, device=self.device),
+                    last=torch.empty(P, dtype=torch.int32, device=self.device) if last else None)
+
+    def new_grads(self, n: int):
+        z = lambda *s: torch.zeros(*s, device=self.device)  # noqa: E731
+        return dict(d_mean=z(n, 3), d_log_scale=z(n, 3), d_quat=z(n, 4), d_opacity_logit=z(n),
+                    d_rgb=z(n, 3), d_pose=z(self.n_views, 6))
+
+    @staticmethod
+    def _images_c(out):
+        im = A.gsr_images()
+        if out:
+            im.rgb, im.depth = _ptr(out.get("rgb")), _ptr(out.get("depth"))
+            im.T_final, im.last = _ptr(out.get("T_final")), _ptr(out.get("last"))
+        return im
+
+    @staticmethod
+    def _grads_c(gr):
+        g = A.gsr_grads()
+        for k in ("d_mean", "d_log_scale", "d_quat", "d_opacity_logit", "d_rgb", "d_pose"):
+            setattr(g, k, _ptr(gr.get(k)))
+        return g
+
+    # --------------------------------------------------------- entry points
+    def render_forward(self, g: Gaussians, cams: torch.Tensor, cfg: Config, out=None, stream=None):
+        """gsr_render_forward; returns the image dict.  Grows the pair buffer
+        and retries once on GSR_E_CAPACITY."""
+        out = out if out is not None else self.new_images()
+        gc, cc = g.c(), cfg.to_c()
+        for attempt in range(2):
+            ws, wsb = self._ws()
+            st = self.lib.gsr_render_forward(self.ctx, ctypes.byref(gc), cams.data_ptr(), self.n_views,
+                                             ctypes.byref(cc), ws, wsb, ctypes.byref(self._images_c(out)),
+                                             _stream_ptr(stream))
+            if st == A.GSR_E_CAPACITY and attempt == 0:
+                need = int(self.lib.gsr_required_pairs(self.ctx))
+                self.plan(self.n, self.sizes, int(need * 1.25) + 1024)
+                continue
+            self._check(st)
+            break
+        return out
+
+    def render_backward(self, g: Gaussians, cams: torch.Tensor, cfg: Config, g_rgb, g_depth, g_T=None,
+                        grads=None, stream=None):
+        grads = grads if grads is not None else self.new_grads(g.n)
+        gc, cc = g.c(), cfg.to_c()
+        ws, wsb = self._ws()
+        self._check(self.lib.gsr_render_backward(
+            self.ctx, ctypes.byref(gc), cams.data_ptr(), self.n_views, ctypes.byref(cc), ws, wsb,
+            _ptr(g_rgb.contiguous()), _ptr(None if g_depth is None else g_depth.contiguous()),
+            _ptr(None if g_T is None else g_T.contiguous()), ctypes.byref(self._grads_c(grads)),
+            _stream_ptr(stream)))
+        return grads
+
+    def l1_loss_grad(self, rgb, depth, target_rgb, target_depth, pixel_mask=None, w_rgb=1.0, w_depth=0.1,
+                     g_rgb=None, g_depth=None, loss=None, stream=None):
+        g_rgb = g_rgb if g_rgb is not None else torch.empty_like(rgb)
+        g_depth = g_depth if g_depth is not None else torch.empty_like(depth)
+        loss = loss if loss is not None else torch.zeros(1, device=self.device)
+        self._check(self.lib.gsr_l1_loss_grad(self.ctx, _ptr(rgb), _ptr(depth), _ptr(target_rgb),
+                                              _ptr(target_depth), _ptr(pixel_mask), float(w_rgb), float(w_depth),
+                                              _ptr(g_rgb), _ptr(g_depth), _ptr(loss), _stream_ptr(stream)))
+        return loss, g_rgb, g_depth
+
+    def _fused_args(self, g, cams, cfg, target_rgb, target_depth, pixel_mask, w_rgb, w_depth, out, grads, loss):
+        ws, wsb = self._ws()
+        self._keep = (g.c(), cfg.to_c(), self._images_c(out), self._grads_c(grads))
+        gc, cc, im, gr = self._keep
+        return (self.ctx, ctypes.byref(gc), cams.data_ptr(), self.n_views, ctypes.byref(cc), _ptr(target_rgb),
+                _ptr(target_depth), _ptr(pixel_mask), float(w_rgb), float(w_depth), ws, wsb,
+                ctypes.byref(im) if out else None, ctypes.byref(gr), _ptr(loss))
+
+    def render_l1_fused(self, g: Gaussians, cams, cfg: Config, target_rgb, target_depth, pixel_mask=None,
+                        w_rgb=1.0, w_depth=0.1, out=None, grads=None, loss=None, stream=None):
+        grads = grads if grads is not None else self.new_grads(g.n)
+        loss = loss if loss is not None else torch.zeros(1, device=self.device)
+        args = self._fused_args(g, cams, cfg, target_rgb, target_depth, pixel_mask, w_rgb, w_depth, out, grads, loss)
+        self._check(self.lib.gsr_render_l1_fused(*args, _stream_ptr(stream)))
+        return loss, grads
+
+    def graph_capture(self, g, cams, cfg, target_rgb, target_depth, pixel_mask=None, w_rgb=1.0, w_depth=0.1,
+                      out=None, grads=None, loss=None, stream=None):
+        """Capture the fused step into a HIP graph (torch.cuda stream required)."""
+        args = self._fused_args(g, cams, cfg, target_rgb, target_depth, pixel_mask, w_rgb, w_depth, out, grads, loss)
+        s = stream if stream is not None else torch.cuda.current_stream()
+        if s.cuda_stream == 0:
+            raise ValueError("graph capture needs a non-default stream")
+        self._check(self.lib.gsr_graph_capture(*args, s.cuda_stream))
+
+    def graph_launch(self, stream=None):
+        self._check(self.lib.gsr_graph_launch(self.ctx, _stream_ptr(stream)))
+
+    def check_overflow(self, stream=None):
+        ws, _ = self._ws()
+        self._check(self.lib.gsr_check_overflow(self.ctx, ws, _stream_ptr(stream)))
+
+    def required_pairs(self) -> int:
+        return int(self.lib.gsr_required_pairs(self.ctx))
+
+    def pair_count(self, stream=None) -> int:
+        ws, _ = self._ws()
+        return int(self.lib.gsr_pair_count(self.ctx, ws, _stream_ptr(stream)))
+
+    def debug_tiles(self):
+        """(tile_ranges [T,2] int32, sorted_ids [pairs] int64) copied to the host."""
+        ws, _ = self._ws()
+        r, ids, tt = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_int64()
+        self._check(self.lib.gsr_debug_tiles(self.ctx, ws, ctypes.byref(r), ctypes.byref(ids), ctypes.byref(tt)))
+        torch.cuda.current_stream().synchronize()
+        base = self.workspace.data_ptr()
+        T = int(tt.value)
+        ro = r.value - base
+        rng = self.workspace[ro:ro + 8 * T].view(torch.int32).reshape(T, 2).cpu()
+        npairs = self.pair_count()
+        io = ids.value - base
+        sid = self.workspace[io:io + 4 * npairs].view(torch.int32).cpu().to(torch.int64) & 0xFFFFFFFF
+        return rng, sid
+
+    def get_tuning(self) -> dict:
+        t = A.gsr_tuning()
+        self._check(self.lib.gsr_get_tuning(self.ctx, ctypes.byref(t)))
+        return dict(blocks_per_cu=t.blocks_per_cu, tiles_per_pop=t.tiles_per_pop, lpt_order=t.lpt_order)
+
+    def set_tuning(self, blocks_per_cu=2, tiles_per_pop=1, lpt_order=1):
+        t = A.gsr_tuning(blocks_per_cu, tiles_per_pop, lpt_order, 0)
+        self._check(self.lib.gsr_set_tuning(self.ctx, ctypes.byref(t)))
+
+    def autotune(self, g, cams, cfg, target_rgb, target_depth, pixel_mask=None, w_rgb=1.0, w_depth=0.1,
+                 reps=3, stream=None) -> dict:
+        grads = self.new_grads(g.n)
+        loss = torch.zeros(1, device=self.device)
+        ws, wsb = self._ws()
+        gc, cc, gr = g.c(), cfg.to_c(), self._grads_c(grads)
+        best = A.gsr_tuning()
+        self._check(self.lib.gsr_autotune(self.ctx, ctypes.byref(gc), cams.data_ptr(), self.n_views,
+                                          ctypes.byref(cc), _ptr(target_rgb), _ptr(target_depth), _ptr(pixel_mask),
+                                          float(w_rgb), float(w_depth), ws, wsb, ctypes.byref(gr), _ptr(loss),
+                                          int(reps), ctypes.byref(best), _stream_ptr(stream)))
+        return dict(blocks_per_cu=best.blocks_per_cu, tiles_per_pop=best.tiles_per_pop, lpt_order=best.lpt_order)
+
+
+    # ------------------------------------------------------------ profiling
+    def set_profiling(self, enable: bool = True):
+        self._check(self.lib.gsr_set_profiling(self.ctx, 1 if enable else 0))
+
+    def stage_times(self) -> dict:
+        """Summed milliseconds per stage since the last query, and the call count."""
+        ms = (ctypes.c_double * len(A.STAGES))()
+        calls = ctypes.c_int64()
+        self._check(self.lib.gsr_stage_times(self.ctx, ms, ctypes.byref(calls)))
+        out = {k: float(ms[i]) for i, k in enumerate(A.STAGES)}
+        out["calls"] = int(calls.value)
+        return out
+
+    def work_counts(self, stream=None) -> dict:
+        ws, _ = self._ws()
+        out = (ctypes.c_int64 * 4)()
+        self._check(self.lib.gsr_work_counts(self.ctx, ws, _stream_ptr(stream), out))
+        return dict(pairs=int(out[0]), fwd_evals=int(out[1]), blended=int(out[2]), bwd_evals=int(out[3]))
+
+
+# ------------------------------------------------------------------ autograd
+
+class _RenderFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, mean, log_scale, quat, opacity_logit, rgb, pose_xi, renderer, cams, cfg, mask):
+        g = Gaussians(mean.contiguous(), log_scale.contiguous(), quat.contiguous(), opacity_logit.contiguous(),
+                      rgb.contiguous(), mask)
+        out = renderer.render_forward(g, cams, cfg)
+        ctx.renderer, ctx.cams, ctx.cfg, ctx.g = renderer, cams, cfg, g
+        ctx.mark_non_differentiable(out["last"])
+        return out["rgb"], out["depth"], out["T_final"]
+
+    @staticmethod
+    def backward(ctx, g_rgb, g_depth, g_T):
+        r, g = ctx.renderer, ctx.g
+        P = r.total_pixels
+        dev = r.device
+        g_rgb = torch.zeros(3 * P, device=dev) if g_rgb is None else g_rgb.contiguous()
+        g_depth = torch.zeros(P, device=dev) if g_depth is None else g_depth.contiguous()
+        g_T = None if g_T is None else g_T.contiguous()
+        grads = r.render_backward(g, ctx.cams, ctx.cfg, g_rgb, g_depth, g_T)
+        return (grads["d_mean"], grads["d_log_scale"], grads["d_quat"], grads["d_opacity_logit"], grads["d_rgb"],
+                grads["d_pose"], None, None, None, None)
+
+
+def render(renderer: Renderer, mean, log_scale, quat, opacity_logit, rgb, cams: torch.Tensor,
+           cfg: Optional[Config] = None, pose_xi: Optional[torch.Tensor] = None, mask=None):
+    """Differentiable render of every planned view.  Returns flat (rgb, depth,
+    T_final) over the concatenated views.  `pose_xi` [n_views, 6] is a zero
+    tangent placeholder: its gradient is dL/dxi of a left perturbation
+    T_cw <- Exp(xi) T_cw at xi = 0 (the cameras themselves define the pose)."""
+    cfg = cfg or Config()
+    if pose_xi is None:
+        pose_xi = torch.zeros(renderer.n_views, 6, device=renderer.device)
+    return _RenderFn.apply(mean, log_scale, quat, opacity_logit, rgb, pose_xi, renderer, cams, cfg, mask)
+
+
+def split_views(flat: torch.Tensor, sizes, channels: int = 1):
+    """Split a concatenated image buffer into per-view [C, H, W] (or [H, W])."""
+    out, off = [], 0
+    for w, h in sizes:
+        k = channels * w * h
+        x = flat[off:off + k]
+        out.append(x.reshape(channels, h, w) if channels > 1 else x.reshape(h, w))
+        off += k
+    return out
