@@ -41,6 +41,11 @@ def assert_images_close(gpu, orc, tol=1e-4, max_ambiguous=5e-3, check_last=True,
         ok &= done
         assert done.any()
     frac = 1.0 - ok.sum() / (done.sum() if done is not None else ok.size)
+    amb = ~ok if done is None else (~ok & done)
+    if amb.any():
+        d_amb = np.maximum(np.abs(gpu["rgb"] - orc["rgb"]).max(0), np.abs(gpu["depth"] - orc["depth"]))[amb]
+        print(f"ambiguous pixels: {int(amb.sum())} ({frac:.4%}); of these within tol: "
+              f"{int((d_amb <= tol).sum())}", flush=True)
     assert frac <= max_ambiguous, f"ambiguous fraction {frac}"
     for k in ("depth", "T_final"):
         d = np.abs(gpu[k] - orc[k])[ok]

@@ -1,0 +1,117 @@
+"""Full-size checks at the benchmark's workload (300k Gaussians, 1200x680) and
+in the launch configuration bench.py times (graph-captured fused step):
+the pair count and sampled tile lists bit-exact against the oracle, sampled
+tiles' pixels within 1e-4, and properties of the backward that hold at any
+size (translation gauge identity, colour-gradient sum, linearity, fused step
+equal to forward + L1 + backward)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+from tests import gpu_helpers as H
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def c2(gsr_lib):
+    gsr = gsr_lib
+    scene, cam = W.room_scene(300_000, seed=0), W.camera_replica()
+    print("CASE full-size 300k 1200x680", flush=True)
+    r = gsr.Renderer()
+    r.plan(scene.n, [(cam.width, cam.height)])
+    g = H.gpu_scene(gsr, scene)
+    cams_d = gsr.pack_cameras([cam])
+    out = r.render_forward(g, cams_d, gsr.Config())
+    torch.cuda.synchronize()
+    proj = O.project(scene, cam, O.Config().as_f32())
+    lists = O.tile_lists(proj)
+    return dict(gsr=gsr, scene=scene, cam=cam, r=r, g=g, cams_d=cams_d, out=out, proj=proj, lists=lists)
+
+
+def test_pairs_and_sampled_lists_bit_exact(c2):
+    r, proj, (starts, gauss) = c2["r"], c2["proj"], c2["lists"]
+    assert not proj["bin_ambiguous"].any()
+    assert r.pair_count() == len(gauss)
+    rng, sid = r.debug_tiles()
+    rng, sid = rng.numpy(), sid.numpy()
+    T = proj["TX"] * proj["TY"]
+    # every tile's range length, then the full content of sampled tiles
+    np.testing.assert_array_equal(rng[:, 1] - rng[:, 0], np.diff(starts))
+    sample = list(np.random.default_rng(0).choice(T, 40, replace=False)) + [0, proj["TX"] - 1, T - proj["TX"], T - 1]
+    for t in sample:
+        a, b = rng[t]
+        np.testing.assert_array_equal(sid[a:b], gauss[starts[t]:starts[t + 1]])
+
+
+def test_sampled_tiles_match_oracle(c2):
+    proj, cam = c2["proj"], c2["cam"]
+    T = proj["TX"] * proj["TY"]
+    sample = list(np.random.default_rng(1).choice(T, 12, replace=False)) + [T - 1]
+    o = O.render(c2["scene"], cam, O.Config(), tiles=sample, proj=proj, lists=c2["lists"])
+    g = H.split_images(c2["out"], [(cam.width, cam.height)])[0]
+    # Dense walls: more pixels terminate with a transmittance close to T_min,
+    # so more pixels carry a decision inside the float32 margin.
+    H.assert_images_close(g, o, done=o["done"], max_ambiguous=0.03)
+
+
+def test_backward_properties_at_full_size(c2):
+    gsr, r, g, cams_d, cam = c2["gsr"], c2["r"], c2["g"], c2["cams_d"], c2["cam"]
+    P = cam.width * cam.height
+    cfg = gsr.Config()
+    gr, gd, gT = H.flat_upstream([(cam.width, cam.height)], seed=2)
+    g1 = H.gpu_grads_numpy(r.render_backward(g, cams_d, cfg, H.to_dev(gr), H.to_dev(gd), H.to_dev(gT)))
+    # translation gauge: dL/drho = R sum_i dL/dmu_i
+    R = np.asarray(cam.R, np.float64)
+    lhs, rhs = g1["pose"][0, :3], R @ g1["mean"].astype(np.float64).sum(0)
+    assert H.rel_err(lhs, rhs) <= 1e-3, (lhs, rhs)
+    # linearity in the upstream gradient
+    gr2, gd2, gT2 = H.flat_upstream([(cam.width, cam.height)], seed=3)
+    g2 = H.gpu_grads_numpy(r.render_backward(g, cams_d, cfg, H.to_dev(gr2), H.to_dev(gd2), H.to_dev(gT2)))
+    g12 = H.gpu_grads_numpy(r.render_backward(g, cams_d, cfg, H.to_dev(gr + gr2), H.to_dev(gd + gd2),
+                                              H.to_dev(gT + gT2)))
+    for k in ("mean", "log_scale", "quat", "opacity_logit", "rgb"):
+        assert H.rel_err(g12[k], g1[k] + g2[k]) <= 1e-4, k
+    # colour gradients sum to the accumulated opacity
+    ones = np.zeros(3 * P, np.float32)
+    ones[:P] = 1.0
+    gc = H.gpu_grads_numpy(r.render_backward(g, cams_d, cfg, H.to_dev(ones), H.to_dev(np.zeros(P, np.float32)), None))
+    A = 1.0 - c2["out"]["T_final"].double().sum().item() / P
+    assert abs(gc["rgb"][:, 0].astype(np.float64).sum() / P - A) <= 1e-4 * A
+
+
+def test_graph_fused_step_equals_unfused_path(c2):
+    """The benchmark's launch configuration (captured fused step) gives the
+    same loss and gradients as forward + L1 + backward called separately."""
+    gsr, r, g, cams_d, cam = c2["gsr"], c2["r"], c2["g"], c2["cams_d"], c2["cam"]
+    sizes = [(cam.width, cam.height)]
+    out = c2["out"]
+    t_rgb, t_d = W.noisy_targets(out["rgb"].cpu().numpy(), out["depth"].cpu().numpy(), seed=1, sigma=0.05,
+                                 min_alpha=0.5, alpha=1.0 - out["T_final"].cpu().numpy())
+    t_rgb, t_d = H.to_dev(t_rgb), H.to_dev(t_d)
+    cfg = gsr.Config()
+    # unfused reference
+    r.render_forward(g, cams_d, cfg, out=out)
+    loss_u, gC, gD = r.l1_loss_grad(out["rgb"], out["depth"], t_rgb, t_d, None, 1.0, 0.1)
+    ref = H.gpu_grads_numpy(r.render_backward(g, cams_d, cfg, gC, gD, None))
+    # captured fused step, replayed twice
+    grads = r.new_grads(g.n)
+    loss = torch.zeros(1, device="cuda")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        r.graph_capture(g, cams_d, cfg, t_rgb, t_d, None, 1.0, 0.1, grads=grads, loss=loss, stream=s)
+    s.synchronize()
+    for rep in range(2):
+        for t in grads.values():
+            t.zero_()
+        loss.zero_()
+        torch.cuda.synchronize()
+        r.graph_launch(stream=s)
+        s.synchronize()
+        got = H.gpu_grads_numpy(grads)
+        assert abs(loss.item() - loss_u.item()) <= 1e-5 * loss_u.item()
+        for k in ref:
+            assert H.rel_err(got[k], ref[k]) <= 1e-4, (rep, k, H.rel_err(got[k], ref[k]))
+    r.check_overflow(stream=s)
