@@ -214,6 +214,149 @@ def run_batched(args, gsr, torch, W):
             "per_frame_mpx_s": round(total_px / (p_ms * 1e-3) / 1e6, 1), "pairs": int(pairs)}
 
 
+def run_hypotheses(args, gsr, torch, W):
+    """500k Gaussians, 64 pose hypotheses at 600x340 plus 8 at 1200x680 in one
+    launch, forward + L1 + backward to the poses only: per-batch latency
+    p50/p99 of the captured step against 72 separate per-pose calls."""
+    import numpy as np
+    scene = W.room_scene(500_000, seed=0)
+    cams = W.hypothesis_views(seed=2)
+    sizes = [(c.width, c.height) for c in cams]
+    g = gsr.Gaussians.from_arrays(*scene.arrays())
+    base_full = W.camera_replica()
+    h = W.camera_hyp_half()
+    base_half = base_full.with_size(h.fx, h.fy, h.cx, h.cy, h.width, h.height)
+    tg = {}
+    for key, cam in (("half", base_half), ("full", base_full)):
+        r = gsr.Renderer(0)
+        r.plan(scene.n, [(cam.width, cam.height)])
+        (trgb, td), _ = make_targets(gsr, torch, W, r, g, gsr.pack_cameras([cam]), [(cam.width, cam.height)])
+        tg[key] = (trgb, td)
+        del r
+    t_rgb = torch.cat([tg["half" if w == 600 else "full"][0] for w, _ in sizes])
+    t_d = torch.cat([tg["half" if w == 600 else "full"][1] for w, _ in sizes])
+    cfg = gsr.Config(flags=gsr.GSR_POSE_GRAD)
+    cams_d = gsr.pack_cameras(cams)
+    rb = gsr.Renderer(0)
+    rb.plan(scene.n, sizes)
+    rb.render_forward(g, cams_d, cfg)
+    pairs = rb.pair_count()
+    rb.plan(scene.n, sizes, pair_capacity=int(pairs * 1.25) + 4096)
+    if not args.no_autotune:
+        rb.autotune(g, cams_d, cfg, t_rgb, t_d, None, 1.0, 0.1, reps=1)
+    grads = {"d_pose": torch.zeros(len(cams), 6, device="cuda")}
+    loss = torch.zeros(1, device="cuda")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        rb.graph_capture(g, cams_d, cfg, t_rgb, t_d, None, 1.0, 0.1, grads=grads, loss=loss, stream=stream)
+    stream.synchronize()
+    lat = []
+    with torch.cuda.stream(stream):
+        for it in range(args.hyp_batches + 3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            grads["d_pose"].zero_()
+            loss.zero_()
+            rb.graph_launch(stream=stream)
+            e1.record(stream)
+            e1.synchronize()
+            if it >= 3:
+                lat.append(e0.elapsed_time(e1))
+    rb.check_overflow(stream=stream)
+    del rb
+    torch.cuda.empty_cache()
+    lat = np.array(lat)
+    # 72 separate calls: one renderer per resolution, reused view after view.
+    rs = {}
+    offs, po = [], 0
+    for w, hh in sizes:
+        offs.append(po)
+        po += w * hh
+    for key, cam in (("half", base_half), ("full", base_full)):
+        r = gsr.Renderer(0)
+        r.plan(scene.n, [(cam.width, cam.height)])
+        rs[(cam.width, cam.height)] = r
+    per_cams = [gsr.pack_cameras([c]) for c in cams]
+    gr1 = {"d_pose": None}
+
+    def step():
+        grads["d_pose"].zero_()
+        loss.zero_()
+        for v, (w, hh) in enumerate(sizes):
+            gr1["d_pose"] = grads["d_pose"][v:v + 1]
+            rs[(w, hh)].render_l1_fused(g, per_cams[v], cfg, t_rgb[3 * offs[v]:3 * (offs[v] + w * hh)],
+                                        t_d[offs[v]:offs[v] + w * hh], None, 1.0, 0.1, grads=gr1, loss=loss)
+
+    step()
+    torch.cuda.synchronize()
+    reps = max(3, args.hyp_batches // 10)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        step()
+    e1.record()
+    e1.synchronize()
+    sep_ms = e0.elapsed_time(e1) / reps
+    del rs
+    torch.cuda.empty_cache()
+    total_px = sum(w * hh for w, hh in sizes)
+    return {"workload": "500k Gaussians, 64 poses at 600x340 + 8 at 1200x680, fwd+L1+bwd to pose only",
+            "batches": int(lat.size), "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3), "separate_ms": round(sep_ms, 3),
+            "speedup": round(sep_ms / float(np.percentile(lat, 50)), 3),
+            "batched_mpx_s": round(total_px / (float(np.percentile(lat, 50)) * 1e-3) / 1e6, 1),
+            "pairs": int(pairs)}
+
+
+def run_tracking(args, gsr, torch, W):
+    """Coarse-to-fine tracking of one frame: 150k Gaussians, 640x480 target
+    rendered at the true pose with 10% of the depth readings removed, start
+    perturbed by 2 cm / 1 deg; 5 coarse (160x120) + 95 fine iterations."""
+    import numpy as np
+    from paper_2311_11700_amd.tracking import Tracker, TrackingConfig
+    scene = W.room_scene(150_000, seed=0)
+    truth = W.camera_tum()
+    g = gsr.Gaussians.from_arrays(*scene.arrays())
+    tc = TrackingConfig()
+    # The observation is rendered from the Gaussians the fine stage trusts
+    # (sigmoid(opacity) > 0.5), so the fine objective's minimum is the truth.
+    reliable = (torch.sigmoid(g.opacity_logit) > tc.reliable_opacity).to(torch.uint8).contiguous()
+    r = gsr.Renderer(0)
+    r.plan(scene.n, [(truth.width, truth.height)])
+    out = r.render_forward(gsr.Gaussians(g.mean, g.log_scale, g.quat, g.opacity_logit, g.rgb, reliable),
+                           gsr.pack_cameras([truth]), gsr.Config())
+    t_rgb, t_d = out["rgb"].clone(), out["depth"].clone()
+    rng = np.random.default_rng(3)
+    t_d[torch.as_tensor(rng.random(t_d.numel()) < 0.1, device="cuda")] = 0.0
+    del r
+    start = W.tracking_start(seed=2, truth=truth)
+    T0 = np.eye(4)
+    T0[:3, :3], T0[:3, 3] = start.R, start.t
+    tr = Tracker(g, truth, tc)
+    tr.track(torch.tensor(T0), t_rgb, t_d)  # warm-up
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    T = tr.track(torch.tensor(T0), t_rgb, t_d)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1)
+    T = T.cpu().numpy()
+    Tt = np.eye(4)
+    Tt[:3, :3], Tt[:3, 3] = truth.R, truth.t
+    E0, E1 = T0 @ np.linalg.inv(Tt), T @ np.linalg.inv(Tt)
+
+    def ang(R):
+        return float(np.degrees(np.arccos(np.clip((np.trace(R) - 1) / 2, -1, 1))))
+
+    iters = tc.coarse_iters + tc.fine_iters
+    return {"workload": "150k Gaussians, 640x480 (coarse 160x120), 5 + 95 iterations, pose-only",
+            "ms_total": round(ms, 2), "ms_per_iter": round(ms / iters, 3),
+            "trans_err_cm": [round(float(np.linalg.norm(E0[:3, 3])) * 100, 3),
+                             round(float(np.linalg.norm(E1[:3, 3])) * 100, 3)],
+            "rot_err_deg": [round(ang(E0[:3, :3]), 3), round(ang(E1[:3, :3]), 3)]}
+
+
 def cpu_baseline(args, W, n_tiles=None):
     """The FP64 oracle on a bounded sample of the headline workload: projection
     and binning of all 300k Gaussians (charged pro rata to the sampled tiles)
@@ -283,7 +426,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the pose-hypothesis and tracking legs")
+    ap.add_argument("--hyp-batches", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="also run a plain device copy of this many MB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); the renderer has no "
@@ -298,6 +445,15 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration_mb:
+        nb = args.copy_calibration_mb << 20
+        src = torch.empty(nb // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 copies of {args.copy_calibration_mb} MB")
+        del src, dst
     log("headline: 300k Gaussians, 1200x680")
     h = run_headline(args, gsr, torch, W)
     batched = None
@@ -305,6 +461,14 @@ def main():
         log("batched: 1M Gaussians, 16 keyframes")
         batched = run_batched(args, gsr, torch, W)
         log("batched:", batched)
+    hyp = trk = None
+    if not args.no_extra:
+        log("pose hypotheses: 500k Gaussians, 72 views")
+        hyp = run_hypotheses(args, gsr, torch, W)
+        log("hypotheses:", hyp)
+        log("tracking: 150k Gaussians, 640x480")
+        trk = run_tracking(args, gsr, torch, W)
+        log("tracking:", trk)
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle sample)")
@@ -329,6 +493,8 @@ def main():
         "roofline": h["roof"],
         "cpu_baseline": cpu,
         "batched": batched,
+        "hypotheses": hyp,
+        "tracking": trk,
         "eager_ms_per_step": round(h["eager_ms"], 4),
         "stages_ms": {k: round(v, 4) for k, v in h["stages"].items()},
         "work": h["work"],

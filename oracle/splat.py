@@ -382,10 +382,12 @@ def _blend_tile_backward(proj, lst, px, py, cfg: Config, r, gC, gD, gT):
 GRAD2D_FIELDS = ("u", "v", "conic_a", "conic_b", "conic_c", "opacity", "r", "g", "b", "depth")
 
 
-def backward_2d(scene, cam, cfg: Config, g_rgb, g_depth, g_T, fwd=None):
+def backward_2d(scene, cam, cfg: Config, g_rgb, g_depth, g_T, fwd=None, tiles=None):
     """Per-Gaussian gradients w.r.t. (u, v, conic a, b, c, opacity, r, g, b,
-    depth), summed over every pixel of the view.  Upstream gradients are images
-    g_rgb [3,H,W], g_depth [H,W], g_T [H,W] (g_T may be None)."""
+    depth), summed over every pixel of the view (or of the tiles listed in
+    `tiles`: exact for Gaussians whose rectangle lies inside them).  Upstream
+    gradients are images g_rgb [3,H,W], g_depth [H,W], g_T [H,W] (g_T may be
+    None)."""
     cfg = (cfg or Config()).as_f32()
     fwd = fwd if fwd is not None else render(scene, cam, cfg)
     proj = fwd["proj"]
@@ -395,7 +397,7 @@ def backward_2d(scene, cam, cfg: Config, g_rgb, g_depth, g_T, fwd=None):
     g_depth = np.asarray(g_depth, F64).reshape(H, Wd)
     g_T = np.zeros((H, Wd)) if g_T is None else np.asarray(g_T, F64).reshape(H, Wd)
     g2 = np.zeros((proj["n"], 10))
-    for tile in range(proj["TX"] * proj["TY"]):
+    for tile in (range(proj["TX"] * proj["TY"]) if tiles is None else tiles):
         lst = gauss[starts[tile]:starts[tile + 1]]
         if lst.size == 0:
             continue

@@ -155,6 +155,51 @@ __device__ __forceinline__ void tile_forward(const TileInfo &ti, int64_t n, cons
 
 // ----------------------------------------------------------------- backward
 
+// Cross-lane folds of gfx950: v_permlane32_swap exchanges the upper half of
+// one register with the lower half of another, v_permlane16_swap does the
+// same for the 16-lane quarters of each half.  Adding the swapped pair
+// reduces two values at once (a reduce-scatter step).
+__device__ __forceinline__ float fold32(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ float fold16(float a, float b) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// Sum over the 16 lanes of each DPP row (rotations fold into v_add_f32_dpp);
+// every lane of the row ends with the row total.
+__device__ __forceinline__ float row_sum16(float x) {
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x128, 0xf, 0xf, false));  // row_ror:8
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x124, 0xf, 0xf, false));  // row_ror:4
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x122, 0xf, 0xf, false));  // row_ror:2
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x121, 0xf, 0xf, false));  // row_ror:1
+  return x;
+}
+
+// Sum the ten gradient fields g[0..9] over the 64 lanes of the wavefront and
+// add the totals to dst[0..9] in LDS (lanes 0, 16, 32, 48 each add two or
+// three of them).  All 64 lanes must be active.  After the two folds the
+// 16-lane rows of u0 hold fields (0, 2, 1, 3), of u1 (4, 6, 5, 7) and of u2
+// (8, 8, 9, 9).
+__device__ __forceinline__ void wave_reduce_add10(const float g[NGRAD2D], float *dst) {
+  const float w0 = fold32(g[0], g[1]), w1 = fold32(g[2], g[3]), w2 = fold32(g[4], g[5]);
+  const float w3 = fold32(g[6], g[7]), w4 = fold32(g[8], g[9]);
+  const float u0 = row_sum16(fold16(w0, w1));
+  const float u1 = row_sum16(fold16(w2, w3));
+  const float u2 = row_sum16(fold16(w4, w4));
+  const int lane = __lane_id();
+  if ((lane & 15) == 0) {
+    const int row = lane >> 4;
+    const int f = ((row & 1) << 1) | (row >> 1);
+    atomicAdd(dst + f, u0);
+    atomicAdd(dst + 4 + f, u1);
+    if ((row & 1) == 0) atomicAdd(dst + 8 + (row >> 1), u2);
+  }
+}
+
 struct BwdIn {
   float T;         // final transmittance
   int last;        // list positions [0, last) to walk
@@ -174,7 +219,6 @@ __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, con
                                               Staged *s_rec, float *s_grad, uint32_t *s_id, int *s_max) {
   const float lx = (float)(threadIdx.x & (TILE - 1));
   const float ly = (float)(threadIdx.x >> 4);
-  const int lane = threadIdx.x & 63;
   if (threadIdx.x == 0) *s_max = 0;
   for (int k = threadIdx.x; k < BATCH * NGRAD2D; k += BLOCK) s_grad[k] = 0.f;
   __syncthreads();
@@ -236,14 +280,7 @@ __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, con
           }
         }
       }
-      if (__any(has)) {
-#pragma unroll
-        for (int f = 0; f < NGRAD2D; ++f) g[f] = wave_sum(g[f]);
-        if (lane == 0) {
-#pragma unroll
-          for (int f = 0; f < NGRAD2D; ++f) atomicAdd(&s_grad[j * NGRAD2D + f], g[f]);
-        }
-      }
+      if (__any(has)) wave_reduce_add10(g, s_grad + j * NGRAD2D);
     }
     __syncthreads();
     // Flush: one thread per Gaussian of the batch; constant factors of the

@@ -113,3 +113,15 @@ def view_slices(flat_rgb, flat_d, flat_T, sizes):
 
 def to_dev(x, dtype=torch.float32):
     return torch.as_tensor(x).to(device="cuda", dtype=dtype).contiguous()
+
+
+def assert_close_scaled(a, b, rtol=1e-3, scale_tol=1e-4, what=""):
+    """Element-wise |a - b| <= rtol |b| + scale_tol max|b|: for comparing two
+    float32 results whose only difference is the order of atomic additions
+    (sums with heavy cancellation lose digits relative to the tensor's scale,
+    not to the element)."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    m = np.abs(b).max() if b.size else 0.0
+    bad = np.abs(a - b) > rtol * np.abs(b) + scale_tol * m
+    assert not bad.any(), (what, int(bad.sum()), a[bad][:5], b[bad][:5], m)

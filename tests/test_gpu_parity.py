@@ -370,14 +370,14 @@ def test_batched_views_equal_separate_calls(gsr_lib):
         ur, ud, uT = H.view_slices(gr, gd, gT, sizes)[v]
         g1 = H.gpu_grads_numpy(r1.render_backward(g, c_d, cfg, H.to_dev(ur.reshape(-1)), H.to_dev(ud.reshape(-1)),
                                                   H.to_dev(uT.reshape(-1))))
-        assert H.rel_err(gb["pose"][v], g1["pose"][0]) <= 1e-5
+        H.assert_close_scaled(gb["pose"][v], g1["pose"][0], what="pose")
         if acc is None:
             acc = g1
         else:
             for k in ("mean", "log_scale", "quat", "opacity_logit", "rgb"):
                 acc[k] = acc[k] + g1[k]
     for k in ("mean", "log_scale", "quat", "opacity_logit", "rgb"):
-        assert H.rel_err(gb[k], acc[k]) <= 1e-5, k
+        H.assert_close_scaled(gb[k], acc[k], what=k)
 
 
 def test_graph_replay_matches_eager(gsr_lib):
@@ -413,7 +413,7 @@ def test_graph_replay_matches_eager(gsr_lib):
         got = H.gpu_grads_numpy(grads)
         assert abs(loss.item() - ref_loss) <= 1e-5 * abs(ref_loss), rep
         for k in ref:
-            assert H.rel_err(got[k], ref[k]) <= 1e-5, (rep, k)
+            H.assert_close_scaled(got[k], ref[k], what=(rep, k))
     r.check_overflow(stream=s)
 
 
