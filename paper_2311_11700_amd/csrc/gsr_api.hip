@@ -18,7 +18,7 @@ struct gsr_ctx {
   std::vector<ViewInfo> views_host;
   ViewInfo *views_dev = nullptr;
   int32_t *tile_view_dev = nullptr;
-  unsigned long long *pinned = nullptr;  // 4 pinned host words
+  unsigned long long *pinned = nullptr;  // 8 pinned host words
   std::string last_error;
   int64_t required = 0;
   Tuning tuning;
@@ -64,7 +64,7 @@ Workspace make_ws(const Plan &p, void *base_v) {
   w.recA = reinterpret_cast<float4 *>(base + p.off_recA);
   w.recB = reinterpret_cast<float4 *>(base + p.off_recB);
   w.recZ = reinterpret_cast<float *>(base + p.off_recZ);
-  w.rect = reinterpret_cast<ushort4 *>(base + p.off_rect);
+  w.tinfo = reinterpret_cast<uint2 *>(base + p.off_rect);
   w.count = reinterpret_cast<uint32_t *>(base + p.off_count);
   for (int k = 0; k < 2; ++k) {
     w.dkeys[k] = reinterpret_cast<uint32_t *>(base + p.off_dkeys[k]);
@@ -82,7 +82,7 @@ Workspace make_ws(const Plan &p, void *base_v) {
   w.nblend = reinterpret_cast<int32_t *>(base + p.off_nblend);
   w.counts = reinterpret_cast<unsigned long long *>(base + p.off_counts);
   w.grad2d = reinterpret_cast<float *>(base + p.off_grad2d);
-  w.pose_part = reinterpret_cast<float *>(base + p.off_pose);
+  w.pose_part = reinterpret_cast<double *>(base + p.off_pose);
   w.queue = reinterpret_cast<uint32_t *>(base + p.off_queue);
   w.loss_part = reinterpret_cast<float *>(base + p.off_loss);
   w.dsorted = passes_for(32) & 1;
@@ -232,7 +232,7 @@ gsr_status gsr_create(int device, gsr_ctx **out) {
   ctx->device = device;
   gsr_status st = hip_check(ctx, hipSetDevice(device), "hipSetDevice");
   if (st == GSR_OK) st = hip_check(ctx, hipDeviceGetAttribute(&ctx->num_cus, hipDeviceAttributeMultiprocessorCount, device), "hipDeviceGetAttribute");
-  if (st == GSR_OK) st = hip_check(ctx, hipHostMalloc(reinterpret_cast<void **>(&ctx->pinned), 4 * sizeof(unsigned long long), hipHostMallocDefault), "hipHostMalloc");
+  if (st == GSR_OK) st = hip_check(ctx, hipHostMalloc(reinterpret_cast<void **>(&ctx->pinned), 8 * sizeof(unsigned long long), hipHostMallocDefault), "hipHostMalloc");
   if (st != GSR_OK) {
     std::fprintf(stderr, "gsr_create: %s\n", ctx->last_error.c_str());
     gsr_destroy(ctx);
@@ -320,7 +320,7 @@ gsr_status gsr_plan(gsr_ctx *ctx, int64_t n, int n_views, const int32_t *wh_host
   p.off_nblend = take(4 * (size_t)pixels);
   p.off_counts = take(64);
   p.off_grad2d = take(4 * NGRAD2D * nr);
-  p.off_pose = take(4 * 6 * (size_t)n_views * p.n_pose_blocks);
+  p.off_pose = take(8 * 6 * (size_t)n_views * p.n_pose_blocks);
   p.off_queue = take(4 * (size_t)p.total_tiles);
   p.off_loss = take(4);
   p.bytes = off;
@@ -488,11 +488,12 @@ gsr_status gsr_check_overflow(gsr_ctx *ctx, void *workspace, gsr_stream stream) 
   if (!ctx->planned || !workspace) return fail(ctx, GSR_E_STATE, "gsr_check_overflow: no plan or workspace");
   hipStream_t s = static_cast<hipStream_t>(stream);
   Workspace ws = make_ws(ctx->plan, workspace);
-  gsr_status st = hip_check(ctx, hipMemcpyAsync(ctx->pinned, ws.hdr, 24, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+  gsr_status st = hip_check(ctx, hipMemcpyAsync(ctx->pinned, ws.hdr, 40, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
   if (st == GSR_OK) st = hip_check(ctx, hipStreamSynchronize(s), "hipStreamSynchronize");
   if (st != GSR_OK) return st;
   const uint32_t flag = static_cast<uint32_t>(ctx->pinned[2] & 0xFFFFFFFFull);
-  if (flag) {
+  const bool used = ctx->pinned[4] == ((unsigned long long)HDR_MAGIC1 << 32 | HDR_MAGIC0);
+  if (used && flag) {
     ctx->required = (int64_t)ctx->pinned[1];
     launch_fill_u32(ws.hdr + HDR_REQUIRED, 0u, 3, s);
     st = hip_check(ctx, hipStreamSynchronize(s), "hipStreamSynchronize");

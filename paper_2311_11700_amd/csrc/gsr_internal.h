@@ -36,8 +36,12 @@ enum HeaderWord {
   HDR_OVERFLOW = 4,    // u32: set when a forward overflowed the pair buffer
   HDR_QUEUE = 5,       // u32: persistent rasteriser work counter
   HDR_FWD_DONE = 6,    // u32: marker that a forward filled this workspace
+  HDR_MAGIC = 8,       // u32 x 2 (words 8-9): set once the header has been initialised
   HDR_WORDS = 64
 };
+// Header magic: a workspace whose words 8-9 do not hold it has never been
+// used (its sticky words may hold any leftover bytes) and is cleared.
+constexpr uint32_t HDR_MAGIC0 = 0x67737248u, HDR_MAGIC1 = 0x2311B700u;
 
 // Device pointers into the caller's workspace (computed on the host).
 struct Workspace {
@@ -45,7 +49,7 @@ struct Workspace {
   float4 *recA;            // [n_rec] (u_hi, u_lo, v_hi, v_lo)
   float4 *recB;            // [n_rec] (conic a, b, c, opacity)
   float *recZ;             // [n_rec] camera-frame depth
-  ushort4 *rect;           // [n_rec] (tx0, tx1, ty0, ty1), local tile coordinates
+  uint2 *tinfo;            // [n_rec] (first global tile of the rectangle, width << 16 | view TX)
   uint32_t *count;         // [n_rec] tiles touched (0 = culled)
   uint32_t *dkeys[2];      // [n_rec] depth keys (float32 bits), ping-pong
   uint32_t *dvals[2];      // [n_rec] record ids, ping-pong
@@ -61,7 +65,7 @@ struct Workspace {
   int32_t *nblend;         // [total_pixels] entries blended
   unsigned long long *counts;  // [4] work totals (gsr_work_counts)
   float *grad2d;           // [n_rec][NGRAD2D]
-  float *pose_part;        // [n_pose_blocks][n_views][6]
+  double *pose_part;       // [n_pose_blocks][n_views][6]
   uint32_t *queue;         // [total_tiles] work order of the persistent rasteriser
   float *loss_part;        // [1] (unused slot kept for alignment)
   int dsorted;             // which depth buffer holds the sorted result

@@ -11,17 +11,27 @@ struct PreConstsB {
   uint32_t flags;
 };
 
+// The chain runs in FP64: gfx950 executes FP64 vector arithmetic at the
+// non-packed FP32 rate, and near-camera Gaussians put 1/z^3 factors and
+// cancelling terms into this chain.
+using R = double;
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
 // Rotation matrix of a unit quaternion (w, x, y, z) (supplement eq. q2R).
-__device__ __forceinline__ void quat_rot_f(float w, float x, float y, float z, float R[9]) {
-  R[0] = 1.f - 2.f * (y * y + z * z);
-  R[1] = 2.f * (x * y - w * z);
-  R[2] = 2.f * (x * z + w * y);
-  R[3] = 2.f * (x * y + w * z);
-  R[4] = 1.f - 2.f * (x * x + z * z);
-  R[5] = 2.f * (y * z - w * x);
-  R[6] = 2.f * (x * z - w * y);
-  R[7] = 2.f * (y * z + w * x);
-  R[8] = 1.f - 2.f * (x * x + y * y);
+__device__ __forceinline__ void quat_rot_r(R w, R x, R y, R z, R M[9]) {
+  M[0] = R(1) - R(2) * (y * y + z * z);
+  M[1] = R(2) * (x * y - w * z);
+  M[2] = R(2) * (x * z + w * y);
+  M[3] = R(2) * (x * y + w * z);
+  M[4] = R(1) - R(2) * (x * x + z * z);
+  M[5] = R(2) * (y * z - w * x);
+  M[6] = R(2) * (x * z - w * y);
+  M[7] = R(2) * (y * z + w * x);
+  M[8] = R(1) - R(2) * (x * x + y * y);
 }
 
 // ----------------------------------------------------------------------------
@@ -37,7 +47,7 @@ __global__ __launch_bounds__(BLOCK) void k_preprocess_bwd(gsr_gaussians g,
                                                           const gsr_camera *__restrict__ cams,
                                                           int n_views, PreConstsB pc, Workspace ws,
                                                           gsr_grads gr) {
-  extern __shared__ float s_dyn[];  // [4 waves][n_views][6]
+  extern __shared__ double s_dyn[];  // [4 waves][n_views][6]
   const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   const bool active = i < g.n;
   const int wave = threadIdx.x >> 6;
@@ -47,112 +57,114 @@ __global__ __launch_bounds__(BLOCK) void k_preprocess_bwd(gsr_gaussians g,
   const bool approx = (pc.flags & GSR_PAPER_POSE_APPROX) != 0;
 
   if (want_pose) {
-    for (int k = threadIdx.x; k < 4 * n_views * 6; k += BLOCK) s_dyn[k] = 0.f;
+    for (int k = threadIdx.x; k < 4 * n_views * 6; k += BLOCK) s_dyn[k] = 0.;
     __syncthreads();
   }
 
-  float mx = 0, my = 0, mz = 0, qw = 1, qx = 0, qy = 0, qz = 0, qn = 1, s0 = 1, s1 = 1, s2 = 1;
-  float opl = 0;
+  R mx = 0, my = 0, mz = 0, qw = 1, qx = 0, qy = 0, qz = 0, qn = 1, s0 = 1, s1 = 1, s2 = 1;
+  R opl = 0;
   if (active) {
     mx = g.mean[3 * i]; my = g.mean[3 * i + 1]; mz = g.mean[3 * i + 2];
-    s0 = __expf(g.log_scale[3 * i]); s1 = __expf(g.log_scale[3 * i + 1]);
-    s2 = __expf(g.log_scale[3 * i + 2]);
+    s0 = exp((R)g.log_scale[3 * i]); s1 = exp((R)g.log_scale[3 * i + 1]);
+    s2 = exp((R)g.log_scale[3 * i + 2]);
     const float4 fq = reinterpret_cast<const float4 *>(g.quat)[i];
-    qn = sqrtf(fq.x * fq.x + fq.y * fq.y + fq.z * fq.z + fq.w * fq.w);
-    const float inv = qn > 0.f ? 1.f / qn : 0.f;
-    qw = fq.x * inv; qx = fq.y * inv; qy = fq.z * inv; qz = fq.w * inv;
+    const R q0 = fq.x, q1 = fq.y, q2 = fq.z, q3 = fq.w;
+    qn = sqrt(q0 * q0 + q1 * q1 + q2 * q2 + q3 * q3);
+    const R inv = qn > 0 ? R(1) / qn : R(0);
+    qw = q0 * inv; qx = q1 * inv; qy = q2 * inv; qz = q3 * inv;
     opl = g.opacity_logit[i];
   }
-  float Rq[9];
-  quat_rot_f(qw, qx, qy, qz, Rq);
-  const float v0 = s0 * s0, v1 = s1 * s1, v2 = s2 * s2;
-  float S[9];
+  R Rq[9];
+  quat_rot_r(qw, qx, qy, qz, Rq);
+  const R v0 = s0 * s0, v1 = s1 * s1, v2 = s2 * s2;
+  R S[9];
   for (int r = 0; r < 3; ++r)
     for (int c = 0; c < 3; ++c)
       S[3 * r + c] = Rq[3 * r] * v0 * Rq[3 * c] + Rq[3 * r + 1] * v1 * Rq[3 * c + 1] +
                      Rq[3 * r + 2] * v2 * Rq[3 * c + 2];
 
-  float gm[3] = {0, 0, 0};
-  float GS[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  float gop = 0.f, gc0 = 0.f, gc1 = 0.f, gc2 = 0.f;
+  R gm[3] = {0, 0, 0};
+  R GS[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  R gop = 0., gc0 = 0., gc1 = 0., gc2 = 0.;
 
   for (int view = 0; view < n_views; ++view) {
     const int64_t rec = (int64_t)view * g.n + i;
-    float g2[NGRAD2D];
+    R g2[NGRAD2D];
     bool has = false;
     if (active && ws.count[rec] != 0u) {
       const float *src = ws.grad2d + rec * NGRAD2D;
 #pragma unroll
       for (int k = 0; k < NGRAD2D; ++k) {
         g2[k] = src[k];
-        has = has || (g2[k] != 0.f);
+        has = has || (g2[k] != 0.);
       }
     }
-    float pr[6] = {0, 0, 0, 0, 0, 0};
+    R pr[6] = {0, 0, 0, 0, 0, 0};
     if (has) {
       const gsr_camera &cam = cams[view];
-      const float *W = cam.R;
-      const float x = W[0] * mx + W[1] * my + W[2] * mz + cam.t[0];
-      const float y = W[3] * mx + W[4] * my + W[5] * mz + cam.t[1];
-      const float z = W[6] * mx + W[7] * my + W[8] * mz + cam.t[2];
-      float Mt[9], Sc[9];
+      R W[9];
+      for (int k = 0; k < 9; ++k) W[k] = cam.R[k];
+      const R x = W[0] * mx + W[1] * my + W[2] * mz + (R)cam.t[0];
+      const R y = W[3] * mx + W[4] * my + W[5] * mz + (R)cam.t[1];
+      const R z = W[6] * mx + W[7] * my + W[8] * mz + (R)cam.t[2];
+      R Mt[9], Sc[9];
       for (int r = 0; r < 3; ++r)
         for (int c = 0; c < 3; ++c)
           Mt[3 * r + c] = W[3 * r] * S[c] + W[3 * r + 1] * S[3 + c] + W[3 * r + 2] * S[6 + c];
       for (int r = 0; r < 3; ++r)
         for (int c = 0; c < 3; ++c)
           Sc[3 * r + c] = Mt[3 * r] * W[3 * c] + Mt[3 * r + 1] * W[3 * c + 1] + Mt[3 * r + 2] * W[3 * c + 2];
-      const float fx = cam.fx, fy = cam.fy;
-      const float iz = 1.f / z, iz2 = iz * iz, iz3 = iz2 * iz;
-      const float J00 = fx * iz, J02 = -fx * x * iz2, J11 = fy * iz, J12 = -fy * y * iz2;
+      const R fx = cam.fx, fy = cam.fy;
+      const R iz = R(1) / z, iz2 = iz * iz, iz3 = iz2 * iz;
+      const R J00 = fx * iz, J02 = -fx * x * iz2, J11 = fy * iz, J12 = -fy * y * iz2;
       // J Sigma_c (2x3)
-      float JS0[3], JS1[3];
+      R JS0[3], JS1[3];
       for (int c = 0; c < 3; ++c) {
         JS0[c] = J00 * Sc[c] + J02 * Sc[6 + c];
         JS1[c] = J11 * Sc[3 + c] + J12 * Sc[6 + c];
       }
-      const float A = JS0[0] * J00 + JS0[2] * J02 + pc.lowpass;
-      const float B = JS0[1] * J11 + JS0[2] * J12;
-      const float C = JS1[1] * J11 + JS1[2] * J12 + pc.lowpass;
-      const float idet = 1.f / (A * C - B * B);
-      const float ca = C * idet, cb = -B * idet, cc = A * idet;
+      const R A = JS0[0] * J00 + JS0[2] * J02 + pc.lowpass;
+      const R B = JS0[1] * J11 + JS0[2] * J12;
+      const R C = JS1[1] * J11 + JS1[2] * J12 + pc.lowpass;
+      const R idet = 1. / (A * C - B * B);
+      const R ca = C * idet, cb = -B * idet, cc = A * idet;
       // dL/dSigma' = -M G_M M with M the conic, G_M = [[ga, gb/2], [gb/2, gc]].
-      const float n00 = g2[2], n01 = 0.5f * g2[3], n11 = g2[4];
-      const float P00 = ca * n00 + cb * n01, P01 = ca * n01 + cb * n11;
-      const float P10 = cb * n00 + cc * n01, P11 = cb * n01 + cc * n11;
-      const float G00 = -(P00 * ca + P01 * cb), G01 = -(P00 * cb + P01 * cc),
+      const R n00 = g2[2], n01 = 0.5 * g2[3], n11 = g2[4];
+      const R P00 = ca * n00 + cb * n01, P01 = ca * n01 + cb * n11;
+      const R P10 = cb * n00 + cc * n01, P11 = cb * n01 + cc * n11;
+      const R G00 = -(P00 * ca + P01 * cb), G01 = -(P00 * cb + P01 * cc),
                   G11 = -(P10 * cb + P11 * cc);
       // dL/dSigma_c = J^T G J (symmetric 3x3).
-      float GSc[9];
+      R GSc[9];
       GSc[0] = J00 * J00 * G00;
       GSc[1] = J00 * J11 * G01;
       GSc[2] = J00 * (G00 * J02 + G01 * J12);
       GSc[4] = J11 * J11 * G11;
       GSc[5] = J11 * (G01 * J02 + G11 * J12);
-      GSc[8] = J02 * J02 * G00 + 2.f * J02 * J12 * G01 + J12 * J12 * G11;
+      GSc[8] = J02 * J02 * G00 + 2. * J02 * J12 * G01 + J12 * J12 * G11;
       GSc[3] = GSc[1]; GSc[6] = GSc[2]; GSc[7] = GSc[5];
       // dL/dJ = 2 G J Sigma_c (only the entries J depends on are needed).
-      const float GJ00 = 2.f * (G00 * JS0[0] + G01 * JS1[0]);
-      const float GJ02 = 2.f * (G00 * JS0[2] + G01 * JS1[2]);
-      const float GJ11 = 2.f * (G01 * JS0[1] + G11 * JS1[1]);
-      const float GJ12 = 2.f * (G01 * JS0[2] + G11 * JS1[2]);
-      const float gu = g2[0], gv = g2[1], gzd = g2[9];
+      const R GJ00 = 2. * (G00 * JS0[0] + G01 * JS1[0]);
+      const R GJ02 = 2. * (G00 * JS0[2] + G01 * JS1[2]);
+      const R GJ11 = 2. * (G01 * JS0[1] + G11 * JS1[1]);
+      const R GJ12 = 2. * (G01 * JS0[2] + G11 * JS1[2]);
+      const R gu = g2[0], gv = g2[1], gzd = g2[9];
       // Through the projected centre and depth.
-      const float pX0 = gu * fx * iz;
-      const float pX1 = gv * fy * iz;
-      const float pX2 = -gu * fx * x * iz2 - gv * fy * y * iz2 + gzd;
+      const R pX0 = gu * fx * iz;
+      const R pX1 = gv * fy * iz;
+      const R pX2 = -gu * fx * x * iz2 - gv * fy * y * iz2 + gzd;
       // Through J (part of the Sigma' path).
-      const float jX0 = -GJ02 * fx * iz2;
-      const float jX1 = -GJ12 * fy * iz2;
-      const float jX2 = -GJ00 * fx * iz2 + 2.f * GJ02 * fx * x * iz3 - GJ11 * fy * iz2 +
-                        2.f * GJ12 * fy * y * iz3;
-      const float gX0 = pX0 + jX0, gX1 = pX1 + jX1, gX2 = pX2 + jX2;
+      const R jX0 = -GJ02 * fx * iz2;
+      const R jX1 = -GJ12 * fy * iz2;
+      const R jX2 = -GJ00 * fx * iz2 + 2. * GJ02 * fx * x * iz3 - GJ11 * fy * iz2 +
+                        2. * GJ12 * fy * y * iz3;
+      const R gX0 = pX0 + jX0, gX1 = pX1 + jX1, gX2 = pX2 + jX2;
       if (want_gauss) {
         gm[0] += W[0] * gX0 + W[3] * gX1 + W[6] * gX2;
         gm[1] += W[1] * gX0 + W[4] * gX1 + W[7] * gX2;
         gm[2] += W[2] * gX0 + W[5] * gX1 + W[8] * gX2;
         // W^T GSc W
-        float T9[9];
+        R T9[9];
         for (int r = 0; r < 3; ++r)
           for (int c = 0; c < 3; ++c)
             T9[3 * r + c] = W[r] * GSc[c] + W[3 + r] * GSc[3 + c] + W[6 + r] * GSc[6 + c];
@@ -163,27 +175,27 @@ __global__ __launch_bounds__(BLOCK) void k_preprocess_bwd(gsr_gaussians g,
         gc0 += g2[6]; gc1 += g2[7]; gc2 += g2[8];
       }
       if (want_pose) {
-        const float rX0 = approx ? pX0 : gX0, rX1 = approx ? pX1 : gX1, rX2 = approx ? pX2 : gX2;
+        const R rX0 = approx ? pX0 : gX0, rX1 = approx ? pX1 : gX1, rX2 = approx ? pX2 : gX2;
         pr[0] = rX0; pr[1] = rX1; pr[2] = rX2;
         pr[3] = y * rX2 - z * rX1;
         pr[4] = z * rX0 - x * rX2;
         pr[5] = x * rX1 - y * rX0;
         if (!approx) {
           // B = Sigma_c GSc; phi += 2 (B12 - B21, B20 - B02, B01 - B10).
-          float Bm[9];
+          R Bm[9];
           for (int r = 0; r < 3; ++r)
             for (int c = 0; c < 3; ++c)
               Bm[3 * r + c] = Sc[3 * r] * GSc[c] + Sc[3 * r + 1] * GSc[3 + c] + Sc[3 * r + 2] * GSc[6 + c];
-          pr[3] += 2.f * (Bm[5] - Bm[7]);
-          pr[4] += 2.f * (Bm[6] - Bm[2]);
-          pr[5] += 2.f * (Bm[1] - Bm[3]);
+          pr[3] += 2. * (Bm[5] - Bm[7]);
+          pr[4] += 2. * (Bm[6] - Bm[2]);
+          pr[5] += 2. * (Bm[1] - Bm[3]);
         }
       }
     }
     if (want_pose && __any(has)) {
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
-        const float t = wave_sum(pr[k]);
+        const R t = wave_sum_d(pr[k]);
         if (lane == 0) s_dyn[(wave * n_views + view) * 6 + k] = t;
       }
     }
@@ -191,61 +203,61 @@ __global__ __launch_bounds__(BLOCK) void k_preprocess_bwd(gsr_gaussians g,
 
   if (active && want_gauss) {
     // Eq. 2 backward: Sigma = Rq diag(s^2) Rq^T.
-    float GR[9];
+    R GR[9];
     for (int r = 0; r < 3; ++r)
       for (int c = 0; c < 3; ++c) {
-        const float vv = c == 0 ? v0 : (c == 1 ? v1 : v2);
-        GR[3 * r + c] = 2.f * (GS[3 * r] * Rq[c] + GS[3 * r + 1] * Rq[3 + c] + GS[3 * r + 2] * Rq[6 + c]) * vv;
+        const R vv = c == 0 ? v0 : (c == 1 ? v1 : v2);
+        GR[3 * r + c] = 2. * (GS[3 * r] * Rq[c] + GS[3 * r + 1] * Rq[3 + c] + GS[3 * r + 2] * Rq[6 + c]) * vv;
       }
-    float d[3];
+    R d[3];
     for (int k = 0; k < 3; ++k) {
-      float acc = 0.f;
+      R acc = 0.;
       for (int r = 0; r < 3; ++r)
         for (int c = 0; c < 3; ++c) acc += Rq[3 * r + k] * GS[3 * r + c] * Rq[3 * c + k];
       d[k] = acc;
     }
-    const float gl0 = 2.f * v0 * d[0], gl1 = 2.f * v1 * d[1], gl2 = 2.f * v2 * d[2];
-    const float w = qw, x = qx, y = qy, z = qz;
-    const float gw = 2.f * (-z * GR[1] + y * GR[2] + z * GR[3] - x * GR[5] - y * GR[6] + x * GR[7]);
-    const float gx = 2.f * (y * GR[1] + z * GR[2] + y * GR[3] - 2.f * x * GR[4] - w * GR[5] + z * GR[6] +
-                            w * GR[7] - 2.f * x * GR[8]);
-    const float gy = 2.f * (-2.f * y * GR[0] + x * GR[1] + w * GR[2] + x * GR[3] + z * GR[5] - w * GR[6] +
-                            z * GR[7] - 2.f * y * GR[8]);
-    const float gz = 2.f * (-2.f * z * GR[0] - w * GR[1] + x * GR[2] + w * GR[3] - 2.f * z * GR[4] + y * GR[5] +
+    const R gl0 = 2. * v0 * d[0], gl1 = 2. * v1 * d[1], gl2 = 2. * v2 * d[2];
+    const R w = qw, x = qx, y = qy, z = qz;
+    const R gw = 2. * (-z * GR[1] + y * GR[2] + z * GR[3] - x * GR[5] - y * GR[6] + x * GR[7]);
+    const R gx = 2. * (y * GR[1] + z * GR[2] + y * GR[3] - 2. * x * GR[4] - w * GR[5] + z * GR[6] +
+                            w * GR[7] - 2. * x * GR[8]);
+    const R gy = 2. * (-2. * y * GR[0] + x * GR[1] + w * GR[2] + x * GR[3] + z * GR[5] - w * GR[6] +
+                            z * GR[7] - 2. * y * GR[8]);
+    const R gz = 2. * (-2. * z * GR[0] - w * GR[1] + x * GR[2] + w * GR[3] - 2. * z * GR[4] + y * GR[5] +
                             x * GR[6] + y * GR[7]);
-    const float dotq = w * gw + x * gx + y * gy + z * gz;
-    const float iq = qn > 0.f ? 1.f / qn : 0.f;
-    const float o = 1.f / (1.f + __expf(-opl));
+    const R dotq = w * gw + x * gx + y * gy + z * gz;
+    const R iq = qn > 0. ? 1. / qn : 0.;
+    const R o = R(1) / (R(1) + exp(-opl));
     if (gr.d_mean) {
-      gr.d_mean[3 * i] += gm[0];
-      gr.d_mean[3 * i + 1] += gm[1];
-      gr.d_mean[3 * i + 2] += gm[2];
+      gr.d_mean[3 * i] += (float)gm[0];
+      gr.d_mean[3 * i + 1] += (float)gm[1];
+      gr.d_mean[3 * i + 2] += (float)gm[2];
     }
     if (gr.d_log_scale) {
-      gr.d_log_scale[3 * i] += gl0;
-      gr.d_log_scale[3 * i + 1] += gl1;
-      gr.d_log_scale[3 * i + 2] += gl2;
+      gr.d_log_scale[3 * i] += (float)gl0;
+      gr.d_log_scale[3 * i + 1] += (float)gl1;
+      gr.d_log_scale[3 * i + 2] += (float)gl2;
     }
     if (gr.d_quat) {
       float4 *dq = reinterpret_cast<float4 *>(gr.d_quat) + i;
       float4 cur = *dq;
-      cur.x += (gw - w * dotq) * iq;
-      cur.y += (gx - x * dotq) * iq;
-      cur.z += (gy - y * dotq) * iq;
-      cur.w += (gz - z * dotq) * iq;
+      cur.x += (float)((gw - w * dotq) * iq);
+      cur.y += (float)((gx - x * dotq) * iq);
+      cur.z += (float)((gy - y * dotq) * iq);
+      cur.w += (float)((gz - z * dotq) * iq);
       *dq = cur;
     }
-    if (gr.d_opacity_logit) gr.d_opacity_logit[i] += gop * o * (1.f - o);
+    if (gr.d_opacity_logit) gr.d_opacity_logit[i] += (float)(gop * o * (R(1) - o));
     if (gr.d_rgb) {
-      gr.d_rgb[3 * i] += gc0;
-      gr.d_rgb[3 * i + 1] += gc1;
-      gr.d_rgb[3 * i + 2] += gc2;
+      gr.d_rgb[3 * i] += (float)gc0;
+      gr.d_rgb[3 * i + 1] += (float)gc1;
+      gr.d_rgb[3 * i + 2] += (float)gc2;
     }
   }
 
   if (want_pose) {
     __syncthreads();
-    float *dst = ws.pose_part + (int64_t)blockIdx.x * n_views * 6;
+    R *dst = ws.pose_part + (int64_t)blockIdx.x * n_views * 6;
     for (int k = threadIdx.x; k < n_views * 6; k += BLOCK)
       dst[k] = s_dyn[k] + s_dyn[n_views * 6 + k] + s_dyn[2 * n_views * 6 + k] + s_dyn[3 * n_views * 6 + k];
   }
@@ -253,11 +265,11 @@ __global__ __launch_bounds__(BLOCK) void k_preprocess_bwd(gsr_gaussians g,
 
 // Deterministic reduction of the per-block pose partials: one block per
 // (view, component), fixed summation order.
-__global__ __launch_bounds__(BLOCK) void k_pose_reduce(const float *__restrict__ part, int n_blocks,
+__global__ __launch_bounds__(BLOCK) void k_pose_reduce(const double *__restrict__ part, int n_blocks,
                                                        int n_views, float *__restrict__ d_pose) {
-  __shared__ float red[BLOCK];
+  __shared__ double red[BLOCK];
   const int vc = blockIdx.x;  // view * 6 + component
-  float acc = 0.f;
+  double acc = 0.0;
   for (int b = threadIdx.x; b < n_blocks; b += BLOCK) acc += part[(int64_t)b * n_views * 6 + vc];
   red[threadIdx.x] = acc;
   __syncthreads();
@@ -265,7 +277,7 @@ __global__ __launch_bounds__(BLOCK) void k_pose_reduce(const float *__restrict__
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) d_pose[vc] += red[0];
+  if (threadIdx.x == 0) d_pose[vc] += (float)red[0];
 }
 
 void launch_preprocess_backward(const Plan &p, const gsr_gaussians &g, const gsr_camera *cams,
@@ -274,7 +286,7 @@ void launch_preprocess_backward(const Plan &p, const gsr_gaussians &g, const gsr
   if (g.n == 0) return;
   PreConstsB pc{cfg.z_near, cfg.lowpass, cfg.cutoff_sigma, cfg.flags};
   const bool want_pose = (cfg.flags & GSR_POSE_GRAD) && gr.d_pose;
-  const size_t lds = want_pose ? (size_t)4 * p.n_views * 6 * sizeof(float) : 0;
+  const size_t lds = want_pose ? (size_t)4 * p.n_views * 6 * sizeof(double) : 0;
   hipLaunchKernelGGL(k_preprocess_bwd, dim3(p.n_pose_blocks), dim3(BLOCK), lds, s, g, cams,
                      p.n_views, pc, ws, gr);
   if (want_pose)

@@ -127,7 +127,7 @@ __global__ __launch_bounds__(BLOCK) void k_preprocess(gsr_gaussians g,
     ws.count[rec] = 0u;
     ws.dkeys[0][rec] = 0xFFFFFFFFu;
     ws.dvals[0][rec] = (uint32_t)rec;
-    ws.rect[rec] = make_ushort4(1, 0, 1, 0);
+    ws.tinfo[rec] = make_uint2(0u, 0u);
     return;
   }
   const float zf = (float)z;
@@ -136,8 +136,10 @@ __global__ __launch_bounds__(BLOCK) void k_preprocess(gsr_gaussians g,
   ws.recA[rec] = make_float4(uh, (float)(u - (double)uh), vh, (float)(v - (double)vh));
   ws.recB[rec] = make_float4((float)(C / det), (float)(-B / det), (float)(A / det), op);
   ws.recZ[rec] = zf;
-  ws.rect[rec] = make_ushort4((unsigned short)tx0, (unsigned short)tx1, (unsigned short)ty0,
-                              (unsigned short)ty1);
+  // First tile of the rectangle (global id), its width and the view's row
+  // stride: pair j of this record covers tile first + (j / w) * TX + j % w.
+  ws.tinfo[rec] = make_uint2((uint32_t)(vi.tile_off + ty0 * vi.TX + tx0),
+                             ((uint32_t)(tx1 - tx0 + 1) << 16) | (uint32_t)vi.TX);
   ws.count[rec] = (uint32_t)(tx1 - tx0 + 1) * (uint32_t)(ty1 - ty0 + 1);
   ws.dkeys[0][rec] = __float_as_uint(zf);
   ws.dvals[0][rec] = (uint32_t)rec;

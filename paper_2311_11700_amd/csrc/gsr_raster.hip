@@ -228,7 +228,16 @@ __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, con
 
   float T = in.T;
   const float Tf = in.T;
-  float aC0 = rc.bg[0], aC1 = rc.bg[1], aC2 = rc.bg[2], aD = 0.f;
+  // Colour behind the current entry, normalised by the transmittance in
+  // front of it (starts at the background).  Depth is accumulated relative
+  // to the depth zr of the pixel's last contributor: with the telescoping
+  // identity sum_m alpha_m T_m = 1 - T_f,
+  //   dD/dalpha_k = T_k ((z_k - zr) - aDs_k) + zr T_f / (1 - alpha_k),
+  // where aDs runs over the shifted depths z - zr.  On a surface all the
+  // depths agree to a few mm, so the shifted terms stay small and float32
+  // keeps their digits (z_k - aD_k itself would cancel).
+  float aC0 = rc.bg[0], aC1 = rc.bg[1], aC2 = rc.bg[2], aDs = 0.f, zr = 0.f;
+  bool have_zr = false;
 
   for (int hi = maxlast; hi > 0; hi -= BATCH) {
     const int lo = hi > BATCH ? hi - BATCH : 0;
@@ -262,13 +271,18 @@ __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, con
           g[7] = in.gC1 * w;
           g[8] = in.gC2 * w;
           g[9] = in.gD * w;
+          if (!have_zr) {
+            zr = geo.w;
+            have_zr = true;
+          }
+          const float zs = geo.w - zr;
           const float dLda = T * (in.gC0 * (col.x - aC0) + in.gC1 * (col.y - aC1) +
-                                  in.gC2 * (col.z - aC2) + in.gD * (geo.w - aD)) -
-                             in.gT * Tf * rinv;
+                                  in.gC2 * (col.z - aC2) + in.gD * (zs - aDs)) +
+                             (in.gD * zr - in.gT) * Tf * rinv;
           aC0 = __fmaf_rn(alpha, col.x - aC0, aC0);
           aC1 = __fmaf_rn(alpha, col.y - aC1, aC1);
           aC2 = __fmaf_rn(alpha, col.z - aC2, aC2);
-          aD = __fmaf_rn(alpha, geo.w - aD, aD);
+          aDs = __fmaf_rn(alpha, zs - aDs, aDs);
           if (oG <= rc.alpha_max) {
             const float dLdP = dLda * oG;
             g[0] = dLdP * __fmaf_rn(con.x, dx, con.y * dy);

@@ -46,9 +46,17 @@ void launch_fill_f32(float *ptr, float value, int64_t count, hipStream_t s) {
 }
 
 // Clear the per-call header words (pair count, queue counter).  The overflow
-// flag and required count are sticky until gsr_check_overflow reads them.
+// flag and required count are sticky until gsr_check_overflow reads them; on
+// a workspace's first use (no magic yet) they are cleared too.
 __global__ void k_reset_header(uint32_t *hdr) {
   if (threadIdx.x == 0) {
+    if (hdr[HDR_MAGIC] != HDR_MAGIC0 || hdr[HDR_MAGIC + 1] != HDR_MAGIC1) {
+      hdr[HDR_REQUIRED] = 0u;
+      hdr[HDR_REQUIRED + 1] = 0u;
+      hdr[HDR_OVERFLOW] = 0u;
+      hdr[HDR_MAGIC] = HDR_MAGIC0;
+      hdr[HDR_MAGIC + 1] = HDR_MAGIC1;
+    }
     hdr[HDR_NPAIRS] = 0u;
     hdr[HDR_NPAIRS + 1] = 0u;
     hdr[HDR_QUEUE] = 0u;
@@ -296,54 +304,98 @@ __global__ __launch_bounds__(BLOCK) void k_scan_top(unsigned long long *__restri
   }
 }
 
-__global__ __launch_bounds__(BLOCK) void k_scan_emit(
-    const uint32_t *__restrict__ order, const uint32_t *__restrict__ count,
-    const ushort4 *__restrict__ rect, int64_t n_rec, int64_t n,
-    const unsigned long long *__restrict__ part, const ViewInfo *__restrict__ views,
-    uint64_t capacity, uint32_t *__restrict__ pkeys, uint32_t *__restrict__ pvals) {
+// Per-record pair offsets in depth order, clamped to the capacity (so the
+// array stays non-decreasing and every offset fits 32 bits).
+__global__ __launch_bounds__(BLOCK) void k_scan_down(const uint32_t *__restrict__ order,
+                                                     const uint32_t *__restrict__ count, int64_t n_rec,
+                                                     const unsigned long long *__restrict__ part,
+                                                     uint64_t capacity, uint32_t *__restrict__ off) {
   __shared__ unsigned long long s_w[4];
   const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + threadIdx.x * SCAN_ITEMS;
-  uint32_t c[SCAN_ITEMS], rid[SCAN_ITEMS];
+  uint32_t c[SCAN_ITEMS];
   unsigned long long sum = 0ull;
 #pragma unroll
   for (int k = 0; k < SCAN_ITEMS; ++k) {
     const int64_t idx = base + k;
-    rid[k] = idx < n_rec ? order[idx] : 0u;
-    c[k] = idx < n_rec ? count[rid[k]] : 0u;
+    c[k] = idx < n_rec ? count[order[idx]] : 0u;
     sum += c[k];
   }
   unsigned long long total;
-  unsigned long long off = block_exclusive_scan<unsigned long long>(sum, s_w, total) + part[blockIdx.x];
+  unsigned long long o = block_exclusive_scan<unsigned long long>(sum, s_w, total) + part[blockIdx.x];
+#pragma unroll
   for (int k = 0; k < SCAN_ITEMS; ++k) {
-    if (c[k] != 0u) {
-      const uint32_t r = rid[k];
-      const int view = (int)(r / (uint64_t)n);
-      const ViewInfo vi = views[view];
-      const ushort4 rc = rect[r];
-      unsigned long long pos = off;
-      for (int ty = rc.z; ty <= rc.w; ++ty) {
-        const uint32_t row = (uint32_t)(vi.tile_off + ty * vi.TX);
-        for (int tx = rc.x; tx <= rc.y; ++tx) {
-          if (pos < capacity) {
-            pkeys[pos] = row + (uint32_t)tx;
-            pvals[pos] = r;
-          }
-          ++pos;
-        }
-      }
+    const int64_t idx = base + k;
+    if (idx < n_rec) off[idx] = (uint32_t)(o < capacity ? o : capacity);
+    o += c[k];
+  }
+}
+
+// Largest k in [lo, hi] with off[k] <= p (off non-decreasing, off[lo] <= p).
+__device__ __forceinline__ uint32_t find_record(const uint32_t *__restrict__ off, uint32_t lo, uint32_t hi,
+                                                uint32_t p) {
+  while (lo < hi) {
+    const uint32_t mid = lo + (hi - lo + 1) / 2;
+    if (off[mid] <= p) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// One thread per (tile, Gaussian) pair: find the record that owns the pair
+// (records are in depth order, so the pairs come out in depth order), decode
+// the tile from the record's rectangle, write key and value.  Every block
+// first brackets the records of its 256 pairs, so the per-thread searches
+// are short.
+__global__ __launch_bounds__(BLOCK) void k_emit_pairs(const uint32_t *__restrict__ order,
+                                                      const uint32_t *__restrict__ off,
+                                                      const uint2 *__restrict__ tinfo, uint32_t n_rec,
+                                                      const unsigned long long *__restrict__ n_dev, uint32_t cap,
+                                                      uint32_t *__restrict__ pkeys, uint32_t *__restrict__ pvals) {
+  __shared__ uint32_t s_lo, s_hi;
+  const uint32_t n = sort_count(n_dev, 0u, cap);
+  for (uint32_t base = blockIdx.x * BLOCK; base < n; base += gridDim.x * BLOCK) {
+    if (threadIdx.x == 0) s_lo = find_record(off, 0u, n_rec - 1u, base);
+    if (threadIdx.x == 1) {
+      const uint32_t last = base + BLOCK - 1u < n ? base + BLOCK - 1u : n - 1u;
+      s_hi = find_record(off, 0u, n_rec - 1u, last);
     }
-    off += c[k];
+    __syncthreads();
+    const uint32_t p = base + threadIdx.x;
+    if (p < n) {
+      const uint32_t k = find_record(off, s_lo, s_hi, p);
+      const uint32_t rec = order[k];
+      const uint32_t j = p - off[k];
+      const uint2 ti = tinfo[rec];
+      const uint32_t w = ti.y >> 16, TX = ti.y & 0xFFFFu;
+      // j < 2^24 and w < 2^16: the float quotient is within one of the
+      // integer quotient; fix it up exactly.
+      uint32_t q = (uint32_t)((float)j / (float)w);
+      if (q * w > j) --q;
+      else if ((q + 1u) * w <= j) ++q;
+      pkeys[p] = ti.x + q * TX + (j - q * w);
+      pvals[p] = rec;
+    }
+    __syncthreads();
   }
 }
 
 void launch_emit_pairs(const Plan &p, const Workspace &ws, const ViewInfo *views, hipStream_t s) {
+  (void)views;
   const uint32_t *order = ws.dvals[ws.dsorted];
+  uint32_t *off = ws.dkeys[ws.dsorted ^ 1];  // free after the depth sort
   hipLaunchKernelGGL(k_scan_reduce, dim3(p.n_scan_blocks), dim3(BLOCK), 0, s, order, ws.count,
                      p.n_rec, ws.scan_part);
   hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(BLOCK), 0, s, ws.scan_part, p.n_scan_blocks, ws.hdr,
                      (uint64_t)p.capacity);
-  hipLaunchKernelGGL(k_scan_emit, dim3(p.n_scan_blocks), dim3(BLOCK), 0, s, order, ws.count, ws.rect,
-                     p.n_rec, p.n, ws.scan_part, views, (uint64_t)p.capacity, ws.pkeys[0], ws.pvals[0]);
+  if (p.n_rec == 0) return;
+  hipLaunchKernelGGL(k_scan_down, dim3(p.n_scan_blocks), dim3(BLOCK), 0, s, order, ws.count, p.n_rec,
+                     ws.scan_part, (uint64_t)p.capacity, off);
+  int64_t blocks = (p.capacity + BLOCK - 1) / BLOCK;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  const unsigned long long *n_dev = reinterpret_cast<const unsigned long long *>(ws.hdr + HDR_NPAIRS);
+  hipLaunchKernelGGL(k_emit_pairs, dim3((unsigned)blocks), dim3(BLOCK), 0, s, order, off, ws.tinfo,
+                     (uint32_t)p.n_rec, n_dev, (uint32_t)p.capacity, ws.pkeys[0], ws.pvals[0]);
 }
 
 // ---------------------------------------------------------------- tile ranges
