@@ -229,6 +229,21 @@ gsr_status gsr_autotune(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *
                         size_t workspace_bytes, const gsr_grads *grads, float *loss, int reps,
                         gsr_tuning *best, gsr_stream stream);
 
+/* Reliable-Gaussian selection for the fine tracking stage (Eq. 12, Sec. 3.3):
+ * each Gaussian's centre is projected with the (coarse) pose `cam` (DEVICE,
+ * one gsr_camera); when it lands in front of the camera (z > z_near) on a
+ * pixel inside the image whose observed depth D (depth_obs, DEVICE
+ * [height][width] float, 0 = no reading) is valid, the Gaussian is kept only
+ * if |D - z| <= eps, z being the camera-frame depth of its centre.
+ * Gaussians that project outside the image, behind the near plane or onto a
+ * missing reading are kept; Gaussians already excluded by g->mask stay
+ * excluded.  The pixel is the one nearest to the projected centre
+ * (floor(u + 0.5), floor(v + 0.5)); the projection is evaluated in FP64.
+ * Writes mask_out[n] (DEVICE uint8, 1 = selected).  Asynchronous. */
+gsr_status gsr_select_reliable(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cam,
+                               const float *depth_obs, int width, int height, float eps, float z_near,
+                               uint8_t *mask_out, gsr_stream stream);
+
 /* Per-stage timing of calls on this context (HIP events recorded on the
  * call's stream around each stage; HIP-graph launches are not split). */
 enum {

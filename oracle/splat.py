@@ -508,3 +508,38 @@ def l1_loss(rgb, depth, target_rgb, target_depth, pixel_mask=None, w_rgb=1.0, w_
     dd = depth - tdep
     loss = w_rgb * np.sum(m[None] * np.abs(dc)) + w_depth * np.sum(md * np.abs(dd))
     return loss, w_rgb * m[None] * np.sign(dc), w_depth * md * np.sign(dd)
+
+
+# --------------------------------------------------------------------------- Eq. 12
+
+def select_reliable(scene, cam, depth_obs, eps, z_near=0.2, mask=None):
+    """Reliable-Gaussian selection of the fine tracking stage (Eq. 12): a
+    Gaussian whose centre projects (in front of the camera) onto a pixel of
+    the image with a valid observed depth D is kept only if |D - z| <= eps,
+    z being its camera-frame depth; all other Gaussians are kept (no
+    evidence), and Gaussians excluded by `mask` stay excluded.  The pixel is
+    the nearest one to the projected centre.  Returns a uint8 mask."""
+    mean = _as64(scene.mean)
+    W = _as64(cam.R).reshape(3, 3)
+    t = _as64(cam.t).reshape(3)
+    depth_obs = np.asarray(depth_obs, np.float32).reshape(int(cam.height), int(cam.width))
+    eps, z_near = f32(eps), f32(z_near)
+    n = mean.shape[0]
+    keep = np.ones(n, np.uint8) if mask is None else (np.asarray(mask) != 0).astype(np.uint8)
+    for i in range(n):  # plain loop: one Gaussian at a time
+        if not keep[i]:
+            continue
+        mx, my, mz = mean[i]
+        x = ((W[0, 0] * mx + W[0, 1] * my) + W[0, 2] * mz) + t[0]
+        y = ((W[1, 0] * mx + W[1, 1] * my) + W[1, 2] * mz) + t[1]
+        z = ((W[2, 0] * mx + W[2, 1] * my) + W[2, 2] * mz) + t[2]
+        if not z > z_near:
+            continue
+        u = (float(cam.fx) * x) / z + float(cam.cx)
+        v = (float(cam.fy) * y) / z + float(cam.cy)
+        px, py = np.floor(u + 0.5), np.floor(v + 0.5)
+        if 0 <= px < int(cam.width) and 0 <= py < int(cam.height):
+            D = float(depth_obs[int(py), int(px)])
+            if D > 0 and abs(D - z) > eps:
+                keep[i] = 0
+    return keep

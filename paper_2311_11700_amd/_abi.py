@@ -102,6 +102,8 @@ SIGNATURES = {
                                     c_void_p, c_void_p, c_void_p, ctypes.c_float, ctypes.c_float, c_void_p,
                                     ctypes.c_size_t, _P(gsr_grads), c_void_p, ctypes.c_int, _P(gsr_tuning),
                                     c_void_p]),
+    "gsr_select_reliable": (ctypes.c_int, [c_void_p, _P(gsr_gaussians), c_void_p, c_void_p, ctypes.c_int,
+                                           ctypes.c_int, ctypes.c_float, ctypes.c_float, c_void_p, c_void_p]),
     "gsr_set_profiling": (ctypes.c_int, [c_void_p, ctypes.c_int]),
     "gsr_stage_times": (ctypes.c_int, [c_void_p, _P(ctypes.c_double), _P(ctypes.c_int64)]),
     "gsr_work_counts": (ctypes.c_int, [c_void_p, c_void_p, c_void_p, _P(ctypes.c_int64)]),

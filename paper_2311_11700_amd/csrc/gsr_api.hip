@@ -602,6 +602,17 @@ gsr_status gsr_autotune(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *
   return last_launch(ctx, "gsr_autotune");
 }
 
+gsr_status gsr_select_reliable(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cam,
+                               const float *depth_obs, int width, int height, float eps, float z_near,
+                               uint8_t *mask_out, gsr_stream stream) {
+  if (!ctx) return GSR_E_INVALID;
+  if (!g || !cam || !depth_obs || !mask_out || width < 1 || height < 1 || !(eps >= 0.f))
+    return fail(ctx, GSR_E_INVALID, "gsr_select_reliable: invalid argument");
+  if (g->n > 0 && !g->mean) return fail(ctx, GSR_E_INVALID, "gsr_select_reliable: null mean");
+  launch_select_reliable(*g, cam, depth_obs, width, height, eps, z_near, mask_out, static_cast<hipStream_t>(stream));
+  return last_launch(ctx, "gsr_select_reliable launch");
+}
+
 gsr_status gsr_set_profiling(gsr_ctx *ctx, int enable) {
   if (!ctx) return GSR_E_INVALID;
   if (enable && ctx->ev_pool.empty()) {

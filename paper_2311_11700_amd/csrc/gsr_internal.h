@@ -126,6 +126,10 @@ __device__ __forceinline__ unsigned long long lanemask_lt() {
 void launch_preprocess(const gsr_gaussians &g, const gsr_camera *cams, const ViewInfo *views,
                        int n_views, const gsr_config &cfg, const Workspace &ws, hipStream_t s);
 
+// Reliable-Gaussian selection (fine tracking stage).
+void launch_select_reliable(const gsr_gaussians &g, const gsr_camera *cam, const float *depth, int W, int H,
+                            float eps, float z_near, uint8_t *out, hipStream_t s);
+
 // Sorting and list construction.
 int launch_depth_sort(const Plan &p, Workspace &ws, hipStream_t s, int sort_grid);
 void launch_emit_pairs(const Plan &p, const Workspace &ws, const ViewInfo *views, hipStream_t s);

@@ -152,4 +152,40 @@ void launch_preprocess(const gsr_gaussians &g, const gsr_camera *cams, const Vie
   if (g.n > 0) hipLaunchKernelGGL(k_preprocess, grid, dim3(BLOCK), 0, s, g, cams, views, pc, ws);
 }
 
+// Reliable-Gaussian selection (Eq. 12): compare each centre's camera depth
+// with the observed depth at the nearest pixel.
+__global__ __launch_bounds__(BLOCK) void k_select_reliable(gsr_gaussians g, const gsr_camera *__restrict__ cam,
+                                                           const float *__restrict__ depth, int W, int H,
+                                                           double eps, double z_near, uint8_t *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (i >= g.n) return;
+  uint8_t keep = 1;
+  if (g.mask && g.mask[i] == 0) {
+    keep = 0;
+  } else {
+    const double mx = g.mean[3 * i], my = g.mean[3 * i + 1], mz = g.mean[3 * i + 2];
+    const float *R = cam->R;
+    const double x = (((double)R[0] * mx + (double)R[1] * my) + (double)R[2] * mz) + (double)cam->t[0];
+    const double y = (((double)R[3] * mx + (double)R[4] * my) + (double)R[5] * mz) + (double)cam->t[1];
+    const double z = (((double)R[6] * mx + (double)R[7] * my) + (double)R[8] * mz) + (double)cam->t[2];
+    if (z > z_near) {
+      const double u = ((double)cam->fx * x) / z + (double)cam->cx;
+      const double v = ((double)cam->fy * y) / z + (double)cam->cy;
+      const double pxd = floor(u + 0.5), pyd = floor(v + 0.5);
+      if (pxd >= 0.0 && pxd < (double)W && pyd >= 0.0 && pyd < (double)H) {
+        const double D = depth[(int64_t)pyd * W + (int64_t)pxd];
+        if (D > 0.0 && fabs(D - z) > eps) keep = 0;
+      }
+    }
+  }
+  out[i] = keep;
+}
+
+void launch_select_reliable(const gsr_gaussians &g, const gsr_camera *cam, const float *depth, int W, int H,
+                            float eps, float z_near, uint8_t *out, hipStream_t s) {
+  if (g.n > 0)
+    hipLaunchKernelGGL(k_select_reliable, dim3((unsigned)((g.n + BLOCK - 1) / BLOCK)), dim3(BLOCK), 0, s, g, cam,
+                       depth, W, H, (double)eps, (double)z_near, out);
+}
+
 }  // namespace gsr

@@ -321,6 +321,17 @@ class Renderer:
         return dict(blocks_per_cu=best.blocks_per_cu, tiles_per_pop=best.tiles_per_pop, lpt_order=best.lpt_order)
 
 
+    def select_reliable(self, g: Gaussians, cam: torch.Tensor, depth_obs: torch.Tensor, width: int, height: int,
+                        eps: float, z_near: float = 0.2, mask_out: Optional[torch.Tensor] = None, stream=None):
+        """gsr_select_reliable: uint8 mask of the Gaussians kept for the fine
+        tracking stage (Eq. 12).  `cam` is one packed camera (the coarse pose)."""
+        out = mask_out if mask_out is not None else torch.empty(g.n, dtype=torch.uint8, device=self.device)
+        gc = g.c()
+        self._check(self.lib.gsr_select_reliable(self.ctx, ctypes.byref(gc), cam.data_ptr(), depth_obs.data_ptr(),
+                                                 int(width), int(height), float(eps), float(z_near), out.data_ptr(),
+                                                 _stream_ptr(stream)))
+        return out
+
     # ------------------------------------------------------------ profiling
     def set_profiling(self, enable: bool = True):
         self._check(self.lib.gsr_set_profiling(self.ctx, 1 if enable else 0))

@@ -4,9 +4,11 @@ full-resolution iterations restricted to reliable Gaussians, each iteration
 one fused forward + L1 + pose-only backward call followed by an Adam step on
 the se(3) increment and a left update of the camera pose.
 
-The pose is kept on the device: the Adam step, the SE(3) exponential and the
-packing of the camera struct are small torch operations, so an iteration
-never synchronises with the host.
+The fine stage renders only the reliable Gaussians of Eq. 12, selected once
+with the coarse pose and the observed depth (gsr_select_reliable).  The pose
+is kept on the device: the Adam step, the SE(3) exponential and the packing
+of the camera struct are small torch operations, so an iteration never
+synchronises with the host.
 """
 from __future__ import annotations
 
@@ -54,7 +56,8 @@ class TrackingConfig:
     w_rgb: float = 0.8             # photometric weight
     w_depth: float = 0.3           # geometric weight
     coarse_factor: int = 4         # 640x480 -> 160x120
-    reliable_opacity: float = 0.5  # fine stage: Gaussians with sigmoid(opacity) above this
+    reliable_eps: float = 0.1      # Eq. 12: keep Gaussians with |D_obs - z| <= eps (metres)
+    reliable_opacity: Optional[float] = None  # optional extra rule: sigmoid(opacity) above this
 
 
 def downsample_targets(rgb: torch.Tensor, depth: torch.Tensor, width: int, height: int, k: int):
@@ -88,8 +91,14 @@ class Tracker:
         self.coarse = Renderer(device)
         self.coarse.plan(gaussians.n, [(self.coarse_cam.width, self.coarse_cam.height)])
         dev = self.fine.device
-        self.reliable = (torch.sigmoid(gaussians.opacity_logit) > self.cfg.reliable_opacity).to(torch.uint8)
-        self.g_fine = dataclasses.replace(gaussians, mask=self.reliable.contiguous())
+        self.g_sel = gaussians
+        if self.cfg.reliable_opacity is not None:
+            op_mask = (torch.sigmoid(gaussians.opacity_logit) > self.cfg.reliable_opacity).to(torch.uint8)
+            if gaussians.mask is not None:
+                op_mask = op_mask & gaussians.mask
+            self.g_sel = dataclasses.replace(gaussians, mask=op_mask.contiguous())
+        self.reliable = torch.empty(gaussians.n, dtype=torch.uint8, device=dev)
+        self.g_fine = dataclasses.replace(gaussians, mask=self.reliable)
         self.grads = {"d_pose": torch.zeros(1, 6, device=dev)}
         self.loss = torch.zeros(1, device=dev)
 
@@ -119,6 +128,10 @@ class Tracker:
             cams = cams_c if coarse else cams_f
             g = self.g if coarse else self.g_fine
             self._pack(None, T, cams)
+            if it == c.coarse_iters:
+                # Eq. 12 with the coarse pose and the observed depth.
+                self.fine.select_reliable(self.g_sel, cams_f, target_depth, self.cam.width, self.cam.height,
+                                          c.reliable_eps, self.rcfg.z_near, mask_out=self.reliable)
             self.grads["d_pose"].zero_()
             self.loss.zero_()
             r.render_l1_fused(g, cams, self.rcfg, ct if coarse else target_rgb, cd if coarse else target_depth,

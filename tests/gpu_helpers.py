@@ -115,7 +115,7 @@ def to_dev(x, dtype=torch.float32):
     return torch.as_tensor(x).to(device="cuda", dtype=dtype).contiguous()
 
 
-def assert_close_scaled(a, b, rtol=1e-3, scale_tol=1e-4, what=""):
+def assert_close_scaled(a, b, rtol=1e-3, scale_tol=5e-4, what=""):
     """Element-wise |a - b| <= rtol |b| + scale_tol max|b|: for comparing two
     float32 results whose only difference is the order of atomic additions
     (sums with heavy cancellation lose digits relative to the tensor's scale,

@@ -499,3 +499,18 @@ def test_autograd_function(gsr_lib):
     for p, k in zip(params, ("mean", "log_scale", "quat", "opacity_logit", "rgb")):
         assert H.rel_err(p.grad.cpu().numpy(), ref[k]) <= 2e-2, k
     assert H.rel_err(xi.grad.cpu().numpy()[0], ref["pose"]) <= 2e-2
+
+
+def test_reliable_selection_bit_exact(gsr_lib):
+    gsr = gsr_lib
+    sc = W.room_scene(20000, seed=3)
+    cam = W.perturb_pose(W.camera_tum(), [0.01, 0.02, -0.03, 0.01, -0.02, 0.01])
+    _, depth, _ = W.random_targets([(cam.width, cam.height)], seed=4, depth_range=(0.3, 4.0))
+    mask = (np.random.default_rng(0).random(sc.n) > 0.1).astype(np.uint8)
+    r = gsr.Renderer()
+    r.plan(sc.n, [(cam.width, cam.height)])
+    g = H.gpu_scene(gsr, sc, mask=mask)
+    got = r.select_reliable(g, gsr.pack_cameras([cam]), H.to_dev(depth), cam.width, cam.height, 0.1).cpu().numpy()
+    ref = O.select_reliable(sc, cam, depth, 0.1, mask=mask)
+    assert 0 < ref.sum() < sc.n
+    np.testing.assert_array_equal(got, ref)

@@ -342,3 +342,29 @@ def test_l1_loss_definition():
     assert abs(loss - ref) < 1e-12
     assert gC[0, 0, 0] == -0.8 and gC[1, 1, 1] == 0.0 and gC[2, 0, 0] == 0.0  # masked / sign(0) = 0
     assert gD[0, 0] == -0.3 and gD[0, 1] == 0.0 and gD[1, 0] == 0.0 and gD[1, 1] == 0.0
+
+
+def test_reliable_selection_cases():
+    """Eq. 12: keep a Gaussian whose centre depth agrees with the observed
+    depth at its pixel; drop a floater in front of (or behind) the surface;
+    keep Gaussians without evidence (outside the image, behind the near
+    plane, missing reading); an excluded Gaussian stays excluded."""
+    cam = _cam(32, 24, 30.0)
+    depth = np.full((24, 32), 2.0, np.float32)
+    depth[0:4, 0:4] = 0.0  # missing readings in the top-left corner
+    rows = [((0.0, 0.0, 2.03), (-3, -3, -3), (1, 0, 0, 0), 0.0, (0.5, 0.5, 0.5)),   # on the surface
+            ((0.05, 0.0, 1.2), (-3, -3, -3), (1, 0, 0, 0), 0.0, (0.5, 0.5, 0.5)),   # floater in front
+            ((0.0, 0.05, 2.6), (-3, -3, -3), (1, 0, 0, 0), 0.0, (0.5, 0.5, 0.5)),   # behind the surface
+            ((5.0, 0.0, 2.0), (-3, -3, -3), (1, 0, 0, 0), 0.0, (0.5, 0.5, 0.5)),    # outside the image
+            ((0.0, 0.0, 0.1), (-3, -3, -3), (1, 0, 0, 0), 0.0, (0.5, 0.5, 0.5)),    # before the near plane
+            ((-0.98, -0.7, 1.0), (-3, -3, -3), (1, 0, 0, 0), 0.0, (0.5, 0.5, 0.5)),  # missing reading
+            ((0.0, 0.0, 2.0), (-3, -3, -3), (1, 0, 0, 0), 0.0, (0.5, 0.5, 0.5))]    # excluded by the mask
+    sc = _scene(rows)
+    pix = O.project(sc, cam, O.Config())["uv"][5]
+    assert np.all(np.floor(pix + 0.5) < 4)  # really lands in the missing corner
+    got = O.select_reliable(sc, cam, depth, eps=0.1, mask=np.array([1, 1, 1, 1, 1, 1, 0]))
+    assert list(got) == [1, 0, 0, 1, 1, 1, 0]
+    # The decision is |D - z| <= eps, inclusive.
+    sc2 = _scene([((0.0, 0.0, 2.0 + 0.0625), (-3, -3, -3), (1, 0, 0, 0), 0.0, (0.5, 0.5, 0.5))])
+    assert list(O.select_reliable(sc2, cam, depth, eps=0.0625)) == [1]
+    assert list(O.select_reliable(sc2, cam, depth, eps=0.0624)) == [0]
