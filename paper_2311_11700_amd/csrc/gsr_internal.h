@@ -56,7 +56,8 @@ struct Workspace {
   unsigned long long *scan_part;  // [n_scan_blocks + 1]
   uint32_t *pkeys[2];      // [capacity] global tile ids, ping-pong
   uint32_t *pvals[2];      // [capacity] record ids, ping-pong
-  uint32_t *hist;          // [RADIX][max_sort_tiles]
+  uint32_t *hist;          // [RADIX][max_sort_tiles] digit counts per sort tile
+  uint32_t *hoff;          // [RADIX][max_sort_tiles] exclusive scan of hist (digit-major)
   uint32_t *digit_total;   // [RADIX]
   int2 *ranges;            // [total_tiles]
   float *T_final;          // [total_pixels]
@@ -87,7 +88,7 @@ struct Plan {
   // byte offsets inside the workspace
   size_t off_hdr, off_recA, off_recB, off_recZ, off_rect, off_count, off_dkeys[2], off_dvals[2],
       off_scan, off_pkeys[2], off_pvals[2], off_hist, off_digit, off_ranges, off_T, off_last,
-      off_grad2d, off_pose, off_queue, off_loss, off_nevals, off_nblend, off_counts;
+      off_grad2d, off_pose, off_queue, off_loss, off_nevals, off_nblend, off_counts, off_hoff;
 };
 
 struct Tuning {

@@ -121,30 +121,36 @@ __device__ __forceinline__ void tile_forward(const TileInfo &ti, int64_t n, cons
     if (pos < ti.range.y)
       s_rec[threadIdx.x] = stage_record(ids[pos], ti.view, n, ti.x0, ti.y0, recA, recB, recZ, rgb);
     __syncthreads();
-    if (!st.done) {
-      const int cnt = min(BATCH, ti.range.y - base);
+    // Branch-free walk: every lane evaluates every entry and keeps or drops
+    // the result with selects; the wave leaves the batch once all of its
+    // pixels have stopped.
+    const int cnt = min(BATCH, ti.range.y - base);
+    if (!__all(st.done)) {
       for (int k = 0; k < cnt; ++k) {
         const float4 geo = s_rec[k].geo;
         const float4 con = s_rec[k].con;
         const float dx = geo.x - lx, dy = geo.y - ly;
         float G, oG;
         const float alpha = splat_alpha(geo, con, dx, dy, rc.alpha_max, G, oG);
-        ++st.nev;
-        if (alpha < rc.alpha_min) continue;
+        const bool live = !st.done;
+        const bool acc = live && alpha >= rc.alpha_min;
         const float Tn = st.T * (1.f - alpha);
-        if (Tn < rc.T_min) {
-          st.done = true;
-          break;
+        const bool stop = acc && Tn < rc.T_min;
+        const bool blend = acc && !stop;
+        st.nev += live ? 1 : 0;
+        st.done = st.done || stop;
+        if (__any(blend)) {
+          const float4 col = s_rec[k].col;
+          const float w = blend ? alpha * st.T : 0.f;
+          st.C0 = __fmaf_rn(w, col.x, st.C0);
+          st.C1 = __fmaf_rn(w, col.y, st.C1);
+          st.C2 = __fmaf_rn(w, col.z, st.C2);
+          st.D = __fmaf_rn(w, geo.w, st.D);
+          st.T = blend ? Tn : st.T;
+          st.last = blend ? base - ti.range.x + k + 1 : st.last;
+          st.nbl += blend ? 1 : 0;
         }
-        ++st.nbl;
-        const float w = alpha * st.T;
-        const float4 col = s_rec[k].col;
-        st.C0 = __fmaf_rn(w, col.x, st.C0);
-        st.C1 = __fmaf_rn(w, col.y, st.C1);
-        st.C2 = __fmaf_rn(w, col.z, st.C2);
-        st.D = __fmaf_rn(w, geo.w, st.D);
-        st.T = Tn;
-        st.last = base - ti.range.x + k + 1;
+        if (__all(st.done)) break;
       }
     }
   }
@@ -250,51 +256,46 @@ __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, con
     __syncthreads();
     for (int k = hi - 1; k >= lo; --k) {
       const int j = k - lo;
-      float g[NGRAD2D];
-#pragma unroll
-      for (int f = 0; f < NGRAD2D; ++f) g[f] = 0.f;
-      bool has = false;
-      if (k < in.last) {
-        const float4 geo = s_rec[j].geo;
-        const float4 con = s_rec[j].con;
-        const float dx = geo.x - lx, dy = geo.y - ly;
-        float G, oG;
-        const float alpha = splat_alpha(geo, con, dx, dy, rc.alpha_max, G, oG);
-        if (alpha >= rc.alpha_min) {
-          has = true;
-          const float4 col = s_rec[j].col;
-          const float om = 1.f - alpha;
-          const float rinv = __builtin_amdgcn_rcpf(om);
-          T = T * rinv;  // transmittance in front of this Gaussian
-          const float w = alpha * T;
-          g[6] = in.gC0 * w;
-          g[7] = in.gC1 * w;
-          g[8] = in.gC2 * w;
-          g[9] = in.gD * w;
-          if (!have_zr) {
-            zr = geo.w;
-            have_zr = true;
-          }
-          const float zs = geo.w - zr;
-          const float dLda = T * (in.gC0 * (col.x - aC0) + in.gC1 * (col.y - aC1) +
-                                  in.gC2 * (col.z - aC2) + in.gD * (zs - aDs)) +
-                             (in.gD * zr - in.gT) * Tf * rinv;
-          aC0 = __fmaf_rn(alpha, col.x - aC0, aC0);
-          aC1 = __fmaf_rn(alpha, col.y - aC1, aC1);
-          aC2 = __fmaf_rn(alpha, col.z - aC2, aC2);
-          aDs = __fmaf_rn(alpha, zs - aDs, aDs);
-          if (oG <= rc.alpha_max) {
-            const float dLdP = dLda * oG;
-            g[0] = dLdP * __fmaf_rn(con.x, dx, con.y * dy);
-            g[1] = dLdP * __fmaf_rn(con.y, dx, con.z * dy);
-            g[2] = dLdP * dx * dx;
-            g[3] = dLdP * dx * dy;
-            g[4] = dLdP * dy * dy;
-            g[5] = dLda * G;
-          }
-        }
+      const float4 geo = s_rec[j].geo;
+      const float4 con = s_rec[j].con;
+      const float dx = geo.x - lx, dy = geo.y - ly;
+      float G, oG;
+      const float alpha = splat_alpha(geo, con, dx, dy, rc.alpha_max, G, oG);
+      const bool has = k < in.last && alpha >= rc.alpha_min;
+      // Wave-uniform guard; inside it every lane computes and the lanes
+      // without a contribution are masked with selects (NaN-safe).
+      if (__any(has)) {
+        const float4 col = s_rec[j].col;
+        const float rinv = __builtin_amdgcn_rcpf(1.f - alpha);
+        const float Tk = T * rinv;  // transmittance in front of this Gaussian
+        T = has ? Tk : T;
+        const float w = has ? alpha * Tk : 0.f;
+        float g[NGRAD2D];
+        g[6] = in.gC0 * w;
+        g[7] = in.gC1 * w;
+        g[8] = in.gC2 * w;
+        g[9] = in.gD * w;
+        zr = (has && !have_zr) ? geo.w : zr;
+        have_zr = have_zr || has;
+        const float zs = geo.w - zr;
+        const float dLda = Tk * (in.gC0 * (col.x - aC0) + in.gC1 * (col.y - aC1) +
+                                 in.gC2 * (col.z - aC2) + in.gD * (zs - aDs)) +
+                           (in.gD * zr - in.gT) * Tf * rinv;
+        const float a = has ? alpha : 0.f;
+        aC0 = __fmaf_rn(a, col.x - aC0, aC0);
+        aC1 = __fmaf_rn(a, col.y - aC1, aC1);
+        aC2 = __fmaf_rn(a, col.z - aC2, aC2);
+        aDs = __fmaf_rn(a, zs - aDs, aDs);
+        const bool open = has && oG <= rc.alpha_max;
+        const float dLdP = open ? dLda * oG : 0.f;
+        g[0] = dLdP * __fmaf_rn(con.x, dx, con.y * dy);
+        g[1] = dLdP * __fmaf_rn(con.y, dx, con.z * dy);
+        g[2] = dLdP * dx * dx;
+        g[3] = dLdP * dx * dy;
+        g[4] = dLdP * dy * dy;
+        g[5] = open ? dLda * G : 0.f;
+        wave_reduce_add10(g, s_grad + j * NGRAD2D);
       }
-      if (__any(has)) wave_reduce_add10(g, s_grad + j * NGRAD2D);
     }
     __syncthreads();
     // Flush: one thread per Gaussian of the batch; constant factors of the

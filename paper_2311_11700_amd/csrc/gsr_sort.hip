@@ -134,15 +134,18 @@ __global__ __launch_bounds__(BLOCK) void k_radix_hist(const uint32_t *__restrict
   }
 }
 
-// One block per digit: exclusive scan over the tiles of that digit's column.
-__global__ __launch_bounds__(BLOCK) void k_radix_scan(uint32_t *__restrict__ hist,
+// One block per digit: exclusive scan over the tiles of that digit's column
+// (counts stay in hist, offsets go to hoff).
+__global__ __launch_bounds__(BLOCK) void k_radix_scan(const uint32_t *__restrict__ hist,
+                                                      uint32_t *__restrict__ hoff,
                                                       const unsigned long long *n_dev,
                                                       uint32_t n_static, uint32_t cap, int max_tiles,
                                                       uint32_t *__restrict__ digit_total) {
   __shared__ uint32_t s_w[4];
   const uint32_t n = sort_count(n_dev, n_static, cap);
   const uint32_t ntiles = (n + SORT_TILE - 1) / SORT_TILE;
-  uint32_t *col = hist + (size_t)blockIdx.x * max_tiles;
+  const uint32_t *col = hist + (size_t)blockIdx.x * max_tiles;
+  uint32_t *ocol = hoff + (size_t)blockIdx.x * max_tiles;
   uint32_t carry = 0u;
   for (uint32_t base = 0; base < ntiles; base += BLOCK * SCAN_ITEMS) {
     uint32_t v[SCAN_ITEMS];
@@ -158,7 +161,7 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scan(uint32_t *__restrict__ his
 #pragma unroll
     for (int k = 0; k < SCAN_ITEMS; ++k) {
       const uint32_t idx = base + threadIdx.x * SCAN_ITEMS + k;
-      if (idx < ntiles) col[idx] = pre;
+      if (idx < ntiles) ocol[idx] = pre;
       pre += v[k];
     }
     carry += total;
@@ -166,15 +169,25 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scan(uint32_t *__restrict__ his
   if (threadIdx.x == 0) digit_total[blockIdx.x] = carry;
 }
 
+// Stable scatter of one digit pass.  Each sort tile (2048 keys) is first
+// ranked into block-local digit order in LDS (wave64 ballot matching gives
+// the rank among equal digits of a wavefront; per-wave digit counts give the
+// rest), then written out so that each digit's keys of the tile form one
+// contiguous run in the output: consecutive threads store consecutive
+// addresses.
 __global__ __launch_bounds__(BLOCK) void k_radix_scatter(
     const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in,
     uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out,
     const unsigned long long *n_dev, uint32_t n_static, uint32_t cap, int shift, int nbits,
-    const uint32_t *__restrict__ hist, int max_tiles, const uint32_t *__restrict__ digit_total) {
-  __shared__ uint32_t s_base[RADIX];
-  __shared__ uint32_t s_run[RADIX];
+    const uint32_t *__restrict__ hist, const uint32_t *__restrict__ hoff, int max_tiles,
+    const uint32_t *__restrict__ digit_total) {
+  __shared__ uint32_t s_base[RADIX];   // first output position of each digit
+  __shared__ uint32_t s_goff[RADIX];   // output position minus local position, per digit
+  __shared__ uint32_t s_run[RADIX];    // next local position per digit
   __shared__ uint32_t s_wcnt[4][RADIX];
   __shared__ uint32_t s_w[4];
+  __shared__ uint32_t s_k[SORT_TILE];
+  __shared__ uint32_t s_v[SORT_TILE];
   const uint32_t n = sort_count(n_dev, n_static, cap);
   const uint32_t ntiles = (n + SORT_TILE - 1) / SORT_TILE;
   const uint32_t mask = (1u << nbits) - 1u;
@@ -186,11 +199,19 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(
   }
   __syncthreads();
   for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    s_run[threadIdx.x] = s_base[threadIdx.x] + hist[(size_t)threadIdx.x * max_tiles + t];
+    const uint32_t t0 = t * SORT_TILE;
+    const uint32_t tn = n - t0 < (uint32_t)SORT_TILE ? n - t0 : (uint32_t)SORT_TILE;
+    {
+      const uint32_t cnt = hist[(size_t)threadIdx.x * max_tiles + t];
+      uint32_t total;
+      const uint32_t lbase = block_exclusive_scan<uint32_t>(cnt, s_w, total);
+      s_run[threadIdx.x] = lbase;
+      s_goff[threadIdx.x] = s_base[threadIdx.x] + hoff[(size_t)threadIdx.x * max_tiles + t] - lbase;
+    }
     __syncthreads();
 #pragma unroll 1
     for (int r = 0; r < SORT_ITEMS; ++r) {
-      const uint32_t idx = t * SORT_TILE + r * BLOCK + threadIdx.x;
+      const uint32_t idx = t0 + r * BLOCK + threadIdx.x;
       const bool valid = idx < n;
       const uint32_t key = valid ? keys_in[idx] : 0u;
       const uint32_t val = valid ? vals_in[idx] : 0u;
@@ -202,8 +223,8 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(
       if (valid) {
         uint32_t pos = s_run[d] + (uint32_t)__popcll(below);
         for (int w = 0; w < wave; ++w) pos += s_wcnt[w][d];
-        keys_out[pos] = key;
-        vals_out[pos] = val;
+        s_k[pos] = key;
+        s_v[pos] = val;
       }
       __syncthreads();
       const int dd = threadIdx.x;
@@ -211,23 +232,30 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(
       s_wcnt[0][dd] = s_wcnt[1][dd] = s_wcnt[2][dd] = s_wcnt[3][dd] = 0u;
       __syncthreads();
     }
+    for (uint32_t i = threadIdx.x; i < tn; i += BLOCK) {
+      const uint32_t key = s_k[i];
+      const uint32_t gpos = s_goff[(key >> shift) & mask] + i;
+      keys_out[gpos] = key;
+      vals_out[gpos] = s_v[i];
+    }
+    __syncthreads();
   }
 }
 
 // Stable LSD radix sort of (key, value) over bits [0, key_bits); returns the
 // index of the buffer holding the result.
 static int radix_sort(uint32_t *keys[2], uint32_t *vals[2], const unsigned long long *n_dev,
-                      uint32_t n_static, uint32_t cap, int key_bits, uint32_t *hist, int max_tiles,
-                      uint32_t *digit_total, int grid, hipStream_t s) {
+                      uint32_t n_static, uint32_t cap, int key_bits, uint32_t *hist, uint32_t *hoff,
+                      int max_tiles, uint32_t *digit_total, int grid, hipStream_t s) {
   int cur = 0;
   for (int shift = 0; shift < key_bits; shift += RADIX_BITS) {
     const int nbits = key_bits - shift < RADIX_BITS ? key_bits - shift : RADIX_BITS;
     hipLaunchKernelGGL(k_radix_hist, dim3(grid), dim3(BLOCK), 0, s, keys[cur], n_dev, n_static, cap,
                        shift, nbits, hist, max_tiles);
-    hipLaunchKernelGGL(k_radix_scan, dim3(RADIX), dim3(BLOCK), 0, s, hist, n_dev, n_static, cap,
+    hipLaunchKernelGGL(k_radix_scan, dim3(RADIX), dim3(BLOCK), 0, s, hist, hoff, n_dev, n_static, cap,
                        max_tiles, digit_total);
     hipLaunchKernelGGL(k_radix_scatter, dim3(grid), dim3(BLOCK), 0, s, keys[cur], vals[cur],
-                       keys[cur ^ 1], vals[cur ^ 1], n_dev, n_static, cap, shift, nbits, hist,
+                       keys[cur ^ 1], vals[cur ^ 1], n_dev, n_static, cap, shift, nbits, hist, hoff,
                        max_tiles, digit_total);
     cur ^= 1;
   }
@@ -242,14 +270,14 @@ static int sort_grid_for(int64_t n, int cap_grid) {
 
 int launch_depth_sort(const Plan &p, Workspace &ws, hipStream_t s, int sort_grid) {
   ws.dsorted = radix_sort(ws.dkeys, ws.dvals, nullptr, (uint32_t)p.n_rec, (uint32_t)p.n_rec, 32,
-                          ws.hist, p.max_sort_tiles, ws.digit_total, sort_grid_for(p.n_rec, sort_grid), s);
+                          ws.hist, ws.hoff, p.max_sort_tiles, ws.digit_total, sort_grid_for(p.n_rec, sort_grid), s);
   return ws.dsorted;
 }
 
 int launch_pair_sort(const Plan &p, Workspace &ws, hipStream_t s, int sort_grid) {
   const unsigned long long *n_dev = reinterpret_cast<const unsigned long long *>(ws.hdr + HDR_NPAIRS);
   ws.psorted = radix_sort(ws.pkeys, ws.pvals, n_dev, 0u, (uint32_t)p.capacity, p.tile_bits, ws.hist,
-                          p.max_sort_tiles, ws.digit_total, sort_grid_for(p.capacity, sort_grid), s);
+                          ws.hoff, p.max_sort_tiles, ws.digit_total, sort_grid_for(p.capacity, sort_grid), s);
   return ws.psorted;
 }
 
