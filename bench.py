@@ -309,20 +309,19 @@ def run_hypotheses(args, gsr, torch, W):
 
 
 def run_tracking(args, gsr, torch, W):
-    """Coarse-to-fine tracking of one frame: 150k Gaussians, 640x480 target
-    rendered at the true pose with 10% of the depth readings removed, start
-    perturbed by 2 cm / 1 deg; 5 coarse (160x120) + 95 fine iterations."""
+    """Coarse-to-fine tracking of one frame: 150k Gaussians (flat surface
+    Gaussians of the room plus 20% outliers 0.5-1 m off the surfaces),
+    640x480 target rendered at the true pose from the surfaces with 10% of
+    the depth readings removed, start perturbed by 2 cm / 1 deg; 5 coarse
+    (160x120) + 95 fine iterations on the Eq. 12 reliable Gaussians."""
     import numpy as np
     from paper_2311_11700_amd.tracking import Tracker, TrackingConfig
-    scene = W.room_scene(150_000, seed=0)
-    truth = W.camera_tum()
+    scene, n_surf = W.tracking_scene(150_000, seed=0, offset=(0.5, 1.0))
+    truth = W.camera_tracking()
     g = gsr.Gaussians.from_arrays(*scene.arrays())
-    tc = TrackingConfig()
-    # The map holds the room's surfaces plus 30% floaters; the observation is
-    # rendered from the surfaces only (room_scene lists them first), so the
-    # fine stage's Eq. 12 selection has floaters to remove.
+    tc = TrackingConfig(reliable_eps=0.3)
     surf = torch.zeros(scene.n, dtype=torch.uint8, device="cuda")
-    surf[:int(round(0.7 * scene.n))] = 1
+    surf[:n_surf] = 1
     r = gsr.Renderer(0)
     r.plan(scene.n, [(truth.width, truth.height)])
     out = r.render_forward(gsr.Gaussians(g.mean, g.log_scale, g.quat, g.opacity_logit, g.rgb, surf),
@@ -352,8 +351,8 @@ def run_tracking(args, gsr, torch, W):
         return float(np.degrees(np.arccos(np.clip((np.trace(R) - 1) / 2, -1, 1))))
 
     iters = tc.coarse_iters + tc.fine_iters
-    return {"workload": "150k Gaussians (surfaces + 30% floaters), 640x480 (coarse 160x120), 5 + 95 iterations, "
-                        "pose-only, fine stage on Eq. 12 reliable Gaussians",
+    return {"workload": "150k Gaussians (flat surface Gaussians + 20% outliers), 640x480 (coarse 160x120), "
+                        "5 + 95 iterations, pose-only, fine stage on Eq. 12 reliable Gaussians (eps 0.3 m)",
             "reliable": int(tr.reliable.sum().item()),
             "ms_total": round(ms, 2), "ms_per_iter": round(ms / iters, 3),
             "trans_err_cm": [round(float(np.linalg.norm(E0[:3, 3])) * 100, 3),

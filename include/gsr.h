@@ -97,11 +97,19 @@ enum {
 /* Renderer constants.  The paper is silent on them; gsr_default_config()
  * returns the values of the 3DGS rasteriser the paper extends:
  * alpha_min 1/255, alpha_max 0.99, T_min 1e-4, cutoff_sigma 3, z_near 0.2 m,
- * lowpass 0.3 px^2, bg 0, flags GSR_GAUSS_GRAD | GSR_POSE_GRAD. */
+ * lowpass 0.3 px^2, bg 0, flags GSR_GAUSS_GRAD | GSR_POSE_GRAD, fov_guard 1.3.
+ *
+ * fov_guard g > 0 limits the Jacobian of Eq. 3 (not the projected centre):
+ * x/z and y/z enter J clamped to +-g W/(2 fx) and +-g H/(2 fy), so a
+ * Gaussian just beyond the near plane far to the side of the view keeps a
+ * bounded footprint instead of a linearisation that smears it over the whole
+ * image; the backward differentiates the clamped function.  g = 0 uses Eq. 3
+ * as printed. */
 typedef struct {
   float alpha_min, alpha_max, T_min, cutoff_sigma, z_near, lowpass;
   float bg[3];
   uint32_t flags;
+  float fov_guard;
 } gsr_config;
 
 /* Forward outputs, DEVICE (any pointer may be NULL to skip that output):

@@ -64,12 +64,16 @@ class Config:
     lowpass: float = 0.3
     bg: tuple = (0.0, 0.0, 0.0)
     full_rect: bool = False
+    # Limit g on x/z and y/z inside the Jacobian of Eq. 3: +-g W/(2 fx),
+    # +-g H/(2 fy) (the paper is silent; 1.3 is the cited rasteriser's
+    # value).  0 evaluates Eq. 3 as printed.
+    fov_guard: float = 1.3
 
     def as_f32(self) -> "Config":
         return dataclasses.replace(
             self, alpha_min=f32(self.alpha_min), alpha_max=f32(self.alpha_max),
             T_min=f32(self.T_min), cutoff=f32(self.cutoff), z_near=f32(self.z_near),
-            lowpass=f32(self.lowpass), bg=tuple(f32(b) for b in self.bg))
+            lowpass=f32(self.lowpass), bg=tuple(f32(b) for b in self.bg), fov_guard=f32(self.fov_guard))
 
     @staticmethod
     def smooth(bg=(0.0, 0.0, 0.0)) -> "Config":
@@ -171,11 +175,23 @@ def project(scene, cam, cfg: Config):
         z = ((W[2, 0] * mx + W[2, 1] * my) + W[2, 2] * mz) + t[2]
         zf = z.astype(np.float32)
         Sigma_c = np.einsum("ij,njk,lk->nil", W, Sigma, W)
+        # Eq. 3's Jacobian with x/z, y/z limited by the guard (the projected
+        # centre u, v below uses the true ratios).
+        rxz, ryz = x / z, y / z
+        free_x = np.ones(n, bool)
+        free_y = np.ones(n, bool)
+        if cfg.fov_guard > 0:
+            lx = float(cfg.fov_guard) * (0.5 * float(cam.width)) / fx
+            ly = float(cfg.fov_guard) * (0.5 * float(cam.height)) / fy
+            free_x = ~((rxz > lx) | (rxz < -lx))
+            free_y = ~((ryz > ly) | (ryz < -ly))
+            rxz = np.minimum(lx, np.maximum(-lx, rxz))
+            ryz = np.minimum(ly, np.maximum(-ly, ryz))
         J = np.zeros((n, 2, 3))
         J[:, 0, 0] = fx / z
-        J[:, 0, 2] = -(fx * x) / (z * z)
+        J[:, 0, 2] = -(fx * rxz) / z
         J[:, 1, 1] = fy / z
-        J[:, 1, 2] = -(fy * y) / (z * z)
+        J[:, 1, 2] = -(fy * ryz) / z
         cov2 = np.einsum("nij,njk,nlk->nil", J, Sigma_c, J)
         cov2[:, 0, 0] += cfg.lowpass
         cov2[:, 1, 1] += cfg.lowpass
@@ -216,7 +232,7 @@ def project(scene, cam, cfg: Config):
         Xc=np.stack([x, y, z], axis=1), z=z, zbits=zf.view(np.uint32),
         Sigma=Sigma, Sigma_c=Sigma_c, Rq=Rq, s=s, qhat=qhat, qn=qn, J=J, cov2=cov2,
         conic=conic, uv=np.stack([u, v], axis=1), opacity=opacity, rgb=rgb,
-        W=W, fx=fx, fy=fy,
+        W=W, fx=fx, fy=fy, rxz=rxz, ryz=ryz, free_x=free_x, free_y=free_y,
     )
 
 
@@ -437,12 +453,19 @@ def backward_params(proj, g2, cfg: Config, approx_pose=False):
     G2 = -np.einsum("nij,njk,nkl->nil", M, GM, M)          # dL/dSigma'
     GSc, GJ = sigma2d_backward(G2, J, Sc)
 
+    # J02 = -fx r/z with r = x/z while x/z is inside the guard (then
+    # dJ02/dx = -fx/z^2, dJ02/dz = 2 fx x/z^3) and r = its limit outside it
+    # (dJ02/dx = 0, dJ02/dz = fx r/z^2); J12 likewise.
+    fxm, fym = proj["free_x"].astype(np.float64), proj["free_y"].astype(np.float64)
+    rxz, ryz = proj["rxz"], proj["ryz"]
     gX = np.zeros((n, 3))
-    gX[:, 0] = g_u * fx / z + GJ[:, 0, 2] * (-fx / (z * z))
-    gX[:, 1] = g_v * fy / z + GJ[:, 1, 2] * (-fy / (z * z))
+    gX[:, 0] = g_u * fx / z + GJ[:, 0, 2] * (-fx / (z * z)) * fxm
+    gX[:, 1] = g_v * fy / z + GJ[:, 1, 2] * (-fy / (z * z)) * fym
+    dJ02_dz = np.where(fxm > 0, 2.0 * fx * x / z ** 3, fx * rxz / (z * z))
+    dJ12_dz = np.where(fym > 0, 2.0 * fy * y / z ** 3, fy * ryz / (z * z))
     gX[:, 2] = (g_u * (-fx * x / (z * z)) + g_v * (-fy * y / (z * z))
-                + GJ[:, 0, 0] * (-fx / (z * z)) + GJ[:, 0, 2] * (2.0 * fx * x / z ** 3)
-                + GJ[:, 1, 1] * (-fy / (z * z)) + GJ[:, 1, 2] * (2.0 * fy * y / z ** 3) + g_zd)
+                + GJ[:, 0, 0] * (-fx / (z * z)) + GJ[:, 0, 2] * dJ02_dz
+                + GJ[:, 1, 1] * (-fy / (z * z)) + GJ[:, 1, 2] * dJ12_dz + g_zd)
 
     g_mean = gX @ W                                          # W^T gX per row
     GS = np.einsum("ji,njk,kl->nil", W, GSc, W)              # W^T GSc W

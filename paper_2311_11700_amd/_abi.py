@@ -46,7 +46,7 @@ class gsr_gaussians(ctypes.Structure):
 class gsr_config(ctypes.Structure):
     _fields_ = [("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float), ("T_min", ctypes.c_float),
                 ("cutoff_sigma", ctypes.c_float), ("z_near", ctypes.c_float), ("lowpass", ctypes.c_float),
-                ("bg", ctypes.c_float * 3), ("flags", ctypes.c_uint32)]
+                ("bg", ctypes.c_float * 3), ("flags", ctypes.c_uint32), ("fov_guard", ctypes.c_float)]
 
 
 class gsr_images(ctypes.Structure):
@@ -64,7 +64,7 @@ class gsr_tuning(ctypes.Structure):
 
 
 assert ctypes.sizeof(gsr_camera) == 80
-assert ctypes.sizeof(gsr_config) == 40
+assert ctypes.sizeof(gsr_config) == 44
 
 _P = ctypes.POINTER
 # name -> (restype, argtypes)

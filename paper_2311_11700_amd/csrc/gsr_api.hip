@@ -82,7 +82,7 @@ Workspace make_ws(const Plan &p, void *base_v) {
   w.nevals = reinterpret_cast<int32_t *>(base + p.off_nevals);
   w.nblend = reinterpret_cast<int32_t *>(base + p.off_nblend);
   w.counts = reinterpret_cast<unsigned long long *>(base + p.off_counts);
-  w.grad2d = reinterpret_cast<float *>(base + p.off_grad2d);
+  w.grad2d = reinterpret_cast<double *>(base + p.off_grad2d);
   w.pose_part = reinterpret_cast<double *>(base + p.off_pose);
   w.queue = reinterpret_cast<uint32_t *>(base + p.off_queue);
   w.loss_part = reinterpret_cast<float *>(base + p.off_loss);
@@ -104,7 +104,7 @@ gsr_status validate(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams
     return fail(ctx, GSR_E_INVALID, "null Gaussian parameter array");
   if (reinterpret_cast<uintptr_t>(g->quat) % 16) return fail(ctx, GSR_E_INVALID, "quat must be 16-byte aligned");
   if (!(cfg->alpha_max > 0.f && cfg->alpha_max <= 1.f) || cfg->alpha_min < 0.f || cfg->T_min < 0.f ||
-      !(cfg->cutoff_sigma > 0.f))
+      !(cfg->cutoff_sigma > 0.f) || !(cfg->fov_guard >= 0.f && cfg->fov_guard < 1e30f))
     return fail(ctx, GSR_E_INVALID, "renderer constants out of range");
   return GSR_OK;
 }
@@ -185,7 +185,7 @@ void enqueue_fused(gsr_ctx *ctx, const gsr_gaussians &g, const gsr_camera *cams,
   prof_begin(ctx, s);
   enqueue_lists(ctx, g, cams, cfg, ws, s);
   launch_queue_order(p, ws, ctx->tuning.lpt_order, s);
-  launch_fill_f32(ws.grad2d, 0.f, p.n_rec * NGRAD2D, s);
+  launch_fill_f32(reinterpret_cast<float *>(ws.grad2d), 0.f, 2 * p.n_rec * NGRAD2D, s);
   prof_mark(ctx, s, GSR_STAGE_RANGES);
   launch_render_fused(p, ws, ctx->views_dev, ctx->tile_view_dev, g, consts(cfg), t_rgb, t_depth, pmask, w_rgb,
                       w_depth, out, loss, ctx->tuning, ctx->num_cus, s);
@@ -196,6 +196,9 @@ void enqueue_fused(gsr_ctx *ctx, const gsr_gaussians &g, const gsr_camera *cams,
 }
 
 }  // namespace
+
+static_assert(sizeof(gsr_camera) == 80, "gsr_camera layout");
+static_assert(sizeof(gsr_config) == 44, "gsr_config layout");
 
 extern "C" {
 
@@ -209,6 +212,7 @@ gsr_config gsr_default_config(void) {
   c.lowpass = 0.3f;
   c.bg[0] = c.bg[1] = c.bg[2] = 0.f;
   c.flags = GSR_GAUSS_GRAD | GSR_POSE_GRAD;
+  c.fov_guard = 1.3f;
   return c;
 }
 
@@ -321,7 +325,7 @@ gsr_status gsr_plan(gsr_ctx *ctx, int64_t n, int n_views, const int32_t *wh_host
   p.off_nevals = take(4 * (size_t)pixels);
   p.off_nblend = take(4 * (size_t)pixels);
   p.off_counts = take(64);
-  p.off_grad2d = take(4 * NGRAD2D * nr);
+  p.off_grad2d = take(8 * NGRAD2D * nr);
   p.off_pose = take(8 * 6 * (size_t)n_views * p.n_pose_blocks);
   p.off_queue = take(4 * (size_t)p.total_tiles);
   p.off_loss = take(4);
@@ -395,7 +399,7 @@ gsr_status gsr_render_backward(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_c
   const Plan &p = ctx->plan;
   prof_begin(ctx, s);
   for (int j = 0; j <= GSR_STAGE_RASTER; ++j) prof_mark(ctx, s, j);
-  launch_fill_f32(ws.grad2d, 0.f, p.n_rec * NGRAD2D, s);
+  launch_fill_f32(reinterpret_cast<float *>(ws.grad2d), 0.f, 2 * p.n_rec * NGRAD2D, s);
   launch_render_backward(p, ws, ctx->views_dev, ctx->tile_view_dev, *g, consts(*cfg), g_rgb, g_depth, g_T, s);
   prof_mark(ctx, s, GSR_STAGE_RASTER_BWD);
   launch_preprocess_backward(p, *g, cams, *cfg, ws, *grads, s);
@@ -580,7 +584,7 @@ gsr_status gsr_autotune(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *
         for (int r = 0; r <= reps && st == GSR_OK; ++r) {
           launch_fill_u32(ws.hdr + HDR_QUEUE, 0u, 1, s);
           launch_queue_order(p, ws, lpt, s);
-          launch_fill_f32(ws.grad2d, 0.f, p.n_rec * NGRAD2D, s);
+          launch_fill_f32(reinterpret_cast<float *>(ws.grad2d), 0.f, 2 * p.n_rec * NGRAD2D, s);
           (void)hipEventRecord(e0, s);
           launch_render_fused(p, ws, ctx->views_dev, ctx->tile_view_dev, *g, consts(*cfg), target_rgb, target_depth,
                               pixel_mask, w_rgb, w_depth, nullptr, loss, t, ctx->num_cus, s);

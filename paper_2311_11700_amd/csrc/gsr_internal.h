@@ -65,7 +65,7 @@ struct Workspace {
   int32_t *nevals;         // [total_pixels] entries the forward walk examined
   int32_t *nblend;         // [total_pixels] entries blended
   unsigned long long *counts;  // [4] work totals (gsr_work_counts)
-  float *grad2d;           // [n_rec][NGRAD2D]
+  double *grad2d;          // [n_rec][NGRAD2D], FP64 sums over tiles
   double *pose_part;       // [n_pose_blocks][n_views][6]
   uint32_t *queue;         // [total_tiles] work order of the persistent rasteriser
   float *loss_part;        // [1] (unused slot kept for alignment)

@@ -9,6 +9,7 @@ namespace gsr {
 struct PreConstsB {
   float z_near, lowpass, cutoff;
   uint32_t flags;
+  float fov_guard;
 };
 
 // The chain runs in FP64: gfx950 executes FP64 vector arithmetic at the
@@ -92,7 +93,7 @@ __global__ __launch_bounds__(BLOCK) void k_preprocess_bwd(gsr_gaussians g,
     R g2[NGRAD2D];
     bool has = false;
     if (active && ws.count[rec] != 0u) {
-      const float *src = ws.grad2d + rec * NGRAD2D;
+      const double *src = ws.grad2d + rec * NGRAD2D;
 #pragma unroll
       for (int k = 0; k < NGRAD2D; ++k) {
         g2[k] = src[k];
@@ -116,7 +117,17 @@ __global__ __launch_bounds__(BLOCK) void k_preprocess_bwd(gsr_gaussians g,
           Sc[3 * r + c] = Mt[3 * r] * W[3 * c] + Mt[3 * r + 1] * W[3 * c + 1] + Mt[3 * r + 2] * W[3 * c + 2];
       const R fx = cam.fx, fy = cam.fy;
       const R iz = R(1) / z, iz2 = iz * iz, iz3 = iz2 * iz;
-      const R J00 = fx * iz, J02 = -fx * x * iz2, J11 = fy * iz, J12 = -fy * y * iz2;
+      // x/z, y/z as they enter J (limited by the guard); a limited ratio no
+      // longer depends on x (or y), and J then depends on z through 1/z only.
+      R rxz = x * iz, ryz = y * iz;
+      R free_x = 1., free_y = 1.;
+      if (pc.fov_guard > 0.f) {
+        const R lx = (R)pc.fov_guard * (0.5 * (R)cam.width) / fx;
+        const R ly = (R)pc.fov_guard * (0.5 * (R)cam.height) / fy;
+        if (rxz > lx || rxz < -lx) { rxz = rxz > 0. ? lx : -lx; free_x = 0.; }
+        if (ryz > ly || ryz < -ly) { ryz = ryz > 0. ? ly : -ly; free_y = 0.; }
+      }
+      const R J00 = fx * iz, J02 = -fx * rxz * iz, J11 = fy * iz, J12 = -fy * ryz * iz;
       // J Sigma_c (2x3)
       R JS0[3], JS1[3];
       for (int c = 0; c < 3; ++c) {
@@ -153,11 +164,13 @@ __global__ __launch_bounds__(BLOCK) void k_preprocess_bwd(gsr_gaussians g,
       const R pX0 = gu * fx * iz;
       const R pX1 = gv * fy * iz;
       const R pX2 = -gu * fx * x * iz2 - gv * fy * y * iz2 + gzd;
-      // Through J (part of the Sigma' path).
-      const R jX0 = -GJ02 * fx * iz2;
-      const R jX1 = -GJ12 * fy * iz2;
-      const R jX2 = -GJ00 * fx * iz2 + 2. * GJ02 * fx * x * iz3 - GJ11 * fy * iz2 +
-                        2. * GJ12 * fy * y * iz3;
+      // Through J (part of the Sigma' path): J02 = -fx r/z with r = x/z (or
+      // its limit), dJ02/dx = -fx/z^2 while r is free, dJ02/dz = fx r/z^2
+      // (+ fx x/z^3 while r is free); J12 likewise.
+      const R jX0 = -GJ02 * fx * iz2 * free_x;
+      const R jX1 = -GJ12 * fy * iz2 * free_y;
+      const R jX2 = -GJ00 * fx * iz2 + GJ02 * fx * (rxz * iz2 + free_x * x * iz3) - GJ11 * fy * iz2 +
+                        GJ12 * fy * (ryz * iz2 + free_y * y * iz3);
       const R gX0 = pX0 + jX0, gX1 = pX1 + jX1, gX2 = pX2 + jX2;
       if (want_gauss) {
         gm[0] += W[0] * gX0 + W[3] * gX1 + W[6] * gX2;
@@ -284,7 +297,7 @@ void launch_preprocess_backward(const Plan &p, const gsr_gaussians &g, const gsr
                                 const gsr_config &cfg, const Workspace &ws, const gsr_grads &gr,
                                 hipStream_t s) {
   if (g.n == 0) return;
-  PreConstsB pc{cfg.z_near, cfg.lowpass, cfg.cutoff_sigma, cfg.flags};
+  PreConstsB pc{cfg.z_near, cfg.lowpass, cfg.cutoff_sigma, cfg.flags, cfg.fov_guard};
   const bool want_pose = (cfg.flags & GSR_POSE_GRAD) && gr.d_pose;
   const size_t lds = want_pose ? (size_t)4 * p.n_views * 6 * sizeof(double) : 0;
   hipLaunchKernelGGL(k_preprocess_bwd, dim3(p.n_pose_blocks), dim3(BLOCK), lds, s, g, cams,

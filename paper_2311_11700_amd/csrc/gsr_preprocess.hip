@@ -18,6 +18,7 @@ namespace gsr {
 struct PreConsts {
   float z_near, lowpass, cutoff;
   uint32_t flags;
+  float fov_guard;
 };
 
 // Rotation matrix of a unit quaternion (w, x, y, z) (GS-SLAM supplement,
@@ -93,11 +94,20 @@ __global__ __launch_bounds__(BLOCK) void k_preprocess(gsr_gaussians g,
   for (int r = 0; r < 3; ++r)
     for (int c = 0; c < 3; ++c)
       Sc[3 * r + c] = (M[3 * r] * Wm[3 * c] + M[3 * r + 1] * Wm[3 * c + 1]) + M[3 * r + 2] * Wm[3 * c + 2];
-  // EWA projection (Eq. 3): J = [[fx/z, 0, -fx x/z^2], [0, fy/z, -fy y/z^2]].
+  // EWA projection (Eq. 3): J = [[fx/z, 0, -fx (x/z)/z], [0, fy/z, -fy (y/z)/z]],
+  // with x/z and y/z limited to +-g W/(2 fx), +-g H/(2 fy) when the guard g
+  // is on (the projected centre below is not limited).
   const double fx = cam.fx, fy = cam.fy;
   const double zz = ok ? z : 1.0;
-  const double J00 = fx / zz, J02 = -(fx * x) / (zz * zz);
-  const double J11 = fy / zz, J12 = -(fy * y) / (zz * zz);
+  double rx_ = x / zz, ry_ = y / zz;
+  if (pc.fov_guard > 0.f) {
+    const double lx = (double)pc.fov_guard * (0.5 * (double)vi.W) / fx;
+    const double ly = (double)pc.fov_guard * (0.5 * (double)vi.H) / fy;
+    rx_ = fmin(lx, fmax(-lx, rx_));
+    ry_ = fmin(ly, fmax(-ly, ry_));
+  }
+  const double J00 = fx / zz, J02 = -(fx * rx_) / zz;
+  const double J11 = fy / zz, J12 = -(fy * ry_) / zz;
   const double T00 = J00 * Sc[0] + J02 * Sc[6], T01 = J00 * Sc[1] + J02 * Sc[7],
                T02 = J00 * Sc[2] + J02 * Sc[8];
   const double T11 = J11 * Sc[4] + J12 * Sc[7], T12 = J11 * Sc[5] + J12 * Sc[8];
@@ -147,7 +157,7 @@ __global__ __launch_bounds__(BLOCK) void k_preprocess(gsr_gaussians g,
 
 void launch_preprocess(const gsr_gaussians &g, const gsr_camera *cams, const ViewInfo *views,
                        int n_views, const gsr_config &cfg, const Workspace &ws, hipStream_t s) {
-  PreConsts pc{cfg.z_near, cfg.lowpass, cfg.cutoff_sigma, cfg.flags};
+  PreConsts pc{cfg.z_near, cfg.lowpass, cfg.cutoff_sigma, cfg.flags, cfg.fov_guard};
   dim3 grid((unsigned)((g.n + BLOCK - 1) / BLOCK), (unsigned)n_views);
   if (g.n > 0) hipLaunchKernelGGL(k_preprocess, grid, dim3(BLOCK), 0, s, g, cams, views, pc, ws);
 }

@@ -214,14 +214,16 @@ struct BwdIn {
 
 // Walk the tile's list back to front.  Per-Gaussian gradients are reduced
 // over the block (wavefront butterflies, then LDS) and added to grad2d with
-// one FP32 atomic per field.  grad2d fields: (u, v, conic a, b, c, opacity,
+// one FP64 atomic per field: a Gaussian that covers many tiles sums partials
+// of both signs, and the FP64 sum keeps the result independent of the order
+// the tiles finish in.  grad2d fields: (u, v, conic a, b, c, opacity,
 // r, g, b, depth).
 __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, const float4 *__restrict__ recA,
                                               const float4 *__restrict__ recB,
                                               const float *__restrict__ recZ,
                                               const float *__restrict__ rgb,
                                               const uint32_t *__restrict__ ids, const RenderConsts &rc,
-                                              const BwdIn &in, float *__restrict__ grad2d,
+                                              const BwdIn &in, double *__restrict__ grad2d,
                                               Staged *s_rec, float *s_grad, uint32_t *s_id, int *s_max) {
   const float lx = (float)(threadIdx.x & (TILE - 1));
   const float ly = (float)(threadIdx.x >> 4);
@@ -234,15 +236,19 @@ __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, con
 
   float T = in.T;
   const float Tf = in.T;
-  // Colour behind the current entry, normalised by the transmittance in
-  // front of it (starts at the background).  Depth is accumulated relative
-  // to the depth zr of the pixel's last contributor: with the telescoping
-  // identity sum_m alpha_m T_m = 1 - T_f,
-  //   dD/dalpha_k = T_k ((z_k - zr) - aDs_k) + zr T_f / (1 - alpha_k),
-  // where aDs runs over the shifted depths z - zr.  On a surface all the
-  // depths agree to a few mm, so the shifted terms stay small and float32
-  // keeps their digits (z_k - aD_k itself would cancel).
-  float aC0 = rc.bg[0], aC1 = rc.bg[1], aC2 = rc.bg[2], aDs = 0.f, zr = 0.f;
+  // Blend behind the current entry, normalised by the transmittance in front
+  // of it, enters dL/dalpha only through the upstream-weighted scalar
+  //   S = gC . aC + gD . aDs,
+  // (aC: colour behind, starting at the background; aDs: depth behind,
+  // relative to the depth zr of the pixel's last contributor), which obeys
+  // the same recurrence S <- S + alpha (Q - S) with Q = gC . c + gD (z - zr).
+  // With the telescoping identity sum_m alpha_m T_m = 1 - T_f,
+  //   dL/dalpha_k = T_k (Q_k - S_k) + (gD zr - gT) T_f / (1 - alpha_k).
+  // On a surface all depths agree to a few mm, so the shifted terms keep
+  // their float32 digits (z_k - aD_k itself would cancel).
+  float S = in.gC0 * rc.bg[0] + in.gC1 * rc.bg[1] + in.gC2 * rc.bg[2];
+  float zr = 0.f;
+  float Kf = -in.gT * Tf;  // (gD zr - gT) T_f
   bool have_zr = false;
 
   for (int hi = maxlast; hi > 0; hi -= BATCH) {
@@ -270,36 +276,40 @@ __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, con
         const float Tk = T * rinv;  // transmittance in front of this Gaussian
         T = has ? Tk : T;
         const float w = has ? alpha * Tk : 0.f;
+        const bool first = has && !have_zr;
+        zr = first ? geo.w : zr;
+        Kf = first ? (in.gD * geo.w - in.gT) * Tf : Kf;
+        have_zr = have_zr || has;
+        const float Q = __fmaf_rn(in.gD, geo.w - zr, __fmaf_rn(in.gC2, col.z, __fmaf_rn(in.gC1, col.y, in.gC0 * col.x)));
+        const float QS = Q - S;
+        const float dLda = __fmaf_rn(Tk, QS, Kf * rinv);
+        S = has ? __fmaf_rn(alpha, QS, S) : S;
+        const bool open = has && oG <= rc.alpha_max;
+        // dL/dP with G = 2^P (the ln 2 and the conic pre-scale are applied
+        // at the flush); dL/d(opacity) = dLdP / o there.
+        const float dLdP = open ? dLda * oG : 0.f;
+        const float sx = dLdP * dx, sy = dLdP * dy;
         float g[NGRAD2D];
+        g[0] = sx;
+        g[1] = sy;
+        g[2] = sx * dx;
+        g[3] = sx * dy;
+        g[4] = sy * dy;
+        g[5] = dLdP;
         g[6] = in.gC0 * w;
         g[7] = in.gC1 * w;
         g[8] = in.gC2 * w;
         g[9] = in.gD * w;
-        zr = (has && !have_zr) ? geo.w : zr;
-        have_zr = have_zr || has;
-        const float zs = geo.w - zr;
-        const float dLda = Tk * (in.gC0 * (col.x - aC0) + in.gC1 * (col.y - aC1) +
-                                 in.gC2 * (col.z - aC2) + in.gD * (zs - aDs)) +
-                           (in.gD * zr - in.gT) * Tf * rinv;
-        const float a = has ? alpha : 0.f;
-        aC0 = __fmaf_rn(a, col.x - aC0, aC0);
-        aC1 = __fmaf_rn(a, col.y - aC1, aC1);
-        aC2 = __fmaf_rn(a, col.z - aC2, aC2);
-        aDs = __fmaf_rn(a, zs - aDs, aDs);
-        const bool open = has && oG <= rc.alpha_max;
-        const float dLdP = open ? dLda * oG : 0.f;
-        g[0] = dLdP * __fmaf_rn(con.x, dx, con.y * dy);
-        g[1] = dLdP * __fmaf_rn(con.y, dx, con.z * dy);
-        g[2] = dLdP * dx * dx;
-        g[3] = dLdP * dx * dy;
-        g[4] = dLdP * dy * dy;
-        g[5] = open ? dLda * G : 0.f;
         wave_reduce_add10(g, s_grad + j * NGRAD2D);
       }
     }
     __syncthreads();
-    // Flush: one thread per Gaussian of the batch; constant factors of the
-    // pre-scaled conic applied here.
+    // Flush: one thread per Gaussian of the batch.  Block sums of
+    // (dLdP dx, dLdP dy, dLdP dx^2, dLdP dx dy, dLdP dy^2, dLdP) become the
+    // gradients of the centre, the conic and the opacity here:
+    //   dL/du = 2 ln2 (a'' Sx + b'' Sy), dL/dv = 2 ln2 (b'' Sx + c'' Sy)
+    // with the pre-scaled conic (a'', b'', c'') = -log2(e)/2 (a, b, c), and
+    //   dL/da = -Sxx/2, dL/db = -Sxy, dL/dc = -Syy/2, dL/do = S1 / o.
     if ((int)threadIdx.x < cnt) {
       float *src = s_grad + threadIdx.x * NGRAD2D;
       float v[NGRAD2D];
@@ -311,17 +321,19 @@ __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, con
         nz = nz || v[f] != 0.f;
       }
       if (nz) {
-        float *dst = grad2d + (size_t)s_id[threadIdx.x] * NGRAD2D;
-        atomicAdd(dst + 0, 2.f * LN2 * v[0]);
-        atomicAdd(dst + 1, 2.f * LN2 * v[1]);
-        atomicAdd(dst + 2, -0.5f * v[2]);
-        atomicAdd(dst + 3, -v[3]);
-        atomicAdd(dst + 4, -0.5f * v[4]);
-        atomicAdd(dst + 5, v[5]);
-        atomicAdd(dst + 6, v[6]);
-        atomicAdd(dst + 7, v[7]);
-        atomicAdd(dst + 8, v[8]);
-        atomicAdd(dst + 9, v[9]);
+        const float4 con = s_rec[threadIdx.x].con;
+        const double o = (double)s_rec[threadIdx.x].geo.z;
+        double *dst = grad2d + (size_t)s_id[threadIdx.x] * NGRAD2D;
+        atomicAdd(dst + 0, 2.0 * (double)LN2 * ((double)con.x * v[0] + (double)con.y * v[1]));
+        atomicAdd(dst + 1, 2.0 * (double)LN2 * ((double)con.y * v[0] + (double)con.z * v[1]));
+        atomicAdd(dst + 2, -0.5 * (double)v[2]);
+        atomicAdd(dst + 3, -(double)v[3]);
+        atomicAdd(dst + 4, -0.5 * (double)v[4]);
+        atomicAdd(dst + 5, (double)v[5] / o);
+        atomicAdd(dst + 6, (double)v[6]);
+        atomicAdd(dst + 7, (double)v[7]);
+        atomicAdd(dst + 8, (double)v[8]);
+        atomicAdd(dst + 9, (double)v[9]);
       }
     }
     __syncthreads();
@@ -379,7 +391,7 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd(RasterArgs a, const float 
                                                       const float *__restrict__ g_rgb,
                                                       const float *__restrict__ g_depth,
                                                       const float *__restrict__ g_T,
-                                                      float *__restrict__ grad2d) {
+                                                      double *__restrict__ grad2d) {
   __shared__ Staged s_rec[BATCH];
   __shared__ float s_grad[BATCH * NGRAD2D];
   __shared__ uint32_t s_id[BATCH];
@@ -411,7 +423,7 @@ __global__ __launch_bounds__(BLOCK) void k_render_fused(RasterArgs a, uint32_t *
                                                         const float *__restrict__ t_depth,
                                                         const uint8_t *__restrict__ pmask, float w_rgb,
                                                         float w_depth, gsr_images out, float *__restrict__ loss,
-                                                        float *__restrict__ grad2d, PixelState ps) {
+                                                        double *__restrict__ grad2d, PixelState ps) {
   __shared__ Staged s_rec[BATCH];
   __shared__ float s_grad[BATCH * NGRAD2D];
   __shared__ uint32_t s_id[BATCH];

@@ -33,6 +33,7 @@ class Config:
     lowpass: float = 0.3
     bg: Sequence[float] = (0.0, 0.0, 0.0)
     flags: int = A.GSR_GAUSS_GRAD | A.GSR_POSE_GRAD
+    fov_guard: float = 1.3
 
     def to_c(self) -> A.gsr_config:
         c = A.gsr_config()
@@ -41,6 +42,7 @@ class Config:
         for k in range(3):
             c.bg[k] = float(self.bg[k])
         c.flags = int(self.flags)
+        c.fov_guard = float(self.fov_guard)
         return c
 
     @staticmethod

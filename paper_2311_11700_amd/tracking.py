@@ -108,10 +108,12 @@ class Tracker:
         out[0, 13:16] = T[:3, 3].to(torch.float32)
 
     def track(self, T_init: torch.Tensor, target_rgb: torch.Tensor, target_depth: torch.Tensor,
-              pixel_mask: Optional[torch.Tensor] = None, losses: Optional[list] = None) -> torch.Tensor:
+              pixel_mask: Optional[torch.Tensor] = None, losses: Optional[list] = None,
+              poses: Optional[list] = None) -> torch.Tensor:
         """Optimise the world->camera pose T (4x4 float64, device) starting at
-        T_init; returns the final pose.  `losses` (optional) collects the
-        per-iteration loss tensors (no host synchronisation here)."""
+        T_init; returns the final pose.  `losses` and `poses` (optional) collect
+        the per-iteration loss tensors and the pose after each update (no host
+        synchronisation here)."""
         c = self.cfg
         dev = self.fine.device
         T = T_init.to(device=dev, dtype=torch.float64).clone()
@@ -145,4 +147,6 @@ class Tracker:
             vh = v / (1 - b2 ** (it + 1))
             step = -lr * mh / (torch.sqrt(vh) + eps)
             T = se3_exp(step) @ T
+            if poses is not None:
+                poses.append(T)
         return T

@@ -38,7 +38,7 @@ def test_struct_layouts():
     from paper_2311_11700_amd import _abi as A
     assert ctypes.sizeof(A.gsr_camera) == 80
     assert ctypes.sizeof(A.gsr_gaussians) == 8 + 6 * 8
-    assert ctypes.sizeof(A.gsr_config) == 40
+    assert ctypes.sizeof(A.gsr_config) == 44
     assert ctypes.sizeof(A.gsr_images) == 32
     assert ctypes.sizeof(A.gsr_grads) == 48
     assert ctypes.sizeof(A.gsr_tuning) == 16
@@ -55,6 +55,7 @@ def test_defaults_match_oracle_constants():
     assert c.cutoff_sigma == o.cutoff and c.z_near == o.z_near and c.lowpass == o.lowpass
     assert list(c.bg) == [0.0, 0.0, 0.0]
     assert c.flags == gsr.GSR_GAUSS_GRAD | gsr.GSR_POSE_GRAD
+    assert c.fov_guard == o.fov_guard == np.float32(gsr.Config().fov_guard)
     assert np.float32(gsr.Config().alpha_min) == np.float32(c.alpha_min)
 
 

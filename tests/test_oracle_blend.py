@@ -262,6 +262,46 @@ def test_backward_matches_central_differences(bg):
         assert abs(fd - g["pose"][k]) <= 1e-6 * (1 + abs(fd)), (k, fd, g["pose"][k])
 
 
+def test_backward_matches_central_differences_outside_the_guard():
+    """Two Gaussians whose x/z (resp. y/z) lies beyond the Jacobian guard
+    but whose footprint reaches into the image: the limited Jacobian is
+    differentiated exactly (no x dependence, 1/z dependence only)."""
+    base = _fd_scene()
+    extra = W.Scene(np.array([[0.8 * 2.0, 0.1, 2.0], [-0.2, 0.7 * 2.3, 2.3]]),
+                    np.full((2, 3), np.log(0.25)), np.array([[0.9, 0.1, -0.3, 0.2], [0.5, -0.5, 0.5, 0.4]]),
+                    np.array([1.2, 0.8]), np.array([[0.9, 0.2, 0.1], [0.1, 0.8, 0.3]]))
+    sc = W.Scene(*(np.concatenate([a, b]) for a, b in zip(base.arrays(), extra.arrays())))
+    cam = _cam(24, 20, 22.0)
+    cfg = O.Config.smooth()
+    p = O.project(sc, cam, cfg)
+    assert not p["free_x"][5] and not p["free_y"][6] and p["free_x"][:5].all() and p["free_y"][:5].all()
+    wts = _weights(cam)
+    g = O.render_backward(sc, cam, cfg, *wts)
+    h = 1e-6
+    for name in ("mean", "log_scale"):
+        arr = getattr(sc, name)
+        for i in (5, 6):
+            for j in range(3):
+                orig = arr[i, j]
+                arr[i, j] = orig + h
+                lp = _objective(sc, cam, cfg, wts)
+                arr[i, j] = orig - h
+                lm = _objective(sc, cam, cfg, wts)
+                arr[i, j] = orig
+                fd = (lp - lm) / (2 * h)
+                assert abs(g[name][i, j]) > 1e-4
+                assert abs(fd - g[name][i, j]) <= 1e-6 * (1 + abs(fd)), (name, i, j, fd, g[name][i, j])
+    for k in range(6):
+        xi = np.zeros(6)
+        vals = []
+        for sgn in (1, -1):
+            xi[k] = sgn * h
+            T = W.se3_exp(xi)
+            vals.append(_objective(sc, dataclasses.replace(cam, R=T[:3, :3], t=T[:3, 3]), cfg, wts))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - g["pose"][k]) <= 1e-6 * (1 + abs(fd)), (k, fd, g["pose"][k])
+
+
 def test_depth_alpha_derivative_matches_printed_formula():
     """Single pixel, three Gaussians: dD/dalpha_i from eq. grad_depth,
     d_i prod_{j<i}(1-a_j) - sum_{k>i} d_k a_k prod_{j<k, j!=i}(1-a_j),

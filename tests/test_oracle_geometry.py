@@ -97,7 +97,7 @@ def test_ewa_closed_form_isotropic_on_axis():
 def test_jacobian_matches_numerical_projection_derivative():
     cam = W.camera_small()
     sc = W.random_scene(8, seed=5)
-    p = O.project(sc, cam, O.Config())
+    p = O.project(sc, cam, O.Config(fov_guard=0.0))  # Eq. 3 as printed
 
     def proj(X):
         return np.array([cam.fx * X[0] / X[2] + cam.cx, cam.fy * X[1] / X[2] + cam.cy])
@@ -107,6 +107,32 @@ def test_jacobian_matches_numerical_projection_derivative():
         X = p["Xc"][k]
         Jn = np.stack([(proj(X + h * e) - proj(X - h * e)) / (2 * h) for e in np.eye(3)], axis=1)
         np.testing.assert_allclose(p["J"][k], Jn, rtol=1e-7, atol=1e-6)
+
+
+def test_guarded_jacobian_is_projection_derivative_at_the_limit():
+    """With the guard on, J is the derivative of the pinhole projection at
+    the point whose x/z and y/z are clipped to +-g W/(2 fx), +-g H/(2 fy);
+    the projected centre is unchanged."""
+    cam = W.camera_small()
+    sc = W.random_scene(40, seed=5, xy=2.5)
+    g = 1.3
+    p = O.project(sc, cam, O.Config(fov_guard=g))
+    p0 = O.project(sc, cam, O.Config(fov_guard=0.0))
+    lx, ly = g * cam.width / (2 * cam.fx), g * cam.height / (2 * cam.fy)
+
+    def proj(X):
+        return np.array([cam.fx * X[0] / X[2] + cam.cx, cam.fy * X[1] / X[2] + cam.cy])
+
+    h = 1e-6
+    n_clip = 0
+    for k in range(sc.n):
+        x, y, z = p["Xc"][k]
+        Xl = np.array([np.clip(x / z, -lx, lx) * z, np.clip(y / z, -ly, ly) * z, z])
+        n_clip += int(abs(x / z) > lx or abs(y / z) > ly)
+        Jn = np.stack([(proj(Xl + h * e) - proj(Xl - h * e)) / (2 * h) for e in np.eye(3)], axis=1)
+        np.testing.assert_allclose(p["J"][k], Jn, rtol=1e-7, atol=1e-6)
+    assert 5 <= n_clip <= sc.n - 5, n_clip
+    np.testing.assert_array_equal(p["uv"], p0["uv"])
 
 
 def test_ewa_covariance_matches_sampled_projection():

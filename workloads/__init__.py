@@ -10,12 +10,14 @@ from .scenes import (  # noqa: F401
     Scene,
     random_scene,
     room_scene,
+    tracking_scene,
     camera_small,
     camera_replica,
     camera_tum,
     camera_tum_coarse,
     camera_quarter_tum,
     camera_hyp_half,
+    camera_tracking,
     se3_exp,
     perturb_pose,
     tracking_start,

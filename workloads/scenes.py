@@ -127,6 +127,52 @@ def room_scene(n=300_000, seed=0, surface_fraction=0.7) -> Scene:
     return Scene(mean, ls, q, op, rgb)
 
 
+def tracking_scene(n=60_000, seed=0, outlier_fraction=0.2, offset=(0.2, 0.6)) -> tuple[Scene, int]:
+    """Map for the tracking workload: (1 - outlier_fraction) n surface
+    Gaussians followed by the outliers.  Surface Gaussians lie on the floor
+    and walls (chosen by area, 1 cm normal jitter) and are flat, as fitted
+    maps of surfaces are: in-plane log-scales N(-3, 0.5^2), 5 mm along the
+    normal, a uniform random rotation about the normal.  Outliers are surface
+    points pushed into the room along the inward normal by a distance uniform
+    in `offset` metres (badly placed geometry a map keeps from earlier frames)
+    with the isotropic appearance of _draw_appearance.  Opacity logits N(0, 1)
+    and RGB uniform for all.  Returns (scene, number of surface Gaussians)."""
+    rng = np.random.default_rng(seed)
+    n_out = int(round(outlier_fraction * n))
+    n_surf = n - n_out
+    lo = np.array([_ROOM["x"][0], _ROOM["y"][0], _ROOM["z"][0]])
+    hi = np.array([_ROOM["x"][1], _ROOM["y"][1], _ROOM["z"][1]])
+    centre = 0.5 * (lo + hi)
+    p = _AREAS / _AREAS.sum()
+    # surfaces
+    which = rng.choice(len(_SURFACES), size=n_surf, p=p)
+    surf = lo + rng.random(size=(n_surf, 3)) * (hi - lo)
+    jitter = rng.normal(0.0, 0.01, size=n_surf)
+    ls_s = rng.normal(-3.0, 0.5, size=(n_surf, 3))
+    theta = rng.uniform(0.0, 2.0 * math.pi, size=n_surf)
+    q_s = np.zeros((n_surf, 4))
+    q_s[:, 0] = np.cos(0.5 * theta)
+    for k, (_, axis, value) in enumerate(_SURFACES):
+        sel = which == k
+        surf[sel, axis] = value + jitter[sel]
+        ls_s[sel, axis] = math.log(0.005)
+        q_s[sel, 1 + axis] = np.sin(0.5 * theta[sel])
+    # outliers
+    which_o = rng.choice(len(_SURFACES), size=n_out, p=p)
+    out = lo + rng.random(size=(n_out, 3)) * (hi - lo)
+    dist = rng.uniform(offset[0], offset[1], size=n_out)
+    for k, (_, axis, value) in enumerate(_SURFACES):
+        sel = which_o == k
+        out[sel, axis] = value - np.sign(value - centre[axis]) * dist[sel]
+    ls_o, q_o, _, _ = _draw_appearance(rng, n_out)
+    op = rng.normal(0.0, 1.0, size=n)
+    rgb = rng.random(size=(n, 3))
+    mean = np.concatenate([surf, out], axis=0).astype(F32)
+    ls = np.concatenate([ls_s, ls_o], axis=0).astype(F32)
+    q = np.concatenate([q_s, q_o], axis=0).astype(F32)
+    return Scene(mean, ls, q, op.astype(F32), rgb.astype(F32)), n_surf
+
+
 def subset(scene: Scene, idx) -> Scene:
     idx = np.asarray(idx)
     return Scene(*(a[idx].copy() for a in scene.arrays()))
@@ -228,6 +274,14 @@ def _look_at(centre, target, roll):
     R = np.stack([x2, y2, z], axis=0)
     t = -R @ centre
     return R, t
+
+
+def camera_tracking() -> Camera:
+    """camera_tum() intrinsics at a pose that sees the floor, the back wall and
+    the right wall: centre (0.5, 0.3, 0.8), looking at the floor corner
+    (3, 1.5, 3.5), no roll."""
+    R, t = _look_at(np.array([0.5, 0.3, 0.8]), np.array([3.0, 1.5, 3.5]), 0.0)
+    return camera_tum().with_pose(R, t)
 
 
 def mapping_views(seed=2):
