@@ -114,10 +114,13 @@ typedef struct {
 
 /* Forward outputs, DEVICE (any pointer may be NULL to skip that output):
  * rgb [3 * sum HW] float, depth / T_final [sum HW] float, last [sum HW] int32
- * (1 + position in the tile list of the pixel's last blended Gaussian). */
+ * (1 + position in the tile list of the pixel's last blended Gaussian),
+ * loss [sum HW] float: the pixel's own term of the L1 loss (written by the
+ * fused step only, before any loss cap; 0 where pixel_mask is 0). */
 typedef struct {
   float *rgb, *depth, *T_final;
   int32_t *last;
+  float *loss;
 } gsr_images;
 
 /* Gradient outputs, DEVICE, accumulated (+=).  d_* match the Gaussian
@@ -176,25 +179,31 @@ gsr_status gsr_render_backward(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_c
 /* Weighted L1 loss (Eq. 6 / Eq. 10) and its gradient w.r.t. the rendered
  * images: loss = w_rgb sum m |C - C*| + w_depth sum m [D* > 0] |D - D*| over
  * all views' pixels with pixel_mask (nullable uint8, 0 = ignore) != 0;
- * sign(0) = 0.  Writes (overwrites) g_rgb / g_depth; ADDS the loss into
+ * sign(0) = 0.  w_rgb, w_depth >= 0.  loss_cap (DEVICE float [n_views],
+ * nullable): a pixel whose own loss term exceeds its view's cap is ignored
+ * (no loss, zero gradient) -- the tracking rule that drops pixels with more
+ * than ten times the median loss (implementation details of the paper; see
+ * gsr_loss_median).  Writes (overwrites) g_rgb / g_depth; ADDS the loss into
  * *loss (DEVICE float).  Asynchronous. */
 gsr_status gsr_l1_loss_grad(gsr_ctx *ctx, const float *rgb, const float *depth,
                             const float *target_rgb, const float *target_depth,
-                            const uint8_t *pixel_mask, float w_rgb, float w_depth, float *g_rgb,
-                            float *g_depth, float *loss, gsr_stream stream);
+                            const uint8_t *pixel_mask, float w_rgb, float w_depth,
+                            const float *loss_cap, float *g_rgb, float *g_depth, float *loss,
+                            gsr_stream stream);
 
 /* One training step of the renderer in a single call: forward, L1 loss and
- * its gradient, and backward, with the per-tile forward, loss gradient and
- * backward fused in one persistent kernel.  Images in `out` are optional
- * (NULL struct or NULL members skip them).  ADDS the loss into *loss.
- * Asynchronous: a pair-capacity overflow is recorded on the device and
- * reported by gsr_check_overflow(). */
+ * its gradient (as gsr_l1_loss_grad, loss_cap included), and backward, with
+ * the per-tile forward, loss gradient and backward fused in one persistent
+ * kernel.  Images in `out` are optional (NULL struct or NULL members skip
+ * them; out->loss receives every pixel's own loss term before the cap).
+ * ADDS the loss into *loss.  Asynchronous: a pair-capacity overflow is
+ * recorded on the device and reported by gsr_check_overflow(). */
 gsr_status gsr_render_l1_fused(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams,
                                int n_views, const gsr_config *cfg, const float *target_rgb,
                                const float *target_depth, const uint8_t *pixel_mask, float w_rgb,
-                               float w_depth, void *workspace, size_t workspace_bytes,
-                               const gsr_images *out, const gsr_grads *grads, float *loss,
-                               gsr_stream stream);
+                               float w_depth, const float *loss_cap, void *workspace,
+                               size_t workspace_bytes, const gsr_images *out, const gsr_grads *grads,
+                               float *loss, gsr_stream stream);
 
 /* Capture gsr_render_l1_fused with these exact arguments (pointers and
  * scalar values are baked in; buffer CONTENTS may change between launches)
@@ -202,9 +211,9 @@ gsr_status gsr_render_l1_fused(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_c
 gsr_status gsr_graph_capture(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams,
                              int n_views, const gsr_config *cfg, const float *target_rgb,
                              const float *target_depth, const uint8_t *pixel_mask, float w_rgb,
-                             float w_depth, void *workspace, size_t workspace_bytes,
-                             const gsr_images *out, const gsr_grads *grads, float *loss,
-                             gsr_stream stream);
+                             float w_depth, const float *loss_cap, void *workspace,
+                             size_t workspace_bytes, const gsr_images *out, const gsr_grads *grads,
+                             float *loss, gsr_stream stream);
 /* Launch the captured graph on `stream` (asynchronous). */
 gsr_status gsr_graph_launch(gsr_ctx *ctx, gsr_stream stream);
 
@@ -236,6 +245,19 @@ gsr_status gsr_autotune(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *
                         const uint8_t *pixel_mask, float w_rgb, float w_depth, void *workspace,
                         size_t workspace_bytes, const gsr_grads *grads, float *loss, int reps,
                         gsr_tuning *best, gsr_stream stream);
+
+/* Loss cap for outlier pixels (implementation details of the paper: a
+ * tracking pixel whose loss exceeds ten times the median loss is ignored).
+ * For every view of the plan: cap_out[v] = factor * the lower median (the
+ * element of rank floor((m - 1) / 2) in ascending order) of px_loss over the
+ * view's m pixels with pixel_mask != 0 (all pixels if pixel_mask is NULL);
+ * +inf when m = 0.  px_loss (DEVICE float [sum HW], e.g. gsr_images.loss of
+ * a fused step) is compared as non-negative floats: negative values and -0
+ * count as 0, NaN above +inf.  The selection is exact (radix select on the
+ * float bits, one block per view).  cap_out is DEVICE float [n_views], the
+ * loss_cap argument of the next step.  Asynchronous. */
+gsr_status gsr_loss_median(gsr_ctx *ctx, const float *px_loss, const uint8_t *pixel_mask, float factor,
+                           float *cap_out, gsr_stream stream);
 
 /* Reliable-Gaussian selection for the fine tracking stage (Eq. 12, Sec. 3.3):
  * each Gaussian's centre is projected with the (coarse) pose `cam` (DEVICE,

@@ -7,4 +7,5 @@ from .splat import (  # noqa: F401
     Config, TILE, GRAD2D_FIELDS, AMBIG_ALPHA, AMBIG_T, AMBIG_BIN,
     quat_to_rotmat, quat_to_rotmat_grads, covariance_3d, project, tile_lists,
     render, backward_2d, sigma2d_backward, select_reliable, backward_params, render_backward, l1_loss, f32,
+    l1_pixel_loss, loss_median, loss_cap,
 )

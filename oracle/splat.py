@@ -517,20 +517,65 @@ def render_backward(scene, cam, cfg: Config, g_rgb, g_depth, g_T=None, approx_po
 
 # --------------------------------------------------------------------------- Eq. 6 / 10
 
-def l1_loss(rgb, depth, target_rgb, target_depth, pixel_mask=None, w_rgb=1.0, w_depth=0.1):
+def l1_pixel_loss(rgb, depth, target_rgb, target_depth, pixel_mask=None, w_rgb=1.0, w_depth=0.1):
+    """Each pixel's own term of the L1 loss: w_rgb sum_c |C_c - C*_c| +
+    w_depth [D* > 0] |D - D*|, 0 where pixel_mask is 0.  [H, W] FP64."""
+    rgb = np.asarray(rgb, F64)
+    depth = np.asarray(depth, F64)
+    trgb = np.asarray(target_rgb, F64).reshape(rgb.shape)
+    tdep = np.asarray(target_depth, F64).reshape(depth.shape)
+    m = np.ones(depth.shape, bool) if pixel_mask is None else (np.asarray(pixel_mask).reshape(depth.shape) != 0)
+    lp = w_rgb * np.abs(rgb - trgb).sum(axis=0) + w_depth * (tdep > 0) * np.abs(depth - tdep)
+    return np.where(m, lp, 0.0)
+
+
+def l1_loss(rgb, depth, target_rgb, target_depth, pixel_mask=None, w_rgb=1.0, w_depth=0.1, loss_cap=None):
     """L = w_rgb * sum |C - C*| + w_depth * sum_{D* > 0} |D - D*| over pixels
-    with pixel_mask != 0 (Eq. 6 sums; Eq. 10 colour term).  Returns
-    (loss, dL/dC, dL/dD) with sign(0) = 0."""
+    with pixel_mask != 0 (Eq. 6 sums; Eq. 10 colour term).  With `loss_cap`,
+    pixels whose own loss term exceeds it are ignored as well (the tracking
+    rule of the implementation details: loss above ten times the median).
+    Returns (loss, dL/dC, dL/dD) with sign(0) = 0."""
     rgb = np.asarray(rgb, F64)
     depth = np.asarray(depth, F64)
     trgb = np.asarray(target_rgb, F64).reshape(rgb.shape)
     tdep = np.asarray(target_depth, F64).reshape(depth.shape)
     m = np.ones(depth.shape) if pixel_mask is None else (np.asarray(pixel_mask).reshape(depth.shape) != 0)
+    if loss_cap is not None:
+        lp = l1_pixel_loss(rgb, depth, trgb, tdep, None, w_rgb, w_depth)
+        m = m * (lp <= loss_cap)
     md = m * (tdep > 0)
     dc = rgb - trgb
     dd = depth - tdep
     loss = w_rgb * np.sum(m[None] * np.abs(dc)) + w_depth * np.sum(md * np.abs(dd))
     return loss, w_rgb * m[None] * np.sign(dc), w_depth * md * np.sign(dd)
+
+
+def loss_median(px_loss, pixel_mask=None):
+    """Lower median (the element of rank floor((m - 1) / 2) in ascending
+    order) of the float32 values px_loss over the m pixels with
+    pixel_mask != 0; None if m = 0.  Values compare as non-negative floats:
+    negative values and -0 count as 0 and NaN ranks above +inf.  One plain
+    sort."""
+    v = np.asarray(px_loss, np.float32).reshape(-1)
+    if pixel_mask is not None:
+        v = v[np.asarray(pixel_mask).reshape(-1) != 0]
+    if v.size == 0:
+        return None
+
+    def key(x):
+        if np.isnan(x):
+            return (1, 0.0)
+        return (0, max(float(x), 0.0))
+
+    ordered = sorted(v.tolist(), key=key)
+    x = ordered[(len(ordered) - 1) // 2]
+    return np.float32(0.0) if (not np.isnan(x) and x <= 0.0) else np.float32(x)
+
+
+def loss_cap(px_loss, pixel_mask=None, factor=10.0):
+    """factor x lower median in float32 arithmetic, +inf without pixels."""
+    med = loss_median(px_loss, pixel_mask)
+    return np.float32(np.inf) if med is None else np.float32(np.float32(factor) * med)
 
 
 # --------------------------------------------------------------------------- Eq. 12

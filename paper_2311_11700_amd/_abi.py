@@ -50,7 +50,8 @@ class gsr_config(ctypes.Structure):
 
 
 class gsr_images(ctypes.Structure):
-    _fields_ = [("rgb", c_void_p), ("depth", c_void_p), ("T_final", c_void_p), ("last", c_void_p)]
+    _fields_ = [("rgb", c_void_p), ("depth", c_void_p), ("T_final", c_void_p), ("last", c_void_p),
+                ("loss", c_void_p)]
 
 
 class gsr_grads(ctypes.Structure):
@@ -82,13 +83,15 @@ SIGNATURES = {
                                            c_void_p, ctypes.c_size_t, c_void_p, c_void_p, c_void_p,
                                            _P(gsr_grads), c_void_p]),
     "gsr_l1_loss_grad": (ctypes.c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
-                                        ctypes.c_float, ctypes.c_float, c_void_p, c_void_p, c_void_p, c_void_p]),
+                                        ctypes.c_float, ctypes.c_float, c_void_p, c_void_p, c_void_p, c_void_p,
+                                        c_void_p]),
+    "gsr_loss_median": (ctypes.c_int, [c_void_p, c_void_p, c_void_p, ctypes.c_float, c_void_p, c_void_p]),
     "gsr_render_l1_fused": (ctypes.c_int, [c_void_p, _P(gsr_gaussians), c_void_p, ctypes.c_int, _P(gsr_config),
-                                           c_void_p, c_void_p, c_void_p, ctypes.c_float, ctypes.c_float,
+                                           c_void_p, c_void_p, c_void_p, ctypes.c_float, ctypes.c_float, c_void_p,
                                            c_void_p, ctypes.c_size_t, _P(gsr_images), _P(gsr_grads), c_void_p,
                                            c_void_p]),
     "gsr_graph_capture": (ctypes.c_int, [c_void_p, _P(gsr_gaussians), c_void_p, ctypes.c_int, _P(gsr_config),
-                                         c_void_p, c_void_p, c_void_p, ctypes.c_float, ctypes.c_float,
+                                         c_void_p, c_void_p, c_void_p, ctypes.c_float, ctypes.c_float, c_void_p,
                                          c_void_p, ctypes.c_size_t, _P(gsr_images), _P(gsr_grads), c_void_p,
                                          c_void_p]),
     "gsr_graph_launch": (ctypes.c_int, [c_void_p, c_void_p]),

@@ -16,7 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgsr.so")
-SOURCES = ["gsr_preprocess.hip", "gsr_pregrad.hip", "gsr_sort.hip", "gsr_raster.hip", "gsr_api.hip"]
+SOURCES = ["gsr_preprocess.hip", "gsr_pregrad.hip", "gsr_sort.hip", "gsr_raster.hip", "gsr_median.hip",
+           "gsr_api.hip"]
 ARCH = os.environ.get("GSR_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

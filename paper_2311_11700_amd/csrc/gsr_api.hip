@@ -180,6 +180,7 @@ void enqueue_lists(gsr_ctx *ctx, const gsr_gaussians &g, const gsr_camera *cams,
 
 void enqueue_fused(gsr_ctx *ctx, const gsr_gaussians &g, const gsr_camera *cams, const gsr_config &cfg,
                    const float *t_rgb, const float *t_depth, const uint8_t *pmask, float w_rgb, float w_depth,
+                   const float *loss_cap,
                    Workspace &ws, const gsr_images *out, const gsr_grads &gr, float *loss, hipStream_t s) {
   const Plan &p = ctx->plan;
   prof_begin(ctx, s);
@@ -188,7 +189,7 @@ void enqueue_fused(gsr_ctx *ctx, const gsr_gaussians &g, const gsr_camera *cams,
   launch_fill_f32(reinterpret_cast<float *>(ws.grad2d), 0.f, 2 * p.n_rec * NGRAD2D, s);
   prof_mark(ctx, s, GSR_STAGE_RANGES);
   launch_render_fused(p, ws, ctx->views_dev, ctx->tile_view_dev, g, consts(cfg), t_rgb, t_depth, pmask, w_rgb,
-                      w_depth, out, loss, ctx->tuning, ctx->num_cus, s);
+                      w_depth, loss_cap, out, loss, ctx->tuning, ctx->num_cus, s);
   prof_mark(ctx, s, GSR_STAGE_RASTER);
   prof_mark(ctx, s, GSR_STAGE_RASTER_BWD);
   launch_preprocess_backward(p, g, cams, cfg, ws, gr, s);
@@ -409,22 +410,35 @@ gsr_status gsr_render_backward(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_c
 
 gsr_status gsr_l1_loss_grad(gsr_ctx *ctx, const float *rgb, const float *depth, const float *target_rgb,
                             const float *target_depth, const uint8_t *pixel_mask, float w_rgb, float w_depth,
-                            float *g_rgb, float *g_depth, float *loss, gsr_stream stream) {
+                            const float *loss_cap, float *g_rgb, float *g_depth, float *loss, gsr_stream stream) {
   if (!ctx) return GSR_E_INVALID;
   if (!ctx->planned) return fail(ctx, GSR_E_STATE, "gsr_plan() has not been called");
   if (!rgb || !depth || !target_rgb || !target_depth || !g_rgb || !g_depth)
     return fail(ctx, GSR_E_INVALID, "gsr_l1_loss_grad: null argument");
-  launch_l1(ctx->plan, ctx->views_dev, rgb, depth, target_rgb, target_depth, pixel_mask, w_rgb, w_depth, g_rgb,
-            g_depth, loss, static_cast<hipStream_t>(stream));
+  if (!(w_rgb >= 0.f) || !(w_depth >= 0.f)) return fail(ctx, GSR_E_INVALID, "loss weights must be >= 0");
+  launch_l1(ctx->plan, ctx->views_dev, rgb, depth, target_rgb, target_depth, pixel_mask, w_rgb, w_depth, loss_cap,
+            g_rgb, g_depth, loss, static_cast<hipStream_t>(stream));
   return last_launch(ctx, "gsr_l1_loss_grad launch");
 }
 
+gsr_status gsr_loss_median(gsr_ctx *ctx, const float *px_loss, const uint8_t *pixel_mask, float factor,
+                           float *cap_out, gsr_stream stream) {
+  if (!ctx) return GSR_E_INVALID;
+  if (!ctx->planned) return fail(ctx, GSR_E_STATE, "gsr_plan() has not been called");
+  if (!px_loss || !cap_out) return fail(ctx, GSR_E_INVALID, "gsr_loss_median: null argument");
+  if (!(factor >= 0.f)) return fail(ctx, GSR_E_INVALID, "gsr_loss_median: factor must be >= 0");
+  launch_loss_median(ctx->plan, ctx->views_dev, px_loss, pixel_mask, factor, cap_out,
+                     static_cast<hipStream_t>(stream));
+  return last_launch(ctx, "gsr_loss_median launch");
+}
+
 static gsr_status fused_checks(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams, int n_views,
-                               const gsr_config *cfg, const float *t_rgb, const float *t_depth, void *ws,
-                               size_t ws_bytes, const gsr_grads *grads) {
+                               const gsr_config *cfg, const float *t_rgb, const float *t_depth, float w_rgb,
+                               float w_depth, void *ws, size_t ws_bytes, const gsr_grads *grads) {
   gsr_status st = validate(ctx, g, cams, n_views, cfg, ws, ws_bytes);
   if (st != GSR_OK) return st;
   if (!t_rgb || !t_depth || !grads) return fail(ctx, GSR_E_INVALID, "fused step: null target or gradient argument");
+  if (!(w_rgb >= 0.f) || !(w_depth >= 0.f)) return fail(ctx, GSR_E_INVALID, "loss weights must be >= 0");
   if ((cfg->flags & GSR_GAUSS_GRAD) && (!grads->d_mean || !grads->d_log_scale || !grads->d_quat ||
                                         !grads->d_opacity_logit || !grads->d_rgb))
     return fail(ctx, GSR_E_INVALID, "GSR_GAUSS_GRAD needs every d_* pointer");
@@ -436,24 +450,26 @@ static gsr_status fused_checks(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_c
 
 gsr_status gsr_render_l1_fused(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams, int n_views,
                                const gsr_config *cfg, const float *target_rgb, const float *target_depth,
-                               const uint8_t *pixel_mask, float w_rgb, float w_depth, void *workspace,
-                               size_t workspace_bytes, const gsr_images *out, const gsr_grads *grads,
-                               float *loss, gsr_stream stream) {
-  gsr_status st = fused_checks(ctx, g, cams, n_views, cfg, target_rgb, target_depth, workspace, workspace_bytes, grads);
+                               const uint8_t *pixel_mask, float w_rgb, float w_depth, const float *loss_cap,
+                               void *workspace, size_t workspace_bytes, const gsr_images *out,
+                               const gsr_grads *grads, float *loss, gsr_stream stream) {
+  gsr_status st = fused_checks(ctx, g, cams, n_views, cfg, target_rgb, target_depth, w_rgb, w_depth, workspace,
+                               workspace_bytes, grads);
   if (st != GSR_OK) return st;
   Workspace ws = make_ws(ctx->plan, workspace);
-  enqueue_fused(ctx, *g, cams, *cfg, target_rgb, target_depth, pixel_mask, w_rgb, w_depth, ws, out, *grads, loss,
-                static_cast<hipStream_t>(stream));
+  enqueue_fused(ctx, *g, cams, *cfg, target_rgb, target_depth, pixel_mask, w_rgb, w_depth, loss_cap, ws, out,
+                *grads, loss, static_cast<hipStream_t>(stream));
   ctx->last_forward_ws = nullptr;
   return last_launch(ctx, "gsr_render_l1_fused launch");
 }
 
 gsr_status gsr_graph_capture(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams, int n_views,
                              const gsr_config *cfg, const float *target_rgb, const float *target_depth,
-                             const uint8_t *pixel_mask, float w_rgb, float w_depth, void *workspace,
-                             size_t workspace_bytes, const gsr_images *out, const gsr_grads *grads, float *loss,
-                             gsr_stream stream) {
-  gsr_status st = fused_checks(ctx, g, cams, n_views, cfg, target_rgb, target_depth, workspace, workspace_bytes, grads);
+                             const uint8_t *pixel_mask, float w_rgb, float w_depth, const float *loss_cap,
+                             void *workspace, size_t workspace_bytes, const gsr_images *out,
+                             const gsr_grads *grads, float *loss, gsr_stream stream) {
+  gsr_status st = fused_checks(ctx, g, cams, n_views, cfg, target_rgb, target_depth, w_rgb, w_depth, workspace,
+                               workspace_bytes, grads);
   if (st != GSR_OK) return st;
   if (!stream) return fail(ctx, GSR_E_INVALID, "gsr_graph_capture needs a non-null stream");
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -466,7 +482,8 @@ gsr_status gsr_graph_capture(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_cam
   Workspace ws = make_ws(ctx->plan, workspace);
   const bool prof = ctx->profiling;
   ctx->profiling = false;  // no event records inside a captured graph
-  enqueue_fused(ctx, *g, cams, *cfg, target_rgb, target_depth, pixel_mask, w_rgb, w_depth, ws, out, *grads, loss, s);
+  enqueue_fused(ctx, *g, cams, *cfg, target_rgb, target_depth, pixel_mask, w_rgb, w_depth, loss_cap, ws, out,
+                *grads, loss, s);
   ctx->profiling = prof;
   hipGraph_t graph = nullptr;
   st = hip_check(ctx, hipStreamEndCapture(s, &graph), "hipStreamEndCapture");
@@ -555,7 +572,8 @@ gsr_status gsr_autotune(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *
                         const uint8_t *pixel_mask, float w_rgb, float w_depth, void *workspace,
                         size_t workspace_bytes, const gsr_grads *grads, float *loss, int reps, gsr_tuning *best,
                         gsr_stream stream) {
-  gsr_status st = fused_checks(ctx, g, cams, n_views, cfg, target_rgb, target_depth, workspace, workspace_bytes, grads);
+  gsr_status st = fused_checks(ctx, g, cams, n_views, cfg, target_rgb, target_depth, w_rgb, w_depth, workspace,
+                               workspace_bytes, grads);
   if (st != GSR_OK) return st;
   if (reps < 1) reps = 1;
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -587,7 +605,7 @@ gsr_status gsr_autotune(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *
           launch_fill_f32(reinterpret_cast<float *>(ws.grad2d), 0.f, 2 * p.n_rec * NGRAD2D, s);
           (void)hipEventRecord(e0, s);
           launch_render_fused(p, ws, ctx->views_dev, ctx->tile_view_dev, *g, consts(*cfg), target_rgb, target_depth,
-                              pixel_mask, w_rgb, w_depth, nullptr, loss, t, ctx->num_cus, s);
+                              pixel_mask, w_rgb, w_depth, nullptr, nullptr, loss, t, ctx->num_cus, s);
           (void)hipEventRecord(e1, s);
           st = hip_check(ctx, hipEventSynchronize(e1), "hipEventSynchronize");
           float ms = 0.f;

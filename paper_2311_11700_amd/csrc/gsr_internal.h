@@ -152,12 +152,15 @@ void launch_render_backward(const Plan &p, const Workspace &ws, const ViewInfo *
 void launch_render_fused(const Plan &p, const Workspace &ws, const ViewInfo *views,
                          const int32_t *tile_view, const gsr_gaussians &g, const RenderConsts &rc,
                          const float *t_rgb, const float *t_depth, const uint8_t *pmask,
-                         float w_rgb, float w_depth, const gsr_images *out, float *loss,
+                         float w_rgb, float w_depth, const float *loss_cap, const gsr_images *out, float *loss,
                          const Tuning &tun, int num_cus, hipStream_t s);
 void launch_work_counts(const Plan &p, const Workspace &ws, hipStream_t s);
 void launch_l1(const Plan &p, const ViewInfo *views, const float *rgb, const float *depth,
                const float *t_rgb, const float *t_depth, const uint8_t *pmask, float w_rgb,
-               float w_depth, float *g_rgb, float *g_depth, float *loss, hipStream_t s);
+               float w_depth, const float *loss_cap, float *g_rgb, float *g_depth, float *loss, hipStream_t s);
+// Loss cap: factor x lower median of each view's per-pixel loss.
+void launch_loss_median(const Plan &p, const ViewInfo *views, const float *px_loss, const uint8_t *pmask,
+                        float factor, float *cap_out, hipStream_t s);
 
 // Backward preprocess (chain to parameters and pose).
 void launch_preprocess_backward(const Plan &p, const gsr_gaussians &g, const gsr_camera *cams,

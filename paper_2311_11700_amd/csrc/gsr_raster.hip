@@ -422,7 +422,8 @@ __global__ __launch_bounds__(BLOCK) void k_render_fused(RasterArgs a, uint32_t *
                                                         int tiles_per_pop, const float *__restrict__ t_rgb,
                                                         const float *__restrict__ t_depth,
                                                         const uint8_t *__restrict__ pmask, float w_rgb,
-                                                        float w_depth, gsr_images out, float *__restrict__ loss,
+                                                        float w_depth, const float *__restrict__ loss_cap,
+                                                        gsr_images out, float *__restrict__ loss,
                                                         double *__restrict__ grad2d, PixelState ps) {
   __shared__ Staged s_rec[BATCH];
   __shared__ float s_grad[BATCH * NGRAD2D];
@@ -453,14 +454,18 @@ __global__ __launch_bounds__(BLOCK) void k_render_fused(RasterArgs a, uint32_t *
         const bool md = m && td > 0.f;
         const float ed = st.D - td;
         if (m) {
+          lpx = w_rgb * (fabsf(e0) + fabsf(e1) + fabsf(e2));
+          if (md) lpx += w_depth * fabsf(ed);
+        }
+        if (out.loss) out.loss[ti.pix] = lpx;
+        // Outlier pixels (own loss above the view's cap) are ignored.
+        const bool keep = m && !(loss_cap && lpx > loss_cap[ti.view]);
+        lpx = keep ? lpx : 0.f;
+        if (keep) {
           in.gC0 = w_rgb * sgnf(e0);
           in.gC1 = w_rgb * sgnf(e1);
           in.gC2 = w_rgb * sgnf(e2);
-          lpx = w_rgb * (fabsf(e0) + fabsf(e1) + fabsf(e2));
-        }
-        if (md) {
-          in.gD = w_depth * sgnf(ed);
-          lpx += w_depth * fabsf(ed);
+          if (md) in.gD = w_depth * sgnf(ed);
         }
         save_state(ps, ti.pix, st);
         if (out.rgb) {
@@ -490,6 +495,7 @@ __global__ __launch_bounds__(BLOCK) void k_l1(const ViewInfo *__restrict__ views
                                               const float *__restrict__ t_rgb,
                                               const float *__restrict__ t_depth,
                                               const uint8_t *__restrict__ pmask, float w_rgb, float w_depth,
+                                              const float *__restrict__ loss_cap,
                                               float *__restrict__ g_rgb, float *__restrict__ g_depth,
                                               float *__restrict__ loss) {
   __shared__ float s_w[4];
@@ -499,19 +505,25 @@ __global__ __launch_bounds__(BLOCK) void k_l1(const ViewInfo *__restrict__ views
   for (int64_t q = (int64_t)blockIdx.x * BLOCK + threadIdx.x; q < HW; q += (int64_t)gridDim.x * BLOCK) {
     const int64_t pix = vi.pix_off + q;
     const int64_t c0 = 3 * vi.pix_off + q;
-    const bool m = pmask ? pmask[pix] != 0 : true;
+    const bool m0 = pmask ? pmask[pix] != 0 : true;
     const float td = t_depth[pix];
-    const bool md = m && td > 0.f;
     const float ed = depth[pix] - td;
+    float e[3];
     float lp = 0.f;
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
-      const float e = rgb[c0 + ch * HW] - t_rgb[c0 + ch * HW];
-      g_rgb[c0 + ch * HW] = m ? w_rgb * sgnf(e) : 0.f;
-      lp += m ? fabsf(e) : 0.f;
+      e[ch] = rgb[c0 + ch * HW] - t_rgb[c0 + ch * HW];
+      lp += fabsf(e[ch]);
     }
+    lp = w_rgb * lp;
+    if (td > 0.f) lp += w_depth * fabsf(ed);
+    // Outlier pixels (own loss above the view's cap) are ignored.
+    const bool m = m0 && !(loss_cap && lp > loss_cap[blockIdx.y]);
+    const bool md = m && td > 0.f;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) g_rgb[c0 + ch * HW] = m ? w_rgb * sgnf(e[ch]) : 0.f;
     g_depth[pix] = md ? w_depth * sgnf(ed) : 0.f;
-    l += w_rgb * lp + (md ? w_depth * fabsf(ed) : 0.f);
+    l += m ? lp : 0.f;
   }
   l = wave_sum(l);
   if ((threadIdx.x & 63) == 0) s_w[threadIdx.x >> 6] = l;
@@ -521,20 +533,18 @@ __global__ __launch_bounds__(BLOCK) void k_l1(const ViewInfo *__restrict__ views
 
 void launch_l1(const Plan &p, const ViewInfo *views, const float *rgb, const float *depth,
                const float *t_rgb, const float *t_depth, const uint8_t *pmask, float w_rgb,
-               float w_depth, float *g_rgb, float *g_depth, float *loss, hipStream_t s) {
-  int64_t maxhw = 0;
-  (void)maxhw;
+               float w_depth, const float *loss_cap, float *g_rgb, float *g_depth, float *loss, hipStream_t s) {
   const unsigned gx = (unsigned)((p.total_pixels / p.n_views + BLOCK - 1) / BLOCK);
   dim3 grid(gx < 1024 ? (gx < 1 ? 1 : gx) : 1024, (unsigned)p.n_views);
   hipLaunchKernelGGL(k_l1, grid, dim3(BLOCK), 0, s, views, rgb, depth, t_rgb, t_depth, pmask, w_rgb, w_depth,
-                     g_rgb, g_depth, loss);
+                     loss_cap, g_rgb, g_depth, loss);
 }
 
 void launch_render_forward(const Plan &p, const Workspace &ws, const ViewInfo *views,
                            const int32_t *tile_view, const gsr_gaussians &g, const RenderConsts &rc,
                            const gsr_images *out, hipStream_t s) {
   RasterArgs a{ws.recA, ws.recB, ws.recZ, g.rgb, ws.pvals[ws.psorted], ws.ranges, views, tile_view, g.n, rc};
-  gsr_images o{nullptr, nullptr, nullptr, nullptr};
+  gsr_images o{nullptr, nullptr, nullptr, nullptr, nullptr};
   if (out) o = *out;
   PixelState ps{ws.T_final, ws.last, ws.nevals, ws.nblend};
   hipLaunchKernelGGL(k_render_fwd, dim3(p.total_tiles), dim3(BLOCK), 0, s, a, ps, o);
@@ -551,10 +561,10 @@ void launch_render_backward(const Plan &p, const Workspace &ws, const ViewInfo *
 void launch_render_fused(const Plan &p, const Workspace &ws, const ViewInfo *views,
                          const int32_t *tile_view, const gsr_gaussians &g, const RenderConsts &rc,
                          const float *t_rgb, const float *t_depth, const uint8_t *pmask, float w_rgb,
-                         float w_depth, const gsr_images *out, float *loss, const Tuning &tun, int num_cus,
-                         hipStream_t s) {
+                         float w_depth, const float *loss_cap, const gsr_images *out, float *loss,
+                         const Tuning &tun, int num_cus, hipStream_t s) {
   RasterArgs a{ws.recA, ws.recB, ws.recZ, g.rgb, ws.pvals[ws.psorted], ws.ranges, views, tile_view, g.n, rc};
-  gsr_images o{nullptr, nullptr, nullptr, nullptr};
+  gsr_images o{nullptr, nullptr, nullptr, nullptr, nullptr};
   if (out) o = *out;
   int grid = tun.blocks_per_cu * num_cus;
   const int need = (p.total_tiles + tun.tiles_per_pop - 1) / tun.tiles_per_pop;
@@ -562,7 +572,7 @@ void launch_render_fused(const Plan &p, const Workspace &ws, const ViewInfo *vie
   if (grid < 1) grid = 1;
   PixelState ps{ws.T_final, ws.last, ws.nevals, ws.nblend};
   hipLaunchKernelGGL(k_render_fused, dim3(grid), dim3(BLOCK), 0, s, a, ws.hdr, ws.queue, p.total_tiles,
-                     tun.tiles_per_pop, t_rgb, t_depth, pmask, w_rgb, w_depth, o, loss, ws.grad2d, ps);
+                     tun.tiles_per_pop, t_rgb, t_depth, pmask, w_rgb, w_depth, loss_cap, o, loss, ws.grad2d, ps);
 }
 
 // Totals of the per-pixel work counters: counts[0] pairs, [1] entries the

@@ -196,6 +196,7 @@ class Renderer:
         if out:
             im.rgb, im.depth = _ptr(out.get("rgb")), _ptr(out.get("depth"))
             im.T_final, im.last = _ptr(out.get("T_final")), _ptr(out.get("last"))
+            im.loss = _ptr(out.get("loss"))
         return im
 
     @staticmethod
@@ -237,35 +238,47 @@ class Renderer:
         return grads
 
     def l1_loss_grad(self, rgb, depth, target_rgb, target_depth, pixel_mask=None, w_rgb=1.0, w_depth=0.1,
-                     g_rgb=None, g_depth=None, loss=None, stream=None):
+                     g_rgb=None, g_depth=None, loss=None, loss_cap=None, stream=None):
         g_rgb = g_rgb if g_rgb is not None else torch.empty_like(rgb)
         g_depth = g_depth if g_depth is not None else torch.empty_like(depth)
         loss = loss if loss is not None else torch.zeros(1, device=self.device)
         self._check(self.lib.gsr_l1_loss_grad(self.ctx, _ptr(rgb), _ptr(depth), _ptr(target_rgb),
                                               _ptr(target_depth), _ptr(pixel_mask), float(w_rgb), float(w_depth),
-                                              _ptr(g_rgb), _ptr(g_depth), _ptr(loss), _stream_ptr(stream)))
+                                              _ptr(loss_cap), _ptr(g_rgb), _ptr(g_depth), _ptr(loss),
+                                              _stream_ptr(stream)))
         return loss, g_rgb, g_depth
 
-    def _fused_args(self, g, cams, cfg, target_rgb, target_depth, pixel_mask, w_rgb, w_depth, out, grads, loss):
+    def loss_median(self, px_loss, pixel_mask=None, factor=10.0, cap_out=None, stream=None):
+        """Per view: factor x lower median of px_loss over the pixels with
+        pixel_mask != 0 (+inf for a view without such pixels)."""
+        cap_out = cap_out if cap_out is not None else torch.empty(self.n_views, device=self.device)
+        self._check(self.lib.gsr_loss_median(self.ctx, _ptr(px_loss), _ptr(pixel_mask), float(factor),
+                                             _ptr(cap_out), _stream_ptr(stream)))
+        return cap_out
+
+    def _fused_args(self, g, cams, cfg, target_rgb, target_depth, pixel_mask, w_rgb, w_depth, out, grads, loss,
+                    loss_cap=None):
         ws, wsb = self._ws()
         self._keep = (g.c(), cfg.to_c(), self._images_c(out), self._grads_c(grads))
         gc, cc, im, gr = self._keep
         return (self.ctx, ctypes.byref(gc), cams.data_ptr(), self.n_views, ctypes.byref(cc), _ptr(target_rgb),
-                _ptr(target_depth), _ptr(pixel_mask), float(w_rgb), float(w_depth), ws, wsb,
+                _ptr(target_depth), _ptr(pixel_mask), float(w_rgb), float(w_depth), _ptr(loss_cap), ws, wsb,
                 ctypes.byref(im) if out else None, ctypes.byref(gr), _ptr(loss))
 
     def render_l1_fused(self, g: Gaussians, cams, cfg: Config, target_rgb, target_depth, pixel_mask=None,
-                        w_rgb=1.0, w_depth=0.1, out=None, grads=None, loss=None, stream=None):
+                        w_rgb=1.0, w_depth=0.1, out=None, grads=None, loss=None, loss_cap=None, stream=None):
         grads = grads if grads is not None else self.new_grads(g.n)
         loss = loss if loss is not None else torch.zeros(1, device=self.device)
-        args = self._fused_args(g, cams, cfg, target_rgb, target_depth, pixel_mask, w_rgb, w_depth, out, grads, loss)
+        args = self._fused_args(g, cams, cfg, target_rgb, target_depth, pixel_mask, w_rgb, w_depth, out, grads, loss,
+                                loss_cap)
         self._check(self.lib.gsr_render_l1_fused(*args, _stream_ptr(stream)))
         return loss, grads
 
     def graph_capture(self, g, cams, cfg, target_rgb, target_depth, pixel_mask=None, w_rgb=1.0, w_depth=0.1,
-                      out=None, grads=None, loss=None, stream=None):
+                      out=None, grads=None, loss=None, loss_cap=None, stream=None):
         """Capture the fused step into a HIP graph (torch.cuda stream required)."""
-        args = self._fused_args(g, cams, cfg, target_rgb, target_depth, pixel_mask, w_rgb, w_depth, out, grads, loss)
+        args = self._fused_args(g, cams, cfg, target_rgb, target_depth, pixel_mask, w_rgb, w_depth, out, grads, loss,
+                                loss_cap)
         s = stream if stream is not None else torch.cuda.current_stream()
         if s.cuda_stream == 0:
             raise ValueError("graph capture needs a non-default stream")

@@ -5,10 +5,14 @@ one fused forward + L1 + pose-only backward call followed by an Adam step on
 the se(3) increment and a left update of the camera pose.
 
 The fine stage renders only the reliable Gaussians of Eq. 12, selected once
-with the coarse pose and the observed depth (gsr_select_reliable).  The pose
-is kept on the device: the Adam step, the SE(3) exponential and the packing
-of the camera struct are small torch operations, so an iteration never
-synchronises with the host.
+with the coarse pose and the observed depth (gsr_select_reliable).  Pixels
+whose loss exceeds `median_factor` times the median pixel loss are left out
+(implementation details of the paper); the median is the one of the previous
+iteration's pixel losses (gsr_loss_median after each fused step), since the
+fused step computes the loss and the backward in one pass; the first
+iteration of each stage uses no cap.  The pose is kept on the device: the
+Adam step, the SE(3) exponential and the packing of the camera struct are
+small torch operations, so an iteration never synchronises with the host.
 """
 from __future__ import annotations
 
@@ -58,6 +62,7 @@ class TrackingConfig:
     coarse_factor: int = 4         # 640x480 -> 160x120
     reliable_eps: float = 0.1      # Eq. 12: keep Gaussians with |D_obs - z| <= eps (metres)
     reliable_opacity: Optional[float] = None  # optional extra rule: sigmoid(opacity) above this
+    median_factor: Optional[float] = 10.0  # drop pixels above this x the median pixel loss (None: keep all)
 
 
 def downsample_targets(rgb: torch.Tensor, depth: torch.Tensor, width: int, height: int, k: int):
@@ -101,6 +106,9 @@ class Tracker:
         self.g_fine = dataclasses.replace(gaussians, mask=self.reliable)
         self.grads = {"d_pose": torch.zeros(1, 6, device=dev)}
         self.loss = torch.zeros(1, device=dev)
+        self.px_loss = {False: torch.zeros(cam_template.width * cam_template.height, device=dev),
+                        True: torch.zeros(self.coarse_cam.width * self.coarse_cam.height, device=dev)}
+        self.cap = torch.full((1,), float("inf"), device=dev)
 
     @staticmethod
     def _pack(template, T: torch.Tensor, out: torch.Tensor):
@@ -134,10 +142,17 @@ class Tracker:
                 # Eq. 12 with the coarse pose and the observed depth.
                 self.fine.select_reliable(self.g_sel, cams_f, target_depth, self.cam.width, self.cam.height,
                                           c.reliable_eps, self.rcfg.z_near, mask_out=self.reliable)
+            if it == 0 or it == c.coarse_iters:
+                self.cap.fill_(float("inf"))
             self.grads["d_pose"].zero_()
             self.loss.zero_()
+            pm = None if coarse else pixel_mask
+            px = self.px_loss[coarse]
             r.render_l1_fused(g, cams, self.rcfg, ct if coarse else target_rgb, cd if coarse else target_depth,
-                              None if coarse else pixel_mask, c.w_rgb, c.w_depth, grads=self.grads, loss=self.loss)
+                              pm, c.w_rgb, c.w_depth, out={"loss": px}, grads=self.grads, loss=self.loss,
+                              loss_cap=self.cap if c.median_factor is not None else None)
+            if c.median_factor is not None:
+                r.loss_median(px, pm, c.median_factor, cap_out=self.cap)
             if losses is not None:
                 losses.append(self.loss.clone())
             gpose = self.grads["d_pose"][0].to(torch.float64)

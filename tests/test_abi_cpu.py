@@ -39,7 +39,7 @@ def test_struct_layouts():
     assert ctypes.sizeof(A.gsr_camera) == 80
     assert ctypes.sizeof(A.gsr_gaussians) == 8 + 6 * 8
     assert ctypes.sizeof(A.gsr_config) == 44
-    assert ctypes.sizeof(A.gsr_images) == 32
+    assert ctypes.sizeof(A.gsr_images) == 40
     assert ctypes.sizeof(A.gsr_grads) == 48
     assert ctypes.sizeof(A.gsr_tuning) == 16
 

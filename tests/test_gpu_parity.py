@@ -279,7 +279,7 @@ def test_backward_matches_finite_differences(gsr_lib):
     assert H.rel_err(grads["pose"][0], pose) <= 1e-3, (grads["pose"][0], pose)
 
 
-def _fused_case(gsr, sc, cams, cfg, w_rgb=1.0, w_depth=0.1, seed=4):
+def _fused_case(gsr, sc, cams, cfg, w_rgb=1.0, w_depth=0.1, seed=4, cap_factor=None):
     sizes = [(c.width, c.height) for c in cams]
     ocfg = H.oracle_cfg_of(cfg)
     fwds = [O.render(sc, c, ocfg) for c in cams]
@@ -295,20 +295,46 @@ def _fused_case(gsr, sc, cams, cfg, w_rgb=1.0, w_depth=0.1, seed=4):
         amb |= np.abs(f["depth"].reshape(-1) - t_d[po:po + n]) < 1e-4
         mask[po:po + n][amb] = 0
         po += n
+    caps = None
+    if cap_factor is not None:
+        # One cap per view from the oracle's own pixel losses; pixels whose
+        # loss lies within float32 reach of the cap are masked on both sides.
+        caps, po = [], 0
+        for (w, h), f in zip(sizes, fwds):
+            n = w * h
+            lp = O.l1_pixel_loss(f["rgb"], f["depth"], t_rgb[3 * po:3 * po + 3 * n].reshape(3, h, w),
+                                 t_d[po:po + n].reshape(h, w), mask[po:po + n].reshape(h, w), w_rgb, w_depth)
+            cap = float(O.loss_cap(lp.astype(np.float32), mask[po:po + n], cap_factor))
+            caps.append(cap)
+            mask[po:po + n][np.abs(lp.reshape(-1) - cap) <= 1e-4 * cap] = 0
+            po += n
     r = gsr.Renderer()
     r.plan(sc.n, sizes)
     g = H.gpu_scene(gsr, sc)
     cams_d = gsr.pack_cameras(cams)
+    imgs = r.new_images()
+    imgs["loss"] = torch.empty(sum(w * h for w, h in sizes), device="cuda")
     loss, grads = r.render_l1_fused(g, cams_d, cfg, H.to_dev(t_rgb), H.to_dev(t_d), H.to_dev(mask, torch.uint8),
-                                    w_rgb=w_rgb, w_depth=w_depth, out=r.new_images())
+                                    w_rgb=w_rgb, w_depth=w_depth, out=imgs,
+                                    loss_cap=None if caps is None else H.to_dev(np.array(caps, np.float32)))
     r.check_overflow()
+    px_loss = imgs["loss"].cpu().numpy()
+    po = 0
+    for v, f in enumerate(fwds):
+        w, h = sizes[v]
+        n = w * h
+        lp = O.l1_pixel_loss(f["rgb"], f["depth"], t_rgb[3 * po:3 * po + 3 * n].reshape(3, h, w),
+                             t_d[po:po + n].reshape(h, w), mask[po:po + n].reshape(h, w), w_rgb, w_depth)
+        np.testing.assert_allclose(px_loss[po:po + n], lp.reshape(-1), rtol=1e-4, atol=1e-5)
+        po += n
     ref_loss, ref = 0.0, None
     po = 0
     for v, (c, f) in enumerate(zip(cams, fwds)):
         w, h = sizes[v]
         n = w * h
         l, gC, gD = O.l1_loss(f["rgb"], f["depth"], t_rgb[3 * po:3 * po + 3 * n].reshape(3, h, w),
-                              t_d[po:po + n].reshape(h, w), mask[po:po + n].reshape(h, w), w_rgb, w_depth)
+                              t_d[po:po + n].reshape(h, w), mask[po:po + n].reshape(h, w), w_rgb, w_depth,
+                              loss_cap=None if caps is None else caps[v])
         ref_loss += l
         b = O.render_backward(sc, c, ocfg, gC, gD, None, fwd=f)
         b["pose"] = b["pose"][None]
@@ -333,6 +359,43 @@ def test_fused_l1_step_matches_oracle(gsr_lib):
     H.assert_grads_close(got, ref)
     for v in range(2):
         assert H.rel_err(got["pose"][v], ref["pose"][v]) <= 1e-3
+
+
+def test_fused_l1_step_with_loss_cap_matches_oracle(gsr_lib):
+    """Outlier rejection: with a per-view cap at 1.5x the median pixel loss
+    about a quarter of the pixels leave the loss and the backward."""
+    gsr = gsr_lib
+    _print_case(test="fused-cap")
+    sc = W.random_scene(2000, seed=0)
+    cams = [W.camera_small(), W.perturb_pose(W.camera_small().with_size(90.0, 90.0, 44.5, 30.0, 90, 61),
+                                             [0.03, 0.0, -0.02, 0.01, -0.02, 0.0])]
+    r, loss, ref_loss, got, ref = _fused_case(gsr, sc, cams, gsr.Config(), w_rgb=0.8, w_depth=0.3,
+                                              cap_factor=1.5)
+    assert abs(loss - ref_loss) <= 1e-4 * abs(ref_loss), (loss, ref_loss)
+    H.assert_grads_close(got, ref)
+    for v in range(2):
+        assert H.rel_err(got["pose"][v], ref["pose"][v]) <= 1e-3
+
+
+def test_loss_median_matches_oracle(gsr_lib):
+    """Exact per-view lower median (radix select) on synthetic loss images:
+    ties, zeros, -0 and negatives, +inf and NaN, masks, a single pixel and a
+    view without eligible pixels."""
+    gsr = gsr_lib
+    sizes = [(37, 23), (160, 120), (1, 1), (16, 16), (64, 48), (640, 480), (33, 17)]
+    px, mask = W.loss_images(sizes, seed=3)
+    r = gsr.Renderer()
+    r.plan(1, sizes)
+    for use_mask in (False, True):
+        for factor in (10.0, 1.0):
+            caps = r.loss_median(H.to_dev(px), H.to_dev(mask, torch.uint8) if use_mask else None, factor).cpu()
+            po = 0
+            for v, (w, h) in enumerate(sizes):
+                n = w * h
+                want = O.loss_cap(px[po:po + n], mask[po:po + n] if use_mask else None, factor)
+                got = np.float32(caps[v].item())
+                assert (np.isnan(want) and np.isnan(got)) or got == want, (v, use_mask, factor, got, want)
+                po += n
 
 
 def test_l1_loss_grad_exact_signs(gsr_lib):

@@ -408,3 +408,70 @@ def test_reliable_selection_cases():
     sc2 = _scene([((0.0, 0.0, 2.0 + 0.0625), (-3, -3, -3), (1, 0, 0, 0), 0.0, (0.5, 0.5, 0.5))])
     assert list(O.select_reliable(sc2, cam, depth, eps=0.0625)) == [1]
     assert list(O.select_reliable(sc2, cam, depth, eps=0.0624)) == [0]
+
+
+# ----------------------------------------------------------------- loss cap
+
+def _rank_element(vals, k):
+    """Brute force: the value x with #(v < x) <= k < #(v <= x) under the
+    order of non-negative floats (negatives and -0 as 0, NaN last)."""
+    def key(x):
+        return (1, 0.0) if math.isnan(x) else (0, max(x, 0.0))
+    for x in vals:
+        below = sum(key(v) < key(x) for v in vals)
+        upto = sum(key(v) <= key(x) for v in vals)
+        if below <= k < upto:
+            return key(x)
+    raise AssertionError("no element of rank k")
+
+
+def test_loss_median_is_the_lower_median_by_brute_force():
+    rng = np.random.default_rng(4)
+    for trial in range(60):
+        m = int(rng.integers(1, 12))
+        v = rng.choice([0.0, -0.0, 0.25, 0.5, 1.0, 3.0, -2.0, np.inf, np.nan], size=m) if trial % 2 else \
+            rng.random(m).astype(np.float32)
+        v = np.asarray(v, np.float32)
+        got = O.loss_median(v)
+        want = _rank_element(v.tolist(), (m - 1) // 2)
+        if want[0] == 1:
+            assert np.isnan(got)
+        else:
+            assert float(got) == want[1], (v, got, want)
+    # odd counts of distinct positive values: numpy's median
+    v = np.random.default_rng(5).random(101).astype(np.float32)
+    assert O.loss_median(v) == np.float32(np.median(v))
+    # even count: the lower of the two middle values
+    assert O.loss_median(np.array([4.0, 1.0, 3.0, 2.0], np.float32)) == np.float32(2.0)
+    # mask, and no eligible pixel
+    mask = np.array([0, 1, 1, 0], np.uint8)
+    assert O.loss_median(np.array([9.0, 1.0, 5.0, 0.0], np.float32), mask) == np.float32(1.0)
+    assert O.loss_median(np.zeros(3, np.float32), np.zeros(3, np.uint8)) is None
+    assert O.loss_cap(np.zeros(3, np.float32), np.zeros(3, np.uint8)) == np.inf
+    assert O.loss_cap(np.array([1.5, 0.5, 2.5], np.float32), None, 10.0) == np.float32(15.0)
+
+
+def test_l1_loss_cap_drops_pixels_above_it():
+    rng = np.random.default_rng(6)
+    H, Wd = 5, 7
+    rgb, trgb = rng.random((3, H, Wd)), rng.random((3, H, Wd))
+    dep, tdep = rng.random((H, Wd)) + 1, rng.random((H, Wd)) + 1
+    tdep[0, :3] = 0.0
+    w_rgb, w_d = 0.8, 0.3
+    # each pixel's own term, written out pixel by pixel
+    lp = np.zeros((H, Wd))
+    for y in range(H):
+        for x in range(Wd):
+            lp[y, x] = w_rgb * sum(abs(rgb[c, y, x] - trgb[c, y, x]) for c in range(3))
+            if tdep[y, x] > 0:
+                lp[y, x] += w_d * abs(dep[y, x] - tdep[y, x])
+    np.testing.assert_allclose(O.l1_pixel_loss(rgb, dep, trgb, tdep, None, w_rgb, w_d), lp, rtol=1e-14)
+    cap = float(np.median(lp))
+    L, gC, gD = O.l1_loss(rgb, dep, trgb, tdep, None, w_rgb, w_d, loss_cap=cap)
+    keep = lp <= cap
+    assert abs(L - lp[keep].sum()) <= 1e-12 * lp.sum()
+    assert not gC[:, ~keep].any() and not gD[~keep].any()
+    L0, gC0, gD0 = O.l1_loss(rgb, dep, trgb, tdep, None, w_rgb, w_d)
+    np.testing.assert_array_equal(gC[:, keep], gC0[:, keep])
+    Linf, _, _ = O.l1_loss(rgb, dep, trgb, tdep, None, w_rgb, w_d, loss_cap=np.inf)
+    assert Linf == L0

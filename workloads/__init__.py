@@ -26,5 +26,6 @@ from .scenes import (  # noqa: F401
     hypothesis_views,
     upstream_grads,
     random_targets,
+    loss_images,
     subset,
 )

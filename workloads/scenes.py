@@ -366,6 +366,39 @@ def random_targets(sizes, seed=1, depth_range=(0.5, 4.0), invalid_fraction=0.1):
     return rgb, depth, mask
 
 
+def loss_images(sizes, seed=3):
+    """Per-pixel loss images (float32 [sum HW], view after view) and a pixel
+    mask for the loss-median selection, one flavour per view in turn:
+    exponential values (long upper tail), values rounded to quarters (ties),
+    many zeros with some -0 and negative values, values with +inf and NaN
+    sprinkled in.  The mask keeps ~70% of the pixels, except that views
+    2, 7, 12, ... have none."""
+    rng = np.random.default_rng(seed)
+    vals, masks = [], []
+    for v, (w, h) in enumerate(sizes):
+        n = int(w) * int(h)
+        kind = v % 4
+        if kind == 0:
+            x = rng.exponential(0.3, n)
+        elif kind == 1:
+            x = np.round(rng.exponential(1.0, n) * 4.0) / 4.0
+        elif kind == 2:
+            x = rng.exponential(0.5, n) * (rng.random(n) < 0.4)
+            x[rng.random(n) < 0.05] = -0.0
+            neg = rng.random(n) < 0.05
+            x[neg] = -rng.uniform(0.1, 2.0, size=int(neg.sum()))
+        else:
+            x = rng.exponential(2.0, n)
+            x[rng.random(n) < 0.02] = np.inf
+            x[rng.random(n) < 0.02] = np.nan
+        m = (rng.random(n) < 0.7).astype(np.uint8)
+        if v % 5 == 2:
+            m[:] = 0
+        vals.append(x.astype(F32))
+        masks.append(m)
+    return np.concatenate(vals), np.concatenate(masks)
+
+
 def noisy_targets(rgb, depth, seed=1, sigma=0.05, min_alpha=None, alpha=None):
     """Targets made from rendered images: C* = C + N(0, sigma^2) and
     D* = D (1 + N(0, sigma^2)); depth is set to 0 where `alpha` < `min_alpha`."""
