@@ -117,6 +117,9 @@ RenderConsts consts(const gsr_config &c) {
   rc.bg[0] = c.bg[0];
   rc.bg[1] = c.bg[1];
   rc.bg[2] = c.bg[2];
+  // Opacity and colour gradients (fields 5-8) feed only the Gaussian
+  // parameters; a pose-only backward skips them.
+  rc.grad_fields = (c.flags & GSR_GAUSS_GRAD) ? 0x3FFu : 0x3FFu & ~0x1E0u;
   return rc;
 }
 

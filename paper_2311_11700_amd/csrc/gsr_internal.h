@@ -101,6 +101,7 @@ struct Tuning {
 struct RenderConsts {
   float alpha_min, alpha_max, T_min;
   float bg[3];
+  uint32_t grad_fields;  // bit f set: the backward accumulates grad2d field f
 };
 
 // ---------------------------------------------------------------- device helpers

@@ -18,7 +18,7 @@
 
 namespace gsr {
 
-constexpr int BATCH = 256;
+constexpr int BATCH = 192;  // staged records per round (<= BLOCK)
 constexpr float NEG_HALF_LOG2E = -0.72134752044448170368f;  // -log2(e) / 2
 constexpr float LN2 = 0.69314718055994530942f;
 
@@ -118,7 +118,7 @@ __device__ __forceinline__ void tile_forward(const TileInfo &ti, int64_t n, cons
   for (int base = ti.range.x; base < ti.range.y; base += BATCH) {
     if (__syncthreads_and(st.done)) break;
     const int pos = base + threadIdx.x;
-    if (pos < ti.range.y)
+    if ((int)threadIdx.x < BATCH && pos < ti.range.y)
       s_rec[threadIdx.x] = stage_record(ids[pos], ti.view, n, ti.x0, ti.y0, recA, recB, recZ, rgb);
     __syncthreads();
     // Branch-free walk: every lane evaluates every entry and keeps or drops
@@ -160,51 +160,26 @@ __device__ __forceinline__ void tile_forward(const TileInfo &ti, int64_t n, cons
 }
 
 // ----------------------------------------------------------------- backward
+//
+// Per list entry the backward needs, summed over the 256 pixels of the tile,
+//   S1 = sum dLdP, Sx = sum dLdP dx, Sy = sum dLdP dy,
+//   Sxx = sum dLdP dx^2, Sxy = sum dLdP dx dy, Syy = sum dLdP dy^2,
+//   Sc = sum w gC_c (c = r, g, b), Sd = sum w gD,
+// with dx = u - x, dy = v - y.  Expanding dx, dy about the tile centre turns
+// all of them into moments of two per-pixel values (dLdP and w) against
+// per-pixel constants: the matrix [dLdP; w] (entries x pixels) times the
+// matrix [1, xc, yc, xc^2, xc yc, yc^2, gC_r, gC_g, gC_b, gD] (pixels x 10),
+// a dense contraction over the pixels.  Each wavefront collects dLdP and w of
+// 8 entries (16 rows) for its 64 pixels in LDS and contracts them on the
+// matrix cores (v_mfma_f32_16x16x4_f32, K = 64 pixels in 16 steps); the four
+// wavefronts add their 16x16 products into the block's per-entry sums.
 
-// Cross-lane folds of gfx950: v_permlane32_swap exchanges the upper half of
-// one register with the lower half of another, v_permlane16_swap does the
-// same for the 16-lane quarters of each half.  Adding the swapped pair
-// reduces two values at once (a reduce-scatter step).
-__device__ __forceinline__ float fold32(float a, float b) {
-  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
-  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
-}
+constexpr int MA_ROWS = 16;               // 8 entries x (dLdP, w)
+constexpr int MA_STRIDE = 64 + 4;         // floats per row (padding spreads LDS banks)
+constexpr int MA_WAVE = MA_ROWS * MA_STRIDE;
+constexpr int NMOM = 10;                  // per-entry sums kept in LDS
 
-__device__ __forceinline__ float fold16(float a, float b) {
-  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
-  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
-}
-
-// Sum over the 16 lanes of each DPP row (rotations fold into v_add_f32_dpp);
-// every lane of the row ends with the row total.
-__device__ __forceinline__ float row_sum16(float x) {
-  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x128, 0xf, 0xf, false));  // row_ror:8
-  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x124, 0xf, 0xf, false));  // row_ror:4
-  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x122, 0xf, 0xf, false));  // row_ror:2
-  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x121, 0xf, 0xf, false));  // row_ror:1
-  return x;
-}
-
-// Sum the ten gradient fields g[0..9] over the 64 lanes of the wavefront and
-// add the totals to dst[0..9] in LDS (lanes 0, 16, 32, 48 each add two or
-// three of them).  All 64 lanes must be active.  After the two folds the
-// 16-lane rows of u0 hold fields (0, 2, 1, 3), of u1 (4, 6, 5, 7) and of u2
-// (8, 8, 9, 9).
-__device__ __forceinline__ void wave_reduce_add10(const float g[NGRAD2D], float *dst) {
-  const float w0 = fold32(g[0], g[1]), w1 = fold32(g[2], g[3]), w2 = fold32(g[4], g[5]);
-  const float w3 = fold32(g[6], g[7]), w4 = fold32(g[8], g[9]);
-  const float u0 = row_sum16(fold16(w0, w1));
-  const float u1 = row_sum16(fold16(w2, w3));
-  const float u2 = row_sum16(fold16(w4, w4));
-  const int lane = __lane_id();
-  if ((lane & 15) == 0) {
-    const int row = lane >> 4;
-    const int f = ((row & 1) << 1) | (row >> 1);
-    atomicAdd(dst + f, u0);
-    atomicAdd(dst + 4 + f, u1);
-    if ((row & 1) == 0) atomicAdd(dst + 8 + (row >> 1), u2);
-  }
-}
+typedef float float4v __attribute__((ext_vector_type(4)));
 
 struct BwdIn {
   float T;         // final transmittance
@@ -212,27 +187,110 @@ struct BwdIn {
   float gC0, gC1, gC2, gD, gT;
 };
 
-// Walk the tile's list back to front.  Per-Gaussian gradients are reduced
-// over the block (wavefront butterflies, then LDS) and added to grad2d with
-// one FP64 atomic per field: a Gaussian that covers many tiles sums partials
-// of both signs, and the FP64 sum keeps the result independent of the order
-// the tiles finish in.  grad2d fields: (u, v, conic a, b, c, opacity,
-// r, g, b, depth).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Contract the wave's collected rows (nq entries, rows 2q = dLdP, 2q+1 = w)
+// with the per-pixel constants Bm and add the useful products to the
+// block's per-entry sums s_sum[entry][NMOM].  Operand layout of
+// v_mfma_f32_16x16x4_f32: lane l supplies A[l % 16][k] and B[k][l % 16] for
+// k = l / 16; D[i][l % 16] lands in register i % 4 of lane 16 (i / 4) + l % 16.
+// The 16 steps map K index k of step s to pixel 16 k + s.
+__device__ __forceinline__ void mfma_group(const float *mA, const float Bm[16], int nq, uint64_t slots,
+                                           float *s_sum) {
+  const int lane = __lane_id();
+  const int r = lane & 15, g = lane >> 4;
+  wave_lds_sync();
+  const float4 *src = reinterpret_cast<const float4 *>(mA + r * MA_STRIDE + 16 * g);
+  const float4 a0 = src[0], a1 = src[1], a2 = src[2], a3 = src[3];
+  float4v D = {0.f, 0.f, 0.f, 0.f};
+  D = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.x, Bm[0], D, 0, 0, 0);
+  D = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.y, Bm[1], D, 0, 0, 0);
+  D = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.z, Bm[2], D, 0, 0, 0);
+  D = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.w, Bm[3], D, 0, 0, 0);
+  D = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.x, Bm[4], D, 0, 0, 0);
+  D = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.y, Bm[5], D, 0, 0, 0);
+  D = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.z, Bm[6], D, 0, 0, 0);
+  D = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.w, Bm[7], D, 0, 0, 0);
+  D = __builtin_amdgcn_mfma_f32_16x16x4f32(a2.x, Bm[8], D, 0, 0, 0);
+  D = __builtin_amdgcn_mfma_f32_16x16x4f32(a2.y, Bm[9], D, 0, 0, 0);
+  D = __builtin_amdgcn_mfma_f32_16x16x4f32(a2.z, Bm[10], D, 0, 0, 0);
+  D = __builtin_amdgcn_mfma_f32_16x16x4f32(a2.w, Bm[11], D, 0, 0, 0);
+  D = __builtin_amdgcn_mfma_f32_16x16x4f32(a3.x, Bm[12], D, 0, 0, 0);
+  D = __builtin_amdgcn_mfma_f32_16x16x4f32(a3.y, Bm[13], D, 0, 0, 0);
+  D = __builtin_amdgcn_mfma_f32_16x16x4f32(a3.z, Bm[14], D, 0, 0, 0);
+  D = __builtin_amdgcn_mfma_f32_16x16x4f32(a3.w, Bm[15], D, 0, 0, 0);
+  // Lane (g, col) holds rows 4g..4g+3: entry 2g (dLdP row, w row) and entry
+  // 2g+1.  Columns 0-5 are taken from the dLdP rows, 6-9 from the w rows.
+  const int col = lane & 15;
+  if (col < NMOM) {
+    const bool mom = col < 6;
+    const int q0 = 2 * g, q1 = 2 * g + 1;
+    if (q0 < nq) atomicAdd(s_sum + (int)((slots >> (8 * q0)) & 255u) * NMOM + col, mom ? D[0] : D[1]);
+    if (q1 < nq) atomicAdd(s_sum + (int)((slots >> (8 * q1)) & 255u) * NMOM + col, mom ? D[2] : D[3]);
+  }
+  wave_lds_sync();
+}
+
+// Walk the tile's list back to front; per entry, dLdP and w of every pixel
+// go through the contraction above, and the flush turns the per-entry sums
+// into the 2D gradients, added to grad2d with one FP64 atomic per field (a
+// Gaussian that covers many tiles sums partials of both signs; the FP64 sum
+// keeps the result independent of the order the tiles finish in).  grad2d
+// fields: (u, v, conic a, b, c, opacity, r, g, b, depth).
 __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, const float4 *__restrict__ recA,
                                               const float4 *__restrict__ recB,
                                               const float *__restrict__ recZ,
                                               const float *__restrict__ rgb,
                                               const uint32_t *__restrict__ ids, const RenderConsts &rc,
                                               const BwdIn &in, double *__restrict__ grad2d,
-                                              Staged *s_rec, float *s_grad, uint32_t *s_id, int *s_max) {
+                                              Staged *s_rec, float *s_grad, uint32_t *s_id, int *s_max,
+                                              float *s_mA) {
   const float lx = (float)(threadIdx.x & (TILE - 1));
   const float ly = (float)(threadIdx.x >> 4);
+  const int lane = __lane_id();
+  const int wv = threadIdx.x >> 6;
+  float *mA = s_mA + wv * MA_WAVE;
   if (threadIdx.x == 0) *s_max = 0;
-  for (int k = threadIdx.x; k < BATCH * NGRAD2D; k += BLOCK) s_grad[k] = 0.f;
+  for (int k = threadIdx.x; k < BATCH * NMOM; k += BLOCK) s_grad[k] = 0.f;
   __syncthreads();
   if (in.last > 0) atomicMax(s_max, in.last);
   __syncthreads();
   const int maxlast = *s_max;
+  if (maxlast == 0) return;
+
+  // Per-pixel constants of the contraction, in the B-operand layout: step s
+  // of lane (g, col) holds column col of pixel 16 g + s of this wavefront
+  // (tile pixel x = s, y = 4 wv + g), coordinates relative to the tile centre.
+  // The upstream gradients reach those lanes through the wave's LDS rows.
+  float Bm[16];
+  {
+    mA[0 * MA_STRIDE + lane] = in.gC0;
+    mA[1 * MA_STRIDE + lane] = in.gC1;
+    mA[2 * MA_STRIDE + lane] = in.gC2;
+    mA[3 * MA_STRIDE + lane] = in.gD;
+    wave_lds_sync();
+    const int col = lane & 15, g = lane >> 4;
+    const bool up = col >= 6 && col < NMOM;
+    const float4 *src = reinterpret_cast<const float4 *>(mA + (up ? col - 6 : 0) * MA_STRIDE + 16 * g);
+    const float4 q0 = src[0], q1 = src[1], q2 = src[2], q3 = src[3];
+    const float gv[16] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w,
+                          q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w};
+    // Moment columns as c0 + c1 xc + c2 xc^2.
+    const float yc = (float)(4 * wv + g) - 7.5f;
+    const float c0 = col == 0 ? 1.f : (col == 2 ? yc : (col == 5 ? yc * yc : 0.f));
+    const float c1 = col == 1 ? 1.f : (col == 4 ? yc : 0.f);
+    const float c2 = col == 3 ? 1.f : 0.f;
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const float xc = (float)s - 7.5f;
+      Bm[s] = up ? gv[s] : __fmaf_rn(__fmaf_rn(c2, xc, c1), xc, c0);
+    }
+    wave_lds_sync();
+  }
 
   float T = in.T;
   const float Tf = in.T;
@@ -251,8 +309,10 @@ __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, con
   float Kf = -in.gT * Tf;  // (gD zr - gT) T_f
   bool have_zr = false;
 
-  for (int hi = maxlast; hi > 0; hi -= BATCH) {
-    const int lo = hi > BATCH ? hi - BATCH : 0;
+  // Batches aligned with the forward's: [b BATCH, (b + 1) BATCH), walked
+  // from the last one that holds an entry below maxlast.
+  for (int lo = ((maxlast - 1) / BATCH) * BATCH; lo >= 0; lo -= BATCH) {
+    const int hi = min(lo + BATCH, maxlast);
     const int cnt = hi - lo;
     if ((int)threadIdx.x < cnt) {
       const uint32_t id = ids[ti.range.x + lo + threadIdx.x];
@@ -260,81 +320,96 @@ __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, con
       s_rec[threadIdx.x] = stage_record(id, ti.view, n, ti.x0, ti.y0, recA, recB, recZ, rgb);
     }
     __syncthreads();
-    for (int k = hi - 1; k >= lo; --k) {
+    int nq = 0;
+    uint64_t slots = 0;
+    // One step past the batch (k = lo - 1) contracts the last partial group.
+    for (int k = hi - 1; k >= lo - 1; --k) {
       const int j = k - lo;
-      const float4 geo = s_rec[j].geo;
-      const float4 con = s_rec[j].con;
-      const float dx = geo.x - lx, dy = geo.y - ly;
-      float G, oG;
-      const float alpha = splat_alpha(geo, con, dx, dy, rc.alpha_max, G, oG);
-      const bool has = k < in.last && alpha >= rc.alpha_min;
-      // Wave-uniform guard; inside it every lane computes and the lanes
-      // without a contribution are masked with selects (NaN-safe).
-      if (__any(has)) {
-        const float4 col = s_rec[j].col;
-        const float rinv = __builtin_amdgcn_rcpf(1.f - alpha);
-        const float Tk = T * rinv;  // transmittance in front of this Gaussian
-        T = has ? Tk : T;
-        const float w = has ? alpha * Tk : 0.f;
-        const bool first = has && !have_zr;
-        zr = first ? geo.w : zr;
-        Kf = first ? (in.gD * geo.w - in.gT) * Tf : Kf;
-        have_zr = have_zr || has;
-        const float Q = __fmaf_rn(in.gD, geo.w - zr, __fmaf_rn(in.gC2, col.z, __fmaf_rn(in.gC1, col.y, in.gC0 * col.x)));
-        const float QS = Q - S;
-        const float dLda = __fmaf_rn(Tk, QS, Kf * rinv);
-        S = has ? __fmaf_rn(alpha, QS, S) : S;
-        const bool open = has && oG <= rc.alpha_max;
-        // dL/dP with G = 2^P (the ln 2 and the conic pre-scale are applied
-        // at the flush); dL/d(opacity) = dLdP / o there.
-        const float dLdP = open ? dLda * oG : 0.f;
-        const float sx = dLdP * dx, sy = dLdP * dy;
-        float g[NGRAD2D];
-        g[0] = sx;
-        g[1] = sy;
-        g[2] = sx * dx;
-        g[3] = sx * dy;
-        g[4] = sy * dy;
-        g[5] = dLdP;
-        g[6] = in.gC0 * w;
-        g[7] = in.gC1 * w;
-        g[8] = in.gC2 * w;
-        g[9] = in.gD * w;
-        wave_reduce_add10(g, s_grad + j * NGRAD2D);
+      if (k >= lo) {
+        const float4 geo = s_rec[j].geo;
+        const float4 con = s_rec[j].con;
+        const float dx = geo.x - lx, dy = geo.y - ly;
+        float G, oG;
+        const float alpha = splat_alpha(geo, con, dx, dy, rc.alpha_max, G, oG);
+        const bool has = k < in.last && alpha >= rc.alpha_min;
+        // Wave-uniform guard; inside it every lane computes and the lanes
+        // without a contribution are masked with selects (NaN-safe).
+        if (__any(has)) {
+          const float4 col = s_rec[j].col;
+          const float rinv = __builtin_amdgcn_rcpf(1.f - alpha);
+          const float Tk = T * rinv;  // transmittance in front of this Gaussian
+          T = has ? Tk : T;
+          const float w = has ? alpha * Tk : 0.f;
+          const bool first = has && !have_zr;
+          zr = first ? geo.w : zr;
+          Kf = first ? (in.gD * geo.w - in.gT) * Tf : Kf;
+          have_zr = have_zr || has;
+          const float Q = __fmaf_rn(in.gD, geo.w - zr, __fmaf_rn(in.gC2, col.z, __fmaf_rn(in.gC1, col.y, in.gC0 * col.x)));
+          const float QS = Q - S;
+          const float dLda = __fmaf_rn(Tk, QS, Kf * rinv);
+          S = has ? __fmaf_rn(alpha, QS, S) : S;
+          const bool open = has && oG <= rc.alpha_max;
+          // dL/dP with G = 2^P (the ln 2 and the conic pre-scale are applied
+          // at the flush); dL/d(opacity) = dLdP / o there.
+          const float dLdP = open ? dLda * oG : 0.f;
+          mA[(2 * nq) * MA_STRIDE + lane] = dLdP;
+          mA[(2 * nq + 1) * MA_STRIDE + lane] = w;
+          slots |= (uint64_t)j << (8 * nq);
+          ++nq;
+        }
+      }
+      if (nq == 8 || (k < lo && nq > 0)) {
+        mfma_group(mA, Bm, nq, slots, s_grad);
+        nq = 0;
+        slots = 0;
       }
     }
     __syncthreads();
-    // Flush: one thread per Gaussian of the batch.  Block sums of
-    // (dLdP dx, dLdP dy, dLdP dx^2, dLdP dx dy, dLdP dy^2, dLdP) become the
-    // gradients of the centre, the conic and the opacity here:
-    //   dL/du = 2 ln2 (a'' Sx + b'' Sy), dL/dv = 2 ln2 (b'' Sx + c'' Sy)
+    // Flush.  First one thread per Gaussian of the batch converts its sums:
+    // with the centre relative to the tile centre (uc, vc) and the pixel
+    // moments M about it,
+    //   Sx = uc M1 - Mx, Sy = vc M1 - My, Sxx = uc^2 M1 - 2 uc Mx + Mxx,
+    //   Sxy = uc vc M1 - uc My - vc Mx + Mxy, Syy = vc^2 M1 - 2 vc My + Myy;
+    // then dL/du = 2 ln2 (a'' Sx + b'' Sy), dL/dv = 2 ln2 (b'' Sx + c'' Sy)
     // with the pre-scaled conic (a'', b'', c'') = -log2(e)/2 (a, b, c), and
-    //   dL/da = -Sxx/2, dL/db = -Sxy, dL/dc = -Syy/2, dL/do = S1 / o.
+    //   dL/da = -Sxx/2, dL/db = -Sxy, dL/dc = -Syy/2, dL/do = M1 / o.
+    // Then the block adds them to grad2d field-parallel: consecutive lanes
+    // take consecutive fields of one Gaussian, so each atomic instruction
+    // touches a few contiguous 80-byte rows.
+    double *s_out = reinterpret_cast<double *>(s_mA);  // [BATCH][NGRAD2D], free during the flush
     if ((int)threadIdx.x < cnt) {
-      float *src = s_grad + threadIdx.x * NGRAD2D;
-      float v[NGRAD2D];
-      bool nz = false;
+      float *src = s_grad + threadIdx.x * NMOM;
+      double m[NMOM];
 #pragma unroll
-      for (int f = 0; f < NGRAD2D; ++f) {
-        v[f] = src[f];
+      for (int f = 0; f < NMOM; ++f) {
+        m[f] = (double)src[f];
         src[f] = 0.f;
-        nz = nz || v[f] != 0.f;
       }
-      if (nz) {
-        const float4 con = s_rec[threadIdx.x].con;
-        const double o = (double)s_rec[threadIdx.x].geo.z;
-        double *dst = grad2d + (size_t)s_id[threadIdx.x] * NGRAD2D;
-        atomicAdd(dst + 0, 2.0 * (double)LN2 * ((double)con.x * v[0] + (double)con.y * v[1]));
-        atomicAdd(dst + 1, 2.0 * (double)LN2 * ((double)con.y * v[0] + (double)con.z * v[1]));
-        atomicAdd(dst + 2, -0.5 * (double)v[2]);
-        atomicAdd(dst + 3, -(double)v[3]);
-        atomicAdd(dst + 4, -0.5 * (double)v[4]);
-        atomicAdd(dst + 5, (double)v[5] / o);
-        atomicAdd(dst + 6, (double)v[6]);
-        atomicAdd(dst + 7, (double)v[7]);
-        atomicAdd(dst + 8, (double)v[8]);
-        atomicAdd(dst + 9, (double)v[9]);
-      }
+      const Staged &sr = s_rec[threadIdx.x];
+      const double uc = (double)sr.geo.x - 7.5, vc = (double)sr.geo.y - 7.5;
+      const double M1 = m[0], Mx = m[1], My = m[2], Mxx = m[3], Mxy = m[4], Myy = m[5];
+      const double Sx = uc * M1 - Mx, Sy = vc * M1 - My;
+      const double Sxx = (uc * uc * M1 - 2.0 * uc * Mx) + Mxx;
+      const double Sxy = ((uc * vc * M1 - uc * My) - vc * Mx) + Mxy;
+      const double Syy = (vc * vc * M1 - 2.0 * vc * My) + Myy;
+      const double a2 = (double)sr.con.x, b2 = (double)sr.con.y, c2 = (double)sr.con.z;
+      double *o = s_out + threadIdx.x * NGRAD2D;
+      o[0] = 2.0 * (double)LN2 * (a2 * Sx + b2 * Sy);
+      o[1] = 2.0 * (double)LN2 * (b2 * Sx + c2 * Sy);
+      o[2] = -0.5 * Sxx;
+      o[3] = -Sxy;
+      o[4] = -0.5 * Syy;
+      o[5] = M1 / (double)sr.geo.z;
+      o[6] = m[6];
+      o[7] = m[7];
+      o[8] = m[8];
+      o[9] = m[9];
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < cnt * NGRAD2D; t += BLOCK) {
+      const int e = t / NGRAD2D, f = t - e * NGRAD2D;
+      const double v = s_out[t];
+      if (v != 0.0 && ((rc.grad_fields >> f) & 1u)) atomicAdd(grad2d + (size_t)s_id[e] * NGRAD2D + f, v);
     }
     __syncthreads();
   }
@@ -386,16 +461,17 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, PixelState p
   if (out.last) out.last[ti.pix] = st.last;
 }
 
-__global__ __launch_bounds__(BLOCK) void k_render_bwd(RasterArgs a, const float *__restrict__ T_ws,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_render_bwd(RasterArgs a, const float *__restrict__ T_ws,
                                                       const int32_t *__restrict__ last_ws,
                                                       const float *__restrict__ g_rgb,
                                                       const float *__restrict__ g_depth,
                                                       const float *__restrict__ g_T,
                                                       double *__restrict__ grad2d) {
   __shared__ Staged s_rec[BATCH];
-  __shared__ float s_grad[BATCH * NGRAD2D];
+  __shared__ float s_grad[BATCH * NMOM];
   __shared__ uint32_t s_id[BATCH];
   __shared__ int s_max;
+  __shared__ __align__(16) float s_mA[4 * MA_WAVE];
   const TileInfo ti = tile_info(blockIdx.x, a.views, a.tile_view, a.ranges);
   BwdIn in{1.f, 0, 0.f, 0.f, 0.f, 0.f, 0.f};
   if (ti.inside) {
@@ -409,7 +485,8 @@ __global__ __launch_bounds__(BLOCK) void k_render_bwd(RasterArgs a, const float 
     in.gD = g_depth ? g_depth[ti.pix] : 0.f;
     in.gT = g_T ? g_T[ti.pix] : 0.f;
   }
-  tile_backward(ti, a.n, a.recA, a.recB, a.recZ, a.rgb, a.ids, a.rc, in, grad2d, s_rec, s_grad, s_id, &s_max);
+  tile_backward(ti, a.n, a.recA, a.recB, a.recZ, a.rgb, a.ids, a.rc, in, grad2d, s_rec, s_grad, s_id, &s_max,
+                s_mA);
 }
 
 __device__ __forceinline__ float sgnf(float x) { return (float)((x > 0.f) - (x < 0.f)); }
@@ -417,7 +494,7 @@ __device__ __forceinline__ float sgnf(float x) { return (float)((x > 0.f) - (x <
 // Persistent fused step: pop tiles from the work queue; per tile run the
 // forward blend, the L1 loss gradient of every pixel, and the backward walk
 // without leaving the block (per-pixel state stays in registers).
-__global__ __launch_bounds__(BLOCK) void k_render_fused(RasterArgs a, uint32_t *__restrict__ hdr,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_render_fused(RasterArgs a, uint32_t *__restrict__ hdr,
                                                         const uint32_t *__restrict__ queue, int total_tiles,
                                                         int tiles_per_pop, const float *__restrict__ t_rgb,
                                                         const float *__restrict__ t_depth,
@@ -426,9 +503,10 @@ __global__ __launch_bounds__(BLOCK) void k_render_fused(RasterArgs a, uint32_t *
                                                         gsr_images out, float *__restrict__ loss,
                                                         double *__restrict__ grad2d, PixelState ps) {
   __shared__ Staged s_rec[BATCH];
-  __shared__ float s_grad[BATCH * NGRAD2D];
+  __shared__ float s_grad[BATCH * NMOM];
   __shared__ uint32_t s_id[BATCH];
   __shared__ int s_max;
+  __shared__ __align__(16) float s_mA[4 * MA_WAVE];
   __shared__ int s_q;
   __shared__ float s_loss[4];
   for (;;) {
@@ -480,7 +558,8 @@ __global__ __launch_bounds__(BLOCK) void k_render_fused(RasterArgs a, uint32_t *
       }
       const float ls = wave_sum(lpx);
       if ((threadIdx.x & 63) == 0) s_loss[threadIdx.x >> 6] = ls;
-      tile_backward(ti, a.n, a.recA, a.recB, a.recZ, a.rgb, a.ids, a.rc, in, grad2d, s_rec, s_grad, s_id, &s_max);
+      tile_backward(ti, a.n, a.recA, a.recB, a.recZ, a.rgb, a.ids, a.rc, in, grad2d, s_rec, s_grad, s_id, &s_max,
+                    s_mA);
       if (threadIdx.x == 0 && loss) atomicAdd(loss, (s_loss[0] + s_loss[1]) + (s_loss[2] + s_loss[3]));
       // The next tile may have an empty list (no barrier in its forward):
       // keep its shared-memory writes behind this tile's reads.
