@@ -38,6 +38,8 @@ METRIC = "fwd+bwd Mpixel/s at 1200×680, 300k Gaussians; batched vs per-frame sp
 #     colour/depth grads (4), dL/dalpha (17), running sums (12), clamp test
 #     and scale (2), centre and conic grads (14), opacity grad (1), block
 #     reduction adds for the 10 gradient fields (10)                      = 63
+#   (the per-entry sums over the tile's pixels run as a matrix-core
+#   contraction; they are counted at this algorithmic rate all the same).
 FLOP_FWD_EVAL, FLOP_BLEND, FLOP_BWD_EVAL, FLOP_BWD_CONTRIB = 13, 12, 13, 63
 # MI355X FP32 vector peak without packed FP32: 256 CUs x 4 SIMDs x 16 lanes
 # x 2 (FMA) x 2.4 GHz.
@@ -46,6 +48,22 @@ PEAK_FP32_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def measured_traffic():
+    """HBM bytes per k_render_fused launch on the headline workload from the
+    committed rocprofv3 FETCH_SIZE / WRITE_SIZE passes (scaled by the copy
+    calibration), or None when the kernel sources changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_render_fused_traffic.json")
+    try:
+        rec = json.load(open(path))
+        src = b"".join(open(os.path.join(ROOT, f), "rb").read() for f in rec["sources"])
+    except (OSError, ValueError, KeyError):
+        return None
+    if hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
+        return None
+    return rec
 
 
 def build_c2(gsr, torch, W, O=None):
@@ -143,6 +161,13 @@ def run_headline(args, gsr, torch, W):
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_FP32_TFLOPS, 1),
             "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
             "kernel": "k_render_fused", "kernel_ms": round(raster_ms, 4), "flop_per_launch": int(flops)}
+    tr = measured_traffic()
+    if tr is not None:
+        # bytes per launch, HBM read + written (rocprofv3 counters, copy-calibrated)
+        roof["traffic"] = int(tr["bytes_total"])
+        roof["traffic_read"] = int(tr["bytes_read"])
+        roof["traffic_written"] = int(tr["bytes_written"])
+        roof["traffic_source"] = tr["summary"]
     px = cam.width * cam.height
     return dict(ms=ms, wall=wall, eager_ms=eager_ms, stages=stages, work=work, roof=roof, tuning=tuning,
                 mpx=px / (ms * 1e-3) / 1e6, pairs=pairs)

@@ -75,6 +75,7 @@ Workspace make_ws(const Plan &p, void *base_v) {
   w.scan_part = reinterpret_cast<unsigned long long *>(base + p.off_scan);
   w.hist = reinterpret_cast<uint32_t *>(base + p.off_hist);
   w.hoff = reinterpret_cast<uint32_t *>(base + p.off_hoff);
+  w.bucket_rec = reinterpret_cast<uint32_t *>(base + p.off_bucket);
   w.digit_total = reinterpret_cast<uint32_t *>(base + p.off_digit);
   w.ranges = reinterpret_cast<int2 *>(base + p.off_ranges);
   w.T_final = reinterpret_cast<float *>(base + p.off_T);
@@ -322,6 +323,7 @@ gsr_status gsr_plan(gsr_ctx *ctx, int64_t n, int n_views, const int32_t *wh_host
   for (int k = 0; k < 2; ++k) p.off_pvals[k] = take(4 * cap);
   p.off_hist = take(4 * (size_t)RADIX * p.max_sort_tiles);
   p.off_hoff = take(4 * (size_t)RADIX * p.max_sort_tiles);
+  p.off_bucket = take(4 * (cap / EMIT_BUCKET + 2));
   p.off_digit = take(4 * RADIX);
   p.off_ranges = take(8 * (size_t)p.total_tiles);
   p.off_T = take(4 * (size_t)pixels);

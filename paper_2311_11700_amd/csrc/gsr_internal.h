@@ -19,6 +19,7 @@ constexpr int RADIX_BITS = 8;
 constexpr int RADIX = 1 << RADIX_BITS;
 constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_CHUNK = BLOCK * SCAN_ITEMS;
+constexpr int EMIT_BUCKET = 256;  // pairs per emission bucket (one block-iteration of k_emit_pairs)
 
 // Per-view geometry of the concatenated output (device copy lives in the
 // context, written at plan time).
@@ -58,6 +59,7 @@ struct Workspace {
   uint32_t *pvals[2];      // [capacity] record ids, ping-pong
   uint32_t *hist;          // [RADIX][max_sort_tiles] digit counts per sort tile
   uint32_t *hoff;          // [RADIX][max_sort_tiles] exclusive scan of hist (digit-major)
+  uint32_t *bucket_rec;    // [capacity / EMIT_BUCKET + 2] depth-order record holding pair EMIT_BUCKET * b
   uint32_t *digit_total;   // [RADIX]
   int2 *ranges;            // [total_tiles]
   float *T_final;          // [total_pixels]
@@ -88,7 +90,7 @@ struct Plan {
   // byte offsets inside the workspace
   size_t off_hdr, off_recA, off_recB, off_recZ, off_rect, off_count, off_dkeys[2], off_dvals[2],
       off_scan, off_pkeys[2], off_pvals[2], off_hist, off_digit, off_ranges, off_T, off_last,
-      off_grad2d, off_pose, off_queue, off_loss, off_nevals, off_nblend, off_counts, off_hoff;
+      off_grad2d, off_pose, off_queue, off_loss, off_nevals, off_nblend, off_counts, off_hoff, off_bucket;
 };
 
 struct Tuning {

@@ -209,12 +209,20 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(
       s_goff[threadIdx.x] = s_base[threadIdx.x] + hoff[(size_t)threadIdx.x * max_tiles + t] - lbase;
     }
     __syncthreads();
-#pragma unroll 1
+    // All loads of the sort tile are issued up front.
+    uint32_t kr[SORT_ITEMS], vr[SORT_ITEMS];
+#pragma unroll
+    for (int r = 0; r < SORT_ITEMS; ++r) {
+      const uint32_t idx = t0 + r * BLOCK + threadIdx.x;
+      kr[r] = idx < n ? keys_in[idx] : 0u;
+      vr[r] = idx < n ? vals_in[idx] : 0u;
+    }
+#pragma unroll
     for (int r = 0; r < SORT_ITEMS; ++r) {
       const uint32_t idx = t0 + r * BLOCK + threadIdx.x;
       const bool valid = idx < n;
-      const uint32_t key = valid ? keys_in[idx] : 0u;
-      const uint32_t val = valid ? vals_in[idx] : 0u;
+      const uint32_t key = kr[r];
+      const uint32_t val = vr[r];
       const uint32_t d = (key >> shift) & mask;
       const uint64_t peers = match_digit(d, nbits, __ballot(valid));
       const uint64_t below = peers & lanemask_lt();
@@ -333,11 +341,14 @@ __global__ __launch_bounds__(BLOCK) void k_scan_top(unsigned long long *__restri
 }
 
 // Per-record pair offsets in depth order, clamped to the capacity (so the
-// array stays non-decreasing and every offset fits 32 bits).
+// array stays non-decreasing and every offset fits 32 bits).  Also records,
+// for every emission bucket b, the record whose pair range holds pair
+// EMIT_BUCKET * b (each such pair lies in exactly one non-empty range).
 __global__ __launch_bounds__(BLOCK) void k_scan_down(const uint32_t *__restrict__ order,
                                                      const uint32_t *__restrict__ count, int64_t n_rec,
                                                      const unsigned long long *__restrict__ part,
-                                                     uint64_t capacity, uint32_t *__restrict__ off) {
+                                                     uint64_t capacity, uint32_t *__restrict__ off,
+                                                     uint32_t *__restrict__ bucket_rec) {
   __shared__ unsigned long long s_w[4];
   const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + threadIdx.x * SCAN_ITEMS;
   uint32_t c[SCAN_ITEMS];
@@ -353,7 +364,12 @@ __global__ __launch_bounds__(BLOCK) void k_scan_down(const uint32_t *__restrict_
 #pragma unroll
   for (int k = 0; k < SCAN_ITEMS; ++k) {
     const int64_t idx = base + k;
-    if (idx < n_rec) off[idx] = (uint32_t)(o < capacity ? o : capacity);
+    if (idx < n_rec) {
+      off[idx] = (uint32_t)(o < capacity ? o : capacity);
+      const unsigned long long e = o + c[k] < capacity ? o + c[k] : capacity;
+      for (unsigned long long b = (o + EMIT_BUCKET - 1) / EMIT_BUCKET; b * EMIT_BUCKET < e; ++b)
+        bucket_rec[b] = (uint32_t)idx;
+    }
     o += c[k];
   }
 }
@@ -371,26 +387,24 @@ __device__ __forceinline__ uint32_t find_record(const uint32_t *__restrict__ off
 
 // One thread per (tile, Gaussian) pair: find the record that owns the pair
 // (records are in depth order, so the pairs come out in depth order), decode
-// the tile from the record's rectangle, write key and value.  Every block
-// first brackets the records of its 256 pairs, so the per-thread searches
-// are short.
+// the tile from the record's rectangle, write key and value.  Block-iteration
+// b covers the pairs of emission bucket b; the bucket index brackets its
+// records, so the per-thread searches are short.
 __global__ __launch_bounds__(BLOCK) void k_emit_pairs(const uint32_t *__restrict__ order,
                                                       const uint32_t *__restrict__ off,
                                                       const uint2 *__restrict__ tinfo, uint32_t n_rec,
                                                       const unsigned long long *__restrict__ n_dev, uint32_t cap,
+                                                      const uint32_t *__restrict__ bucket_rec,
                                                       uint32_t *__restrict__ pkeys, uint32_t *__restrict__ pvals) {
-  __shared__ uint32_t s_lo, s_hi;
+  static_assert(EMIT_BUCKET == BLOCK, "one emission bucket per block-iteration");
   const uint32_t n = sort_count(n_dev, 0u, cap);
-  for (uint32_t base = blockIdx.x * BLOCK; base < n; base += gridDim.x * BLOCK) {
-    if (threadIdx.x == 0) s_lo = find_record(off, 0u, n_rec - 1u, base);
-    if (threadIdx.x == 1) {
-      const uint32_t last = base + BLOCK - 1u < n ? base + BLOCK - 1u : n - 1u;
-      s_hi = find_record(off, 0u, n_rec - 1u, last);
-    }
-    __syncthreads();
-    const uint32_t p = base + threadIdx.x;
+  const uint32_t nb = (n + EMIT_BUCKET - 1) / EMIT_BUCKET;
+  for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
+    const uint32_t lo = bucket_rec[b];
+    const uint32_t hi = b + 1 < nb ? bucket_rec[b + 1] : n_rec - 1u;
+    const uint32_t p = b * EMIT_BUCKET + threadIdx.x;
     if (p < n) {
-      const uint32_t k = find_record(off, s_lo, s_hi, p);
+      const uint32_t k = find_record(off, lo, hi, p);
       const uint32_t rec = order[k];
       const uint32_t j = p - off[k];
       const uint2 ti = tinfo[rec];
@@ -403,7 +417,6 @@ __global__ __launch_bounds__(BLOCK) void k_emit_pairs(const uint32_t *__restrict
       pkeys[p] = ti.x + q * TX + (j - q * w);
       pvals[p] = rec;
     }
-    __syncthreads();
   }
 }
 
@@ -417,13 +430,13 @@ void launch_emit_pairs(const Plan &p, const Workspace &ws, const ViewInfo *views
                      (uint64_t)p.capacity);
   if (p.n_rec == 0) return;
   hipLaunchKernelGGL(k_scan_down, dim3(p.n_scan_blocks), dim3(BLOCK), 0, s, order, ws.count, p.n_rec,
-                     ws.scan_part, (uint64_t)p.capacity, off);
+                     ws.scan_part, (uint64_t)p.capacity, off, ws.bucket_rec);
   int64_t blocks = (p.capacity + BLOCK - 1) / BLOCK;
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
   const unsigned long long *n_dev = reinterpret_cast<const unsigned long long *>(ws.hdr + HDR_NPAIRS);
   hipLaunchKernelGGL(k_emit_pairs, dim3((unsigned)blocks), dim3(BLOCK), 0, s, order, off, ws.tinfo,
-                     (uint32_t)p.n_rec, n_dev, (uint32_t)p.capacity, ws.pkeys[0], ws.pvals[0]);
+                     (uint32_t)p.n_rec, n_dev, (uint32_t)p.capacity, ws.bucket_rec, ws.pkeys[0], ws.pvals[0]);
 }
 
 // ---------------------------------------------------------------- tile ranges
