@@ -226,14 +226,88 @@ def project(scene, cam, cfg: Config):
             amb |= ok & (d < AMBIG_BIN * np.maximum(1.0, np.abs(b)))
     valid &= (rect[:, 0] <= rect[:, 1]) & (rect[:, 2] <= rect[:, 3])
     rect[~valid] = (0, -1, 0, -1)
+    runs = None
+    if not cfg.full_rect and cfg.alpha_min > 0:
+        runs, amb_s = _support_runs(u, v, conic, opacity, rect, valid, float(cfg.alpha_min))
+        amb |= amb_s
 
     return dict(
         n=n, TX=TX, TY=TY, valid=valid, rect=rect, bin_ambiguous=amb & valid,
         Xc=np.stack([x, y, z], axis=1), z=z, zbits=zf.view(np.uint32),
         Sigma=Sigma, Sigma_c=Sigma_c, Rq=Rq, s=s, qhat=qhat, qn=qn, J=J, cov2=cov2,
         conic=conic, uv=np.stack([u, v], axis=1), opacity=opacity, rgb=rgb,
-        W=W, fx=fx, fy=fy, rxz=rxz, ryz=ryz, free_x=free_x, free_y=free_y,
+        W=W, fx=fx, fy=fy, rxz=rxz, ryz=ryz, free_x=free_x, free_y=free_y, runs=runs,
     )
+
+
+def _support_runs(u, v, conic, opacity, rect, valid, alpha_min):
+    """Tiles of each rectangle that the Gaussian reaches with alpha >= alpha_min.
+
+    alpha = o exp(-Q/2) reaches alpha_min only where Q <= t = 2 ln(o/alpha_min)
+    (plus a 1e-4 margin on t for float32 rounding of alpha).  Per row of tiles
+    the ellipse {Q <= t} meets the columns whose pixel-centre range
+    [16 tx, 16 tx + 15] overlaps the ellipse's x-range inside the row's
+    pixel-centre band [16 ty, 16 ty + 15]; that x-range is bounded by the
+    ellipse's boundary at the band row nearest to its leftmost / rightmost
+    point.  Inputs are the float32 values the renderer stores (centre as
+    hi + lo, conic, opacity).  Returns ((records, rows, first columns,
+    lengths), ambiguous) with `ambiguous` flagging records with a decision
+    within rounding of a tile edge."""
+    n = u.shape[0]
+    idx = np.nonzero(valid)[0]
+    amb = np.zeros(n, bool)
+
+    def f(x):
+        return np.asarray(x, np.float32).astype(F64)
+
+    uh = f(u[idx])
+    vh = f(v[idx])
+    U = uh + f(u[idx] - uh)
+    V = vh + f(v[idx] - vh)
+    a, b, c = f(conic[idx, 0]), f(conic[idx, 1]), f(conic[idx, 2])
+    o = f(opacity[idx])
+    with np.errstate(all="ignore"):
+        det = a * c - b * b
+        t = 2.0 * np.log(o / alpha_min) + 1e-4
+        ok = (det > 0.0) & (t > 0.0)
+        SA, SB, SC = c / det, -b / det, a / det
+        hy = np.sqrt(t * SC)
+        dys = SB * np.sqrt(t / SA)
+        ra = 1.0 / a
+    tx0, tx1, ty0, ty1 = (rect[idx, k] for k in range(4))
+    out = ([], [], [], [])
+
+    def near(x, scale):
+        return np.abs(x) <= 1e-12 * np.maximum(1.0, np.abs(scale))
+
+    nrows = int((ty1 - ty0).max()) + 1 if idx.size else 0
+    for r in range(nrows):  # one row offset at a time, all records at once
+        ty = ty0 + r
+        m = ok & (ty <= ty1)
+        with np.errstate(all="ignore"):
+            p = (16 * ty).astype(F64) - V
+            q = (16 * ty + 15).astype(F64) - V
+            inband = ~((q < -hy) | (p > hy))
+            dr = np.fmin(np.fmax(dys, p), q)
+            dl = np.fmin(np.fmax(-dys, p), q)
+            br, bl = b * dr, b * dl
+            er = np.fmax(br * br - a * ((c * dr) * dr - t), 0.0)
+            el = np.fmax(bl * bl - a * ((c * dl) * dl - t), 0.0)
+            R = (-br + np.sqrt(er)) * ra
+            L = (-bl - np.sqrt(el)) * ra
+            xlo = ((U + L) - 15.0) * 0.0625
+            xhi = (U + R) * 0.0625
+            clo = np.fmax(np.ceil(xlo), tx0.astype(F64))
+            chi = np.fmin(np.floor(xhi), tx1.astype(F64))
+        keep = m & inband & (clo <= chi)
+        amb[idx[m & (near(q + hy, hy) | near(p - hy, hy))]] = True
+        amb[idx[m & inband & (near(xlo - np.round(xlo), xlo) | near(xhi - np.round(xhi), xhi))]] = True
+        out[0].append(idx[keep])
+        out[1].append(ty[keep])
+        out[2].append(clo[keep].astype(np.int64))
+        out[3].append((chi - clo + 1)[keep].astype(np.int64))
+    runs = tuple(np.concatenate(x) if x else np.zeros(0, np.int64) for x in out)
+    return runs, amb
 
 
 def tile_lists(proj):
@@ -246,11 +320,17 @@ def tile_lists(proj):
     rect = proj["rect"]
     idx = np.nonzero(proj["valid"])[0]
     tiles_g, gauss = [], []
-    for i in idx:  # plain loop over Gaussians: tiles of the rectangle
-        tx0, tx1, ty0, ty1 = rect[i]
-        ty, tx = np.meshgrid(np.arange(ty0, ty1 + 1), np.arange(tx0, tx1 + 1), indexing="ij")
-        tiles_g.append((ty * TX + tx).ravel())
-        gauss.append(np.full(tiles_g[-1].size, i))
+    runs = proj.get("runs")
+    if runs is not None:  # the tiles of each rectangle the alpha support reaches
+        for rec, ty, lo, ln in zip(*runs):
+            tiles_g.append(ty * TX + lo + np.arange(ln))
+            gauss.append(np.full(ln, rec))
+    else:
+        for i in idx:  # plain loop over Gaussians: tiles of the rectangle
+            tx0, tx1, ty0, ty1 = rect[i]
+            ty, tx = np.meshgrid(np.arange(ty0, ty1 + 1), np.arange(tx0, tx1 + 1), indexing="ij")
+            tiles_g.append((ty * TX + tx).ravel())
+            gauss.append(np.full(tiles_g[-1].size, i))
     if tiles_g:
         tiles_g = np.concatenate(tiles_g)
         gauss = np.concatenate(gauss)

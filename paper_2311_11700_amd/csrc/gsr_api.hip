@@ -64,7 +64,8 @@ Workspace make_ws(const Plan &p, void *base_v) {
   w.recA = reinterpret_cast<float4 *>(base + p.off_recA);
   w.recB = reinterpret_cast<float4 *>(base + p.off_recB);
   w.recZ = reinterpret_cast<float *>(base + p.off_recZ);
-  w.tinfo = reinterpret_cast<uint2 *>(base + p.off_rect);
+  w.tinfo = reinterpret_cast<uint4 *>(base + p.off_rect);
+  w.support = reinterpret_cast<Support *>(base + p.off_support);
   w.count = reinterpret_cast<uint32_t *>(base + p.off_count);
   for (int k = 0; k < 2; ++k) {
     w.dkeys[k] = reinterpret_cast<uint32_t *>(base + p.off_dkeys[k]);
@@ -296,8 +297,10 @@ gsr_status gsr_plan(gsr_ctx *ctx, int64_t n, int n_views, const int32_t *wh_host
   if (tiles >= (1ll << 31)) return fail(ctx, GSR_E_UNSUPPORTED, "gsr_plan: too many tiles");
   p.total_tiles = (int)tiles;
   p.total_pixels = pixels;
+  // Tile keys 0..tiles-1 plus one key past the last tile for the pairs
+  // outside a Gaussian's alpha support.
   int bits = 0;
-  while ((1ll << bits) < tiles) ++bits;
+  while ((1ll << bits) < tiles + 1) ++bits;
   p.tile_bits = bits;
   const int64_t sort_elems = std::max<int64_t>(p.capacity, p.n_rec);
   p.max_sort_tiles = (int)((sort_elems + SORT_TILE - 1) / SORT_TILE);
@@ -314,7 +317,8 @@ gsr_status gsr_plan(gsr_ctx *ctx, int64_t n, int n_views, const int32_t *wh_host
   p.off_recA = take(16 * nr);
   p.off_recB = take(16 * nr);
   p.off_recZ = take(4 * nr);
-  p.off_rect = take(8 * nr);
+  p.off_rect = take(16 * nr);
+  p.off_support = take(sizeof(Support) * nr);
   p.off_count = take(4 * nr);
   for (int k = 0; k < 2; ++k) p.off_dkeys[k] = take(4 * nr);
   for (int k = 0; k < 2; ++k) p.off_dvals[k] = take(4 * nr);

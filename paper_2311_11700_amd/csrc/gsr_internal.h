@@ -45,12 +45,65 @@ enum HeaderWord {
 constexpr uint32_t HDR_MAGIC0 = 0x67737248u, HDR_MAGIC1 = 0x2311B700u;
 
 // Device pointers into the caller's workspace (computed on the host).
+// ------------------------------------------------------- alpha support
+//
+// Tiles of a Gaussian's rectangle that it can reach with alpha >= alpha_min.
+// Its alpha at a pixel is o exp(-Q/2), Q the conic quadratic form of the
+// offset, so it reaches alpha_min only where Q <= t = 2 ln(o / alpha_min);
+// a margin of 1e-4 on t keeps tiles where a float32 alpha could round up to
+// alpha_min.  Inside one row of tiles the ellipse {Q <= t} meets a
+// contiguous run of tiles: the x-range of the ellipse within the row's band
+// of pixel-centre rows [16 ty, 16 ty + 15], mapped to the columns whose
+// pixel centres [16 tx, 16 tx + 15] it overlaps.  Every input is a stored
+// float32 value (centre as hi + lo, conic, opacity), so the projection
+// kernel (parameters) and the emission kernel (per-pair test) agree with an
+// FP64 reference evaluated in the same order.
+struct Support {
+  double U, V, t, hy, dys, ra;  // centre, level, half-height, dy of the rightmost point, 1 / a
+};
+
+__device__ inline bool support_of(float4 A, float4 B, float alpha_min, Support &s) {
+#pragma clang fp contract(off)
+  s.U = (double)A.x + (double)A.y;
+  s.V = (double)A.z + (double)A.w;
+  const double a = (double)B.x, b = (double)B.y, c = (double)B.z;
+  const double det = a * c - b * b;
+  s.t = 2.0 * log((double)B.w / (double)alpha_min) + 1e-4;
+  if (!(det > 0.0) || !(s.t > 0.0)) return false;
+  const double SA = c / det, SB = -b / det, SC = a / det;  // covariance
+  s.hy = sqrt(s.t * SC);
+  s.dys = SB * sqrt(s.t / SA);
+  s.ra = 1.0 / a;
+  return true;
+}
+
+// Run of tile columns of row ty (within [tx0, tx1]) reached by the support
+// of the Gaussian with conic (a, b, c): returns its length and writes its
+// first column to lo.
+__device__ inline int support_row(const Support &s, double a, double b, double c, int ty, int tx0, int tx1,
+                                  int &lo) {
+#pragma clang fp contract(off)
+  const double p = (double)(16 * ty) - s.V, q = (double)(16 * ty + 15) - s.V;
+  if (q < -s.hy || p > s.hy) return 0;
+  const double dr = fmin(fmax(s.dys, p), q), dl = fmin(fmax(-s.dys, p), q);
+  const double br = b * dr, bl = b * dl;
+  const double er = fmax(br * br - a * ((c * dr) * dr - s.t), 0.0);
+  const double el = fmax(bl * bl - a * ((c * dl) * dl - s.t), 0.0);
+  const double R = (-br + sqrt(er)) * s.ra, L = (-bl - sqrt(el)) * s.ra;
+  const double clo = fmax(ceil(((s.U + L) - 15.0) * 0.0625), (double)tx0);
+  const double chi = fmin(floor((s.U + R) * 0.0625), (double)tx1);
+  if (!(clo <= chi)) return 0;
+  lo = (int)clo;
+  return (int)(chi - clo) + 1;
+}
+
 struct Workspace {
   uint32_t *hdr;
   float4 *recA;            // [n_rec] (u_hi, u_lo, v_hi, v_lo)
   float4 *recB;            // [n_rec] (conic a, b, c, opacity)
   float *recZ;             // [n_rec] camera-frame depth
-  uint2 *tinfo;            // [n_rec] (first global tile of the rectangle, width << 16 | view TX)
+  uint4 *tinfo;            // [n_rec] (view tile offset, view TX | cull << 31, tx0 | tx1 << 16, ty0 | ty1 << 16)
+  Support *support;        // [n_rec] alpha-support parameters (records with the cull bit)
   uint32_t *count;         // [n_rec] tiles touched (0 = culled)
   uint32_t *dkeys[2];      // [n_rec] depth keys (float32 bits), ping-pong
   uint32_t *dvals[2];      // [n_rec] record ids, ping-pong
@@ -90,7 +143,8 @@ struct Plan {
   // byte offsets inside the workspace
   size_t off_hdr, off_recA, off_recB, off_recZ, off_rect, off_count, off_dkeys[2], off_dvals[2],
       off_scan, off_pkeys[2], off_pvals[2], off_hist, off_digit, off_ranges, off_T, off_last,
-      off_grad2d, off_pose, off_queue, off_loss, off_nevals, off_nblend, off_counts, off_hoff, off_bucket;
+      off_grad2d, off_pose, off_queue, off_loss, off_nevals, off_nblend, off_counts, off_hoff, off_bucket,
+      off_support;
 };
 
 struct Tuning {

@@ -19,6 +19,7 @@ struct PreConsts {
   float z_near, lowpass, cutoff;
   uint32_t flags;
   float fov_guard;
+  float alpha_min;
 };
 
 // Rotation matrix of a unit quaternion (w, x, y, z) (GS-SLAM supplement,
@@ -137,19 +138,31 @@ __global__ __launch_bounds__(BLOCK) void k_preprocess(gsr_gaussians g,
     ws.count[rec] = 0u;
     ws.dkeys[0][rec] = 0xFFFFFFFFu;
     ws.dvals[0][rec] = (uint32_t)rec;
-    ws.tinfo[rec] = make_uint2(0u, 0u);
+    ws.tinfo[rec] = make_uint4(0u, 0u, 0u, 0u);
     return;
   }
   const float zf = (float)z;
   const float uh = (float)u, vh = (float)v;
   const float op = (float)(1.0 / (1.0 + exp(-(double)fop)));
-  ws.recA[rec] = make_float4(uh, (float)(u - (double)uh), vh, (float)(v - (double)vh));
-  ws.recB[rec] = make_float4((float)(C / det), (float)(-B / det), (float)(A / det), op);
+  const float4 fa = make_float4(uh, (float)(u - (double)uh), vh, (float)(v - (double)vh));
+  const float4 fb = make_float4((float)(C / det), (float)(-B / det), (float)(A / det), op);
+  ws.recA[rec] = fa;
+  ws.recB[rec] = fb;
   ws.recZ[rec] = zf;
-  // First tile of the rectangle (global id), its width and the view's row
-  // stride: pair j of this record covers tile first + (j / w) * TX + j % w.
-  ws.tinfo[rec] = make_uint2((uint32_t)(vi.tile_off + ty0 * vi.TX + tx0),
-                             ((uint32_t)(tx1 - tx0 + 1) << 16) | (uint32_t)vi.TX);
+  // Every tile of the rectangle gets a pair; the emission marks the ones the
+  // alpha support does not reach (none in the full-rectangle mode or
+  // without an alpha threshold).
+  const bool cull = !(pc.flags & GSR_FULL_RECT) && pc.alpha_min > 0.f;
+  if (cull) {
+    Support sp;
+    if (!support_of(fa, fb, pc.alpha_min, sp)) {
+      sp.U = sp.V = sp.t = sp.dys = sp.ra = 0.0;
+      sp.hy = -1.0;  // no row reaches it: every pair is dropped
+    }
+    ws.support[rec] = sp;
+  }
+  ws.tinfo[rec] = make_uint4((uint32_t)vi.tile_off, (uint32_t)vi.TX | (cull ? 0x80000000u : 0u),
+                             (uint32_t)tx0 | ((uint32_t)tx1 << 16), (uint32_t)ty0 | ((uint32_t)ty1 << 16));
   ws.count[rec] = (uint32_t)(tx1 - tx0 + 1) * (uint32_t)(ty1 - ty0 + 1);
   ws.dkeys[0][rec] = __float_as_uint(zf);
   ws.dvals[0][rec] = (uint32_t)rec;
@@ -157,7 +170,7 @@ __global__ __launch_bounds__(BLOCK) void k_preprocess(gsr_gaussians g,
 
 void launch_preprocess(const gsr_gaussians &g, const gsr_camera *cams, const ViewInfo *views,
                        int n_views, const gsr_config &cfg, const Workspace &ws, hipStream_t s) {
-  PreConsts pc{cfg.z_near, cfg.lowpass, cfg.cutoff_sigma, cfg.flags, cfg.fov_guard};
+  PreConsts pc{cfg.z_near, cfg.lowpass, cfg.cutoff_sigma, cfg.flags, cfg.fov_guard, cfg.alpha_min};
   dim3 grid((unsigned)((g.n + BLOCK - 1) / BLOCK), (unsigned)n_views);
   if (g.n > 0) hipLaunchKernelGGL(k_preprocess, grid, dim3(BLOCK), 0, s, g, cams, views, pc, ws);
 }

@@ -387,14 +387,17 @@ __device__ __forceinline__ uint32_t find_record(const uint32_t *__restrict__ off
 
 // One thread per (tile, Gaussian) pair: find the record that owns the pair
 // (records are in depth order, so the pairs come out in depth order), decode
-// the tile from the record's rectangle, write key and value.  Block-iteration
-// b covers the pairs of emission bucket b; the bucket index brackets its
-// records, so the per-thread searches are short.
+// the tile from the record's rectangle, test it against the alpha support,
+// write key and value.  Block-iteration b covers the pairs of emission
+// bucket b; the bucket index brackets its records, so the per-thread
+// searches are short.
 __global__ __launch_bounds__(BLOCK) void k_emit_pairs(const uint32_t *__restrict__ order,
                                                       const uint32_t *__restrict__ off,
-                                                      const uint2 *__restrict__ tinfo, uint32_t n_rec,
-                                                      const unsigned long long *__restrict__ n_dev, uint32_t cap,
-                                                      const uint32_t *__restrict__ bucket_rec,
+                                                      const uint4 *__restrict__ tinfo,
+                                                      const Support *__restrict__ support,
+                                                      const float4 *__restrict__ recB, uint32_t dropped_key,
+                                                      uint32_t n_rec, const unsigned long long *__restrict__ n_dev,
+                                                      uint32_t cap, const uint32_t *__restrict__ bucket_rec,
                                                       uint32_t *__restrict__ pkeys, uint32_t *__restrict__ pvals) {
   static_assert(EMIT_BUCKET == BLOCK, "one emission bucket per block-iteration");
   const uint32_t n = sort_count(n_dev, 0u, cap);
@@ -407,14 +410,28 @@ __global__ __launch_bounds__(BLOCK) void k_emit_pairs(const uint32_t *__restrict
       const uint32_t k = find_record(off, lo, hi, p);
       const uint32_t rec = order[k];
       const uint32_t j = p - off[k];
-      const uint2 ti = tinfo[rec];
-      const uint32_t w = ti.y >> 16, TX = ti.y & 0xFFFFu;
+      const uint4 ti = tinfo[rec];
+      const int TX = (int)(ti.y & 0x7FFFFFFFu);
+      const int tx0 = (int)(ti.z & 0xFFFFu), tx1 = (int)(ti.z >> 16);
+      const int ty0 = (int)(ti.w & 0xFFFFu);
+      const uint32_t w = (uint32_t)(tx1 - tx0 + 1);
       // j < 2^24 and w < 2^16: the float quotient is within one of the
       // integer quotient; fix it up exactly.
       uint32_t q = (uint32_t)((float)j / (float)w);
       if (q * w > j) --q;
       else if ((q + 1u) * w <= j) ++q;
-      pkeys[p] = ti.x + q * TX + (j - q * w);
+      const int ty = ty0 + (int)q, tx = tx0 + (int)(j - q * w);
+      uint32_t tile = ti.x + (uint32_t)(ty * TX + tx);
+      if (ti.y & 0x80000000u) {
+        // Tiles of the rectangle that the alpha support does not reach get
+        // the key past the last tile: the sort moves them behind every list.
+        const Support sp = support[rec];
+        const float4 cb = recB[rec];
+        int c0 = 0;
+        const int len = support_row(sp, (double)cb.x, (double)cb.y, (double)cb.z, ty, tx0, tx1, c0);
+        if (tx < c0 || tx >= c0 + len) tile = dropped_key;
+      }
+      pkeys[p] = tile;
       pvals[p] = rec;
     }
   }
@@ -435,18 +452,20 @@ void launch_emit_pairs(const Plan &p, const Workspace &ws, const ViewInfo *views
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
   const unsigned long long *n_dev = reinterpret_cast<const unsigned long long *>(ws.hdr + HDR_NPAIRS);
-  hipLaunchKernelGGL(k_emit_pairs, dim3((unsigned)blocks), dim3(BLOCK), 0, s, order, off, ws.tinfo,
-                     (uint32_t)p.n_rec, n_dev, (uint32_t)p.capacity, ws.bucket_rec, ws.pkeys[0], ws.pvals[0]);
+  hipLaunchKernelGGL(k_emit_pairs, dim3((unsigned)blocks), dim3(BLOCK), 0, s, order, off, ws.tinfo, ws.support,
+                     ws.recB, (uint32_t)p.total_tiles, (uint32_t)p.n_rec, n_dev, (uint32_t)p.capacity,
+                     ws.bucket_rec, ws.pkeys[0], ws.pvals[0]);
 }
 
 // ---------------------------------------------------------------- tile ranges
 
 __global__ __launch_bounds__(BLOCK) void k_tile_ranges(const uint32_t *__restrict__ keys,
                                                        const unsigned long long *n_dev, uint32_t cap,
-                                                       int2 *__restrict__ ranges) {
+                                                       uint32_t total_tiles, int2 *__restrict__ ranges) {
   const uint32_t n = sort_count(n_dev, 0u, cap);
   for (uint32_t i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) {
     const uint32_t t = keys[i];
+    if (t >= total_tiles) continue;  // pairs outside the alpha support
     if (i == 0 || keys[i - 1] != t) ranges[t].x = (int)i;
     if (i + 1 == n || keys[i + 1] != t) ranges[t].y = (int)(i + 1);
   }
@@ -459,7 +478,7 @@ void launch_tile_ranges(const Plan &p, const Workspace &ws, hipStream_t s) {
   if (blocks > 8192) blocks = 8192;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)blocks), dim3(BLOCK), 0, s, ws.pkeys[ws.psorted],
-                     n_dev, (uint32_t)p.capacity, ws.ranges);
+                     n_dev, (uint32_t)p.capacity, (uint32_t)p.total_tiles, ws.ranges);
 }
 
 // ------------------------------------------------------- work order (LPT)

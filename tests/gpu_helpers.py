@@ -125,3 +125,10 @@ def assert_close_scaled(a, b, rtol=1e-3, scale_tol=5e-4, what=""):
     m = np.abs(b).max() if b.size else 0.0
     bad = np.abs(a - b) > rtol * np.abs(b) + scale_tol * m
     assert not bad.any(), (what, int(bad.sum()), a[bad][:5], b[bad][:5], m)
+
+
+def rect_pairs(proj):
+    """Pairs the renderer emits: every tile of every valid Gaussian's
+    rectangle (the lists then skip the tiles outside its alpha support)."""
+    r = proj["rect"][proj["valid"]]
+    return int(((r[:, 1] - r[:, 0] + 1) * (r[:, 3] - r[:, 2] + 1)).sum())

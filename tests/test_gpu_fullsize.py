@@ -34,7 +34,7 @@ def c2(gsr_lib):
 def test_pairs_and_sampled_lists_bit_exact(c2):
     r, proj, (starts, gauss) = c2["r"], c2["proj"], c2["lists"]
     assert not proj["bin_ambiguous"].any()
-    assert r.pair_count() == len(gauss)
+    assert r.pair_count() == H.rect_pairs(proj)
     rng, sid = r.debug_tiles()
     rng, sid = rng.numpy(), sid.numpy()
     T = proj["TX"] * proj["TY"]

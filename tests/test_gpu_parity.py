@@ -73,7 +73,7 @@ def test_forward_and_lists_match_oracle(gsr_lib, case):
     g = H.split_images(out, r.sizes)[0]
     o = O.render(sc, cam, H.oracle_cfg_of(cfg))
     H.assert_images_close(g, o)
-    assert r.pair_count() == len(o["lists"][1])
+    assert r.pair_count() == H.rect_pairs(o["proj"])
     _check_lists(r, [sc], [cam], H.oracle_cfg_of(cfg))
 
 
@@ -502,7 +502,7 @@ def test_graph_replay_matches_eager(gsr_lib):
 def test_capacity_overflow_reports_required_pairs(gsr_lib):
     gsr = gsr_lib
     sc, cam = W.random_scene(2000, seed=0), W.camera_small()
-    need = len(O.render(sc, cam)["lists"][1])
+    need = H.rect_pairs(O.project(sc, cam, O.Config().as_f32()))
     r = gsr.Renderer()
     r.plan(sc.n, [(cam.width, cam.height)], pair_capacity=1000)
     lib = r.lib
