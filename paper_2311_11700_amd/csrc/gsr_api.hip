@@ -302,8 +302,8 @@ gsr_status gsr_plan(gsr_ctx *ctx, int64_t n, int n_views, const int32_t *wh_host
   int bits = 0;
   while ((1ll << bits) < tiles + 1) ++bits;
   p.tile_bits = bits;
-  const int64_t sort_elems = std::max<int64_t>(p.capacity, p.n_rec);
-  p.max_sort_tiles = (int)((sort_elems + SORT_TILE - 1) / SORT_TILE);
+  const int64_t dtile = (int64_t)BLOCK * SORT_ITEMS_DEPTH, ptile = (int64_t)BLOCK * SORT_ITEMS_PAIR;
+  p.max_sort_tiles = (int)std::max<int64_t>((p.n_rec + dtile - 1) / dtile, (p.capacity + ptile - 1) / ptile);
   p.n_scan_blocks = (int)std::max<int64_t>(1, (p.n_rec + SCAN_CHUNK - 1) / SCAN_CHUNK);
   p.n_pose_blocks = (int)std::max<int64_t>(1, (n + BLOCK - 1) / BLOCK);
   size_t off = 0;

@@ -13,8 +13,8 @@ namespace gsr {
 constexpr int TILE = 16;          // tile edge in pixels
 constexpr int BLOCK = 256;        // one thread per pixel of a tile
 constexpr int NGRAD2D = 10;       // u, v, conic a, b, c, opacity, r, g, b, depth
-constexpr int SORT_ITEMS = 8;     // keys per thread per sort tile
-constexpr int SORT_TILE = BLOCK * SORT_ITEMS;
+constexpr int SORT_ITEMS_DEPTH = 2;  // keys per thread per sort tile, depth sort of the records
+constexpr int SORT_ITEMS_PAIR = 8;  // keys per thread per sort tile, tile sort of the pairs
 constexpr int RADIX_BITS = 8;
 constexpr int RADIX = 1 << RADIX_BITS;
 constexpr int SCAN_ITEMS = 8;

@@ -106,7 +106,9 @@ __device__ __forceinline__ void tile_forward(const TileInfo &ti, int64_t n, cons
                                              const float *__restrict__ recZ,
                                              const float *__restrict__ rgb,
                                              const uint32_t *__restrict__ ids, const RenderConsts &rc,
-                                             Staged *s_rec, FwdState &st) {
+                                             Staged *s_rec, FwdState &st, uint32_t *s_id = nullptr,
+                                             int *staged_lo = nullptr) {
+  if (staged_lo) *staged_lo = -1;
   st.T = 1.f;
   st.C0 = st.C1 = st.C2 = st.D = 0.f;
   st.last = 0;
@@ -118,8 +120,12 @@ __device__ __forceinline__ void tile_forward(const TileInfo &ti, int64_t n, cons
   for (int base = ti.range.x; base < ti.range.y; base += BATCH) {
     if (__syncthreads_and(st.done)) break;
     const int pos = base + threadIdx.x;
-    if ((int)threadIdx.x < BATCH && pos < ti.range.y)
-      s_rec[threadIdx.x] = stage_record(ids[pos], ti.view, n, ti.x0, ti.y0, recA, recB, recZ, rgb);
+    if ((int)threadIdx.x < BATCH && pos < ti.range.y) {
+      const uint32_t id = ids[pos];
+      if (s_id) s_id[threadIdx.x] = id;
+      s_rec[threadIdx.x] = stage_record(id, ti.view, n, ti.x0, ti.y0, recA, recB, recZ, rgb);
+    }
+    if (staged_lo) *staged_lo = base - ti.range.x;
     __syncthreads();
     // Branch-free walk: every lane evaluates every entry and keeps or drops
     // the result with selects; the wave leaves the batch once all of its
@@ -248,7 +254,7 @@ __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, con
                                               const uint32_t *__restrict__ ids, const RenderConsts &rc,
                                               const BwdIn &in, double *__restrict__ grad2d,
                                               Staged *s_rec, float *s_grad, uint32_t *s_id, int *s_max,
-                                              float *s_mA) {
+                                              float *s_mA, int staged_lo = -1) {
   const float lx = (float)(threadIdx.x & (TILE - 1));
   const float ly = (float)(threadIdx.x >> 4);
   const int lane = __lane_id();
@@ -314,11 +320,14 @@ __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, con
   for (int lo = ((maxlast - 1) / BATCH) * BATCH; lo >= 0; lo -= BATCH) {
     const int hi = min(lo + BATCH, maxlast);
     const int cnt = hi - lo;
-    if ((int)threadIdx.x < cnt) {
+    // The forward's last batch is still staged (records and ids) when it is
+    // this one.
+    if (lo != staged_lo && (int)threadIdx.x < cnt) {
       const uint32_t id = ids[ti.range.x + lo + threadIdx.x];
       s_id[threadIdx.x] = id;
       s_rec[threadIdx.x] = stage_record(id, ti.view, n, ti.x0, ti.y0, recA, recB, recZ, rgb);
     }
+    staged_lo = -1;
     __syncthreads();
     int nq = 0;
     uint64_t slots = 0;
@@ -520,7 +529,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
       const int tile = (int)queue[q];
       const TileInfo ti = tile_info(tile, a.views, a.tile_view, a.ranges);
       FwdState st;
-      tile_forward(ti, a.n, a.recA, a.recB, a.recZ, a.rgb, a.ids, a.rc, s_rec, st);
+      int staged_lo;
+      tile_forward(ti, a.n, a.recA, a.recB, a.recZ, a.rgb, a.ids, a.rc, s_rec, st, s_id, &staged_lo);
       BwdIn in{st.T, ti.inside ? st.last : 0, 0.f, 0.f, 0.f, 0.f, 0.f};
       float lpx = 0.f;
       if (ti.inside) {
@@ -559,7 +569,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
       const float ls = wave_sum(lpx);
       if ((threadIdx.x & 63) == 0) s_loss[threadIdx.x >> 6] = ls;
       tile_backward(ti, a.n, a.recA, a.recB, a.recZ, a.rgb, a.ids, a.rc, in, grad2d, s_rec, s_grad, s_id, &s_max,
-                    s_mA);
+                    s_mA, staged_lo);
       if (threadIdx.x == 0 && loss) atomicAdd(loss, (s_loss[0] + s_loss[1]) + (s_loss[2] + s_loss[3]));
       // The next tile may have an empty list (no barrier in its forward):
       // keep its shared-memory writes behind this tile's reads.

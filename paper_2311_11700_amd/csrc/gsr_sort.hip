@@ -108,6 +108,7 @@ __device__ __forceinline__ uint32_t sort_count(const unsigned long long *n_dev, 
   return n < cap ? (uint32_t)n : cap;
 }
 
+template <int ITEMS>
 __global__ __launch_bounds__(BLOCK) void k_radix_hist(const uint32_t *__restrict__ keys,
                                                       const unsigned long long *n_dev,
                                                       uint32_t n_static, uint32_t cap, int shift,
@@ -115,14 +116,15 @@ __global__ __launch_bounds__(BLOCK) void k_radix_hist(const uint32_t *__restrict
                                                       int max_tiles) {
   __shared__ uint32_t cnt[RADIX];
   const uint32_t n = sort_count(n_dev, n_static, cap);
-  const uint32_t ntiles = (n + SORT_TILE - 1) / SORT_TILE;
+  constexpr int STILE = BLOCK * ITEMS;
+  const uint32_t ntiles = (n + STILE - 1) / STILE;
   const uint32_t mask = (1u << nbits) - 1u;
   for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     cnt[threadIdx.x] = 0u;
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < SORT_ITEMS; ++r) {
-      const uint32_t idx = t * SORT_TILE + r * BLOCK + threadIdx.x;
+    for (int r = 0; r < ITEMS; ++r) {
+      const uint32_t idx = t * STILE + r * BLOCK + threadIdx.x;
       const bool valid = idx < n;
       const uint32_t d = valid ? (keys[idx] >> shift) & mask : 0u;
       const uint64_t peers = match_digit(d, nbits, __ballot(valid));
@@ -136,6 +138,7 @@ __global__ __launch_bounds__(BLOCK) void k_radix_hist(const uint32_t *__restrict
 
 // One block per digit: exclusive scan over the tiles of that digit's column
 // (counts stay in hist, offsets go to hoff).
+template <int ITEMS>
 __global__ __launch_bounds__(BLOCK) void k_radix_scan(const uint32_t *__restrict__ hist,
                                                       uint32_t *__restrict__ hoff,
                                                       const unsigned long long *n_dev,
@@ -143,7 +146,8 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scan(const uint32_t *__restrict
                                                       uint32_t *__restrict__ digit_total) {
   __shared__ uint32_t s_w[4];
   const uint32_t n = sort_count(n_dev, n_static, cap);
-  const uint32_t ntiles = (n + SORT_TILE - 1) / SORT_TILE;
+  constexpr int STILE = BLOCK * ITEMS;
+  const uint32_t ntiles = (n + STILE - 1) / STILE;
   const uint32_t *col = hist + (size_t)blockIdx.x * max_tiles;
   uint32_t *ocol = hoff + (size_t)blockIdx.x * max_tiles;
   uint32_t carry = 0u;
@@ -175,6 +179,7 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scan(const uint32_t *__restrict
 // rest), then written out so that each digit's keys of the tile form one
 // contiguous run in the output: consecutive threads store consecutive
 // addresses.
+template <int ITEMS>
 __global__ __launch_bounds__(BLOCK) void k_radix_scatter(
     const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in,
     uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out,
@@ -186,10 +191,11 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(
   __shared__ uint32_t s_run[RADIX];    // next local position per digit
   __shared__ uint32_t s_wcnt[4][RADIX];
   __shared__ uint32_t s_w[4];
-  __shared__ uint32_t s_k[SORT_TILE];
-  __shared__ uint32_t s_v[SORT_TILE];
+  __shared__ uint32_t s_k[BLOCK * ITEMS];
+  __shared__ uint32_t s_v[BLOCK * ITEMS];
   const uint32_t n = sort_count(n_dev, n_static, cap);
-  const uint32_t ntiles = (n + SORT_TILE - 1) / SORT_TILE;
+  constexpr int STILE = BLOCK * ITEMS;
+  const uint32_t ntiles = (n + STILE - 1) / STILE;
   const uint32_t mask = (1u << nbits) - 1u;
   const int wave = threadIdx.x >> 6;
   {
@@ -199,8 +205,8 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(
   }
   __syncthreads();
   for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const uint32_t t0 = t * SORT_TILE;
-    const uint32_t tn = n - t0 < (uint32_t)SORT_TILE ? n - t0 : (uint32_t)SORT_TILE;
+    const uint32_t t0 = t * STILE;
+    const uint32_t tn = n - t0 < (uint32_t)STILE ? n - t0 : (uint32_t)STILE;
     {
       const uint32_t cnt = hist[(size_t)threadIdx.x * max_tiles + t];
       uint32_t total;
@@ -210,15 +216,15 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(
     }
     __syncthreads();
     // All loads of the sort tile are issued up front.
-    uint32_t kr[SORT_ITEMS], vr[SORT_ITEMS];
+    uint32_t kr[ITEMS], vr[ITEMS];
 #pragma unroll
-    for (int r = 0; r < SORT_ITEMS; ++r) {
+    for (int r = 0; r < ITEMS; ++r) {
       const uint32_t idx = t0 + r * BLOCK + threadIdx.x;
       kr[r] = idx < n ? keys_in[idx] : 0u;
       vr[r] = idx < n ? vals_in[idx] : 0u;
     }
 #pragma unroll
-    for (int r = 0; r < SORT_ITEMS; ++r) {
+    for (int r = 0; r < ITEMS; ++r) {
       const uint32_t idx = t0 + r * BLOCK + threadIdx.x;
       const bool valid = idx < n;
       const uint32_t key = kr[r];
@@ -252,17 +258,18 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(
 
 // Stable LSD radix sort of (key, value) over bits [0, key_bits); returns the
 // index of the buffer holding the result.
+template <int ITEMS>
 static int radix_sort(uint32_t *keys[2], uint32_t *vals[2], const unsigned long long *n_dev,
                       uint32_t n_static, uint32_t cap, int key_bits, uint32_t *hist, uint32_t *hoff,
                       int max_tiles, uint32_t *digit_total, int grid, hipStream_t s) {
   int cur = 0;
   for (int shift = 0; shift < key_bits; shift += RADIX_BITS) {
     const int nbits = key_bits - shift < RADIX_BITS ? key_bits - shift : RADIX_BITS;
-    hipLaunchKernelGGL(k_radix_hist, dim3(grid), dim3(BLOCK), 0, s, keys[cur], n_dev, n_static, cap,
+    hipLaunchKernelGGL(k_radix_hist<ITEMS>, dim3(grid), dim3(BLOCK), 0, s, keys[cur], n_dev, n_static, cap,
                        shift, nbits, hist, max_tiles);
-    hipLaunchKernelGGL(k_radix_scan, dim3(RADIX), dim3(BLOCK), 0, s, hist, hoff, n_dev, n_static, cap,
+    hipLaunchKernelGGL(k_radix_scan<ITEMS>, dim3(RADIX), dim3(BLOCK), 0, s, hist, hoff, n_dev, n_static, cap,
                        max_tiles, digit_total);
-    hipLaunchKernelGGL(k_radix_scatter, dim3(grid), dim3(BLOCK), 0, s, keys[cur], vals[cur],
+    hipLaunchKernelGGL(k_radix_scatter<ITEMS>, dim3(grid), dim3(BLOCK), 0, s, keys[cur], vals[cur],
                        keys[cur ^ 1], vals[cur ^ 1], n_dev, n_static, cap, shift, nbits, hist, hoff,
                        max_tiles, digit_total);
     cur ^= 1;
@@ -270,22 +277,24 @@ static int radix_sort(uint32_t *keys[2], uint32_t *vals[2], const unsigned long 
   return cur;
 }
 
-static int sort_grid_for(int64_t n, int cap_grid) {
-  int64_t t = (n + SORT_TILE - 1) / SORT_TILE;
+static int sort_grid_for(int64_t n, int items, int cap_grid) {
+  int64_t t = (n + (int64_t)BLOCK * items - 1) / ((int64_t)BLOCK * items);
   if (t > cap_grid) t = cap_grid;
   return t < 1 ? 1 : (int)t;
 }
 
 int launch_depth_sort(const Plan &p, Workspace &ws, hipStream_t s, int sort_grid) {
-  ws.dsorted = radix_sort(ws.dkeys, ws.dvals, nullptr, (uint32_t)p.n_rec, (uint32_t)p.n_rec, 32,
-                          ws.hist, ws.hoff, p.max_sort_tiles, ws.digit_total, sort_grid_for(p.n_rec, sort_grid), s);
+  ws.dsorted = radix_sort<SORT_ITEMS_DEPTH>(ws.dkeys, ws.dvals, nullptr, (uint32_t)p.n_rec, (uint32_t)p.n_rec, 32,
+                                            ws.hist, ws.hoff, p.max_sort_tiles, ws.digit_total,
+                                            sort_grid_for(p.n_rec, SORT_ITEMS_DEPTH, sort_grid), s);
   return ws.dsorted;
 }
 
 int launch_pair_sort(const Plan &p, Workspace &ws, hipStream_t s, int sort_grid) {
   const unsigned long long *n_dev = reinterpret_cast<const unsigned long long *>(ws.hdr + HDR_NPAIRS);
-  ws.psorted = radix_sort(ws.pkeys, ws.pvals, n_dev, 0u, (uint32_t)p.capacity, p.tile_bits, ws.hist,
-                          ws.hoff, p.max_sort_tiles, ws.digit_total, sort_grid_for(p.capacity, sort_grid), s);
+  ws.psorted = radix_sort<SORT_ITEMS_PAIR>(ws.pkeys, ws.pvals, n_dev, 0u, (uint32_t)p.capacity, p.tile_bits,
+                                           ws.hist, ws.hoff, p.max_sort_tiles, ws.digit_total,
+                                           sort_grid_for(p.capacity, SORT_ITEMS_PAIR, sort_grid), s);
   return ws.psorted;
 }
 
@@ -400,16 +409,39 @@ __global__ __launch_bounds__(BLOCK) void k_emit_pairs(const uint32_t *__restrict
                                                       uint32_t cap, const uint32_t *__restrict__ bucket_rec,
                                                       uint32_t *__restrict__ pkeys, uint32_t *__restrict__ pvals) {
   static_assert(EMIT_BUCKET == BLOCK, "one emission bucket per block-iteration");
+  __shared__ uint32_t s_off[BLOCK], s_ord[BLOCK];
   const uint32_t n = sort_count(n_dev, 0u, cap);
   const uint32_t nb = (n + EMIT_BUCKET - 1) / EMIT_BUCKET;
   for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
     const uint32_t lo = bucket_rec[b];
     const uint32_t hi = b + 1 < nb ? bucket_rec[b + 1] : n_rec - 1u;
+    // The bucket's records (offsets and ids) go to LDS when they fit (a
+    // bucket of 256 pairs spans at most 257 records with pairs).
+    const uint32_t nr = hi - lo + 1u;
+    const bool in_lds = nr <= (uint32_t)BLOCK;
+    __syncthreads();
+    if (in_lds && threadIdx.x < nr) {
+      s_off[threadIdx.x] = off[lo + threadIdx.x];
+      s_ord[threadIdx.x] = order[lo + threadIdx.x];
+    }
+    __syncthreads();
     const uint32_t p = b * EMIT_BUCKET + threadIdx.x;
     if (p < n) {
-      const uint32_t k = find_record(off, lo, hi, p);
-      const uint32_t rec = order[k];
-      const uint32_t j = p - off[k];
+      uint32_t rec, j;
+      if (in_lds) {
+        uint32_t a = 0u, z = nr - 1u;  // largest index with s_off <= p
+        while (a < z) {
+          const uint32_t mid = a + (z - a + 1u) / 2u;
+          if (s_off[mid] <= p) a = mid;
+          else z = mid - 1u;
+        }
+        rec = s_ord[a];
+        j = p - s_off[a];
+      } else {
+        const uint32_t k = find_record(off, lo, hi, p);
+        rec = order[k];
+        j = p - off[k];
+      }
       const uint4 ti = tinfo[rec];
       const int TX = (int)(ti.y & 0x7FFFFFFFu);
       const int tx0 = (int)(ti.z & 0xFFFFu), tx1 = (int)(ti.z >> 16);
