@@ -154,6 +154,9 @@ def run_headline(args, gsr, torch, W):
     calls = max(1, st.pop("calls"))
     stages = {k: v / calls for k, v in st.items()}
     work = r.work_counts()
+    rng, _ = r.debug_tiles()
+    # pairs inside the tile lists (the rest lie outside their Gaussian's alpha support)
+    work["pairs_listed"] = int((rng[:, 1] - rng[:, 0]).clamp(min=0).sum())
     raster_ms = stages["raster"]
     flops = (work["fwd_evals"] * FLOP_FWD_EVAL + work["blended"] * FLOP_BLEND +
              work["bwd_evals"] * FLOP_BWD_EVAL + work["blended"] * FLOP_BWD_CONTRIB)

@@ -21,6 +21,12 @@ constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_CHUNK = BLOCK * SCAN_ITEMS;
 constexpr int EMIT_BUCKET = 256;  // pairs per emission bucket (one block-iteration of k_emit_pairs)
 
+// Bits per radix pass for keys of key_bits bits: ceil(key_bits / 8) passes
+// with the bits spread evenly (fewer digit values make longer output runs).
+__host__ __device__ constexpr int radix_digit_bits(int key_bits) {
+  return (key_bits + (key_bits + RADIX_BITS - 1) / RADIX_BITS - 1) / ((key_bits + RADIX_BITS - 1) / RADIX_BITS);
+}
+
 // Per-view geometry of the concatenated output (device copy lives in the
 // context, written at plan time).
 struct ViewInfo {

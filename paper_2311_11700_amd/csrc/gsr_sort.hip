@@ -108,6 +108,7 @@ __device__ __forceinline__ uint32_t sort_count(const unsigned long long *n_dev, 
   return n < cap ? (uint32_t)n : cap;
 }
 
+// Digit counts of each sort tile (STILE consecutive keys), digit-major.
 template <int ITEMS>
 __global__ __launch_bounds__(BLOCK) void k_radix_hist(const uint32_t *__restrict__ keys,
                                                       const unsigned long long *n_dev,
@@ -121,12 +122,17 @@ __global__ __launch_bounds__(BLOCK) void k_radix_hist(const uint32_t *__restrict
   const uint32_t mask = (1u << nbits) - 1u;
   for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     cnt[threadIdx.x] = 0u;
-    __syncthreads();
+    uint32_t kr[ITEMS];
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
       const uint32_t idx = t * STILE + r * BLOCK + threadIdx.x;
-      const bool valid = idx < n;
-      const uint32_t d = valid ? (keys[idx] >> shift) & mask : 0u;
+      kr[r] = idx < n ? keys[idx] : 0u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+      const bool valid = t * STILE + r * BLOCK + threadIdx.x < n;
+      const uint32_t d = (kr[r] >> shift) & mask;
       const uint64_t peers = match_digit(d, nbits, __ballot(valid));
       if (valid && (peers & lanemask_lt()) == 0ull) atomicAdd(&cnt[d], (uint32_t)__popcll(peers));
     }
@@ -173,12 +179,13 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scan(const uint32_t *__restrict
   if (threadIdx.x == 0) digit_total[blockIdx.x] = carry;
 }
 
-// Stable scatter of one digit pass.  Each sort tile (2048 keys) is first
-// ranked into block-local digit order in LDS (wave64 ballot matching gives
-// the rank among equal digits of a wavefront; per-wave digit counts give the
-// rest), then written out so that each digit's keys of the tile form one
-// contiguous run in the output: consecutive threads store consecutive
-// addresses.
+// Stable scatter of one digit pass.  Wavefront w ranks the w-th quarter of
+// the sort tile: equal digits inside a row of 64 keys by ballot matching, and
+// across its rows by wavefront-private counts per digit in LDS (no block
+// barrier between rows).  The per-wavefront counts, the tile's digit counts
+// and the digit offsets then place every key in block-local digit order in
+// LDS, and each digit's keys of the tile are written as one contiguous run:
+// consecutive threads store consecutive addresses.
 template <int ITEMS>
 __global__ __launch_bounds__(BLOCK) void k_radix_scatter(
     const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in,
@@ -186,66 +193,73 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(
     const unsigned long long *n_dev, uint32_t n_static, uint32_t cap, int shift, int nbits,
     const uint32_t *__restrict__ hist, const uint32_t *__restrict__ hoff, int max_tiles,
     const uint32_t *__restrict__ digit_total) {
+  constexpr int STILE = BLOCK * ITEMS;
+  constexpr int WKEYS = 64 * ITEMS;
   __shared__ uint32_t s_base[RADIX];   // first output position of each digit
   __shared__ uint32_t s_goff[RADIX];   // output position minus local position, per digit
-  __shared__ uint32_t s_run[RADIX];    // next local position per digit
-  __shared__ uint32_t s_wcnt[4][RADIX];
+  __shared__ uint32_t s_lbase[RADIX];  // first local position of each digit
+  __shared__ uint32_t s_wc[4][RADIX];  // per-wavefront digit counts, then their prefix over wavefronts
   __shared__ uint32_t s_w[4];
-  __shared__ uint32_t s_k[BLOCK * ITEMS];
-  __shared__ uint32_t s_v[BLOCK * ITEMS];
+  __shared__ uint32_t s_k[STILE];
+  __shared__ uint32_t s_v[STILE];
   const uint32_t n = sort_count(n_dev, n_static, cap);
-  constexpr int STILE = BLOCK * ITEMS;
   const uint32_t ntiles = (n + STILE - 1) / STILE;
   const uint32_t mask = (1u << nbits) - 1u;
-  const int wave = threadIdx.x >> 6;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int dig = threadIdx.x;
   {
     uint32_t total;
-    s_base[threadIdx.x] = block_exclusive_scan<uint32_t>(digit_total[threadIdx.x], s_w, total);
-    s_wcnt[0][threadIdx.x] = s_wcnt[1][threadIdx.x] = s_wcnt[2][threadIdx.x] = s_wcnt[3][threadIdx.x] = 0u;
+    s_base[dig] = block_exclusive_scan<uint32_t>(digit_total[dig], s_w, total);
   }
-  __syncthreads();
   for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const uint32_t t0 = t * STILE;
     const uint32_t tn = n - t0 < (uint32_t)STILE ? n - t0 : (uint32_t)STILE;
-    {
-      const uint32_t cnt = hist[(size_t)threadIdx.x * max_tiles + t];
-      uint32_t total;
-      const uint32_t lbase = block_exclusive_scan<uint32_t>(cnt, s_w, total);
-      s_run[threadIdx.x] = lbase;
-      s_goff[threadIdx.x] = s_base[threadIdx.x] + hoff[(size_t)threadIdx.x * max_tiles + t] - lbase;
-    }
-    __syncthreads();
-    // All loads of the sort tile are issued up front.
-    uint32_t kr[ITEMS], vr[ITEMS];
+    const uint32_t wbase = t0 + wave * WKEYS + lane;
+    uint32_t kr[ITEMS], vr[ITEMS], rank[ITEMS];
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
-      const uint32_t idx = t0 + r * BLOCK + threadIdx.x;
+      const uint32_t idx = wbase + r * 64;
       kr[r] = idx < n ? keys_in[idx] : 0u;
       vr[r] = idx < n ? vals_in[idx] : 0u;
     }
+    s_wc[0][dig] = s_wc[1][dig] = s_wc[2][dig] = s_wc[3][dig] = 0u;
+    {
+      const uint32_t cnt = hist[(size_t)dig * max_tiles + t];
+      uint32_t total;
+      const uint32_t lbase = block_exclusive_scan<uint32_t>(cnt, s_w, total);
+      s_lbase[dig] = lbase;
+      s_goff[dig] = s_base[dig] + hoff[(size_t)dig * max_tiles + t] - lbase;
+    }
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
-      const uint32_t idx = t0 + r * BLOCK + threadIdx.x;
-      const bool valid = idx < n;
-      const uint32_t key = kr[r];
-      const uint32_t val = vr[r];
-      const uint32_t d = (key >> shift) & mask;
+      const bool valid = wbase + r * 64 < n;
+      const uint32_t d = (kr[r] >> shift) & mask;
       const uint64_t peers = match_digit(d, nbits, __ballot(valid));
       const uint64_t below = peers & lanemask_lt();
-      if (valid && below == 0ull) s_wcnt[wave][d] = (uint32_t)__popcll(peers);
-      __syncthreads();
-      if (valid) {
-        uint32_t pos = s_run[d] + (uint32_t)__popcll(below);
-        for (int w = 0; w < wave; ++w) pos += s_wcnt[w][d];
-        s_k[pos] = key;
-        s_v[pos] = val;
-      }
-      __syncthreads();
-      const int dd = threadIdx.x;
-      s_run[dd] += s_wcnt[0][dd] + s_wcnt[1][dd] + s_wcnt[2][dd] + s_wcnt[3][dd];
-      s_wcnt[0][dd] = s_wcnt[1][dd] = s_wcnt[2][dd] = s_wcnt[3][dd] = 0u;
-      __syncthreads();
+      // Wavefront-private counts: every lane reads before the group's
+      // leader adds the group size (program order within the wavefront).
+      const uint32_t before = valid ? s_wc[wave][d] : 0u;
+      rank[r] = before + (uint32_t)__popcll(below);
+      if (valid && below == 0ull) s_wc[wave][d] = before + (uint32_t)__popcll(peers);
     }
+    __syncthreads();
+    {
+      const uint32_t c0 = s_wc[0][dig], c1 = s_wc[1][dig], c2 = s_wc[2][dig];
+      s_wc[0][dig] = s_lbase[dig];
+      s_wc[1][dig] = s_lbase[dig] + c0;
+      s_wc[2][dig] = s_lbase[dig] + c0 + c1;
+      s_wc[3][dig] = s_lbase[dig] + c0 + c1 + c2;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r) {
+      if (wbase + r * 64 < n) {
+        const uint32_t lp = s_wc[wave][(kr[r] >> shift) & mask] + rank[r];
+        s_k[lp] = kr[r];
+        s_v[lp] = vr[r];
+      }
+    }
+    __syncthreads();
     for (uint32_t i = threadIdx.x; i < tn; i += BLOCK) {
       const uint32_t key = s_k[i];
       const uint32_t gpos = s_goff[(key >> shift) & mask] + i;
@@ -258,15 +272,19 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(
 
 // Stable LSD radix sort of (key, value) over bits [0, key_bits); returns the
 // index of the buffer holding the result.
+// When hist0_ready, the first pass's per-tile digit counts are already in
+// hist (written by the kernel that produced the keys).
 template <int ITEMS>
 static int radix_sort(uint32_t *keys[2], uint32_t *vals[2], const unsigned long long *n_dev,
                       uint32_t n_static, uint32_t cap, int key_bits, uint32_t *hist, uint32_t *hoff,
-                      int max_tiles, uint32_t *digit_total, int grid, hipStream_t s) {
+                      int max_tiles, uint32_t *digit_total, int grid, bool hist0_ready, hipStream_t s) {
+  const int per = radix_digit_bits(key_bits);
   int cur = 0;
-  for (int shift = 0; shift < key_bits; shift += RADIX_BITS) {
-    const int nbits = key_bits - shift < RADIX_BITS ? key_bits - shift : RADIX_BITS;
-    hipLaunchKernelGGL(k_radix_hist<ITEMS>, dim3(grid), dim3(BLOCK), 0, s, keys[cur], n_dev, n_static, cap,
-                       shift, nbits, hist, max_tiles);
+  for (int shift = 0; shift < key_bits; shift += per) {
+    const int nbits = key_bits - shift < per ? key_bits - shift : per;
+    if (shift > 0 || !hist0_ready)
+      hipLaunchKernelGGL(k_radix_hist<ITEMS>, dim3(grid), dim3(BLOCK), 0, s, keys[cur], n_dev, n_static, cap,
+                         shift, nbits, hist, max_tiles);
     hipLaunchKernelGGL(k_radix_scan<ITEMS>, dim3(RADIX), dim3(BLOCK), 0, s, hist, hoff, n_dev, n_static, cap,
                        max_tiles, digit_total);
     hipLaunchKernelGGL(k_radix_scatter<ITEMS>, dim3(grid), dim3(BLOCK), 0, s, keys[cur], vals[cur],
@@ -286,7 +304,7 @@ static int sort_grid_for(int64_t n, int items, int cap_grid) {
 int launch_depth_sort(const Plan &p, Workspace &ws, hipStream_t s, int sort_grid) {
   ws.dsorted = radix_sort<SORT_ITEMS_DEPTH>(ws.dkeys, ws.dvals, nullptr, (uint32_t)p.n_rec, (uint32_t)p.n_rec, 32,
                                             ws.hist, ws.hoff, p.max_sort_tiles, ws.digit_total,
-                                            sort_grid_for(p.n_rec, SORT_ITEMS_DEPTH, sort_grid), s);
+                                            sort_grid_for(p.n_rec, SORT_ITEMS_DEPTH, sort_grid), false, s);
   return ws.dsorted;
 }
 
@@ -294,7 +312,7 @@ int launch_pair_sort(const Plan &p, Workspace &ws, hipStream_t s, int sort_grid)
   const unsigned long long *n_dev = reinterpret_cast<const unsigned long long *>(ws.hdr + HDR_NPAIRS);
   ws.psorted = radix_sort<SORT_ITEMS_PAIR>(ws.pkeys, ws.pvals, n_dev, 0u, (uint32_t)p.capacity, p.tile_bits,
                                            ws.hist, ws.hoff, p.max_sort_tiles, ws.digit_total,
-                                           sort_grid_for(p.capacity, SORT_ITEMS_PAIR, sort_grid), s);
+                                           sort_grid_for(p.capacity, SORT_ITEMS_PAIR, sort_grid), true, s);
   return ws.psorted;
 }
 
@@ -397,9 +415,11 @@ __device__ __forceinline__ uint32_t find_record(const uint32_t *__restrict__ off
 // One thread per (tile, Gaussian) pair: find the record that owns the pair
 // (records are in depth order, so the pairs come out in depth order), decode
 // the tile from the record's rectangle, test it against the alpha support,
-// write key and value.  Block-iteration b covers the pairs of emission
-// bucket b; the bucket index brackets its records, so the per-thread
-// searches are short.
+// write key and value.  A block-iteration covers one sort tile of the pair
+// sort (SORT_ITEMS_PAIR emission buckets of EMIT_BUCKET pairs) and also
+// writes that tile's digit counts for the sort's first pass.  Within a
+// bucket the bucket index brackets the records, so the per-thread searches
+// are short.
 __global__ __launch_bounds__(BLOCK) void k_emit_pairs(const uint32_t *__restrict__ order,
                                                       const uint32_t *__restrict__ off,
                                                       const uint4 *__restrict__ tinfo,
@@ -407,65 +427,80 @@ __global__ __launch_bounds__(BLOCK) void k_emit_pairs(const uint32_t *__restrict
                                                       const float4 *__restrict__ recB, uint32_t dropped_key,
                                                       uint32_t n_rec, const unsigned long long *__restrict__ n_dev,
                                                       uint32_t cap, const uint32_t *__restrict__ bucket_rec,
-                                                      uint32_t *__restrict__ pkeys, uint32_t *__restrict__ pvals) {
+                                                      uint32_t *__restrict__ pkeys, uint32_t *__restrict__ pvals,
+                                                      int nbits0, uint32_t *__restrict__ hist, int max_tiles) {
   static_assert(EMIT_BUCKET == BLOCK, "one emission bucket per block-iteration");
+  constexpr int STILE = BLOCK * SORT_ITEMS_PAIR;
   __shared__ uint32_t s_off[BLOCK], s_ord[BLOCK];
+  __shared__ uint32_t s_cnt[RADIX];
   const uint32_t n = sort_count(n_dev, 0u, cap);
   const uint32_t nb = (n + EMIT_BUCKET - 1) / EMIT_BUCKET;
-  for (uint32_t b = blockIdx.x; b < nb; b += gridDim.x) {
-    const uint32_t lo = bucket_rec[b];
-    const uint32_t hi = b + 1 < nb ? bucket_rec[b + 1] : n_rec - 1u;
-    // The bucket's records (offsets and ids) go to LDS when they fit (a
-    // bucket of 256 pairs spans at most 257 records with pairs).
-    const uint32_t nr = hi - lo + 1u;
-    const bool in_lds = nr <= (uint32_t)BLOCK;
-    __syncthreads();
-    if (in_lds && threadIdx.x < nr) {
-      s_off[threadIdx.x] = off[lo + threadIdx.x];
-      s_ord[threadIdx.x] = order[lo + threadIdx.x];
-    }
-    __syncthreads();
-    const uint32_t p = b * EMIT_BUCKET + threadIdx.x;
-    if (p < n) {
-      uint32_t rec, j;
-      if (in_lds) {
-        uint32_t a = 0u, z = nr - 1u;  // largest index with s_off <= p
-        while (a < z) {
-          const uint32_t mid = a + (z - a + 1u) / 2u;
-          if (s_off[mid] <= p) a = mid;
-          else z = mid - 1u;
+  const uint32_t ntiles = (n + STILE - 1) / STILE;
+  const uint32_t mask0 = (1u << nbits0) - 1u;
+  for (uint32_t T = blockIdx.x; T < ntiles; T += gridDim.x) {
+    s_cnt[threadIdx.x] = 0u;
+    for (uint32_t b = T * SORT_ITEMS_PAIR; b < (T + 1) * SORT_ITEMS_PAIR && b < nb; ++b) {
+      const uint32_t lo = bucket_rec[b];
+      const uint32_t hi = b + 1 < nb ? bucket_rec[b + 1] : n_rec - 1u;
+      // The bucket's records (offsets and ids) go to LDS when they fit (a
+      // bucket of 256 pairs spans at most 257 records with pairs).
+      const uint32_t nr = hi - lo + 1u;
+      const bool in_lds = nr <= (uint32_t)BLOCK;
+      __syncthreads();
+      if (in_lds && threadIdx.x < nr) {
+        s_off[threadIdx.x] = off[lo + threadIdx.x];
+        s_ord[threadIdx.x] = order[lo + threadIdx.x];
+      }
+      __syncthreads();
+      const uint32_t p = b * EMIT_BUCKET + threadIdx.x;
+      uint32_t tile = 0u;
+      if (p < n) {
+        uint32_t rec, j;
+        if (in_lds) {
+          uint32_t a = 0u, z = nr - 1u;  // largest index with s_off <= p
+          while (a < z) {
+            const uint32_t mid = a + (z - a + 1u) / 2u;
+            if (s_off[mid] <= p) a = mid;
+            else z = mid - 1u;
+          }
+          rec = s_ord[a];
+          j = p - s_off[a];
+        } else {
+          const uint32_t k = find_record(off, lo, hi, p);
+          rec = order[k];
+          j = p - off[k];
         }
-        rec = s_ord[a];
-        j = p - s_off[a];
-      } else {
-        const uint32_t k = find_record(off, lo, hi, p);
-        rec = order[k];
-        j = p - off[k];
+        const uint4 ti = tinfo[rec];
+        const int TX = (int)(ti.y & 0x7FFFFFFFu);
+        const int tx0 = (int)(ti.z & 0xFFFFu), tx1 = (int)(ti.z >> 16);
+        const int ty0 = (int)(ti.w & 0xFFFFu);
+        const uint32_t w = (uint32_t)(tx1 - tx0 + 1);
+        // j < 2^24 and w < 2^16: the float quotient is within one of the
+        // integer quotient; fix it up exactly.
+        uint32_t q = (uint32_t)((float)j / (float)w);
+        if (q * w > j) --q;
+        else if ((q + 1u) * w <= j) ++q;
+        const int ty = ty0 + (int)q, tx = tx0 + (int)(j - q * w);
+        tile = ti.x + (uint32_t)(ty * TX + tx);
+        if (ti.y & 0x80000000u) {
+          // Tiles of the rectangle that the alpha support does not reach get
+          // the key past the last tile: the sort moves them behind every list.
+          const Support sp = support[rec];
+          const float4 cb = recB[rec];
+          int c0 = 0;
+          const int len = support_row(sp, (double)cb.x, (double)cb.y, (double)cb.z, ty, tx0, tx1, c0);
+          if (tx < c0 || tx >= c0 + len) tile = dropped_key;
+        }
+        pkeys[p] = tile;
+        pvals[p] = rec;
       }
-      const uint4 ti = tinfo[rec];
-      const int TX = (int)(ti.y & 0x7FFFFFFFu);
-      const int tx0 = (int)(ti.z & 0xFFFFu), tx1 = (int)(ti.z >> 16);
-      const int ty0 = (int)(ti.w & 0xFFFFu);
-      const uint32_t w = (uint32_t)(tx1 - tx0 + 1);
-      // j < 2^24 and w < 2^16: the float quotient is within one of the
-      // integer quotient; fix it up exactly.
-      uint32_t q = (uint32_t)((float)j / (float)w);
-      if (q * w > j) --q;
-      else if ((q + 1u) * w <= j) ++q;
-      const int ty = ty0 + (int)q, tx = tx0 + (int)(j - q * w);
-      uint32_t tile = ti.x + (uint32_t)(ty * TX + tx);
-      if (ti.y & 0x80000000u) {
-        // Tiles of the rectangle that the alpha support does not reach get
-        // the key past the last tile: the sort moves them behind every list.
-        const Support sp = support[rec];
-        const float4 cb = recB[rec];
-        int c0 = 0;
-        const int len = support_row(sp, (double)cb.x, (double)cb.y, (double)cb.z, ty, tx0, tx1, c0);
-        if (tx < c0 || tx >= c0 + len) tile = dropped_key;
-      }
-      pkeys[p] = tile;
-      pvals[p] = rec;
+      const uint32_t d = tile & mask0;
+      const uint64_t peers = match_digit(d, nbits0, __ballot(p < n));
+      if (p < n && (peers & lanemask_lt()) == 0ull) atomicAdd(&s_cnt[d], (uint32_t)__popcll(peers));
     }
+    __syncthreads();
+    hist[(size_t)threadIdx.x * max_tiles + T] = s_cnt[threadIdx.x];
+    __syncthreads();
   }
 }
 
@@ -480,13 +515,14 @@ void launch_emit_pairs(const Plan &p, const Workspace &ws, const ViewInfo *views
   if (p.n_rec == 0) return;
   hipLaunchKernelGGL(k_scan_down, dim3(p.n_scan_blocks), dim3(BLOCK), 0, s, order, ws.count, p.n_rec,
                      ws.scan_part, (uint64_t)p.capacity, off, ws.bucket_rec);
-  int64_t blocks = (p.capacity + BLOCK - 1) / BLOCK;
+  int64_t blocks = (p.capacity + (int64_t)BLOCK * SORT_ITEMS_PAIR - 1) / ((int64_t)BLOCK * SORT_ITEMS_PAIR);
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
   const unsigned long long *n_dev = reinterpret_cast<const unsigned long long *>(ws.hdr + HDR_NPAIRS);
   hipLaunchKernelGGL(k_emit_pairs, dim3((unsigned)blocks), dim3(BLOCK), 0, s, order, off, ws.tinfo, ws.support,
                      ws.recB, (uint32_t)p.total_tiles, (uint32_t)p.n_rec, n_dev, (uint32_t)p.capacity,
-                     ws.bucket_rec, ws.pkeys[0], ws.pvals[0]);
+                     ws.bucket_rec, ws.pkeys[0], ws.pvals[0], radix_digit_bits(p.tile_bits), ws.hist,
+                     p.max_sort_tiles);
 }
 
 // ---------------------------------------------------------------- tile ranges
