@@ -84,11 +84,9 @@ def make_targets(gsr, torch, W, r, g, cams_d, sizes, seed=1):
     return (torch.as_tensor(t_rgb).cuda(), torch.as_tensor(t_d).cuda()), r.pair_count()
 
 
-def time_graph(torch, r, grads, loss, steps, warmup, stream):
+def time_graph(torch, r, steps, warmup, stream):
+    # The captured step overwrites gradients and loss (GSR_GRAD_OVERWRITE).
     def step():
-        for t in grads.values():
-            t.zero_()
-        loss.zero_()
         r.graph_launch(stream=stream)
 
     with torch.cuda.stream(stream):
@@ -117,7 +115,7 @@ def run_headline(args, gsr, torch, W):
     r.plan(scene.n, sizes)
     (t_rgb, t_d), pairs = make_targets(gsr, torch, W, r, g, cams_d, sizes)
     r.plan(scene.n, sizes, pair_capacity=int(pairs * 1.25) + 4096)
-    cfg = gsr.Config()
+    cfg = gsr.Config(flags=gsr.GSR_GAUSS_GRAD | gsr.GSR_POSE_GRAD | gsr.GSR_GRAD_OVERWRITE)
     tuning = r.get_tuning()
     if args.tuning:
         b, p, l = (int(x) for x in args.tuning.split(","))
@@ -133,7 +131,7 @@ def run_headline(args, gsr, torch, W):
     with torch.cuda.stream(stream):
         r.graph_capture(g, cams_d, cfg, t_rgb, t_d, None, 1.0, 0.1, grads=grads, loss=loss, stream=stream)
     stream.synchronize()
-    ms, wall = time_graph(torch, r, grads, loss, args.steps, args.warmup, stream)
+    ms, wall = time_graph(torch, r, args.steps, args.warmup, stream)
     r.check_overflow(stream=stream)
     log(f"graph step: {ms:.3f} ms (wall {wall:.3f} ms), loss {loss.item():.2f}")
 
@@ -189,7 +187,7 @@ def run_batched(args, gsr, torch, W):
     rb.plan(scene.n, sizes)
     (t_rgb, t_d), pairs = make_targets(gsr, torch, W, rb, g, cams_d, sizes)
     rb.plan(scene.n, sizes, pair_capacity=int(pairs * 1.25) + 4096)
-    cfg = gsr.Config()
+    cfg = gsr.Config(flags=gsr.GSR_GAUSS_GRAD | gsr.GSR_POSE_GRAD | gsr.GSR_GRAD_OVERWRITE)
     if not args.no_autotune:
         rb.autotune(g, cams_d, cfg, t_rgb, t_d, None, 1.0, 0.1, reps=1)
     grads = rb.new_grads(scene.n)
@@ -199,7 +197,7 @@ def run_batched(args, gsr, torch, W):
         rb.graph_capture(g, cams_d, cfg, t_rgb, t_d, None, 1.0, 0.1, grads=grads, loss=loss, stream=stream)
     stream.synchronize()
     steps = max(3, args.steps // 4)
-    b_ms, _ = time_graph(torch, rb, grads, loss, steps, 2, stream)
+    b_ms, _ = time_graph(torch, rb, steps, 2, stream)
     rb.check_overflow(stream=stream)
     del rb
     torch.cuda.empty_cache()
@@ -219,6 +217,7 @@ def run_batched(args, gsr, torch, W):
         per.append((r, gsr.pack_cameras([c]), tr, td))
     pose = torch.zeros(1, 6, device="cuda")
     gr1 = dict(grads)
+    cfg_acc = gsr.Config()  # the frames add into the same buffers
 
     def step():
         for t in grads.values():
@@ -226,7 +225,7 @@ def run_batched(args, gsr, torch, W):
         loss.zero_()
         for v, (r, cd, tr, td) in enumerate(per):
             gr1["d_pose"] = grads["d_pose"][v:v + 1]
-            r.render_l1_fused(g, cd, cfg, tr, td, None, 1.0, 0.1, grads=gr1, loss=loss)
+            r.render_l1_fused(g, cd, cfg_acc, tr, td, None, 1.0, 0.1, grads=gr1, loss=loss)
 
     for _ in range(2):
         step()
@@ -268,7 +267,8 @@ def run_hypotheses(args, gsr, torch, W):
         del r
     t_rgb = torch.cat([tg["half" if w == 600 else "full"][0] for w, _ in sizes])
     t_d = torch.cat([tg["half" if w == 600 else "full"][1] for w, _ in sizes])
-    cfg = gsr.Config(flags=gsr.GSR_POSE_GRAD)
+    cfg = gsr.Config(flags=gsr.GSR_POSE_GRAD | gsr.GSR_GRAD_OVERWRITE)
+    cfg_acc = gsr.Config(flags=gsr.GSR_POSE_GRAD)
     cams_d = gsr.pack_cameras(cams)
     rb = gsr.Renderer(0)
     rb.plan(scene.n, sizes)
@@ -288,8 +288,6 @@ def run_hypotheses(args, gsr, torch, W):
         for it in range(args.hyp_batches + 3):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            grads["d_pose"].zero_()
-            loss.zero_()
             rb.graph_launch(stream=stream)
             e1.record(stream)
             e1.synchronize()
@@ -317,7 +315,7 @@ def run_hypotheses(args, gsr, torch, W):
         loss.zero_()
         for v, (w, hh) in enumerate(sizes):
             gr1["d_pose"] = grads["d_pose"][v:v + 1]
-            rs[(w, hh)].render_l1_fused(g, per_cams[v], cfg, t_rgb[3 * offs[v]:3 * (offs[v] + w * hh)],
+            rs[(w, hh)].render_l1_fused(g, per_cams[v], cfg_acc, t_rgb[3 * offs[v]:3 * (offs[v] + w * hh)],
                                         t_d[offs[v]:offs[v] + w * hh], None, 1.0, 0.1, grads=gr1, loss=loss)
 
     step()

@@ -91,7 +91,11 @@ enum {
   GSR_POSE_GRAD = 1u << 2,
   /* Pose gradient through the projected centre and depth only, dropping
    * the Sigma' term as the paper does for speed (Sec. 3.3, supplement). */
-  GSR_PAPER_POSE_APPROX = 1u << 3
+  GSR_PAPER_POSE_APPROX = 1u << 3,
+  /* Fused step and backward: write the gradients (and the fused step's
+   * loss) instead of adding them to the caller's buffers, so the caller
+   * need not clear them between steps. */
+  GSR_GRAD_OVERWRITE = 1u << 4
 };
 
 /* Renderer constants.  The paper is silent on them; gsr_default_config()

@@ -7,7 +7,7 @@ parameter and the se(3) camera pose -- all in hand-written HIP kernels
 behind the C ABI of include/gsr.h.  This package is the ctypes binding.
 """
 from ._abi import (  # noqa: F401
-    GSR_FULL_RECT, GSR_GAUSS_GRAD, GSR_POSE_GRAD, GSR_PAPER_POSE_APPROX,
+    GSR_FULL_RECT, GSR_GAUSS_GRAD, GSR_POSE_GRAD, GSR_PAPER_POSE_APPROX, GSR_GRAD_OVERWRITE,
     GSR_OK, GSR_E_INVALID, GSR_E_CAPACITY, GSR_E_HIP, GSR_E_UNSUPPORTED, GSR_E_STATE,
     load, exported_symbols, LIB_PATH,
 )

@@ -30,6 +30,7 @@ GSR_FULL_RECT = 1 << 0
 GSR_GAUSS_GRAD = 1 << 1
 GSR_POSE_GRAD = 1 << 2
 GSR_PAPER_POSE_APPROX = 1 << 3
+GSR_GRAD_OVERWRITE = 1 << 4
 
 
 class gsr_camera(ctypes.Structure):

@@ -179,6 +179,23 @@ __device__ __forceinline__ float wave_sum(float v) {
   return v;
 }
 
+// Per-call header reset (one thread).  The overflow flag and required count
+// are sticky until gsr_check_overflow reads them; on a workspace's first use
+// (no magic yet) they are cleared too.
+__device__ __forceinline__ void reset_header_words(uint32_t *hdr) {
+  if (hdr[HDR_MAGIC] != HDR_MAGIC0 || hdr[HDR_MAGIC + 1] != HDR_MAGIC1) {
+    hdr[HDR_REQUIRED] = 0u;
+    hdr[HDR_REQUIRED + 1] = 0u;
+    hdr[HDR_OVERFLOW] = 0u;
+    hdr[HDR_MAGIC] = HDR_MAGIC0;
+    hdr[HDR_MAGIC + 1] = HDR_MAGIC1;
+  }
+  hdr[HDR_NPAIRS] = 0u;
+  hdr[HDR_NPAIRS + 1] = 0u;
+  hdr[HDR_QUEUE] = 0u;
+  hdr[HDR_FWD_DONE] = 1u;
+}
+
 __device__ __forceinline__ unsigned long long lanemask_lt() {
   const unsigned lane = __lane_id();
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
@@ -187,8 +204,11 @@ __device__ __forceinline__ unsigned long long lanemask_lt() {
 // --------------------------------------------------------------- launchers (host)
 
 // Preprocess (projection, binning data, depth keys) for every (view, Gaussian).
+// Also resets the per-call header words, clears grad2d when clear_grad2d,
+// and zeroes *loss_zero when it is not null (start of a fused step).
 void launch_preprocess(const gsr_gaussians &g, const gsr_camera *cams, const ViewInfo *views,
-                       int n_views, const gsr_config &cfg, const Workspace &ws, hipStream_t s);
+                       int n_views, const gsr_config &cfg, const Workspace &ws, bool clear_grad2d,
+                       float *loss_zero, hipStream_t s);
 
 // Reliable-Gaussian selection (fine tracking stage).
 void launch_select_reliable(const gsr_gaussians &g, const gsr_camera *cam, const float *depth, int W, int H,

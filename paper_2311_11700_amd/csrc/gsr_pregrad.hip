@@ -12,6 +12,11 @@ struct PreConstsB {
   float fov_guard;
 };
 
+// dst += v, or dst = v when the gradients are overwritten.
+__device__ __forceinline__ void put(float &dst, double v, bool overwrite) {
+  dst = overwrite ? (float)v : dst + (float)v;
+}
+
 // The chain runs in FP64: gfx950 executes FP64 vector arithmetic at the
 // non-packed FP32 rate, and near-camera Gaussians put 1/z^3 factors and
 // cancelling terms into this chain.
@@ -241,45 +246,47 @@ __global__ __launch_bounds__(BLOCK) void k_preprocess_bwd(gsr_gaussians g,
     const R dotq = w * gw + x * gx + y * gy + z * gz;
     const R iq = qn > 0. ? 1. / qn : 0.;
     const R o = R(1) / (R(1) + exp(-opl));
+    const bool ow = (pc.flags & GSR_GRAD_OVERWRITE) != 0;
     if (gr.d_mean) {
-      gr.d_mean[3 * i] += (float)gm[0];
-      gr.d_mean[3 * i + 1] += (float)gm[1];
-      gr.d_mean[3 * i + 2] += (float)gm[2];
+      put(gr.d_mean[3 * i], gm[0], ow);
+      put(gr.d_mean[3 * i + 1], gm[1], ow);
+      put(gr.d_mean[3 * i + 2], gm[2], ow);
     }
     if (gr.d_log_scale) {
-      gr.d_log_scale[3 * i] += (float)gl0;
-      gr.d_log_scale[3 * i + 1] += (float)gl1;
-      gr.d_log_scale[3 * i + 2] += (float)gl2;
+      put(gr.d_log_scale[3 * i], gl0, ow);
+      put(gr.d_log_scale[3 * i + 1], gl1, ow);
+      put(gr.d_log_scale[3 * i + 2], gl2, ow);
     }
     if (gr.d_quat) {
       float4 *dq = reinterpret_cast<float4 *>(gr.d_quat) + i;
-      float4 cur = *dq;
+      float4 cur = ow ? make_float4(0.f, 0.f, 0.f, 0.f) : *dq;
       cur.x += (float)((gw - w * dotq) * iq);
       cur.y += (float)((gx - x * dotq) * iq);
       cur.z += (float)((gy - y * dotq) * iq);
       cur.w += (float)((gz - z * dotq) * iq);
       *dq = cur;
     }
-    if (gr.d_opacity_logit) gr.d_opacity_logit[i] += (float)(gop * o * (R(1) - o));
+    if (gr.d_opacity_logit) put(gr.d_opacity_logit[i], gop * o * (R(1) - o), ow);
     if (gr.d_rgb) {
-      gr.d_rgb[3 * i] += (float)gc0;
-      gr.d_rgb[3 * i + 1] += (float)gc1;
-      gr.d_rgb[3 * i + 2] += (float)gc2;
+      put(gr.d_rgb[3 * i], gc0, ow);
+      put(gr.d_rgb[3 * i + 1], gc1, ow);
+      put(gr.d_rgb[3 * i + 2], gc2, ow);
     }
   }
 
   if (want_pose) {
     __syncthreads();
-    R *dst = ws.pose_part + (int64_t)blockIdx.x * n_views * 6;
-    for (int k = threadIdx.x; k < n_views * 6; k += BLOCK)
-      dst[k] = s_dyn[k] + s_dyn[n_views * 6 + k] + s_dyn[2 * n_views * 6 + k] + s_dyn[3 * n_views * 6 + k];
+    const int V6 = n_views * 6;
+    R *dst = ws.pose_part + (int64_t)blockIdx.x * V6;
+    for (int k = threadIdx.x; k < V6; k += BLOCK)
+      dst[k] = s_dyn[k] + s_dyn[V6 + k] + s_dyn[2 * V6 + k] + s_dyn[3 * V6 + k];
   }
 }
 
 // Deterministic reduction of the per-block pose partials: one block per
 // (view, component), fixed summation order.
 __global__ __launch_bounds__(BLOCK) void k_pose_reduce(const double *__restrict__ part, int n_blocks,
-                                                       int n_views, float *__restrict__ d_pose) {
+                                                       int n_views, int overwrite, float *__restrict__ d_pose) {
   __shared__ double red[BLOCK];
   const int vc = blockIdx.x;  // view * 6 + component
   double acc = 0.0;
@@ -290,21 +297,21 @@ __global__ __launch_bounds__(BLOCK) void k_pose_reduce(const double *__restrict_
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) d_pose[vc] += (float)red[0];
+  if (threadIdx.x == 0) put(d_pose[vc], red[0], overwrite != 0);
 }
 
 void launch_preprocess_backward(const Plan &p, const gsr_gaussians &g, const gsr_camera *cams,
                                 const gsr_config &cfg, const Workspace &ws, const gsr_grads &gr,
                                 hipStream_t s) {
   if (g.n == 0) return;
-  PreConstsB pc{cfg.z_near, cfg.lowpass, cfg.cutoff_sigma, cfg.flags, cfg.fov_guard};
   const bool want_pose = (cfg.flags & GSR_POSE_GRAD) && gr.d_pose;
+  PreConstsB pc{cfg.z_near, cfg.lowpass, cfg.cutoff_sigma, cfg.flags, cfg.fov_guard};
   const size_t lds = want_pose ? (size_t)4 * p.n_views * 6 * sizeof(double) : 0;
   hipLaunchKernelGGL(k_preprocess_bwd, dim3(p.n_pose_blocks), dim3(BLOCK), lds, s, g, cams,
                      p.n_views, pc, ws, gr);
   if (want_pose)
-    hipLaunchKernelGGL(k_pose_reduce, dim3(p.n_views * 6), dim3(BLOCK), 0, s, ws.pose_part,
-                       p.n_pose_blocks, p.n_views, gr.d_pose);
+    hipLaunchKernelGGL(k_pose_reduce, dim3(p.n_views * 6), dim3(BLOCK), 0, s, ws.pose_part, p.n_pose_blocks,
+                       p.n_views, (cfg.flags & GSR_GRAD_OVERWRITE) ? 1 : 0, gr.d_pose);
 }
 
 }  // namespace gsr

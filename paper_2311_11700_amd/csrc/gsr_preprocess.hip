@@ -20,6 +20,8 @@ struct PreConsts {
   uint32_t flags;
   float fov_guard;
   float alpha_min;
+  int clear_grad2d;  // zero each record's grad2d row (start of a fused step)
+  float *loss_zero;  // zeroed by one thread when not null
 };
 
 // Rotation matrix of a unit quaternion (w, x, y, z) (GS-SLAM supplement,
@@ -43,8 +45,17 @@ __global__ __launch_bounds__(BLOCK) void k_preprocess(gsr_gaussians g,
                                                       PreConsts pc, Workspace ws) {
   const int view = blockIdx.y;
   const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  if (blockIdx.x == 0 && view == 0 && threadIdx.x == 0) {
+    reset_header_words(ws.hdr);
+    if (pc.loss_zero) *pc.loss_zero = 0.f;
+  }
   if (i >= g.n) return;
   const int64_t rec = (int64_t)view * g.n + i;
+  if (pc.clear_grad2d) {
+    double2 *gz = reinterpret_cast<double2 *>(ws.grad2d + rec * NGRAD2D);
+#pragma unroll
+    for (int k = 0; k < NGRAD2D / 2; ++k) gz[k] = make_double2(0.0, 0.0);
+  }
   const ViewInfo vi = views[view];
   const gsr_camera &cam = cams[view];
 
@@ -169,10 +180,17 @@ __global__ __launch_bounds__(BLOCK) void k_preprocess(gsr_gaussians g,
 }
 
 void launch_preprocess(const gsr_gaussians &g, const gsr_camera *cams, const ViewInfo *views,
-                       int n_views, const gsr_config &cfg, const Workspace &ws, hipStream_t s) {
-  PreConsts pc{cfg.z_near, cfg.lowpass, cfg.cutoff_sigma, cfg.flags, cfg.fov_guard, cfg.alpha_min};
+                       int n_views, const gsr_config &cfg, const Workspace &ws, bool clear_grad2d,
+                       float *loss_zero, hipStream_t s) {
+  PreConsts pc{cfg.z_near, cfg.lowpass, cfg.cutoff_sigma, cfg.flags, cfg.fov_guard, cfg.alpha_min,
+               clear_grad2d ? 1 : 0, loss_zero};
   dim3 grid((unsigned)((g.n + BLOCK - 1) / BLOCK), (unsigned)n_views);
-  if (g.n > 0) hipLaunchKernelGGL(k_preprocess, grid, dim3(BLOCK), 0, s, g, cams, views, pc, ws);
+  if (g.n > 0) {
+    hipLaunchKernelGGL(k_preprocess, grid, dim3(BLOCK), 0, s, g, cams, views, pc, ws);
+  } else {
+    launch_reset_header(ws, s);
+    if (loss_zero) launch_fill_f32(loss_zero, 0.f, 1, s);
+  }
 }
 
 // Reliable-Gaussian selection (Eq. 12): compare each centre's camera depth

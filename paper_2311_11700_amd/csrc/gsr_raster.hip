@@ -526,7 +526,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     if (q0 >= total_tiles) break;
     const int q1 = min(q0 + tiles_per_pop, total_tiles);
     for (int q = q0; q < q1; ++q) {
-      const int tile = (int)queue[q];
+      const int tile = queue ? (int)queue[q] : q;
       const TileInfo ti = tile_info(tile, a.views, a.tile_view, a.ranges);
       FwdState st;
       int staged_lo;
@@ -660,7 +660,8 @@ void launch_render_fused(const Plan &p, const Workspace &ws, const ViewInfo *vie
   if (grid > need) grid = need;
   if (grid < 1) grid = 1;
   PixelState ps{ws.T_final, ws.last, ws.nevals, ws.nblend};
-  hipLaunchKernelGGL(k_render_fused, dim3(grid), dim3(BLOCK), 0, s, a, ws.hdr, ws.queue, p.total_tiles,
+  const uint32_t *queue = tun.lpt_order ? ws.queue : nullptr;
+  hipLaunchKernelGGL(k_render_fused, dim3(grid), dim3(BLOCK), 0, s, a, ws.hdr, queue, p.total_tiles,
                      tun.tiles_per_pop, t_rgb, t_depth, pmask, w_rgb, w_depth, loss_cap, o, loss, ws.grad2d, ps);
 }
 

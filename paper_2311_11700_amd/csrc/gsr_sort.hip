@@ -49,19 +49,7 @@ void launch_fill_f32(float *ptr, float value, int64_t count, hipStream_t s) {
 // flag and required count are sticky until gsr_check_overflow reads them; on
 // a workspace's first use (no magic yet) they are cleared too.
 __global__ void k_reset_header(uint32_t *hdr) {
-  if (threadIdx.x == 0) {
-    if (hdr[HDR_MAGIC] != HDR_MAGIC0 || hdr[HDR_MAGIC + 1] != HDR_MAGIC1) {
-      hdr[HDR_REQUIRED] = 0u;
-      hdr[HDR_REQUIRED + 1] = 0u;
-      hdr[HDR_OVERFLOW] = 0u;
-      hdr[HDR_MAGIC] = HDR_MAGIC0;
-      hdr[HDR_MAGIC + 1] = HDR_MAGIC1;
-    }
-    hdr[HDR_NPAIRS] = 0u;
-    hdr[HDR_NPAIRS + 1] = 0u;
-    hdr[HDR_QUEUE] = 0u;
-    hdr[HDR_FWD_DONE] = 1u;
-  }
+  if (threadIdx.x == 0) reset_header_words(hdr);
 }
 
 void launch_reset_header(const Workspace &ws, hipStream_t s) {
@@ -553,14 +541,12 @@ void launch_tile_ranges(const Plan &p, const Workspace &ws, hipStream_t s) {
 
 // One block: bucket the tiles by the bit length of their list length and
 // lay them out longest bucket first.  Order inside a bucket is arbitrary.
+// (Without the longest-first order the rasteriser takes the tiles in index
+// order and reads no queue.)
 __global__ __launch_bounds__(1024) void k_queue_order(const int2 *__restrict__ ranges, int total,
-                                                      int lpt, uint32_t *__restrict__ queue) {
+                                                      uint32_t *__restrict__ queue) {
   __shared__ uint32_t s_cnt[33];
   __shared__ uint32_t s_cur[33];
-  if (!lpt) {
-    for (int t = threadIdx.x; t < total; t += blockDim.x) queue[t] = (uint32_t)t;
-    return;
-  }
   if (threadIdx.x < 33) s_cnt[threadIdx.x] = 0u;
   __syncthreads();
   for (int t = threadIdx.x; t < total; t += blockDim.x) {
@@ -587,7 +573,7 @@ __global__ __launch_bounds__(1024) void k_queue_order(const int2 *__restrict__ r
 }
 
 void launch_queue_order(const Plan &p, const Workspace &ws, int lpt, hipStream_t s) {
-  hipLaunchKernelGGL(k_queue_order, dim3(1), dim3(1024), 0, s, ws.ranges, p.total_tiles, lpt, ws.queue);
+  if (lpt) hipLaunchKernelGGL(k_queue_order, dim3(1), dim3(1024), 0, s, ws.ranges, p.total_tiles, ws.queue);
 }
 
 }  // namespace gsr

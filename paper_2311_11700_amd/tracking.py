@@ -85,7 +85,8 @@ class Tracker:
         self.g = gaussians
         self.cfg = cfg or TrackingConfig()
         rc = render_cfg or Config()
-        self.rcfg = dataclasses.replace(rc, flags=A.GSR_POSE_GRAD)
+        # Pose only; each step writes the pose gradient and loss afresh.
+        self.rcfg = dataclasses.replace(rc, flags=A.GSR_POSE_GRAD | A.GSR_GRAD_OVERWRITE)
         self.cam = cam_template
         k = self.cfg.coarse_factor
         self.coarse_cam = dataclasses.replace(
@@ -144,8 +145,6 @@ class Tracker:
                                           c.reliable_eps, self.rcfg.z_near, mask_out=self.reliable)
             if it == 0 or it == c.coarse_iters:
                 self.cap.fill_(float("inf"))
-            self.grads["d_pose"].zero_()
-            self.loss.zero_()
             pm = None if coarse else pixel_mask
             px = self.px_loss[coarse]
             r.render_l1_fused(g, cams, self.rcfg, ct if coarse else target_rgb, cd if coarse else target_depth,

@@ -462,6 +462,57 @@ def test_batched_views_equal_separate_calls(gsr_lib):
         H.assert_close_scaled(gb[k], acc[k], what=k)
 
 
+@pytest.mark.parametrize("n_views", [2, 48])
+def test_overwrite_mode_equals_accumulation_into_zeros(gsr_lib, n_views):
+    """GSR_GRAD_OVERWRITE: a fused step into buffers holding garbage gives the
+    gradients and loss that the accumulating mode adds into zeroed buffers,
+    on two calls in a row and on graph replays (2 and 48 views)."""
+    gsr = gsr_lib
+    sc = W.room_scene(3000, seed=4)
+    base = W.camera_tum_coarse()
+    base = base.with_size(base.fx / 3, base.fy / 3, 26.5, 19.5, 54, 40)
+    cams = [W.perturb_pose(base, [0.01 * (v % 5), -0.004 * (v % 3), 0.002 * v, 0.003 * (v % 4), 0.0, 0.001 * v])
+            for v in range(n_views)]
+    sizes = [(c.width, c.height) for c in cams]
+    t_rgb, t_d, mask = W.random_targets(sizes, seed=8)
+    g = H.gpu_scene(gsr, sc)
+    cams_d = gsr.pack_cameras(cams)
+    args = (H.to_dev(t_rgb), H.to_dev(t_d), H.to_dev(mask, torch.uint8))
+    r = gsr.Renderer()
+    r.plan(sc.n, sizes)
+    loss_a, grads_a = r.render_l1_fused(g, cams_d, gsr.Config(), *args)
+    ref = H.gpu_grads_numpy(grads_a)
+    ref_loss = loss_a.item()
+    assert np.abs(ref["pose"]).sum() > 0
+    cfg_o = gsr.Config(flags=gsr.GSR_GAUSS_GRAD | gsr.GSR_POSE_GRAD | gsr.GSR_GRAD_OVERWRITE)
+
+    def check(grads, loss, what):
+        got = H.gpu_grads_numpy(grads)
+        for k in ("mean", "log_scale", "quat", "opacity_logit", "rgb", "pose"):
+            np.testing.assert_allclose(got[k], ref[k], rtol=1e-5, atol=1e-6 * float(np.abs(ref[k]).max()),
+                                       err_msg=f"{what} {k}")
+        assert abs(loss.item() - ref_loss) <= 1e-5 * abs(ref_loss), what
+
+    grads = r.new_grads(sc.n)
+    loss = torch.full((1,), 5.0, device="cuda")
+    for t in grads.values():
+        t.fill_(7.0)
+    for call in range(2):
+        r.render_l1_fused(g, cams_d, cfg_o, *args, grads=grads, loss=loss)
+        check(grads, loss, f"eager call {call}")
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        r.graph_capture(g, cams_d, cfg_o, *args, grads=grads, loss=loss, stream=s)
+    s.synchronize()
+    for rep in range(3):
+        for t in grads.values():
+            t.fill_(-3.0)
+        torch.cuda.synchronize()
+        r.graph_launch(stream=s)
+        s.synchronize()
+        check(grads, loss, f"graph replay {rep}")
+
+
 def test_graph_replay_matches_eager(gsr_lib):
     gsr = gsr_lib
     sc = W.room_scene(30000, seed=1)
