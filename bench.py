@@ -151,7 +151,7 @@ def run_headline(args, gsr, torch, W):
     r.set_profiling(False)
     calls = max(1, st.pop("calls"))
     stages = {k: v / calls for k, v in st.items()}
-    work = r.work_counts()
+    work = r.work_counts(g, cfg)
     rng, _ = r.debug_tiles()
     # pairs inside the tile lists (the rest lie outside their Gaussian's alpha support)
     work["pairs_listed"] = int((rng[:, 1] - rng[:, 0]).clamp(min=0).sum())

@@ -304,8 +304,12 @@ gsr_status gsr_stage_times(gsr_ctx *ctx, double *ms, int64_t *calls);
  * `stream`): out[0] = (tile, Gaussian) pairs, out[1] = pixel-Gaussian
  * evaluations of the forward walk (every list entry a pixel examined, up to
  * and including the one that stopped it), out[2] = entries blended,
- * out[3] = list entries the backward walk examines (sum of `last`). */
-gsr_status gsr_work_counts(gsr_ctx *ctx, void *workspace, gsr_stream stream, int64_t *out);
+ * out[3] = list entries the backward walk examines (sum of `last`).  The
+ * render kernels do not count: this call walks the lists of that call again
+ * with counting on, so `g` and `cfg` must be the ones that call used, with
+ * their buffers unchanged.  Not on the hot path. */
+gsr_status gsr_work_counts(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_config *cfg, void *workspace,
+                           gsr_stream stream, int64_t *out);
 
 #ifdef __cplusplus
 }

@@ -110,7 +110,8 @@ SIGNATURES = {
                                            ctypes.c_int, ctypes.c_float, ctypes.c_float, c_void_p, c_void_p]),
     "gsr_set_profiling": (ctypes.c_int, [c_void_p, ctypes.c_int]),
     "gsr_stage_times": (ctypes.c_int, [c_void_p, _P(ctypes.c_double), _P(ctypes.c_int64)]),
-    "gsr_work_counts": (ctypes.c_int, [c_void_p, c_void_p, c_void_p, _P(ctypes.c_int64)]),
+    "gsr_work_counts": (ctypes.c_int, [c_void_p, _P(gsr_gaussians), _P(gsr_config), c_void_p, c_void_p,
+                                        _P(ctypes.c_int64)]),
 }
 
 STAGES = ("preprocess", "depth_sort", "emit", "pair_sort", "ranges", "raster", "raster_bwd", "pregrad")

@@ -81,8 +81,6 @@ Workspace make_ws(const Plan &p, void *base_v) {
   w.ranges = reinterpret_cast<int2 *>(base + p.off_ranges);
   w.T_final = reinterpret_cast<float *>(base + p.off_T);
   w.last = reinterpret_cast<int32_t *>(base + p.off_last);
-  w.nevals = reinterpret_cast<int32_t *>(base + p.off_nevals);
-  w.nblend = reinterpret_cast<int32_t *>(base + p.off_nblend);
   w.counts = reinterpret_cast<unsigned long long *>(base + p.off_counts);
   w.grad2d = reinterpret_cast<double *>(base + p.off_grad2d);
   w.pose_part = reinterpret_cast<double *>(base + p.off_pose);
@@ -332,8 +330,6 @@ gsr_status gsr_plan(gsr_ctx *ctx, int64_t n, int n_views, const int32_t *wh_host
   p.off_ranges = take(8 * (size_t)p.total_tiles);
   p.off_T = take(4 * (size_t)pixels);
   p.off_last = take(4 * (size_t)pixels);
-  p.off_nevals = take(4 * (size_t)pixels);
-  p.off_nblend = take(4 * (size_t)pixels);
   p.off_counts = take(64);
   p.off_grad2d = take(8 * NGRAD2D * nr);
   p.off_pose = take(8 * 6 * (size_t)n_views * p.n_pose_blocks);
@@ -672,12 +668,14 @@ gsr_status gsr_stage_times(gsr_ctx *ctx, double *ms, int64_t *calls) {
   return GSR_OK;
 }
 
-gsr_status gsr_work_counts(gsr_ctx *ctx, void *workspace, gsr_stream stream, int64_t *out) {
-  if (!ctx || !out) return GSR_E_INVALID;
+gsr_status gsr_work_counts(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_config *cfg, void *workspace,
+                           gsr_stream stream, int64_t *out) {
+  if (!ctx || !out || !g || !cfg) return GSR_E_INVALID;
   if (!ctx->planned || !workspace) return fail(ctx, GSR_E_STATE, "gsr_work_counts: no plan or workspace");
+  if (g->n != ctx->plan.n) return fail(ctx, GSR_E_INVALID, "Gaussian count differs from the plan");
   hipStream_t s = static_cast<hipStream_t>(stream);
   Workspace ws = make_ws(ctx->plan, workspace);
-  launch_work_counts(ctx->plan, ws, s);
+  launch_work_counts(ctx->plan, ws, ctx->views_dev, ctx->tile_view_dev, *g, consts(*cfg), s);
   unsigned long long host[4];
   gsr_status st = hip_check(ctx, hipMemcpyAsync(host, ws.counts, sizeof(host), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
   if (st == GSR_OK) st = hip_check(ctx, hipStreamSynchronize(s), "hipStreamSynchronize");

@@ -123,8 +123,6 @@ struct Workspace {
   int2 *ranges;            // [total_tiles]
   float *T_final;          // [total_pixels]
   int32_t *last;           // [total_pixels]
-  int32_t *nevals;         // [total_pixels] entries the forward walk examined
-  int32_t *nblend;         // [total_pixels] entries blended
   unsigned long long *counts;  // [4] work totals (gsr_work_counts)
   double *grad2d;          // [n_rec][NGRAD2D], FP64 sums over tiles
   double *pose_part;       // [n_pose_blocks][n_views][6]
@@ -149,7 +147,7 @@ struct Plan {
   // byte offsets inside the workspace
   size_t off_hdr, off_recA, off_recB, off_recZ, off_rect, off_count, off_dkeys[2], off_dvals[2],
       off_scan, off_pkeys[2], off_pvals[2], off_hist, off_digit, off_ranges, off_T, off_last,
-      off_grad2d, off_pose, off_queue, off_loss, off_nevals, off_nblend, off_counts, off_hoff, off_bucket,
+      off_grad2d, off_pose, off_queue, off_loss, off_counts, off_hoff, off_bucket,
       off_support;
 };
 
@@ -237,7 +235,10 @@ void launch_render_fused(const Plan &p, const Workspace &ws, const ViewInfo *vie
                          const float *t_rgb, const float *t_depth, const uint8_t *pmask,
                          float w_rgb, float w_depth, const float *loss_cap, const gsr_images *out, float *loss,
                          const Tuning &tun, int num_cus, hipStream_t s);
-void launch_work_counts(const Plan &p, const Workspace &ws, hipStream_t s);
+// Work totals of the last forward (re-walks its lists; needs the Gaussians'
+// colours and the constants of that call).
+void launch_work_counts(const Plan &p, const Workspace &ws, const ViewInfo *views, const int32_t *tile_view,
+                        const gsr_gaussians &g, const RenderConsts &rc, hipStream_t s);
 void launch_l1(const Plan &p, const ViewInfo *views, const float *rgb, const float *depth,
                const float *t_rgb, const float *t_depth, const uint8_t *pmask, float w_rgb,
                float w_depth, const float *loss_cap, float *g_rgb, float *g_depth, float *loss, hipStream_t s);

@@ -24,7 +24,7 @@ constexpr float LN2 = 0.69314718055994530942f;
 
 struct Staged {
   float4 geo;  // (u_rel, v_rel, opacity, depth)
-  float4 con;  // (a'', b'', c'', unused)
+  float4 con;  // (a'', 2 b'', c'', unused)
   float4 col;  // (r, g, b, unused)
 };
 
@@ -76,19 +76,20 @@ __device__ __forceinline__ Staged stage_record(uint32_t id, int view, int64_t n,
   // (u_hi - x0) is exact for |u_hi| < 2^24 and integer x0; the low word adds
   // the remaining bits.
   s.geo = make_float4((A.x - x0) + A.y, (A.z - y0) + A.w, Bc.w, recZ[id]);
-  s.con = make_float4(NEG_HALF_LOG2E * Bc.x, NEG_HALF_LOG2E * Bc.y, NEG_HALF_LOG2E * Bc.z, 0.f);
+  s.con = make_float4(NEG_HALF_LOG2E * Bc.x, 2.f * (NEG_HALF_LOG2E * Bc.y), NEG_HALF_LOG2E * Bc.z, 0.f);
   s.col = make_float4(rgb[3 * gi], rgb[3 * gi + 1], rgb[3 * gi + 2], 0.f);
   return s;
 }
 
-// alpha of a staged Gaussian at pixel offset (dx, dy) = centre - pixel.
+// alpha of a staged Gaussian at pixel offset (dx, dy) = centre - pixel;
+// oG >= 0, so the clamp to [0, alpha_max] is min(oG, alpha_max).
 __device__ __forceinline__ float splat_alpha(const float4 &geo, const float4 &con, float dx, float dy,
                                              float alpha_max, float &G, float &oG) {
-  const float t = __fmaf_rn(con.x, dx, 2.f * con.y * dy);
+  const float t = __fmaf_rn(con.x, dx, con.y * dy);
   const float P = __fmaf_rn(con.z * dy, dy, dx * t);
   G = __builtin_amdgcn_exp2f(P);
   oG = geo.z * G;
-  return fminf(alpha_max, oG);
+  return __builtin_amdgcn_fmed3f(oG, 0.f, alpha_max);
 }
 
 // ------------------------------------------------------------------ forward
@@ -96,29 +97,32 @@ __device__ __forceinline__ float splat_alpha(const float4 &geo, const float4 &co
 struct FwdState {
   float T, C0, C1, C2, D;
   int last;
-  int nev;   // list entries examined (including the one that stopped the pixel)
-  int nbl;   // entries blended
-  bool done;
 };
 
+// With COUNT, the walk also adds its work to counts (wave totals, once per
+// tile): counts[1] += list entries examined by live pixels (including the
+// entry that stopped a pixel), counts[2] += entries blended.  The render
+// kernels do not count; gsr_work_counts re-walks the lists with counting on.
+template <bool COUNT>
 __device__ __forceinline__ void tile_forward(const TileInfo &ti, int64_t n, const float4 *__restrict__ recA,
                                              const float4 *__restrict__ recB,
                                              const float *__restrict__ recZ,
                                              const float *__restrict__ rgb,
                                              const uint32_t *__restrict__ ids, const RenderConsts &rc,
-                                             Staged *s_rec, FwdState &st, uint32_t *s_id = nullptr,
-                                             int *staged_lo = nullptr) {
+                                             Staged *s_rec, FwdState &st, unsigned long long *counts,
+                                             uint32_t *s_id = nullptr, int *staged_lo = nullptr) {
   if (staged_lo) *staged_lo = -1;
   st.T = 1.f;
   st.C0 = st.C1 = st.C2 = st.D = 0.f;
   st.last = 0;
-  st.nev = 0;
-  st.nbl = 0;
-  st.done = !ti.inside;
+  // The pixel's alpha threshold; +inf once it has stopped (or outside the
+  // image), so that no later entry is accepted.
+  float amin = ti.inside ? rc.alpha_min : __builtin_inff();
+  uint32_t nev_w = 0u, nbl_w = 0u;
   const float lx = (float)(threadIdx.x & (TILE - 1));
   const float ly = (float)(threadIdx.x >> 4);
   for (int base = ti.range.x; base < ti.range.y; base += BATCH) {
-    if (__syncthreads_and(st.done)) break;
+    if (__syncthreads_and(amin == __builtin_inff())) break;
     const int pos = base + threadIdx.x;
     if ((int)threadIdx.x < BATCH && pos < ti.range.y) {
       const uint32_t id = ids[pos];
@@ -129,36 +133,38 @@ __device__ __forceinline__ void tile_forward(const TileInfo &ti, int64_t n, cons
     __syncthreads();
     // Branch-free walk: every lane evaluates every entry and keeps or drops
     // the result with selects; the wave leaves the batch once all of its
-    // pixels have stopped.
+    // pixels have stopped.  `live` (wave-uniform) holds the lanes still
+    // blending.
     const int cnt = min(BATCH, ti.range.y - base);
-    if (!__all(st.done)) {
-      for (int k = 0; k < cnt; ++k) {
-        const float4 geo = s_rec[k].geo;
-        const float4 con = s_rec[k].con;
-        const float dx = geo.x - lx, dy = geo.y - ly;
-        float G, oG;
-        const float alpha = splat_alpha(geo, con, dx, dy, rc.alpha_max, G, oG);
-        const bool live = !st.done;
-        const bool acc = live && alpha >= rc.alpha_min;
-        const float Tn = st.T * (1.f - alpha);
-        const bool stop = acc && Tn < rc.T_min;
-        const bool blend = acc && !stop;
-        st.nev += live ? 1 : 0;
-        st.done = st.done || stop;
-        if (__any(blend)) {
-          const float4 col = s_rec[k].col;
-          const float w = blend ? alpha * st.T : 0.f;
-          st.C0 = __fmaf_rn(w, col.x, st.C0);
-          st.C1 = __fmaf_rn(w, col.y, st.C1);
-          st.C2 = __fmaf_rn(w, col.z, st.C2);
-          st.D = __fmaf_rn(w, geo.w, st.D);
-          st.T = blend ? Tn : st.T;
-          st.last = blend ? base - ti.range.x + k + 1 : st.last;
-          st.nbl += blend ? 1 : 0;
-        }
-        if (__all(st.done)) break;
-      }
+    uint64_t live = __builtin_amdgcn_ballot_w64(amin != __builtin_inff());
+    for (int k = 0; k < cnt && live; ++k) {
+      if (COUNT) nev_w += (uint32_t)__popcll(live);
+      const float4 geo = s_rec[k].geo;
+      const float4 con = s_rec[k].con;
+      const float dx = geo.x - lx, dy = geo.y - ly;
+      float G, oG;
+      const float alpha = splat_alpha(geo, con, dx, dy, rc.alpha_max, G, oG);
+      const bool acc = alpha >= amin;
+      const float Tn = st.T * (1.f - alpha);
+      const bool stop = acc && Tn < rc.T_min;
+      const bool blend = acc && !stop;
+      if (COUNT) nbl_w += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(blend));
+      amin = stop ? __builtin_inff() : amin;
+      // Nearly every entry blends in some lane: no branch around the update.
+      const float4 col = s_rec[k].col;
+      const float w = blend ? alpha * st.T : 0.f;
+      st.C0 = __fmaf_rn(w, col.x, st.C0);
+      st.C1 = __fmaf_rn(w, col.y, st.C1);
+      st.C2 = __fmaf_rn(w, col.z, st.C2);
+      st.D = __fmaf_rn(w, geo.w, st.D);
+      st.T = blend ? Tn : st.T;
+      st.last = blend ? base - ti.range.x + k + 1 : st.last;
+      live = __builtin_amdgcn_ballot_w64(amin != __builtin_inff());
     }
+  }
+  if (COUNT && __lane_id() == 0 && nev_w) {
+    atomicAdd(counts + 1, (unsigned long long)nev_w);
+    atomicAdd(counts + 2, (unsigned long long)nbl_w);
   }
   st.C0 = __fmaf_rn(st.T, rc.bg[0], st.C0);
   st.C1 = __fmaf_rn(st.T, rc.bg[1], st.C1);
@@ -401,7 +407,7 @@ __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, con
       const double Sxx = (uc * uc * M1 - 2.0 * uc * Mx) + Mxx;
       const double Sxy = ((uc * vc * M1 - uc * My) - vc * Mx) + Mxy;
       const double Syy = (vc * vc * M1 - 2.0 * vc * My) + Myy;
-      const double a2 = (double)sr.con.x, b2 = (double)sr.con.y, c2 = (double)sr.con.z;
+      const double a2 = (double)sr.con.x, b2 = 0.5 * (double)sr.con.y, c2 = (double)sr.con.z;
       double *o = s_out + threadIdx.x * NGRAD2D;
       o[0] = 2.0 * (double)LN2 * (a2 * Sx + b2 * Sy);
       o[1] = 2.0 * (double)LN2 * (b2 * Sx + c2 * Sy);
@@ -441,21 +447,19 @@ struct RasterArgs {
 
 struct PixelState {
   float *T;
-  int32_t *last, *nevals, *nblend;
+  int32_t *last;
 };
 
 __device__ __forceinline__ void save_state(const PixelState &ps, int64_t pix, const FwdState &st) {
   ps.T[pix] = st.T;
   ps.last[pix] = st.last;
-  ps.nevals[pix] = st.nev;
-  ps.nblend[pix] = st.nbl;
 }
 
 __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, PixelState ps, gsr_images out) {
   __shared__ Staged s_rec[BATCH];
   const TileInfo ti = tile_info(blockIdx.x, a.views, a.tile_view, a.ranges);
   FwdState st;
-  tile_forward(ti, a.n, a.recA, a.recB, a.recZ, a.rgb, a.ids, a.rc, s_rec, st);
+  tile_forward<false>(ti, a.n, a.recA, a.recB, a.recZ, a.rgb, a.ids, a.rc, s_rec, st, nullptr);
   if (!ti.inside) return;
   save_state(ps, ti.pix, st);
   const int64_t loc = ti.pix - ti.pix_off;
@@ -530,7 +534,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
       const TileInfo ti = tile_info(tile, a.views, a.tile_view, a.ranges);
       FwdState st;
       int staged_lo;
-      tile_forward(ti, a.n, a.recA, a.recB, a.recZ, a.rgb, a.ids, a.rc, s_rec, st, s_id, &staged_lo);
+      tile_forward<false>(ti, a.n, a.recA, a.recB, a.recZ, a.rgb, a.ids, a.rc, s_rec, st, nullptr, s_id,
+                          &staged_lo);
       BwdIn in{st.T, ti.inside ? st.last : 0, 0.f, 0.f, 0.f, 0.f, 0.f};
       float lpx = 0.f;
       if (ti.inside) {
@@ -635,7 +640,7 @@ void launch_render_forward(const Plan &p, const Workspace &ws, const ViewInfo *v
   RasterArgs a{ws.recA, ws.recB, ws.recZ, g.rgb, ws.pvals[ws.psorted], ws.ranges, views, tile_view, g.n, rc};
   gsr_images o{nullptr, nullptr, nullptr, nullptr, nullptr};
   if (out) o = *out;
-  PixelState ps{ws.T_final, ws.last, ws.nevals, ws.nblend};
+  PixelState ps{ws.T_final, ws.last};
   hipLaunchKernelGGL(k_render_fwd, dim3(p.total_tiles), dim3(BLOCK), 0, s, a, ps, o);
 }
 
@@ -659,7 +664,7 @@ void launch_render_fused(const Plan &p, const Workspace &ws, const ViewInfo *vie
   const int need = (p.total_tiles + tun.tiles_per_pop - 1) / tun.tiles_per_pop;
   if (grid > need) grid = need;
   if (grid < 1) grid = 1;
-  PixelState ps{ws.T_final, ws.last, ws.nevals, ws.nblend};
+  PixelState ps{ws.T_final, ws.last};
   const uint32_t *queue = tun.lpt_order ? ws.queue : nullptr;
   hipLaunchKernelGGL(k_render_fused, dim3(grid), dim3(BLOCK), 0, s, a, ws.hdr, queue, p.total_tiles,
                      tun.tiles_per_pop, t_rgb, t_depth, pmask, w_rgb, w_depth, loss_cap, o, loss, ws.grad2d, ps);
@@ -667,35 +672,36 @@ void launch_render_fused(const Plan &p, const Workspace &ws, const ViewInfo *vie
 
 // Totals of the per-pixel work counters: counts[0] pairs, [1] entries the
 // forward examined, [2] entries blended, [3] sum of last.
-__global__ __launch_bounds__(BLOCK) void k_work_counts(const int32_t *__restrict__ nevals,
-                                                       const int32_t *__restrict__ nblend,
-                                                       const int32_t *__restrict__ last, int64_t total,
+// Work of the last forward, for the roofline: the forward walk of every
+// tile again, with counting on and no outputs (the workspace still holds the
+// records, lists and ranges of that call).
+__global__ __launch_bounds__(BLOCK) void k_count_walk(RasterArgs a, unsigned long long *__restrict__ counts) {
+  __shared__ Staged s_rec[BATCH];
+  const TileInfo ti = tile_info(blockIdx.x, a.views, a.tile_view, a.ranges);
+  FwdState st;
+  tile_forward<true>(ti, a.n, a.recA, a.recB, a.recZ, a.rgb, a.ids, a.rc, s_rec, st, counts);
+}
+
+// counts[0] = pairs (from the header), counts[3] = sum of `last`.
+__global__ __launch_bounds__(BLOCK) void k_work_counts(const int32_t *__restrict__ last, int64_t total,
                                                        const uint32_t *__restrict__ hdr,
                                                        unsigned long long *__restrict__ counts) {
-  unsigned long long a = 0, b = 0, c = 0;
-  for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < total; p += (int64_t)gridDim.x * BLOCK) {
-    a += (unsigned long long)nevals[p];
-    b += (unsigned long long)nblend[p];
+  unsigned long long c = 0;
+  for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < total; p += (int64_t)gridDim.x * BLOCK)
     c += (unsigned long long)last[p];
-  }
-  for (int o = 32; o > 0; o >>= 1) {
-    a += __shfl_xor(a, o);
-    b += __shfl_xor(b, o);
-    c += __shfl_xor(c, o);
-  }
-  if ((threadIdx.x & 63) == 0) {
-    atomicAdd(counts + 1, a);
-    atomicAdd(counts + 2, b);
-    atomicAdd(counts + 3, c);
-  }
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+  if ((threadIdx.x & 63) == 0) atomicAdd(counts + 3, c);
   if (blockIdx.x == 0 && threadIdx.x == 0)
     counts[0] = *reinterpret_cast<const unsigned long long *>(hdr + HDR_NPAIRS);
 }
 
-void launch_work_counts(const Plan &p, const Workspace &ws, hipStream_t s) {
+void launch_work_counts(const Plan &p, const Workspace &ws, const ViewInfo *views, const int32_t *tile_view,
+                        const gsr_gaussians &g, const RenderConsts &rc, hipStream_t s) {
   launch_fill_u32(reinterpret_cast<uint32_t *>(ws.counts), 0u, 8, s);
-  hipLaunchKernelGGL(k_work_counts, dim3(256), dim3(BLOCK), 0, s, ws.nevals, ws.nblend, ws.last, p.total_pixels,
-                     ws.hdr, ws.counts);
+  RasterArgs a{ws.recA, ws.recB, ws.recZ, g.rgb, ws.pvals[ws.psorted], ws.ranges, views, tile_view, g.n, rc};
+  if (p.total_tiles > 0)
+    hipLaunchKernelGGL(k_count_walk, dim3(p.total_tiles), dim3(BLOCK), 0, s, a, ws.counts);
+  hipLaunchKernelGGL(k_work_counts, dim3(256), dim3(BLOCK), 0, s, ws.last, p.total_pixels, ws.hdr, ws.counts);
 }
 
 }  // namespace gsr

@@ -360,10 +360,13 @@ class Renderer:
         out["calls"] = int(calls.value)
         return out
 
-    def work_counts(self, stream=None) -> dict:
+    def work_counts(self, g: Gaussians, cfg: Config, stream=None) -> dict:
+        """Work of the last forward or fused call, which used `g` and `cfg`."""
         ws, _ = self._ws()
         out = (ctypes.c_int64 * 4)()
-        self._check(self.lib.gsr_work_counts(self.ctx, ws, _stream_ptr(stream), out))
+        gc, cc = g.c(), cfg.to_c()
+        self._check(self.lib.gsr_work_counts(self.ctx, ctypes.byref(gc), ctypes.byref(cc), ws, _stream_ptr(stream),
+                                             out))
         return dict(pairs=int(out[0]), fwd_evals=int(out[1]), blended=int(out[2]), bwd_evals=int(out[3]))
 
 

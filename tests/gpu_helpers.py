@@ -132,3 +132,32 @@ def rect_pairs(proj):
     rectangle (the lists then skip the tiles outside its alpha support)."""
     r = proj["rect"][proj["valid"]]
     return int(((r[:, 1] - r[:, 0] + 1) * (r[:, 3] - r[:, 2] + 1)).sum())
+
+
+def oracle_work(o, cam, cfg_o):
+    """Work totals of the oracle render `o` (from O.render) in the renderer's
+    definitions: entries examined per pixel up to and including the one that
+    stopped it, entries blended, and the sum of `last`; plus the summed list
+    length of pixels with an ambiguous threshold decision (the most their
+    counts can differ by)."""
+    from oracle import splat as OS
+    proj = o["proj"]
+    starts, gauss = o["lists"]
+    cfg = cfg_o.as_f32()
+    TX = proj["TX"]
+    evals = blended = slack = 0
+    for tile in range(TX * proj["TY"]):
+        px, py = OS._tile_pixels(tile, TX, int(cam.width), int(cam.height))
+        lst = gauss[starts[tile]:starts[tile + 1]]
+        L = lst.size
+        if L == 0:
+            continue
+        r = OS._blend_tile(proj, lst, px, py, cfg)
+        gate = r["alpha"] >= cfg.alpha_min
+        P = np.cumprod(1.0 - np.where(gate, r["alpha"], 0.0), axis=1)
+        stop = gate & (P < cfg.T_min)
+        s = np.where(stop.any(axis=1), np.argmax(stop, axis=1) + 1, L)
+        evals += int(s.sum())
+        blended += int(r["contrib"].sum())
+        slack += int(L * r["amb"].sum())
+    return dict(fwd_evals=evals, blended=blended, bwd_evals=int(o["last"].sum()), slack=slack)

@@ -75,6 +75,14 @@ def test_forward_and_lists_match_oracle(gsr_lib, case):
     H.assert_images_close(g, o)
     assert r.pair_count() == H.rect_pairs(o["proj"])
     _check_lists(r, [sc], [cam], H.oracle_cfg_of(cfg))
+    # Work totals (the roofline's FLOP count) against the oracle's walk.
+    work = r.work_counts(H.gpu_scene(gsr, sc), cfg)
+    ow = H.oracle_work(o, cam, H.oracle_cfg_of(cfg))
+    assert work["pairs"] == H.rect_pairs(o["proj"])
+    assert work["bwd_evals"] == int(g["last"].sum())
+    for k in ("fwd_evals", "blended"):
+        assert abs(work[k] - ow[k]) <= ow["slack"], (k, work[k], ow[k], ow["slack"])
+    assert ow["fwd_evals"] > 0 and ow["blended"] > 0
 
 
 def test_edge_cases(gsr_lib):
