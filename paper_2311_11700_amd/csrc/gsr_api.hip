@@ -81,6 +81,7 @@ Workspace make_ws(const Plan &p, void *base_v) {
   w.ranges = reinterpret_cast<int2 *>(base + p.off_ranges);
   w.T_final = reinterpret_cast<float *>(base + p.off_T);
   w.last = reinterpret_cast<int32_t *>(base + p.off_last);
+  w.zr = reinterpret_cast<float *>(base + p.off_zr);
   w.counts = reinterpret_cast<unsigned long long *>(base + p.off_counts);
   w.grad2d = reinterpret_cast<double *>(base + p.off_grad2d);
   w.pose_part = reinterpret_cast<double *>(base + p.off_pose);
@@ -330,6 +331,7 @@ gsr_status gsr_plan(gsr_ctx *ctx, int64_t n, int n_views, const int32_t *wh_host
   p.off_ranges = take(8 * (size_t)p.total_tiles);
   p.off_T = take(4 * (size_t)pixels);
   p.off_last = take(4 * (size_t)pixels);
+  p.off_zr = take(4 * (size_t)pixels);
   p.off_counts = take(64);
   p.off_grad2d = take(8 * NGRAD2D * nr);
   p.off_pose = take(8 * 6 * (size_t)n_views * p.n_pose_blocks);

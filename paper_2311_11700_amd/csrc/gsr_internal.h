@@ -123,6 +123,7 @@ struct Workspace {
   int2 *ranges;            // [total_tiles]
   float *T_final;          // [total_pixels]
   int32_t *last;           // [total_pixels]
+  float *zr;               // [total_pixels] depth of the last blended entry (forward -> backward)
   unsigned long long *counts;  // [4] work totals (gsr_work_counts)
   double *grad2d;          // [n_rec][NGRAD2D], FP64 sums over tiles
   double *pose_part;       // [n_pose_blocks][n_views][6]
@@ -146,7 +147,7 @@ struct Plan {
   size_t bytes = 0;
   // byte offsets inside the workspace
   size_t off_hdr, off_recA, off_recB, off_recZ, off_rect, off_count, off_dkeys[2], off_dvals[2],
-      off_scan, off_pkeys[2], off_pvals[2], off_hist, off_digit, off_ranges, off_T, off_last,
+      off_scan, off_pkeys[2], off_pvals[2], off_hist, off_digit, off_ranges, off_T, off_last, off_zr,
       off_grad2d, off_pose, off_queue, off_loss, off_counts, off_hoff, off_bucket,
       off_support;
 };

@@ -97,6 +97,7 @@ __device__ __forceinline__ float splat_alpha(const float4 &geo, const float4 &co
 struct FwdState {
   float T, C0, C1, C2, D;
   int last;
+  float zr;  // depth of the last blended entry (0 if none): the backward's reference depth
 };
 
 // With COUNT, the walk also adds its work to counts (wave totals, once per
@@ -115,6 +116,7 @@ __device__ __forceinline__ void tile_forward(const TileInfo &ti, int64_t n, cons
   st.T = 1.f;
   st.C0 = st.C1 = st.C2 = st.D = 0.f;
   st.last = 0;
+  st.zr = 0.f;
   // The pixel's alpha threshold; +inf once it has stopped (or outside the
   // image), so that no later entry is accepted.
   float amin = ti.inside ? rc.alpha_min : __builtin_inff();
@@ -159,6 +161,7 @@ __device__ __forceinline__ void tile_forward(const TileInfo &ti, int64_t n, cons
       st.D = __fmaf_rn(w, geo.w, st.D);
       st.T = blend ? Tn : st.T;
       st.last = blend ? base - ti.range.x + k + 1 : st.last;
+      st.zr = blend ? geo.w : st.zr;
       live = __builtin_amdgcn_ballot_w64(amin != __builtin_inff());
     }
   }
@@ -196,6 +199,7 @@ typedef float float4v __attribute__((ext_vector_type(4)));
 struct BwdIn {
   float T;         // final transmittance
   int last;        // list positions [0, last) to walk
+  float zr;        // depth of the last contributor (0 if none)
   float gC0, gC1, gC2, gD, gT;
 };
 
@@ -317,9 +321,8 @@ __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, con
   // On a surface all depths agree to a few mm, so the shifted terms keep
   // their float32 digits (z_k - aD_k itself would cancel).
   float S = in.gC0 * rc.bg[0] + in.gC1 * rc.bg[1] + in.gC2 * rc.bg[2];
-  float zr = 0.f;
-  float Kf = -in.gT * Tf;  // (gD zr - gT) T_f
-  bool have_zr = false;
+  const float zr = in.zr;
+  const float Kf = (in.gD * zr - in.gT) * Tf;
 
   // Batches aligned with the forward's: [b BATCH, (b + 1) BATCH), walked
   // from the last one that holds an entry below maxlast.
@@ -355,10 +358,6 @@ __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, con
           const float Tk = T * rinv;  // transmittance in front of this Gaussian
           T = has ? Tk : T;
           const float w = has ? alpha * Tk : 0.f;
-          const bool first = has && !have_zr;
-          zr = first ? geo.w : zr;
-          Kf = first ? (in.gD * geo.w - in.gT) * Tf : Kf;
-          have_zr = have_zr || has;
           const float Q = __fmaf_rn(in.gD, geo.w - zr, __fmaf_rn(in.gC2, col.z, __fmaf_rn(in.gC1, col.y, in.gC0 * col.x)));
           const float QS = Q - S;
           const float dLda = __fmaf_rn(Tk, QS, Kf * rinv);
@@ -448,11 +447,13 @@ struct RasterArgs {
 struct PixelState {
   float *T;
   int32_t *last;
+  float *zr;  // null when no separate backward reads it (fused step)
 };
 
 __device__ __forceinline__ void save_state(const PixelState &ps, int64_t pix, const FwdState &st) {
   ps.T[pix] = st.T;
   ps.last[pix] = st.last;
+  if (ps.zr) ps.zr[pix] = st.zr;
 }
 
 __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, PixelState ps, gsr_images out) {
@@ -476,6 +477,7 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, PixelState p
 
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_render_bwd(RasterArgs a, const float *__restrict__ T_ws,
                                                       const int32_t *__restrict__ last_ws,
+                                                      const float *__restrict__ zr_ws,
                                                       const float *__restrict__ g_rgb,
                                                       const float *__restrict__ g_depth,
                                                       const float *__restrict__ g_T,
@@ -486,9 +488,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
   __shared__ int s_max;
   __shared__ __align__(16) float s_mA[4 * MA_WAVE];
   const TileInfo ti = tile_info(blockIdx.x, a.views, a.tile_view, a.ranges);
-  BwdIn in{1.f, 0, 0.f, 0.f, 0.f, 0.f, 0.f};
+  BwdIn in{1.f, 0, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   if (ti.inside) {
     const int64_t loc = ti.pix - ti.pix_off;
+    in.zr = zr_ws[ti.pix];
     in.T = T_ws[ti.pix];
     in.last = last_ws[ti.pix];
     const float *gc = g_rgb + 3 * ti.pix_off + loc;
@@ -536,7 +539,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
       int staged_lo;
       tile_forward<false>(ti, a.n, a.recA, a.recB, a.recZ, a.rgb, a.ids, a.rc, s_rec, st, nullptr, s_id,
                           &staged_lo);
-      BwdIn in{st.T, ti.inside ? st.last : 0, 0.f, 0.f, 0.f, 0.f, 0.f};
+      BwdIn in{st.T, ti.inside ? st.last : 0, st.zr, 0.f, 0.f, 0.f, 0.f, 0.f};
       float lpx = 0.f;
       if (ti.inside) {
         const int64_t loc = ti.pix - ti.pix_off;
@@ -640,7 +643,7 @@ void launch_render_forward(const Plan &p, const Workspace &ws, const ViewInfo *v
   RasterArgs a{ws.recA, ws.recB, ws.recZ, g.rgb, ws.pvals[ws.psorted], ws.ranges, views, tile_view, g.n, rc};
   gsr_images o{nullptr, nullptr, nullptr, nullptr, nullptr};
   if (out) o = *out;
-  PixelState ps{ws.T_final, ws.last};
+  PixelState ps{ws.T_final, ws.last, ws.zr};
   hipLaunchKernelGGL(k_render_fwd, dim3(p.total_tiles), dim3(BLOCK), 0, s, a, ps, o);
 }
 
@@ -648,7 +651,7 @@ void launch_render_backward(const Plan &p, const Workspace &ws, const ViewInfo *
                             const int32_t *tile_view, const gsr_gaussians &g, const RenderConsts &rc,
                             const float *g_rgb, const float *g_depth, const float *g_T, hipStream_t s) {
   RasterArgs a{ws.recA, ws.recB, ws.recZ, g.rgb, ws.pvals[ws.psorted], ws.ranges, views, tile_view, g.n, rc};
-  hipLaunchKernelGGL(k_render_bwd, dim3(p.total_tiles), dim3(BLOCK), 0, s, a, ws.T_final, ws.last, g_rgb,
+  hipLaunchKernelGGL(k_render_bwd, dim3(p.total_tiles), dim3(BLOCK), 0, s, a, ws.T_final, ws.last, ws.zr, g_rgb,
                      g_depth, g_T, ws.grad2d);
 }
 
@@ -664,7 +667,7 @@ void launch_render_fused(const Plan &p, const Workspace &ws, const ViewInfo *vie
   const int need = (p.total_tiles + tun.tiles_per_pop - 1) / tun.tiles_per_pop;
   if (grid > need) grid = need;
   if (grid < 1) grid = 1;
-  PixelState ps{ws.T_final, ws.last};
+  PixelState ps{ws.T_final, ws.last, nullptr};
   const uint32_t *queue = tun.lpt_order ? ws.queue : nullptr;
   hipLaunchKernelGGL(k_render_fused, dim3(grid), dim3(BLOCK), 0, s, a, ws.hdr, queue, p.total_tiles,
                      tun.tiles_per_pop, t_rgb, t_depth, pmask, w_rgb, w_depth, loss_cap, o, loss, ws.grad2d, ps);
