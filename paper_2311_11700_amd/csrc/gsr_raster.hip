@@ -189,6 +189,7 @@ __device__ __forceinline__ void tile_forward(const TileInfo &ti, int64_t n, cons
 // matrix cores (v_mfma_f32_16x16x4_f32, K = 64 pixels in 16 steps); the four
 // wavefronts add their 16x16 products into the block's per-entry sums.
 
+constexpr int SUB = 64;                   // entries per backward sub-batch
 constexpr int MA_ROWS = 16;               // 8 entries x (dLdP, w)
 constexpr int MA_STRIDE = 64 + 4;         // floats per row (padding spreads LDS banks)
 constexpr int MA_WAVE = MA_ROWS * MA_STRIDE;
@@ -209,14 +210,14 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Contract the wave's collected rows (nq entries, rows 2q = dLdP, 2q+1 = w)
-// with the per-pixel constants Bm and add the useful products to the
-// block's per-entry sums s_sum[entry][NMOM].  Operand layout of
+// Contract the wave's collected rows (rows 2q = dLdP, 2q+1 = w of entry q)
+// with the per-pixel constants Bm into D.  Operand layout of
 // v_mfma_f32_16x16x4_f32: lane l supplies A[l % 16][k] and B[k][l % 16] for
 // k = l / 16; D[i][l % 16] lands in register i % 4 of lane 16 (i / 4) + l % 16.
-// The 16 steps map K index k of step s to pixel 16 k + s.
-__device__ __forceinline__ void mfma_group(const float *mA, const float Bm[16], int nq, uint64_t slots,
-                                           float *s_sum) {
+// The 16 steps map K index k of step s to pixel 16 k + s.  The result is
+// consumed (mfma_consume) only at the next group, so the matrix-core chain
+// runs while the wavefront walks on.
+__device__ __forceinline__ float4v mfma_issue(const float *mA, const float Bm[16]) {
   const int lane = __lane_id();
   const int r = lane & 15, g = lane >> 4;
   wave_lds_sync();
@@ -239,16 +240,25 @@ __device__ __forceinline__ void mfma_group(const float *mA, const float Bm[16], 
   D = __builtin_amdgcn_mfma_f32_16x16x4f32(a3.y, Bm[13], D, 0, 0, 0);
   D = __builtin_amdgcn_mfma_f32_16x16x4f32(a3.z, Bm[14], D, 0, 0, 0);
   D = __builtin_amdgcn_mfma_f32_16x16x4f32(a3.w, Bm[15], D, 0, 0, 0);
-  // Lane (g, col) holds rows 4g..4g+3: entry 2g (dLdP row, w row) and entry
-  // 2g+1.  Columns 0-5 are taken from the dLdP rows, 6-9 from the w rows.
+  return D;
+}
+
+// Store the useful products of a contraction of nq entries into the
+// wavefront's own per-entry sums s_sum[entry][NMOM] (entry q's slot in byte
+// q of slots; a wavefront meets each entry once per sub-batch, so plain
+// stores suffice and the four wavefronts never contend for an address).
+// Lane (g, col) holds rows 4g..4g+3: entry 2g (dLdP row, w row) and entry
+// 2g+1.  Columns 0-5 are taken from the dLdP rows, 6-9 from the w rows.
+__device__ __forceinline__ void mfma_consume(const float4v &D, int nq, uint64_t slots, float *s_sum) {
+  const int lane = __lane_id();
+  const int g = lane >> 4;
   const int col = lane & 15;
   if (col < NMOM) {
     const bool mom = col < 6;
     const int q0 = 2 * g, q1 = 2 * g + 1;
-    if (q0 < nq) atomicAdd(s_sum + (int)((slots >> (8 * q0)) & 255u) * NMOM + col, mom ? D[0] : D[1]);
-    if (q1 < nq) atomicAdd(s_sum + (int)((slots >> (8 * q1)) & 255u) * NMOM + col, mom ? D[2] : D[3]);
+    if (q0 < nq) s_sum[(int)((slots >> (8 * q0)) & 255u) * NMOM + col] = mom ? D[0] : D[1];
+    if (q1 < nq) s_sum[(int)((slots >> (8 * q1)) & 255u) * NMOM + col] = mom ? D[2] : D[3];
   }
-  wave_lds_sync();
 }
 
 // Walk the tile's list back to front; per entry, dLdP and w of every pixel
@@ -263,15 +273,15 @@ __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, con
                                               const float *__restrict__ rgb,
                                               const uint32_t *__restrict__ ids, const RenderConsts &rc,
                                               const BwdIn &in, double *__restrict__ grad2d,
-                                              Staged *s_rec, float *s_grad, uint32_t *s_id, int *s_max,
+                                              Staged *s_rec, float *s_part, uint32_t *s_id, int *s_max,
                                               float *s_mA, int staged_lo = -1) {
   const float lx = (float)(threadIdx.x & (TILE - 1));
   const float ly = (float)(threadIdx.x >> 4);
   const int lane = __lane_id();
   const int wv = threadIdx.x >> 6;
   float *mA = s_mA + wv * MA_WAVE;
+  float *my_part = s_part + wv * SUB * NMOM;  // this wavefront's per-entry sums
   if (threadIdx.x == 0) *s_max = 0;
-  for (int k = threadIdx.x; k < BATCH * NMOM; k += BLOCK) s_grad[k] = 0.f;
   __syncthreads();
   if (in.last > 0) atomicMax(s_max, in.last);
   __syncthreads();
@@ -324,28 +334,41 @@ __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, con
   const float zr = in.zr;
   const float Kf = (in.gD * zr - in.gT) * Tf;
 
-  // Batches aligned with the forward's: [b BATCH, (b + 1) BATCH), walked
-  // from the last one that holds an entry below maxlast.
-  for (int lo = ((maxlast - 1) / BATCH) * BATCH; lo >= 0; lo -= BATCH) {
-    const int hi = min(lo + BATCH, maxlast);
+  // Sub-batches [b SUB, (b + 1) SUB), walked from the last one that holds
+  // an entry below maxlast.  Those inside the forward's last batch (still
+  // staged, records and ids, from list position staged_lo on) are read in
+  // place; the others are staged into the first SUB slots.
+  for (int lo = ((maxlast - 1) / SUB) * SUB; lo >= 0; lo -= SUB) {
+    const int hi = min(lo + SUB, maxlast);
     const int cnt = hi - lo;
-    // The forward's last batch is still staged (records and ids) when it is
-    // this one.
-    if (lo != staged_lo && (int)threadIdx.x < cnt) {
-      const uint32_t id = ids[ti.range.x + lo + threadIdx.x];
-      s_id[threadIdx.x] = id;
-      s_rec[threadIdx.x] = stage_record(id, ti.view, n, ti.x0, ti.y0, recA, recB, recZ, rgb);
+    int off = 0;  // slot of entry lo in s_rec / s_id
+    if (staged_lo >= 0 && lo >= staged_lo) {
+      off = lo - staged_lo;
+    } else {
+      staged_lo = -1;
+      if ((int)threadIdx.x < cnt) {
+        const uint32_t id = ids[ti.range.x + lo + threadIdx.x];
+        s_id[threadIdx.x] = id;
+        s_rec[threadIdx.x] = stage_record(id, ti.view, n, ti.x0, ti.y0, recA, recB, recZ, rgb);
+      }
     }
-    staged_lo = -1;
+    {
+      // Entries without a contribution in this wavefront keep zero sums.
+      float4 *z = reinterpret_cast<float4 *>(my_part);
+      for (int k = lane; k < SUB * NMOM / 4; k += 64) z[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
     __syncthreads();
     int nq = 0;
     uint64_t slots = 0;
+    float4v pD = {0.f, 0.f, 0.f, 0.f};  // contraction of the previous group, not yet added
+    int p_nq = 0;
+    uint64_t p_slots = 0;
     // One step past the batch (k = lo - 1) contracts the last partial group.
     for (int k = hi - 1; k >= lo - 1; --k) {
       const int j = k - lo;
       if (k >= lo) {
-        const float4 geo = s_rec[j].geo;
-        const float4 con = s_rec[j].con;
+        const float4 geo = s_rec[off + j].geo;
+        const float4 con = s_rec[off + j].con;
         const float dx = geo.x - lx, dy = geo.y - ly;
         float G, oG;
         const float alpha = splat_alpha(geo, con, dx, dy, rc.alpha_max, G, oG);
@@ -353,7 +376,7 @@ __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, con
         // Wave-uniform guard; inside it every lane computes and the lanes
         // without a contribution are masked with selects (NaN-safe).
         if (__any(has)) {
-          const float4 col = s_rec[j].col;
+          const float4 col = s_rec[off + j].col;
           const float rinv = __builtin_amdgcn_rcpf(1.f - alpha);
           const float Tk = T * rinv;  // transmittance in front of this Gaussian
           T = has ? Tk : T;
@@ -373,11 +396,17 @@ __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, con
         }
       }
       if (nq == 8 || (k < lo && nq > 0)) {
-        mfma_group(mA, Bm, nq, slots, s_grad);
+        if (p_nq > 0) mfma_consume(pD, p_nq, p_slots, my_part);
+        pD = mfma_issue(mA, Bm);
+        p_nq = nq;
+        p_slots = slots;
         nq = 0;
         slots = 0;
+        // The rows were read into registers; the next group may rewrite them.
+        wave_lds_sync();
       }
     }
+    if (p_nq > 0) mfma_consume(pD, p_nq, p_slots, my_part);
     __syncthreads();
     // Flush.  First one thread per Gaussian of the batch converts its sums:
     // with the centre relative to the tile centre (uc, vc) and the pixel
@@ -390,16 +419,15 @@ __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, con
     // Then the block adds them to grad2d field-parallel: consecutive lanes
     // take consecutive fields of one Gaussian, so each atomic instruction
     // touches a few contiguous 80-byte rows.
-    double *s_out = reinterpret_cast<double *>(s_mA);  // [BATCH][NGRAD2D], free during the flush
+    double *s_out = reinterpret_cast<double *>(s_mA);  // [SUB][NGRAD2D], free during the flush
     if ((int)threadIdx.x < cnt) {
-      float *src = s_grad + threadIdx.x * NMOM;
+      // The four wavefronts' sums, added in a fixed order.
+      const float *src = s_part + threadIdx.x * NMOM;
       double m[NMOM];
 #pragma unroll
-      for (int f = 0; f < NMOM; ++f) {
-        m[f] = (double)src[f];
-        src[f] = 0.f;
-      }
-      const Staged &sr = s_rec[threadIdx.x];
+      for (int f = 0; f < NMOM; ++f)
+        m[f] = (double)((src[f] + src[SUB * NMOM + f]) + (src[2 * SUB * NMOM + f] + src[3 * SUB * NMOM + f]));
+      const Staged &sr = s_rec[off + threadIdx.x];
       const double uc = (double)sr.geo.x - 7.5, vc = (double)sr.geo.y - 7.5;
       const double M1 = m[0], Mx = m[1], My = m[2], Mxx = m[3], Mxy = m[4], Myy = m[5];
       const double Sx = uc * M1 - Mx, Sy = vc * M1 - My;
@@ -423,7 +451,7 @@ __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, con
     for (int t = threadIdx.x; t < cnt * NGRAD2D; t += BLOCK) {
       const int e = t / NGRAD2D, f = t - e * NGRAD2D;
       const double v = s_out[t];
-      if (v != 0.0 && ((rc.grad_fields >> f) & 1u)) atomicAdd(grad2d + (size_t)s_id[e] * NGRAD2D + f, v);
+      if (v != 0.0 && ((rc.grad_fields >> f) & 1u)) atomicAdd(grad2d + (size_t)s_id[off + e] * NGRAD2D + f, v);
     }
     __syncthreads();
   }
@@ -483,7 +511,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
                                                       const float *__restrict__ g_T,
                                                       double *__restrict__ grad2d) {
   __shared__ Staged s_rec[BATCH];
-  __shared__ float s_grad[BATCH * NMOM];
+  __shared__ float s_part[4 * SUB * NMOM];
   __shared__ uint32_t s_id[BATCH];
   __shared__ int s_max;
   __shared__ __align__(16) float s_mA[4 * MA_WAVE];
@@ -501,7 +529,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     in.gD = g_depth ? g_depth[ti.pix] : 0.f;
     in.gT = g_T ? g_T[ti.pix] : 0.f;
   }
-  tile_backward(ti, a.n, a.recA, a.recB, a.recZ, a.rgb, a.ids, a.rc, in, grad2d, s_rec, s_grad, s_id, &s_max,
+  tile_backward(ti, a.n, a.recA, a.recB, a.recZ, a.rgb, a.ids, a.rc, in, grad2d, s_rec, s_part, s_id, &s_max,
                 s_mA);
 }
 
@@ -519,7 +547,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
                                                         gsr_images out, float *__restrict__ loss,
                                                         double *__restrict__ grad2d, PixelState ps) {
   __shared__ Staged s_rec[BATCH];
-  __shared__ float s_grad[BATCH * NMOM];
+  __shared__ float s_part[4 * SUB * NMOM];
   __shared__ uint32_t s_id[BATCH];
   __shared__ int s_max;
   __shared__ __align__(16) float s_mA[4 * MA_WAVE];
@@ -576,7 +604,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
       }
       const float ls = wave_sum(lpx);
       if ((threadIdx.x & 63) == 0) s_loss[threadIdx.x >> 6] = ls;
-      tile_backward(ti, a.n, a.recA, a.recB, a.recZ, a.rgb, a.ids, a.rc, in, grad2d, s_rec, s_grad, s_id, &s_max,
+      tile_backward(ti, a.n, a.recA, a.recB, a.recZ, a.rgb, a.ids, a.rc, in, grad2d, s_rec, s_part, s_id, &s_max,
                     s_mA, staged_lo);
       if (threadIdx.x == 0 && loss) atomicAdd(loss, (s_loss[0] + s_loss[1]) + (s_loss[2] + s_loss[3]));
       // The next tile may have an empty list (no barrier in its forward):
