@@ -89,6 +89,8 @@ Workspace make_ws(const Plan &p, void *base_v) {
   w.loss_part = reinterpret_cast<float *>(base + p.off_loss);
   w.dsorted = passes_for(32) & 1;
   w.psorted = passes_for(p.tile_bits) & 1;
+  w.pack_shift = p.pack_shift;
+  w.id_mask = p.pack_shift ? (1u << p.pack_shift) - 1u : 0xFFFFFFFFu;
   return w;
 }
 
@@ -121,6 +123,7 @@ RenderConsts consts(const gsr_config &c) {
   // Opacity and colour gradients (fields 5-8) feed only the Gaussian
   // parameters; a pose-only backward skips them.
   rc.grad_fields = (c.flags & GSR_GAUSS_GRAD) ? 0x3FFu : 0x3FFu & ~0x1E0u;
+  rc.id_mask = 0xFFFFFFFFu;
   return rc;
 }
 
@@ -301,6 +304,9 @@ gsr_status gsr_plan(gsr_ctx *ctx, int64_t n, int n_views, const int32_t *wh_host
   int bits = 0;
   while ((1ll << bits) < tiles + 1) ++bits;
   p.tile_bits = bits;
+  int rbits = 1;
+  while ((1ll << rbits) < p.n_rec) ++rbits;
+  p.pack_shift = bits + rbits <= 32 ? rbits : 0;
   const int64_t dtile = (int64_t)BLOCK * SORT_ITEMS_DEPTH, ptile = (int64_t)BLOCK * SORT_ITEMS_PAIR;
   p.max_sort_tiles = (int)std::max<int64_t>((p.n_rec + dtile - 1) / dtile, (p.capacity + ptile - 1) / ptile);
   p.n_scan_blocks = (int)std::max<int64_t>(1, (p.n_rec + SCAN_CHUNK - 1) / SCAN_CHUNK);
@@ -550,7 +556,17 @@ gsr_status gsr_debug_tiles(gsr_ctx *ctx, void *workspace, const int32_t **tile_r
   if (!ctx->planned || !workspace) return fail(ctx, GSR_E_STATE, "gsr_debug_tiles: no plan or workspace");
   Workspace ws = make_ws(ctx->plan, workspace);
   if (tile_ranges) *tile_ranges = reinterpret_cast<const int32_t *>(ws.ranges);
-  if (sorted_ids) *sorted_ids = ws.pvals[ws.psorted];
+  if (sorted_ids) {
+    if (ws.pack_shift) {
+      // Packed words: write the record ids into the (unused) value buffer.
+      gsr_status st = hip_check(ctx, hipDeviceSynchronize(), "hipDeviceSynchronize");
+      if (st != GSR_OK) return st;
+      launch_unpack_ids(ctx->plan, ws, nullptr);
+      st = hip_check(ctx, hipDeviceSynchronize(), "hipDeviceSynchronize");
+      if (st != GSR_OK) return st;
+    }
+    *sorted_ids = ws.pvals[ws.psorted];
+  }
   if (total_tiles) *total_tiles = ctx->plan.total_tiles;
   return GSR_OK;
 }

@@ -131,6 +131,11 @@ struct Workspace {
   float *loss_part;        // [1] (unused slot kept for alignment)
   int dsorted;             // which depth buffer holds the sorted result
   int psorted;             // which pair buffer holds the sorted result
+  // Packed pairs (when tile and record bits fit 32): one word per pair,
+  // tile << pack_shift | record id, sorted without a value array; else
+  // pack_shift = 0, keys hold tiles and pvals the record ids.
+  int pack_shift;
+  uint32_t id_mask;        // record id of a sorted word: word & id_mask
 };
 
 struct Plan {
@@ -141,6 +146,7 @@ struct Plan {
   int64_t total_pixels = 0;
   int64_t capacity = 0;
   int tile_bits = 0;
+  int pack_shift = 0;      // record-id bits below the tile in a packed pair word (0: unpacked)
   int max_sort_tiles = 0;
   int n_scan_blocks = 0;
   int n_pose_blocks = 0;
@@ -163,6 +169,7 @@ struct RenderConsts {
   float alpha_min, alpha_max, T_min;
   float bg[3];
   uint32_t grad_fields;  // bit f set: the backward accumulates grad2d field f
+  uint32_t id_mask;      // record id of a sorted pair word (set by the launchers)
 };
 
 // ---------------------------------------------------------------- device helpers
@@ -218,6 +225,8 @@ int launch_depth_sort(const Plan &p, Workspace &ws, hipStream_t s, int sort_grid
 void launch_emit_pairs(const Plan &p, const Workspace &ws, const ViewInfo *views, hipStream_t s);
 int launch_pair_sort(const Plan &p, Workspace &ws, hipStream_t s, int sort_grid);
 void launch_tile_ranges(const Plan &p, const Workspace &ws, hipStream_t s);
+// Packed pairs: record ids of the sorted words into pvals[psorted].
+void launch_unpack_ids(const Plan &p, const Workspace &ws, hipStream_t s);
 void launch_fill_u32(uint32_t *ptr, uint32_t value, int64_t count, hipStream_t s);
 void launch_fill_f32(float *ptr, float value, int64_t count, hipStream_t s);
 void launch_reset_header(const Workspace &ws, hipStream_t s);

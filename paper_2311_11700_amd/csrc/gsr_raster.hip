@@ -127,7 +127,7 @@ __device__ __forceinline__ void tile_forward(const TileInfo &ti, int64_t n, cons
     if (__syncthreads_and(amin == __builtin_inff())) break;
     const int pos = base + threadIdx.x;
     if ((int)threadIdx.x < BATCH && pos < ti.range.y) {
-      const uint32_t id = ids[pos];
+      const uint32_t id = ids[pos] & rc.id_mask;
       if (s_id) s_id[threadIdx.x] = id;
       s_rec[threadIdx.x] = stage_record(id, ti.view, n, ti.x0, ti.y0, recA, recB, recZ, rgb);
     }
@@ -347,7 +347,7 @@ __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, con
     } else {
       staged_lo = -1;
       if ((int)threadIdx.x < cnt) {
-        const uint32_t id = ids[ti.range.x + lo + threadIdx.x];
+        const uint32_t id = ids[ti.range.x + lo + threadIdx.x] & rc.id_mask;
         s_id[threadIdx.x] = id;
         s_rec[threadIdx.x] = stage_record(id, ti.view, n, ti.x0, ti.y0, recA, recB, recZ, rgb);
       }
@@ -471,6 +471,15 @@ struct RasterArgs {
   int64_t n;
   RenderConsts rc;
 };
+
+// Raster arguments of a workspace: the sorted pair words and the mask that
+// extracts a record id from them.
+static RasterArgs raster_args(const Workspace &ws, const ViewInfo *views, const int32_t *tile_view,
+                              const gsr_gaussians &g, RenderConsts rc) {
+  rc.id_mask = ws.id_mask;
+  const uint32_t *ids = ws.pack_shift ? ws.pkeys[ws.psorted] : ws.pvals[ws.psorted];
+  return RasterArgs{ws.recA, ws.recB, ws.recZ, g.rgb, ids, ws.ranges, views, tile_view, g.n, rc};
+}
 
 struct PixelState {
   float *T;
@@ -668,7 +677,7 @@ void launch_l1(const Plan &p, const ViewInfo *views, const float *rgb, const flo
 void launch_render_forward(const Plan &p, const Workspace &ws, const ViewInfo *views,
                            const int32_t *tile_view, const gsr_gaussians &g, const RenderConsts &rc,
                            const gsr_images *out, hipStream_t s) {
-  RasterArgs a{ws.recA, ws.recB, ws.recZ, g.rgb, ws.pvals[ws.psorted], ws.ranges, views, tile_view, g.n, rc};
+  const RasterArgs a = raster_args(ws, views, tile_view, g, rc);
   gsr_images o{nullptr, nullptr, nullptr, nullptr, nullptr};
   if (out) o = *out;
   PixelState ps{ws.T_final, ws.last, ws.zr};
@@ -678,7 +687,7 @@ void launch_render_forward(const Plan &p, const Workspace &ws, const ViewInfo *v
 void launch_render_backward(const Plan &p, const Workspace &ws, const ViewInfo *views,
                             const int32_t *tile_view, const gsr_gaussians &g, const RenderConsts &rc,
                             const float *g_rgb, const float *g_depth, const float *g_T, hipStream_t s) {
-  RasterArgs a{ws.recA, ws.recB, ws.recZ, g.rgb, ws.pvals[ws.psorted], ws.ranges, views, tile_view, g.n, rc};
+  const RasterArgs a = raster_args(ws, views, tile_view, g, rc);
   hipLaunchKernelGGL(k_render_bwd, dim3(p.total_tiles), dim3(BLOCK), 0, s, a, ws.T_final, ws.last, ws.zr, g_rgb,
                      g_depth, g_T, ws.grad2d);
 }
@@ -688,7 +697,7 @@ void launch_render_fused(const Plan &p, const Workspace &ws, const ViewInfo *vie
                          const float *t_rgb, const float *t_depth, const uint8_t *pmask, float w_rgb,
                          float w_depth, const float *loss_cap, const gsr_images *out, float *loss,
                          const Tuning &tun, int num_cus, hipStream_t s) {
-  RasterArgs a{ws.recA, ws.recB, ws.recZ, g.rgb, ws.pvals[ws.psorted], ws.ranges, views, tile_view, g.n, rc};
+  const RasterArgs a = raster_args(ws, views, tile_view, g, rc);
   gsr_images o{nullptr, nullptr, nullptr, nullptr, nullptr};
   if (out) o = *out;
   int grid = tun.blocks_per_cu * num_cus;
@@ -729,7 +738,7 @@ __global__ __launch_bounds__(BLOCK) void k_work_counts(const int32_t *__restrict
 void launch_work_counts(const Plan &p, const Workspace &ws, const ViewInfo *views, const int32_t *tile_view,
                         const gsr_gaussians &g, const RenderConsts &rc, hipStream_t s) {
   launch_fill_u32(reinterpret_cast<uint32_t *>(ws.counts), 0u, 8, s);
-  RasterArgs a{ws.recA, ws.recB, ws.recZ, g.rgb, ws.pvals[ws.psorted], ws.ranges, views, tile_view, g.n, rc};
+  const RasterArgs a = raster_args(ws, views, tile_view, g, rc);
   if (p.total_tiles > 0)
     hipLaunchKernelGGL(k_count_walk, dim3(p.total_tiles), dim3(BLOCK), 0, s, a, ws.counts);
   hipLaunchKernelGGL(k_work_counts, dim3(256), dim3(BLOCK), 0, s, ws.last, p.total_pixels, ws.hdr, ws.counts);

@@ -174,7 +174,7 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scan(const uint32_t *__restrict
 // and the digit offsets then place every key in block-local digit order in
 // LDS, and each digit's keys of the tile are written as one contiguous run:
 // consecutive threads store consecutive addresses.
-template <int ITEMS>
+template <int ITEMS, bool VALS>
 __global__ __launch_bounds__(BLOCK) void k_radix_scatter(
     const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in,
     uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out,
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(
   __shared__ uint32_t s_wc[4][RADIX];  // per-wavefront digit counts, then their prefix over wavefronts
   __shared__ uint32_t s_w[4];
   __shared__ uint32_t s_k[STILE];
-  __shared__ uint32_t s_v[STILE];
+  __shared__ uint32_t s_v[VALS ? STILE : 1];
   const uint32_t n = sort_count(n_dev, n_static, cap);
   const uint32_t ntiles = (n + STILE - 1) / STILE;
   const uint32_t mask = (1u << nbits) - 1u;
@@ -208,7 +208,7 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(
     for (int r = 0; r < ITEMS; ++r) {
       const uint32_t idx = wbase + r * 64;
       kr[r] = idx < n ? keys_in[idx] : 0u;
-      vr[r] = idx < n ? vals_in[idx] : 0u;
+      if (VALS) vr[r] = idx < n ? vals_in[idx] : 0u;
     }
     s_wc[0][dig] = s_wc[1][dig] = s_wc[2][dig] = s_wc[3][dig] = 0u;
     {
@@ -244,7 +244,7 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(
       if (wbase + r * 64 < n) {
         const uint32_t lp = s_wc[wave][(kr[r] >> shift) & mask] + rank[r];
         s_k[lp] = kr[r];
-        s_v[lp] = vr[r];
+        if (VALS) s_v[lp] = vr[r];
       }
     }
     __syncthreads();
@@ -252,7 +252,7 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(
       const uint32_t key = s_k[i];
       const uint32_t gpos = s_goff[(key >> shift) & mask] + i;
       keys_out[gpos] = key;
-      vals_out[gpos] = s_v[i];
+      if (VALS) vals_out[gpos] = s_v[i];
     }
     __syncthreads();
   }
@@ -260,24 +260,32 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(
 
 // Stable LSD radix sort of (key, value) over bits [0, key_bits); returns the
 // index of the buffer holding the result.
-// When hist0_ready, the first pass's per-tile digit counts are already in
-// hist (written by the kernel that produced the keys).
+// The key occupies bits [base, base + key_bits) of each word; without vals
+// the words are sorted alone (packed pairs).  When hist0_ready, the first
+// pass's per-tile digit counts are already in hist (written by the kernel
+// that produced the keys).
 template <int ITEMS>
 static int radix_sort(uint32_t *keys[2], uint32_t *vals[2], const unsigned long long *n_dev,
-                      uint32_t n_static, uint32_t cap, int key_bits, uint32_t *hist, uint32_t *hoff,
+                      uint32_t n_static, uint32_t cap, int base, int key_bits, uint32_t *hist, uint32_t *hoff,
                       int max_tiles, uint32_t *digit_total, int grid, bool hist0_ready, hipStream_t s) {
   const int per = radix_digit_bits(key_bits);
   int cur = 0;
-  for (int shift = 0; shift < key_bits; shift += per) {
-    const int nbits = key_bits - shift < per ? key_bits - shift : per;
-    if (shift > 0 || !hist0_ready)
+  for (int sh = 0; sh < key_bits; sh += per) {
+    const int nbits = key_bits - sh < per ? key_bits - sh : per;
+    const int shift = base + sh;
+    if (sh > 0 || !hist0_ready)
       hipLaunchKernelGGL(k_radix_hist<ITEMS>, dim3(grid), dim3(BLOCK), 0, s, keys[cur], n_dev, n_static, cap,
                          shift, nbits, hist, max_tiles);
     hipLaunchKernelGGL(k_radix_scan<ITEMS>, dim3(RADIX), dim3(BLOCK), 0, s, hist, hoff, n_dev, n_static, cap,
                        max_tiles, digit_total);
-    hipLaunchKernelGGL(k_radix_scatter<ITEMS>, dim3(grid), dim3(BLOCK), 0, s, keys[cur], vals[cur],
-                       keys[cur ^ 1], vals[cur ^ 1], n_dev, n_static, cap, shift, nbits, hist, hoff,
-                       max_tiles, digit_total);
+    if (vals)
+      hipLaunchKernelGGL((k_radix_scatter<ITEMS, true>), dim3(grid), dim3(BLOCK), 0, s, keys[cur], vals[cur],
+                         keys[cur ^ 1], vals[cur ^ 1], n_dev, n_static, cap, shift, nbits, hist, hoff,
+                         max_tiles, digit_total);
+    else
+      hipLaunchKernelGGL((k_radix_scatter<ITEMS, false>), dim3(grid), dim3(BLOCK), 0, s, keys[cur],
+                         (const uint32_t *)nullptr, keys[cur ^ 1], (uint32_t *)nullptr, n_dev, n_static, cap,
+                         shift, nbits, hist, hoff, max_tiles, digit_total);
     cur ^= 1;
   }
   return cur;
@@ -290,7 +298,7 @@ static int sort_grid_for(int64_t n, int items, int cap_grid) {
 }
 
 int launch_depth_sort(const Plan &p, Workspace &ws, hipStream_t s, int sort_grid) {
-  ws.dsorted = radix_sort<SORT_ITEMS_DEPTH>(ws.dkeys, ws.dvals, nullptr, (uint32_t)p.n_rec, (uint32_t)p.n_rec, 32,
+  ws.dsorted = radix_sort<SORT_ITEMS_DEPTH>(ws.dkeys, ws.dvals, nullptr, (uint32_t)p.n_rec, (uint32_t)p.n_rec, 0, 32,
                                             ws.hist, ws.hoff, p.max_sort_tiles, ws.digit_total,
                                             sort_grid_for(p.n_rec, SORT_ITEMS_DEPTH, sort_grid), false, s);
   return ws.dsorted;
@@ -298,7 +306,8 @@ int launch_depth_sort(const Plan &p, Workspace &ws, hipStream_t s, int sort_grid
 
 int launch_pair_sort(const Plan &p, Workspace &ws, hipStream_t s, int sort_grid) {
   const unsigned long long *n_dev = reinterpret_cast<const unsigned long long *>(ws.hdr + HDR_NPAIRS);
-  ws.psorted = radix_sort<SORT_ITEMS_PAIR>(ws.pkeys, ws.pvals, n_dev, 0u, (uint32_t)p.capacity, p.tile_bits,
+  ws.psorted = radix_sort<SORT_ITEMS_PAIR>(ws.pkeys, ws.pack_shift ? nullptr : ws.pvals, n_dev, 0u,
+                                           (uint32_t)p.capacity, ws.pack_shift, p.tile_bits,
                                            ws.hist, ws.hoff, p.max_sort_tiles, ws.digit_total,
                                            sort_grid_for(p.capacity, SORT_ITEMS_PAIR, sort_grid), true, s);
   return ws.psorted;
@@ -416,7 +425,8 @@ __global__ __launch_bounds__(BLOCK) void k_emit_pairs(const uint32_t *__restrict
                                                       uint32_t n_rec, const unsigned long long *__restrict__ n_dev,
                                                       uint32_t cap, const uint32_t *__restrict__ bucket_rec,
                                                       uint32_t *__restrict__ pkeys, uint32_t *__restrict__ pvals,
-                                                      int nbits0, uint32_t *__restrict__ hist, int max_tiles) {
+                                                      int pack_shift, int nbits0, uint32_t *__restrict__ hist,
+                                                      int max_tiles) {
   static_assert(EMIT_BUCKET == BLOCK, "one emission bucket per block-iteration");
   constexpr int STILE = BLOCK * SORT_ITEMS_PAIR;
   __shared__ uint32_t s_off[BLOCK], s_ord[BLOCK];
@@ -479,8 +489,12 @@ __global__ __launch_bounds__(BLOCK) void k_emit_pairs(const uint32_t *__restrict
           const int len = support_row(sp, (double)cb.x, (double)cb.y, (double)cb.z, ty, tx0, tx1, c0);
           if (tx < c0 || tx >= c0 + len) tile = dropped_key;
         }
-        pkeys[p] = tile;
-        pvals[p] = rec;
+        if (pvals) {
+          pkeys[p] = tile;
+          pvals[p] = rec;
+        } else {
+          pkeys[p] = tile << pack_shift | rec;
+        }
       }
       const uint32_t d = tile & mask0;
       const uint64_t peers = match_digit(d, nbits0, __ballot(p < n));
@@ -509,7 +523,8 @@ void launch_emit_pairs(const Plan &p, const Workspace &ws, const ViewInfo *views
   const unsigned long long *n_dev = reinterpret_cast<const unsigned long long *>(ws.hdr + HDR_NPAIRS);
   hipLaunchKernelGGL(k_emit_pairs, dim3((unsigned)blocks), dim3(BLOCK), 0, s, order, off, ws.tinfo, ws.support,
                      ws.recB, (uint32_t)p.total_tiles, (uint32_t)p.n_rec, n_dev, (uint32_t)p.capacity,
-                     ws.bucket_rec, ws.pkeys[0], ws.pvals[0], radix_digit_bits(p.tile_bits), ws.hist,
+                     ws.bucket_rec, ws.pkeys[0], ws.pack_shift ? nullptr : ws.pvals[0], ws.pack_shift,
+                     radix_digit_bits(p.tile_bits), ws.hist,
                      p.max_sort_tiles);
 }
 
@@ -517,14 +532,28 @@ void launch_emit_pairs(const Plan &p, const Workspace &ws, const ViewInfo *views
 
 __global__ __launch_bounds__(BLOCK) void k_tile_ranges(const uint32_t *__restrict__ keys,
                                                        const unsigned long long *n_dev, uint32_t cap,
-                                                       uint32_t total_tiles, int2 *__restrict__ ranges) {
+                                                       uint32_t total_tiles, int shift,
+                                                       int2 *__restrict__ ranges) {
   const uint32_t n = sort_count(n_dev, 0u, cap);
   for (uint32_t i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) {
-    const uint32_t t = keys[i];
+    const uint32_t t = keys[i] >> shift;
     if (t >= total_tiles) continue;  // pairs outside the alpha support
-    if (i == 0 || keys[i - 1] != t) ranges[t].x = (int)i;
-    if (i + 1 == n || keys[i + 1] != t) ranges[t].y = (int)(i + 1);
+    if (i == 0 || keys[i - 1] >> shift != t) ranges[t].x = (int)i;
+    if (i + 1 == n || keys[i + 1] >> shift != t) ranges[t].y = (int)(i + 1);
   }
+}
+
+__global__ __launch_bounds__(BLOCK) void k_unpack_ids(const uint32_t *__restrict__ words,
+                                                      const unsigned long long *n_dev, uint32_t cap,
+                                                      uint32_t mask, uint32_t *__restrict__ ids) {
+  const uint32_t n = sort_count(n_dev, 0u, cap);
+  for (uint32_t i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) ids[i] = words[i] & mask;
+}
+
+void launch_unpack_ids(const Plan &p, const Workspace &ws, hipStream_t s) {
+  const unsigned long long *n_dev = reinterpret_cast<const unsigned long long *>(ws.hdr + HDR_NPAIRS);
+  hipLaunchKernelGGL(k_unpack_ids, dim3(1024), dim3(BLOCK), 0, s, ws.pkeys[ws.psorted], n_dev,
+                     (uint32_t)p.capacity, ws.id_mask, ws.pvals[ws.psorted]);
 }
 
 void launch_tile_ranges(const Plan &p, const Workspace &ws, hipStream_t s) {
@@ -534,7 +563,7 @@ void launch_tile_ranges(const Plan &p, const Workspace &ws, hipStream_t s) {
   if (blocks > 8192) blocks = 8192;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)blocks), dim3(BLOCK), 0, s, ws.pkeys[ws.psorted],
-                     n_dev, (uint32_t)p.capacity, (uint32_t)p.total_tiles, ws.ranges);
+                     n_dev, (uint32_t)p.capacity, (uint32_t)p.total_tiles, ws.pack_shift, ws.ranges);
 }
 
 // ------------------------------------------------------- work order (LPT)

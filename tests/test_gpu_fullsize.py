@@ -150,3 +150,38 @@ def test_sampled_gaussian_gradients_match_oracle(c2):
         assert not np.any(got[k][rest]), k
     H.assert_grads_close({k: got[k][sel] for k in got if k != "pose"}, {k: ref[k][sel] for k in ref if k != "pose"})
     assert H.rel_err(got["pose"][0], ref["pose"]) <= 1e-3, (got["pose"], ref["pose"])
+
+
+def test_unpacked_pair_words_two_large_views(gsr_lib):
+    """Two 1920x1080 views of the 300k scene: 16 321 tile keys (14 bits) and
+    600k records (20 bits) do not fit one 32-bit word, so the pairs are sorted
+    as separate key and value arrays; the pair count and sampled tile lists of
+    both views are bit-exact against the oracle."""
+    gsr = gsr_lib
+    scene = W.room_scene(300_000, seed=0)
+    base = W.camera_replica()
+    cams = [base.with_size(960.0, 960.0, 959.5, 539.5, 1920, 1080),
+            W.perturb_pose(base.with_size(960.0, 960.0, 959.5, 539.5, 1920, 1080),
+                           [0.0, 0.05, 0.15, 0.01, -0.04, 0.02])]
+    print("CASE unpacked 300k 2x1920x1080", flush=True)
+    tiles = sum(((c.width + 15) // 16) * ((c.height + 15) // 16) for c in cams)
+    assert int(tiles + 1).bit_length() + int(2 * scene.n - 1).bit_length() > 32
+    r = gsr.Renderer()
+    r.plan(scene.n, [(c.width, c.height) for c in cams])
+    r.render_forward(H.gpu_scene(gsr, scene), gsr.pack_cameras(cams), gsr.Config())
+    torch.cuda.synchronize()
+    rng, sid = r.debug_tiles()
+    rng, sid = rng.numpy(), sid.numpy()
+    total, off = 0, 0
+    for v, cam in enumerate(cams):
+        proj = O.project(scene, cam, O.Config().as_f32())
+        assert not proj["bin_ambiguous"].any()
+        starts, gauss = O.tile_lists(proj)
+        total += H.rect_pairs(proj)
+        T = proj["TX"] * proj["TY"]
+        np.testing.assert_array_equal(rng[off:off + T, 1] - rng[off:off + T, 0], np.diff(starts))
+        for t in np.random.default_rng(v).choice(T, 12, replace=False):
+            a, b = rng[off + t]
+            np.testing.assert_array_equal(sid[a:b] - v * scene.n, gauss[starts[t]:starts[t + 1]])
+        off += T
+    assert r.pair_count() == total
