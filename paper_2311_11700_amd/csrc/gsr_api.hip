@@ -63,7 +63,7 @@ Workspace make_ws(const Plan &p, void *base_v) {
   w.hdr = reinterpret_cast<uint32_t *>(base + p.off_hdr);
   w.recA = reinterpret_cast<float4 *>(base + p.off_recA);
   w.recB = reinterpret_cast<float4 *>(base + p.off_recB);
-  w.recZ = reinterpret_cast<float *>(base + p.off_recZ);
+  w.recC = reinterpret_cast<float4 *>(base + p.off_recC);
   w.tinfo = reinterpret_cast<uint4 *>(base + p.off_rect);
   w.support = reinterpret_cast<Support *>(base + p.off_support);
   w.count = reinterpret_cast<uint32_t *>(base + p.off_count);
@@ -321,7 +321,7 @@ gsr_status gsr_plan(gsr_ctx *ctx, int64_t n, int n_views, const int32_t *wh_host
   p.off_hdr = take(HDR_WORDS * 4);
   p.off_recA = take(16 * nr);
   p.off_recB = take(16 * nr);
-  p.off_recZ = take(4 * nr);
+  p.off_recC = take(16 * nr);
   p.off_rect = take(16 * nr);
   p.off_support = take(sizeof(Support) * nr);
   p.off_count = take(4 * nr);

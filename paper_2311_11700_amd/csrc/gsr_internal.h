@@ -107,7 +107,7 @@ struct Workspace {
   uint32_t *hdr;
   float4 *recA;            // [n_rec] (u_hi, u_lo, v_hi, v_lo)
   float4 *recB;            // [n_rec] (conic a, b, c, opacity)
-  float *recZ;             // [n_rec] camera-frame depth
+  float4 *recC;            // [n_rec] (r, g, b, camera-frame depth)
   uint4 *tinfo;            // [n_rec] (view tile offset, view TX | cull << 31, tx0 | tx1 << 16, ty0 | ty1 << 16)
   Support *support;        // [n_rec] alpha-support parameters (records with the cull bit)
   uint32_t *count;         // [n_rec] tiles touched (0 = culled)
@@ -152,7 +152,7 @@ struct Plan {
   int n_pose_blocks = 0;
   size_t bytes = 0;
   // byte offsets inside the workspace
-  size_t off_hdr, off_recA, off_recB, off_recZ, off_rect, off_count, off_dkeys[2], off_dvals[2],
+  size_t off_hdr, off_recA, off_recB, off_recC, off_rect, off_count, off_dkeys[2], off_dvals[2],
       off_scan, off_pkeys[2], off_pvals[2], off_hist, off_digit, off_ranges, off_T, off_last, off_zr,
       off_grad2d, off_pose, off_queue, off_loss, off_counts, off_hoff, off_bucket,
       off_support;

@@ -159,7 +159,7 @@ __global__ __launch_bounds__(BLOCK) void k_preprocess(gsr_gaussians g,
   const float4 fb = make_float4((float)(C / det), (float)(-B / det), (float)(A / det), op);
   ws.recA[rec] = fa;
   ws.recB[rec] = fb;
-  ws.recZ[rec] = zf;
+  ws.recC[rec] = make_float4(fc0, fc1, fc2, zf);
   // Every tile of the rectangle gets a pair; the emission marks the ones the
   // alpha support does not reach (none in the full-rectangle mode or
   // without an alpha threshold).

@@ -63,21 +63,19 @@ __device__ __forceinline__ TileInfo tile_info(int tile, const ViewInfo *__restri
   return ti;
 }
 
-// Load the record of list position `pos` into this thread's staging slot.
-__device__ __forceinline__ Staged stage_record(uint32_t id, int view, int64_t n, float x0, float y0,
-                                               const float4 *__restrict__ recA,
+// Load record `id` into this thread's staging slot (three 16-byte loads).
+__device__ __forceinline__ Staged stage_record(uint32_t id, float x0, float y0, const float4 *__restrict__ recA,
                                                const float4 *__restrict__ recB,
-                                               const float *__restrict__ recZ,
-                                               const float *__restrict__ rgb) {
+                                               const float4 *__restrict__ recC) {
   const float4 A = recA[id];
   const float4 Bc = recB[id];
-  const int64_t gi = (int64_t)id - (int64_t)view * n;
+  const float4 C = recC[id];
   Staged s;
   // (u_hi - x0) is exact for |u_hi| < 2^24 and integer x0; the low word adds
   // the remaining bits.
-  s.geo = make_float4((A.x - x0) + A.y, (A.z - y0) + A.w, Bc.w, recZ[id]);
+  s.geo = make_float4((A.x - x0) + A.y, (A.z - y0) + A.w, Bc.w, C.w);
   s.con = make_float4(NEG_HALF_LOG2E * Bc.x, 2.f * (NEG_HALF_LOG2E * Bc.y), NEG_HALF_LOG2E * Bc.z, 0.f);
-  s.col = make_float4(rgb[3 * gi], rgb[3 * gi + 1], rgb[3 * gi + 2], 0.f);
+  s.col = make_float4(C.x, C.y, C.z, 0.f);
   return s;
 }
 
@@ -107,8 +105,7 @@ struct FwdState {
 template <bool COUNT>
 __device__ __forceinline__ void tile_forward(const TileInfo &ti, int64_t n, const float4 *__restrict__ recA,
                                              const float4 *__restrict__ recB,
-                                             const float *__restrict__ recZ,
-                                             const float *__restrict__ rgb,
+                                             const float4 *__restrict__ recC,
                                              const uint32_t *__restrict__ ids, const RenderConsts &rc,
                                              Staged *s_rec, FwdState &st, unsigned long long *counts,
                                              uint32_t *s_id = nullptr, int *staged_lo = nullptr) {
@@ -123,13 +120,17 @@ __device__ __forceinline__ void tile_forward(const TileInfo &ti, int64_t n, cons
   uint32_t nev_w = 0u, nbl_w = 0u;
   const float lx = (float)(threadIdx.x & (TILE - 1));
   const float ly = (float)(threadIdx.x >> 4);
+  // This thread's list word of the next batch, loaded one batch ahead.
+  uint32_t next_id = 0u;
+  if ((int)threadIdx.x < BATCH && ti.range.x + (int)threadIdx.x < ti.range.y) next_id = ids[ti.range.x + threadIdx.x];
   for (int base = ti.range.x; base < ti.range.y; base += BATCH) {
     if (__syncthreads_and(amin == __builtin_inff())) break;
     const int pos = base + threadIdx.x;
     if ((int)threadIdx.x < BATCH && pos < ti.range.y) {
-      const uint32_t id = ids[pos] & rc.id_mask;
+      const uint32_t id = next_id & rc.id_mask;
       if (s_id) s_id[threadIdx.x] = id;
-      s_rec[threadIdx.x] = stage_record(id, ti.view, n, ti.x0, ti.y0, recA, recB, recZ, rgb);
+      s_rec[threadIdx.x] = stage_record(id, ti.x0, ti.y0, recA, recB, recC);
+      if (pos + BATCH < ti.range.y) next_id = ids[pos + BATCH];
     }
     if (staged_lo) *staged_lo = base - ti.range.x;
     __syncthreads();
@@ -269,8 +270,7 @@ __device__ __forceinline__ void mfma_consume(const float4v &D, int nq, uint64_t 
 // fields: (u, v, conic a, b, c, opacity, r, g, b, depth).
 __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, const float4 *__restrict__ recA,
                                               const float4 *__restrict__ recB,
-                                              const float *__restrict__ recZ,
-                                              const float *__restrict__ rgb,
+                                              const float4 *__restrict__ recC,
                                               const uint32_t *__restrict__ ids, const RenderConsts &rc,
                                               const BwdIn &in, double *__restrict__ grad2d,
                                               Staged *s_rec, float *s_part, uint32_t *s_id, int *s_max,
@@ -338,6 +338,8 @@ __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, con
   // an entry below maxlast.  Those inside the forward's last batch (still
   // staged, records and ids, from list position staged_lo on) are read in
   // place; the others are staged into the first SUB slots.
+  uint32_t next_id = 0u;  // list word of this thread's slot in sub-batch next_lo, loaded ahead
+  int next_lo = -1;
   for (int lo = ((maxlast - 1) / SUB) * SUB; lo >= 0; lo -= SUB) {
     const int hi = min(lo + SUB, maxlast);
     const int cnt = hi - lo;
@@ -347,10 +349,14 @@ __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, con
     } else {
       staged_lo = -1;
       if ((int)threadIdx.x < cnt) {
-        const uint32_t id = ids[ti.range.x + lo + threadIdx.x] & rc.id_mask;
+        const uint32_t id = (next_lo == lo ? next_id : ids[ti.range.x + lo + threadIdx.x]) & rc.id_mask;
         s_id[threadIdx.x] = id;
-        s_rec[threadIdx.x] = stage_record(id, ti.view, n, ti.x0, ti.y0, recA, recB, recZ, rgb);
+        s_rec[threadIdx.x] = stage_record(id, ti.x0, ti.y0, recA, recB, recC);
       }
+    }
+    if (lo >= SUB && !(staged_lo >= 0 && lo - SUB >= staged_lo)) {
+      if ((int)threadIdx.x < SUB) next_id = ids[ti.range.x + lo - SUB + threadIdx.x];
+      next_lo = lo - SUB;
     }
     {
       // Entries without a contribution in this wavefront keep zero sums.
@@ -462,8 +468,7 @@ __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, con
 struct RasterArgs {
   const float4 *recA;
   const float4 *recB;
-  const float *recZ;
-  const float *rgb;
+  const float4 *recC;  // (r, g, b, camera-frame depth) per record
   const uint32_t *ids;
   const int2 *ranges;
   const ViewInfo *views;
@@ -478,7 +483,7 @@ static RasterArgs raster_args(const Workspace &ws, const ViewInfo *views, const 
                               const gsr_gaussians &g, RenderConsts rc) {
   rc.id_mask = ws.id_mask;
   const uint32_t *ids = ws.pack_shift ? ws.pkeys[ws.psorted] : ws.pvals[ws.psorted];
-  return RasterArgs{ws.recA, ws.recB, ws.recZ, g.rgb, ids, ws.ranges, views, tile_view, g.n, rc};
+  return RasterArgs{ws.recA, ws.recB, ws.recC, ids, ws.ranges, views, tile_view, g.n, rc};
 }
 
 struct PixelState {
@@ -497,7 +502,7 @@ __global__ __launch_bounds__(BLOCK) void k_render_fwd(RasterArgs a, PixelState p
   __shared__ Staged s_rec[BATCH];
   const TileInfo ti = tile_info(blockIdx.x, a.views, a.tile_view, a.ranges);
   FwdState st;
-  tile_forward<false>(ti, a.n, a.recA, a.recB, a.recZ, a.rgb, a.ids, a.rc, s_rec, st, nullptr);
+  tile_forward<false>(ti, a.n, a.recA, a.recB, a.recC, a.ids, a.rc, s_rec, st, nullptr);
   if (!ti.inside) return;
   save_state(ps, ti.pix, st);
   const int64_t loc = ti.pix - ti.pix_off;
@@ -538,7 +543,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     in.gD = g_depth ? g_depth[ti.pix] : 0.f;
     in.gT = g_T ? g_T[ti.pix] : 0.f;
   }
-  tile_backward(ti, a.n, a.recA, a.recB, a.recZ, a.rgb, a.ids, a.rc, in, grad2d, s_rec, s_part, s_id, &s_max,
+  tile_backward(ti, a.n, a.recA, a.recB, a.recC, a.ids, a.rc, in, grad2d, s_rec, s_part, s_id, &s_max,
                 s_mA);
 }
 
@@ -574,7 +579,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
       const TileInfo ti = tile_info(tile, a.views, a.tile_view, a.ranges);
       FwdState st;
       int staged_lo;
-      tile_forward<false>(ti, a.n, a.recA, a.recB, a.recZ, a.rgb, a.ids, a.rc, s_rec, st, nullptr, s_id,
+      tile_forward<false>(ti, a.n, a.recA, a.recB, a.recC, a.ids, a.rc, s_rec, st, nullptr, s_id,
                           &staged_lo);
       BwdIn in{st.T, ti.inside ? st.last : 0, st.zr, 0.f, 0.f, 0.f, 0.f, 0.f};
       float lpx = 0.f;
@@ -613,7 +618,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
       }
       const float ls = wave_sum(lpx);
       if ((threadIdx.x & 63) == 0) s_loss[threadIdx.x >> 6] = ls;
-      tile_backward(ti, a.n, a.recA, a.recB, a.recZ, a.rgb, a.ids, a.rc, in, grad2d, s_rec, s_part, s_id, &s_max,
+      tile_backward(ti, a.n, a.recA, a.recB, a.recC, a.ids, a.rc, in, grad2d, s_rec, s_part, s_id, &s_max,
                     s_mA, staged_lo);
       if (threadIdx.x == 0 && loss) atomicAdd(loss, (s_loss[0] + s_loss[1]) + (s_loss[2] + s_loss[3]));
       // The next tile may have an empty list (no barrier in its forward):
@@ -719,7 +724,7 @@ __global__ __launch_bounds__(BLOCK) void k_count_walk(RasterArgs a, unsigned lon
   __shared__ Staged s_rec[BATCH];
   const TileInfo ti = tile_info(blockIdx.x, a.views, a.tile_view, a.ranges);
   FwdState st;
-  tile_forward<true>(ti, a.n, a.recA, a.recB, a.recZ, a.rgb, a.ids, a.rc, s_rec, st, counts);
+  tile_forward<true>(ti, a.n, a.recA, a.recB, a.recC, a.ids, a.rc, s_rec, st, counts);
 }
 
 // counts[0] = pairs (from the header), counts[3] = sum of `last`.
