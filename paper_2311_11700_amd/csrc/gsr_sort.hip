@@ -367,11 +367,13 @@ __global__ __launch_bounds__(BLOCK) void k_scan_top(unsigned long long *__restri
 // Per-record pair offsets in depth order, clamped to the capacity (so the
 // array stays non-decreasing and every offset fits 32 bits).  Also records,
 // for every emission bucket b, the record whose pair range holds pair
-// EMIT_BUCKET * b (each such pair lies in exactly one non-empty range).
+// EMIT_BUCKET * b (each such pair lies in exactly one non-empty range), and
+// after the last bucket the record that holds the last pair.
 __global__ __launch_bounds__(BLOCK) void k_scan_down(const uint32_t *__restrict__ order,
                                                      const uint32_t *__restrict__ count, int64_t n_rec,
                                                      const unsigned long long *__restrict__ part,
-                                                     uint64_t capacity, uint32_t *__restrict__ off,
+                                                     uint64_t capacity, const uint32_t *__restrict__ hdr,
+                                                     uint32_t *__restrict__ off,
                                                      uint32_t *__restrict__ bucket_rec) {
   __shared__ unsigned long long s_w[4];
   const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + threadIdx.x * SCAN_ITEMS;
@@ -385,6 +387,8 @@ __global__ __launch_bounds__(BLOCK) void k_scan_down(const uint32_t *__restrict_
   }
   unsigned long long total;
   unsigned long long o = block_exclusive_scan<unsigned long long>(sum, s_w, total) + part[blockIdx.x];
+  const unsigned long long np = *reinterpret_cast<const unsigned long long *>(hdr + HDR_NPAIRS);
+  const unsigned long long n = np < capacity ? np : capacity;  // pairs emitted
 #pragma unroll
   for (int k = 0; k < SCAN_ITEMS; ++k) {
     const int64_t idx = base + k;
@@ -393,30 +397,21 @@ __global__ __launch_bounds__(BLOCK) void k_scan_down(const uint32_t *__restrict_
       const unsigned long long e = o + c[k] < capacity ? o + c[k] : capacity;
       for (unsigned long long b = (o + EMIT_BUCKET - 1) / EMIT_BUCKET; b * EMIT_BUCKET < e; ++b)
         bucket_rec[b] = (uint32_t)idx;
+      if (o < n && n <= e) bucket_rec[(n + EMIT_BUCKET - 1) / EMIT_BUCKET] = (uint32_t)idx;
     }
     o += c[k];
   }
 }
 
-// Largest k in [lo, hi] with off[k] <= p (off non-decreasing, off[lo] <= p).
-__device__ __forceinline__ uint32_t find_record(const uint32_t *__restrict__ off, uint32_t lo, uint32_t hi,
-                                                uint32_t p) {
-  while (lo < hi) {
-    const uint32_t mid = lo + (hi - lo + 1) / 2;
-    if (off[mid] <= p) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
-// One thread per (tile, Gaussian) pair: find the record that owns the pair
-// (records are in depth order, so the pairs come out in depth order), decode
-// the tile from the record's rectangle, test it against the alpha support,
-// write key and value.  A block-iteration covers one sort tile of the pair
-// sort (SORT_ITEMS_PAIR emission buckets of EMIT_BUCKET pairs) and also
-// writes that tile's digit counts for the sort's first pass.  Within a
-// bucket the bucket index brackets the records, so the per-thread searches
-// are short.
+// Pair emission.  A block-iteration produces one sort tile of the pair sort
+// (STILE consecutive pairs, in depth order): the records that own those pairs
+// (found through the bucket index) are staged in LDS, up to BLOCK at a time,
+// with their pair offsets, rectangles, alpha-support parameters and conics;
+// then one thread per pair finds its record among the staged ones, decodes
+// the tile from the rectangle, tests it against the alpha support and writes
+// the word(s).  The block also counts the first radix pass's digits of its
+// tile.  Global loads come in two dependent rounds per staged chunk of
+// records instead of per pair.
 __global__ __launch_bounds__(BLOCK) void k_emit_pairs(const uint32_t *__restrict__ order,
                                                       const uint32_t *__restrict__ off,
                                                       const uint4 *__restrict__ tinfo,
@@ -427,82 +422,90 @@ __global__ __launch_bounds__(BLOCK) void k_emit_pairs(const uint32_t *__restrict
                                                       uint32_t *__restrict__ pkeys, uint32_t *__restrict__ pvals,
                                                       int pack_shift, int nbits0, uint32_t *__restrict__ hist,
                                                       int max_tiles) {
-  static_assert(EMIT_BUCKET == BLOCK, "one emission bucket per block-iteration");
+  static_assert(EMIT_BUCKET == BLOCK, "one emission bucket per BLOCK pairs");
   constexpr int STILE = BLOCK * SORT_ITEMS_PAIR;
-  __shared__ uint32_t s_off[BLOCK], s_ord[BLOCK];
+  __shared__ uint32_t s_off[BLOCK + 1];  // first pair of each staged record, then the end
+  __shared__ uint32_t s_id[BLOCK];
+  __shared__ uint4 s_ti[BLOCK];
+  __shared__ Support s_sp[BLOCK];
+  __shared__ float4 s_cb[BLOCK];
   __shared__ uint32_t s_cnt[RADIX];
   const uint32_t n = sort_count(n_dev, 0u, cap);
-  const uint32_t nb = (n + EMIT_BUCKET - 1) / EMIT_BUCKET;
   const uint32_t ntiles = (n + STILE - 1) / STILE;
   const uint32_t mask0 = (1u << nbits0) - 1u;
+  const int t = threadIdx.x;
   for (uint32_t T = blockIdx.x; T < ntiles; T += gridDim.x) {
-    s_cnt[threadIdx.x] = 0u;
-    for (uint32_t b = T * SORT_ITEMS_PAIR; b < (T + 1) * SORT_ITEMS_PAIR && b < nb; ++b) {
-      const uint32_t lo = bucket_rec[b];
-      const uint32_t hi = b + 1 < nb ? bucket_rec[b + 1] : n_rec - 1u;
-      // The bucket's records (offsets and ids) go to LDS when they fit (a
-      // bucket of 256 pairs spans at most 257 records with pairs).
-      const uint32_t nr = hi - lo + 1u;
-      const bool in_lds = nr <= (uint32_t)BLOCK;
+    const uint32_t p0 = T * STILE;
+    const uint32_t p1 = p0 + STILE < n ? p0 + STILE : n;
+    // Records holding pairs p0 .. p1 - 1: from the one holding p0 (a bucket
+    // start) to the one holding the next tile's first pair (or the last).
+    const uint32_t r_first = bucket_rec[p0 / EMIT_BUCKET];
+    const uint32_t r_last = bucket_rec[(p1 + EMIT_BUCKET - 1) / EMIT_BUCKET];
+    s_cnt[t] = 0u;
+    for (uint32_t rb = r_first; rb <= r_last; rb += BLOCK) {
+      const uint32_t nr = r_last - rb + 1u < (uint32_t)BLOCK ? r_last - rb + 1u : (uint32_t)BLOCK;
       __syncthreads();
-      if (in_lds && threadIdx.x < nr) {
-        s_off[threadIdx.x] = off[lo + threadIdx.x];
-        s_ord[threadIdx.x] = order[lo + threadIdx.x];
+      if ((uint32_t)t < nr) {
+        const uint32_t k = rb + t;
+        const uint32_t rec = order[k];
+        s_off[t] = off[k];
+        s_id[t] = rec;
+        s_ti[t] = tinfo[rec];
+        s_sp[t] = support[rec];
+        s_cb[t] = recB[rec];
       }
+      if (t == 0) s_off[nr] = rb + nr < n_rec ? off[rb + nr] : n;
       __syncthreads();
-      const uint32_t p = b * EMIT_BUCKET + threadIdx.x;
-      uint32_t tile = 0u;
-      if (p < n) {
-        uint32_t rec, j;
-        if (in_lds) {
-          uint32_t a = 0u, z = nr - 1u;  // largest index with s_off <= p
+      const uint32_t q0 = s_off[0] > p0 ? s_off[0] : p0;
+      const uint32_t q1 = s_off[nr] < p1 ? s_off[nr] : p1;
+      for (uint32_t base = q0; base < q1; base += BLOCK) {
+        const uint32_t p = base + t;
+        const bool valid = p < q1;
+        uint32_t tile = 0u;
+        if (valid) {
+          uint32_t a = 0u, z = nr - 1u;  // largest staged record with s_off <= p
           while (a < z) {
             const uint32_t mid = a + (z - a + 1u) / 2u;
             if (s_off[mid] <= p) a = mid;
             else z = mid - 1u;
           }
-          rec = s_ord[a];
-          j = p - s_off[a];
-        } else {
-          const uint32_t k = find_record(off, lo, hi, p);
-          rec = order[k];
-          j = p - off[k];
+          const uint32_t j = p - s_off[a];
+          const uint4 ti = s_ti[a];
+          const int TX = (int)(ti.y & 0x7FFFFFFFu);
+          const int tx0 = (int)(ti.z & 0xFFFFu), tx1 = (int)(ti.z >> 16);
+          const int ty0 = (int)(ti.w & 0xFFFFu);
+          const uint32_t w = (uint32_t)(tx1 - tx0 + 1);
+          // j < 2^24 and w < 2^16: the float quotient is within one of the
+          // integer quotient; fix it up exactly.
+          uint32_t q = (uint32_t)((float)j / (float)w);
+          if (q * w > j) --q;
+          else if ((q + 1u) * w <= j) ++q;
+          const int ty = ty0 + (int)q, tx = tx0 + (int)(j - q * w);
+          tile = ti.x + (uint32_t)(ty * TX + tx);
+          if (ti.y & 0x80000000u) {
+            // Tiles of the rectangle that the alpha support does not reach
+            // get the key past the last tile: the sort moves them behind
+            // every list.
+            const float4 cb = s_cb[a];
+            int c0 = 0;
+            const int len = support_row(s_sp[a], (double)cb.x, (double)cb.y, (double)cb.z, ty, tx0, tx1, c0);
+            if (tx < c0 || tx >= c0 + len) tile = dropped_key;
+          }
+          const uint32_t rec = s_id[a];
+          if (pvals) {
+            pkeys[p] = tile;
+            pvals[p] = rec;
+          } else {
+            pkeys[p] = tile << pack_shift | rec;
+          }
         }
-        const uint4 ti = tinfo[rec];
-        const int TX = (int)(ti.y & 0x7FFFFFFFu);
-        const int tx0 = (int)(ti.z & 0xFFFFu), tx1 = (int)(ti.z >> 16);
-        const int ty0 = (int)(ti.w & 0xFFFFu);
-        const uint32_t w = (uint32_t)(tx1 - tx0 + 1);
-        // j < 2^24 and w < 2^16: the float quotient is within one of the
-        // integer quotient; fix it up exactly.
-        uint32_t q = (uint32_t)((float)j / (float)w);
-        if (q * w > j) --q;
-        else if ((q + 1u) * w <= j) ++q;
-        const int ty = ty0 + (int)q, tx = tx0 + (int)(j - q * w);
-        tile = ti.x + (uint32_t)(ty * TX + tx);
-        if (ti.y & 0x80000000u) {
-          // Tiles of the rectangle that the alpha support does not reach get
-          // the key past the last tile: the sort moves them behind every list.
-          const Support sp = support[rec];
-          const float4 cb = recB[rec];
-          int c0 = 0;
-          const int len = support_row(sp, (double)cb.x, (double)cb.y, (double)cb.z, ty, tx0, tx1, c0);
-          if (tx < c0 || tx >= c0 + len) tile = dropped_key;
-        }
-        if (pvals) {
-          pkeys[p] = tile;
-          pvals[p] = rec;
-        } else {
-          pkeys[p] = tile << pack_shift | rec;
-        }
+        const uint32_t d = tile & mask0;
+        const uint64_t peers = match_digit(d, nbits0, __ballot(valid));
+        if (valid && (peers & lanemask_lt()) == 0ull) atomicAdd(&s_cnt[d], (uint32_t)__popcll(peers));
       }
-      const uint32_t d = tile & mask0;
-      const uint64_t peers = match_digit(d, nbits0, __ballot(p < n));
-      if (p < n && (peers & lanemask_lt()) == 0ull) atomicAdd(&s_cnt[d], (uint32_t)__popcll(peers));
     }
     __syncthreads();
-    hist[(size_t)threadIdx.x * max_tiles + T] = s_cnt[threadIdx.x];
-    __syncthreads();
+    hist[(size_t)t * max_tiles + T] = s_cnt[t];
   }
 }
 
@@ -516,7 +519,7 @@ void launch_emit_pairs(const Plan &p, const Workspace &ws, const ViewInfo *views
                      (uint64_t)p.capacity);
   if (p.n_rec == 0) return;
   hipLaunchKernelGGL(k_scan_down, dim3(p.n_scan_blocks), dim3(BLOCK), 0, s, order, ws.count, p.n_rec,
-                     ws.scan_part, (uint64_t)p.capacity, off, ws.bucket_rec);
+                     ws.scan_part, (uint64_t)p.capacity, ws.hdr, off, ws.bucket_rec);
   int64_t blocks = (p.capacity + (int64_t)BLOCK * SORT_ITEMS_PAIR - 1) / ((int64_t)BLOCK * SORT_ITEMS_PAIR);
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
