@@ -104,6 +104,28 @@ def _ptr(t: Optional[torch.Tensor]):
     return None if t is None else t.data_ptr()
 
 
+def _need(t: Optional[torch.Tensor], numel: int, name: str, dtype=None):
+    """The kernels index device buffers by the plan's sizes and cannot see a
+    tensor's length: reject a buffer that is too small, on the host, or of
+    the wrong dtype before its pointer is passed."""
+    if t is None:
+        return
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.numel() < numel:
+        raise ValueError(f"{name} holds {t.numel()} elements, the plan needs {numel}")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _cams_ptr(cams: torch.Tensor, n_views: int):
+    """Pointer to packed cameras (pack_cameras), checked to hold n_views."""
+    _need(cams, 20 * n_views, "cams", torch.float32)
+    return cams.data_ptr()
+
+
 def _stream_ptr(stream=None):
     s = stream if stream is not None else torch.cuda.current_stream()
     return s.cuda_stream
@@ -200,21 +222,31 @@ class Renderer:
         return im
 
     @staticmethod
-    def _grads_c(gr):
+    def _grads_c(gr, n=0, n_views=0):
         g = A.gsr_grads()
+        per = dict(d_mean=3 * n, d_log_scale=3 * n, d_quat=4 * n, d_opacity_logit=n, d_rgb=3 * n, d_pose=6 * n_views)
         for k in ("d_mean", "d_log_scale", "d_quat", "d_opacity_logit", "d_rgb", "d_pose"):
+            _need(gr.get(k), per[k], k, torch.float32)
             setattr(g, k, _ptr(gr.get(k)))
         return g
+
+    def _check_images(self, out):
+        P = self.total_pixels
+        if out:
+            for k, m, dt in (("rgb", 3 * P, torch.float32), ("depth", P, torch.float32),
+                             ("T_final", P, torch.float32), ("last", P, torch.int32), ("loss", P, torch.float32)):
+                _need(out.get(k), m, k, dt)
 
     # --------------------------------------------------------- entry points
     def render_forward(self, g: Gaussians, cams: torch.Tensor, cfg: Config, out=None, stream=None):
         """gsr_render_forward; returns the image dict.  Grows the pair buffer
         and retries once on GSR_E_CAPACITY."""
         out = out if out is not None else self.new_images()
+        self._check_images(out)
         gc, cc = g.c(), cfg.to_c()
         for attempt in range(2):
             ws, wsb = self._ws()
-            st = self.lib.gsr_render_forward(self.ctx, ctypes.byref(gc), cams.data_ptr(), self.n_views,
+            st = self.lib.gsr_render_forward(self.ctx, ctypes.byref(gc), _cams_ptr(cams, self.n_views), self.n_views,
                                              ctypes.byref(cc), ws, wsb, ctypes.byref(self._images_c(out)),
                                              _stream_ptr(stream))
             if st == A.GSR_E_CAPACITY and attempt == 0:
@@ -228,12 +260,18 @@ class Renderer:
     def render_backward(self, g: Gaussians, cams: torch.Tensor, cfg: Config, g_rgb, g_depth, g_T=None,
                         grads=None, stream=None):
         grads = grads if grads is not None else self.new_grads(g.n)
+        P = self.total_pixels
+        g_rgb = g_rgb.contiguous()
+        g_depth = None if g_depth is None else g_depth.contiguous()
+        g_T = None if g_T is None else g_T.contiguous()
+        _need(g_rgb, 3 * P, "g_rgb", torch.float32)
+        _need(g_depth, P, "g_depth", torch.float32)
+        _need(g_T, P, "g_T", torch.float32)
         gc, cc = g.c(), cfg.to_c()
         ws, wsb = self._ws()
         self._check(self.lib.gsr_render_backward(
-            self.ctx, ctypes.byref(gc), cams.data_ptr(), self.n_views, ctypes.byref(cc), ws, wsb,
-            _ptr(g_rgb.contiguous()), _ptr(None if g_depth is None else g_depth.contiguous()),
-            _ptr(None if g_T is None else g_T.contiguous()), ctypes.byref(self._grads_c(grads)),
+            self.ctx, ctypes.byref(gc), _cams_ptr(cams, self.n_views), self.n_views, ctypes.byref(cc), ws, wsb,
+            _ptr(g_rgb), _ptr(g_depth), _ptr(g_T), ctypes.byref(self._grads_c(grads, g.n, self.n_views)),
             _stream_ptr(stream)))
         return grads
 
@@ -242,6 +280,12 @@ class Renderer:
         g_rgb = g_rgb if g_rgb is not None else torch.empty_like(rgb)
         g_depth = g_depth if g_depth is not None else torch.empty_like(depth)
         loss = loss if loss is not None else torch.zeros(1, device=self.device)
+        P = self.total_pixels
+        for t, m, name in ((rgb, 3 * P, "rgb"), (depth, P, "depth"), (target_rgb, 3 * P, "target_rgb"),
+                           (target_depth, P, "target_depth"), (g_rgb, 3 * P, "g_rgb"), (g_depth, P, "g_depth"),
+                           (loss, 1, "loss"), (loss_cap, self.n_views, "loss_cap")):
+            _need(t, m, name, torch.float32)
+        _need(pixel_mask, P, "pixel_mask", torch.uint8)
         self._check(self.lib.gsr_l1_loss_grad(self.ctx, _ptr(rgb), _ptr(depth), _ptr(target_rgb),
                                               _ptr(target_depth), _ptr(pixel_mask), float(w_rgb), float(w_depth),
                                               _ptr(loss_cap), _ptr(g_rgb), _ptr(g_depth), _ptr(loss),
@@ -252,6 +296,9 @@ class Renderer:
         """Per view: factor x lower median of px_loss over the pixels with
         pixel_mask != 0 (+inf for a view without such pixels)."""
         cap_out = cap_out if cap_out is not None else torch.empty(self.n_views, device=self.device)
+        _need(px_loss, self.total_pixels, "px_loss", torch.float32)
+        _need(pixel_mask, self.total_pixels, "pixel_mask", torch.uint8)
+        _need(cap_out, self.n_views, "cap_out", torch.float32)
         self._check(self.lib.gsr_loss_median(self.ctx, _ptr(px_loss), _ptr(pixel_mask), float(factor),
                                              _ptr(cap_out), _stream_ptr(stream)))
         return cap_out
@@ -259,9 +306,15 @@ class Renderer:
     def _fused_args(self, g, cams, cfg, target_rgb, target_depth, pixel_mask, w_rgb, w_depth, out, grads, loss,
                     loss_cap=None):
         ws, wsb = self._ws()
-        self._keep = (g.c(), cfg.to_c(), self._images_c(out), self._grads_c(grads))
+        P = self.total_pixels
+        for t, m, name in ((target_rgb, 3 * P, "target_rgb"), (target_depth, P, "target_depth"), (loss, 1, "loss"),
+                           (loss_cap, self.n_views, "loss_cap")):
+            _need(t, m, name, torch.float32)
+        _need(pixel_mask, P, "pixel_mask", torch.uint8)
+        self._check_images(out)
+        self._keep = (g.c(), cfg.to_c(), self._images_c(out), self._grads_c(grads, g.n, self.n_views))
         gc, cc, im, gr = self._keep
-        return (self.ctx, ctypes.byref(gc), cams.data_ptr(), self.n_views, ctypes.byref(cc), _ptr(target_rgb),
+        return (self.ctx, ctypes.byref(gc), _cams_ptr(cams, self.n_views), self.n_views, ctypes.byref(cc), _ptr(target_rgb),
                 _ptr(target_depth), _ptr(pixel_mask), float(w_rgb), float(w_depth), _ptr(loss_cap), ws, wsb,
                 ctypes.byref(im) if out else None, ctypes.byref(gr), _ptr(loss))
 
@@ -327,9 +380,13 @@ class Renderer:
         grads = self.new_grads(g.n)
         loss = torch.zeros(1, device=self.device)
         ws, wsb = self._ws()
-        gc, cc, gr = g.c(), cfg.to_c(), self._grads_c(grads)
+        P = self.total_pixels
+        _need(target_rgb, 3 * P, "target_rgb", torch.float32)
+        _need(target_depth, P, "target_depth", torch.float32)
+        _need(pixel_mask, P, "pixel_mask", torch.uint8)
+        gc, cc, gr = g.c(), cfg.to_c(), self._grads_c(grads, g.n, self.n_views)
         best = A.gsr_tuning()
-        self._check(self.lib.gsr_autotune(self.ctx, ctypes.byref(gc), cams.data_ptr(), self.n_views,
+        self._check(self.lib.gsr_autotune(self.ctx, ctypes.byref(gc), _cams_ptr(cams, self.n_views), self.n_views,
                                           ctypes.byref(cc), _ptr(target_rgb), _ptr(target_depth), _ptr(pixel_mask),
                                           float(w_rgb), float(w_depth), ws, wsb, ctypes.byref(gr), _ptr(loss),
                                           int(reps), ctypes.byref(best), _stream_ptr(stream)))
@@ -341,8 +398,10 @@ class Renderer:
         """gsr_select_reliable: uint8 mask of the Gaussians kept for the fine
         tracking stage (Eq. 12).  `cam` is one packed camera (the coarse pose)."""
         out = mask_out if mask_out is not None else torch.empty(g.n, dtype=torch.uint8, device=self.device)
+        _need(depth_obs, int(width) * int(height), "depth_obs", torch.float32)
+        _need(out, g.n, "mask_out", torch.uint8)
         gc = g.c()
-        self._check(self.lib.gsr_select_reliable(self.ctx, ctypes.byref(gc), cam.data_ptr(), depth_obs.data_ptr(),
+        self._check(self.lib.gsr_select_reliable(self.ctx, ctypes.byref(gc), _cams_ptr(cam, 1), depth_obs.data_ptr(),
                                                  int(width), int(height), float(eps), float(z_near), out.data_ptr(),
                                                  _stream_ptr(stream)))
         return out

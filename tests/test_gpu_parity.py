@@ -601,6 +601,19 @@ def test_invalid_arguments_and_call_order(gsr_lib):
     ws, wsb = r._ws()
     assert r.lib.gsr_render_forward(r.ctx, ctypes.byref(g.c()), gsr.pack_cameras([cam]).data_ptr(), 1,
                                     ctypes.byref(gsr.Config().to_c()), ws, wsb - 4096, None, None) == gsr.GSR_E_INVALID
+    # The binding rejects device buffers shorter than the plan needs (the
+    # kernels cannot see a tensor's length), before anything is launched.
+    P = cam.width * cam.height
+    short = torch.zeros(1, device="cuda")
+    with pytest.raises(ValueError):
+        r.render_backward(g, gsr.pack_cameras([cam]), gsr.Config(), short, torch.zeros(P, device="cuda"))
+    with pytest.raises(ValueError):
+        r.l1_loss_grad(torch.zeros(3 * P, device="cuda"), short, torch.zeros(3 * P, device="cuda"),
+                       torch.zeros(P, device="cuda"))
+    with pytest.raises(ValueError):
+        r.render_l1_fused(g, gsr.pack_cameras([cam]), gsr.Config(), torch.zeros(3 * P, device="cuda"), short)
+    with pytest.raises(ValueError):
+        r.render_forward(g, short, gsr.Config())
 
 
 def test_autograd_function(gsr_lib):
