@@ -533,16 +533,35 @@ void launch_emit_pairs(const Plan &p, const Workspace &ws, const ViewInfo *views
 
 // ---------------------------------------------------------------- tile ranges
 
+// Every tile's [start, end) in the sorted words, each written once: at a
+// change of tile between positions i - 1 and i, the thread of position i
+// closes the earlier tile, writes (i, i) for the empty tiles in between and
+// opens the later one; the last position closes its tile and empties the
+// rest.  Keys past the last tile (pairs outside the alpha support) sort to
+// the end and open nothing.
 __global__ __launch_bounds__(BLOCK) void k_tile_ranges(const uint32_t *__restrict__ keys,
                                                        const unsigned long long *n_dev, uint32_t cap,
                                                        uint32_t total_tiles, int shift,
                                                        int2 *__restrict__ ranges) {
   const uint32_t n = sort_count(n_dev, 0u, cap);
+  const int64_t T = total_tiles;
+  if (n == 0u) {
+    for (int64_t t = (int64_t)blockIdx.x * BLOCK + threadIdx.x; t < T; t += (int64_t)gridDim.x * BLOCK)
+      ranges[t] = make_int2(0, 0);
+    return;
+  }
   for (uint32_t i = blockIdx.x * BLOCK + threadIdx.x; i < n; i += gridDim.x * BLOCK) {
-    const uint32_t t = keys[i] >> shift;
-    if (t >= total_tiles) continue;  // pairs outside the alpha support
-    if (i == 0 || keys[i - 1] >> shift != t) ranges[t].x = (int)i;
-    if (i + 1 == n || keys[i + 1] >> shift != t) ranges[t].y = (int)(i + 1);
+    const int64_t t = (int64_t)(keys[i] >> shift);
+    const int64_t tp = i == 0u ? -1 : (int64_t)(keys[i - 1] >> shift);
+    if (t != tp) {
+      if (tp >= 0 && tp < T) ranges[tp].y = (int)i;
+      for (int64_t e = tp + 1; e < t && e < T; ++e) ranges[e] = make_int2((int)i, (int)i);
+      if (t < T) ranges[t].x = (int)i;
+    }
+    if (i + 1u == n) {
+      if (t < T) ranges[t].y = (int)n;
+      for (int64_t e = t + 1; e < T; ++e) ranges[e] = make_int2((int)n, (int)n);
+    }
   }
 }
 
@@ -560,7 +579,6 @@ void launch_unpack_ids(const Plan &p, const Workspace &ws, hipStream_t s) {
 }
 
 void launch_tile_ranges(const Plan &p, const Workspace &ws, hipStream_t s) {
-  launch_fill_u32(reinterpret_cast<uint32_t *>(ws.ranges), 0u, 2 * (int64_t)p.total_tiles, s);
   const unsigned long long *n_dev = reinterpret_cast<const unsigned long long *>(ws.hdr + HDR_NPAIRS);
   int64_t blocks = (p.capacity + BLOCK - 1) / BLOCK;
   if (blocks > 8192) blocks = 8192;
