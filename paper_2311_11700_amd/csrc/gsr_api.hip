@@ -175,7 +175,7 @@ void prof_end(gsr_ctx *ctx, hipStream_t s, int first_unmarked) {
 void enqueue_lists(gsr_ctx *ctx, const gsr_gaussians &g, const gsr_camera *cams, const gsr_config &cfg,
                    Workspace &ws, bool clear_grad2d, float *loss_zero, hipStream_t s) {
   const Plan &p = ctx->plan;
-  launch_preprocess(g, cams, ctx->views_dev, p.n_views, cfg, ws, clear_grad2d, loss_zero, s);
+  launch_preprocess(g, cams, ctx->views_dev, p.n_views, cfg, ws, clear_grad2d, loss_zero, p.max_sort_tiles, s);
   prof_mark(ctx, s, GSR_STAGE_PREPROCESS);
   launch_depth_sort(p, ws, s, ctx->sort_grid);
   prof_mark(ctx, s, GSR_STAGE_DEPTH_SORT);

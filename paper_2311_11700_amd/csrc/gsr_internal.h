@@ -207,14 +207,26 @@ __device__ __forceinline__ unsigned long long lanemask_lt() {
   return lane == 0 ? 0ull : (~0ull >> (64 - lane));
 }
 
+// Lanes of the wavefront whose digit equals this lane's digit (and valid).
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, int nbits, uint64_t valid) {
+  uint64_t m = valid;
+  for (int b = 0; b < nbits; ++b) {
+    const bool bit = (d >> b) & 1u;
+    const uint64_t bb = __ballot(bit);
+    m &= bit ? bb : ~bb;
+  }
+  return m;
+}
+
 // --------------------------------------------------------------- launchers (host)
 
 // Preprocess (projection, binning data, depth keys) for every (view, Gaussian).
 // Also resets the per-call header words, clears grad2d when clear_grad2d,
-// and zeroes *loss_zero when it is not null (start of a fused step).
+// zeroes *loss_zero when it is not null (start of a fused step), and writes
+// the depth sort's first-pass digit counts into hist.
 void launch_preprocess(const gsr_gaussians &g, const gsr_camera *cams, const ViewInfo *views,
                        int n_views, const gsr_config &cfg, const Workspace &ws, bool clear_grad2d,
-                       float *loss_zero, hipStream_t s);
+                       float *loss_zero, int max_sort_tiles, hipStream_t s);
 
 // Reliable-Gaussian selection (fine tracking stage).
 void launch_select_reliable(const gsr_gaussians &g, const gsr_camera *cam, const float *depth, int W, int H,

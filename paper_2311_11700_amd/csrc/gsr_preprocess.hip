@@ -39,18 +39,11 @@ __device__ __forceinline__ void quat_rot(T w, T x, T y, T z, T R[9]) {
   R[8] = T(1) - T(2) * (x * x + y * y);
 }
 
-__global__ __launch_bounds__(BLOCK) void k_preprocess(gsr_gaussians g,
-                                                      const gsr_camera *__restrict__ cams,
-                                                      const ViewInfo *__restrict__ views,
-                                                      PreConsts pc, Workspace ws) {
-  const int view = blockIdx.y;
-  const int64_t i = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
-  if (blockIdx.x == 0 && view == 0 && threadIdx.x == 0) {
-    reset_header_words(ws.hdr);
-    if (pc.loss_zero) *pc.loss_zero = 0.f;
-  }
-  if (i >= g.n) return;
-  const int64_t rec = (int64_t)view * g.n + i;
+// Project record rec = view * n + i; returns its depth sort key (float32
+// depth bits, 0xFFFFFFFF when culled).
+__device__ __forceinline__ uint32_t project_record(const gsr_gaussians &g, const gsr_camera *__restrict__ cams,
+                                                   const ViewInfo *__restrict__ views, const PreConsts &pc,
+                                                   const Workspace &ws, int view, int64_t i, int64_t rec) {
   if (pc.clear_grad2d) {
     double2 *gz = reinterpret_cast<double2 *>(ws.grad2d + rec * NGRAD2D);
 #pragma unroll
@@ -150,7 +143,7 @@ __global__ __launch_bounds__(BLOCK) void k_preprocess(gsr_gaussians g,
     ws.dkeys[0][rec] = 0xFFFFFFFFu;
     ws.dvals[0][rec] = (uint32_t)rec;
     ws.tinfo[rec] = make_uint4(0u, 0u, 0u, 0u);
-    return;
+    return 0xFFFFFFFFu;
   }
   const float zf = (float)z;
   const float uh = (float)u, vh = (float)v;
@@ -177,16 +170,47 @@ __global__ __launch_bounds__(BLOCK) void k_preprocess(gsr_gaussians g,
   ws.count[rec] = (uint32_t)(tx1 - tx0 + 1) * (uint32_t)(ty1 - ty0 + 1);
   ws.dkeys[0][rec] = __float_as_uint(zf);
   ws.dvals[0][rec] = (uint32_t)rec;
+  return __float_as_uint(zf);
+}
+
+// One block per sort tile of the depth sort: project its records, then
+// count the depth keys' first radix digit (bits 0-7) for the sort, which
+// then needs no counting kernel for its first pass.  Block 0 also resets the
+// per-call header words (and the fused step's loss when it is overwritten).
+constexpr int PRE_BLOCK = BLOCK * SORT_ITEMS_DEPTH;
+__global__ __launch_bounds__(PRE_BLOCK) void k_preprocess(gsr_gaussians g, const gsr_camera *__restrict__ cams,
+                                                          const ViewInfo *__restrict__ views, PreConsts pc,
+                                                          Workspace ws, int n_views, int max_tiles) {
+  __shared__ uint32_t cnt[RADIX];
+  const int64_t rec = (int64_t)blockIdx.x * PRE_BLOCK + threadIdx.x;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    reset_header_words(ws.hdr);
+    if (pc.loss_zero) *pc.loss_zero = 0.f;
+  }
+  if (threadIdx.x < RADIX) cnt[threadIdx.x] = 0u;
+  __syncthreads();
+  const bool valid = rec < g.n * (int64_t)n_views;
+  uint32_t key = 0u;
+  if (valid) {
+    const int view = (int)(rec / g.n);
+    key = project_record(g, cams, views, pc, ws, view, rec - (int64_t)view * g.n, rec);
+  }
+  const uint32_t d = key & (RADIX - 1u);
+  const uint64_t peers = match_digit(d, RADIX_BITS, __ballot(valid));
+  if (valid && (peers & lanemask_lt()) == 0ull) atomicAdd(&cnt[d], (uint32_t)__popcll(peers));
+  __syncthreads();
+  if (threadIdx.x < RADIX) ws.hist[(size_t)threadIdx.x * max_tiles + blockIdx.x] = cnt[threadIdx.x];
 }
 
 void launch_preprocess(const gsr_gaussians &g, const gsr_camera *cams, const ViewInfo *views,
                        int n_views, const gsr_config &cfg, const Workspace &ws, bool clear_grad2d,
-                       float *loss_zero, hipStream_t s) {
+                       float *loss_zero, int max_sort_tiles, hipStream_t s) {
   PreConsts pc{cfg.z_near, cfg.lowpass, cfg.cutoff_sigma, cfg.flags, cfg.fov_guard, cfg.alpha_min,
                clear_grad2d ? 1 : 0, loss_zero};
-  dim3 grid((unsigned)((g.n + BLOCK - 1) / BLOCK), (unsigned)n_views);
+  const int64_t n_rec = g.n * (int64_t)n_views;
   if (g.n > 0) {
-    hipLaunchKernelGGL(k_preprocess, grid, dim3(BLOCK), 0, s, g, cams, views, pc, ws);
+    hipLaunchKernelGGL(k_preprocess, dim3((unsigned)((n_rec + PRE_BLOCK - 1) / PRE_BLOCK)), dim3(PRE_BLOCK), 0, s,
+                       g, cams, views, pc, ws, n_views, max_sort_tiles);
   } else {
     launch_reset_header(ws, s);
     if (loss_zero) launch_fill_f32(loss_zero, 0.f, 1, s);

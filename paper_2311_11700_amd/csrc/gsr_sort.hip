@@ -78,17 +78,6 @@ __device__ __forceinline__ T block_exclusive_scan(T v, T *s_w, T &total) {
 
 // ----------------------------------------------------------------- radix sort
 
-// Lanes of the wavefront whose digit equals this lane's digit (and valid).
-__device__ __forceinline__ uint64_t match_digit(uint32_t d, int nbits, uint64_t valid) {
-  uint64_t m = valid;
-  for (int b = 0; b < nbits; ++b) {
-    const bool bit = (d >> b) & 1u;
-    const uint64_t bb = __ballot(bit);
-    m &= bit ? bb : ~bb;
-  }
-  return m;
-}
-
 __device__ __forceinline__ uint32_t sort_count(const unsigned long long *n_dev, uint32_t n_static,
                                                uint32_t cap) {
   if (!n_dev) return n_static;
@@ -300,7 +289,7 @@ static int sort_grid_for(int64_t n, int items, int cap_grid) {
 int launch_depth_sort(const Plan &p, Workspace &ws, hipStream_t s, int sort_grid) {
   ws.dsorted = radix_sort<SORT_ITEMS_DEPTH>(ws.dkeys, ws.dvals, nullptr, (uint32_t)p.n_rec, (uint32_t)p.n_rec, 0, 32,
                                             ws.hist, ws.hoff, p.max_sort_tiles, ws.digit_total,
-                                            sort_grid_for(p.n_rec, SORT_ITEMS_DEPTH, sort_grid), false, s);
+                                            sort_grid_for(p.n_rec, SORT_ITEMS_DEPTH, sort_grid), true, s);
   return ws.dsorted;
 }
 
