@@ -357,14 +357,51 @@ __global__ __launch_bounds__(BLOCK) void k_scan_top(unsigned long long *__restri
 // array stays non-decreasing and every offset fits 32 bits).  Also records,
 // for every emission bucket b, the record whose pair range holds pair
 // EMIT_BUCKET * b (each such pair lies in exactly one non-empty range), and
-// after the last bucket the record that holds the last pair.
+// after the last bucket the record that holds the last pair.  With INLINE
+// the block sums the per-block totals before it itself (and all of them for
+// the pair count, which block 0 stores in the header) instead of reading a
+// scanned array: for few blocks this saves the single-block scan kernel.
+template <bool INLINE>
 __global__ __launch_bounds__(BLOCK) void k_scan_down(const uint32_t *__restrict__ order,
                                                      const uint32_t *__restrict__ count, int64_t n_rec,
-                                                     const unsigned long long *__restrict__ part,
-                                                     uint64_t capacity, const uint32_t *__restrict__ hdr,
+                                                     const unsigned long long *__restrict__ part, int nblocks,
+                                                     uint64_t capacity, uint32_t *__restrict__ hdr,
                                                      uint32_t *__restrict__ off,
                                                      uint32_t *__restrict__ bucket_rec) {
   __shared__ unsigned long long s_w[4];
+  __shared__ unsigned long long s_pre, s_tot;
+  unsigned long long block_off, np;
+  if (INLINE) {
+    unsigned long long pre = 0ull, tot = 0ull;
+    for (int b = threadIdx.x; b < nblocks; b += BLOCK) {
+      const unsigned long long v = part[b];
+      tot += v;
+      if (b < (int)blockIdx.x) pre += v;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      pre += __shfl_xor(pre, o);
+      tot += __shfl_xor(tot, o);
+    }
+    if (threadIdx.x == 0) s_pre = s_tot = 0ull;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+      atomicAdd(&s_pre, pre);
+      atomicAdd(&s_tot, tot);
+    }
+    __syncthreads();
+    block_off = s_pre;
+    np = s_tot;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      *reinterpret_cast<unsigned long long *>(hdr + HDR_NPAIRS) = np;
+      if (np > capacity) {
+        atomicOr(hdr + HDR_OVERFLOW, 1u);
+        atomicMax(reinterpret_cast<unsigned long long *>(hdr + HDR_REQUIRED), np);
+      }
+    }
+  } else {
+    block_off = part[blockIdx.x];
+    np = *reinterpret_cast<const unsigned long long *>(hdr + HDR_NPAIRS);
+  }
   const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + threadIdx.x * SCAN_ITEMS;
   uint32_t c[SCAN_ITEMS];
   unsigned long long sum = 0ull;
@@ -375,8 +412,7 @@ __global__ __launch_bounds__(BLOCK) void k_scan_down(const uint32_t *__restrict_
     sum += c[k];
   }
   unsigned long long total;
-  unsigned long long o = block_exclusive_scan<unsigned long long>(sum, s_w, total) + part[blockIdx.x];
-  const unsigned long long np = *reinterpret_cast<const unsigned long long *>(hdr + HDR_NPAIRS);
+  unsigned long long o = block_exclusive_scan<unsigned long long>(sum, s_w, total) + block_off;
   const unsigned long long n = np < capacity ? np : capacity;  // pairs emitted
 #pragma unroll
   for (int k = 0; k < SCAN_ITEMS; ++k) {
@@ -504,11 +540,17 @@ void launch_emit_pairs(const Plan &p, const Workspace &ws, const ViewInfo *views
   uint32_t *off = ws.dkeys[ws.dsorted ^ 1];  // free after the depth sort
   hipLaunchKernelGGL(k_scan_reduce, dim3(p.n_scan_blocks), dim3(BLOCK), 0, s, order, ws.count,
                      p.n_rec, ws.scan_part);
-  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(BLOCK), 0, s, ws.scan_part, p.n_scan_blocks, ws.hdr,
-                     (uint64_t)p.capacity);
+  const bool inline_top = p.n_rec > 0 && p.n_scan_blocks <= 512;
+  if (!inline_top)
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(BLOCK), 0, s, ws.scan_part, p.n_scan_blocks, ws.hdr,
+                       (uint64_t)p.capacity);
   if (p.n_rec == 0) return;
-  hipLaunchKernelGGL(k_scan_down, dim3(p.n_scan_blocks), dim3(BLOCK), 0, s, order, ws.count, p.n_rec,
-                     ws.scan_part, (uint64_t)p.capacity, ws.hdr, off, ws.bucket_rec);
+  if (inline_top)
+    hipLaunchKernelGGL(k_scan_down<true>, dim3(p.n_scan_blocks), dim3(BLOCK), 0, s, order, ws.count, p.n_rec,
+                       ws.scan_part, p.n_scan_blocks, (uint64_t)p.capacity, ws.hdr, off, ws.bucket_rec);
+  else
+    hipLaunchKernelGGL(k_scan_down<false>, dim3(p.n_scan_blocks), dim3(BLOCK), 0, s, order, ws.count, p.n_rec,
+                       ws.scan_part, p.n_scan_blocks, (uint64_t)p.capacity, ws.hdr, off, ws.bucket_rec);
   int64_t blocks = (p.capacity + (int64_t)BLOCK * SORT_ITEMS_PAIR - 1) / ((int64_t)BLOCK * SORT_ITEMS_PAIR);
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
