@@ -152,20 +152,25 @@ def test_sampled_gaussian_gradients_match_oracle(c2):
     assert H.rel_err(got["pose"][0], ref["pose"]) <= 1e-3, (got["pose"], ref["pose"])
 
 
-def test_unpacked_pair_words_two_large_views(gsr_lib):
-    """Two 1920x1080 views of the 300k scene: 16 321 tile keys (14 bits) and
-    600k records (20 bits) do not fit one 32-bit word, so the pairs are sorted
-    as separate key and value arrays; the pair count and sampled tile lists of
-    both views are bit-exact against the oracle."""
+def test_unpacked_pair_words_four_views(gsr_lib):
+    """Four views of the 300k scene (two 1920x1080, two 1200x680): 22 771
+    tile keys (15 bits) and 1.2M records (21 bits) do not fit one 32-bit
+    word, so the pairs are sorted as separate key and value arrays, and the
+    record scan runs with its separate block-scan kernel (586 scan blocks);
+    the pair count and sampled tile lists of every view are bit-exact against
+    the oracle."""
     gsr = gsr_lib
     scene = W.room_scene(300_000, seed=0)
     base = W.camera_replica()
-    cams = [base.with_size(960.0, 960.0, 959.5, 539.5, 1920, 1080),
-            W.perturb_pose(base.with_size(960.0, 960.0, 959.5, 539.5, 1920, 1080),
-                           [0.0, 0.05, 0.15, 0.01, -0.04, 0.02])]
-    print("CASE unpacked 300k 2x1920x1080", flush=True)
+    big = base.with_size(960.0, 960.0, 959.5, 539.5, 1920, 1080)
+    cams = [big, W.perturb_pose(big, [0.0, 0.05, 0.15, 0.01, -0.04, 0.02]),
+            W.perturb_pose(base, [-0.1, 0.02, 0.05, -0.02, 0.03, 0.01]),
+            W.perturb_pose(base, [0.08, -0.03, -0.05, 0.01, 0.02, -0.03])]
+    print("CASE unpacked 300k 2x1920x1080 + 2x1200x680", flush=True)
     tiles = sum(((c.width + 15) // 16) * ((c.height + 15) // 16) for c in cams)
-    assert int(tiles + 1).bit_length() + int(2 * scene.n - 1).bit_length() > 32
+    n_rec = len(cams) * scene.n
+    assert int(tiles + 1).bit_length() + int(n_rec - 1).bit_length() > 32
+    assert (n_rec + 2047) // 2048 > 512
     r = gsr.Renderer()
     r.plan(scene.n, [(c.width, c.height) for c in cams])
     r.render_forward(H.gpu_scene(gsr, scene), gsr.pack_cameras(cams), gsr.Config())
