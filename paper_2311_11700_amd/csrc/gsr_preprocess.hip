@@ -44,11 +44,6 @@ __device__ __forceinline__ void quat_rot(T w, T x, T y, T z, T R[9]) {
 __device__ __forceinline__ uint32_t project_record(const gsr_gaussians &g, const gsr_camera *__restrict__ cams,
                                                    const ViewInfo *__restrict__ views, const PreConsts &pc,
                                                    const Workspace &ws, int view, int64_t i, int64_t rec) {
-  if (pc.clear_grad2d) {
-    double2 *gz = reinterpret_cast<double2 *>(ws.grad2d + rec * NGRAD2D);
-#pragma unroll
-    for (int k = 0; k < NGRAD2D / 2; ++k) gz[k] = make_double2(0.0, 0.0);
-  }
   const ViewInfo vi = views[view];
   const gsr_camera &cam = cams[view];
 
@@ -144,6 +139,12 @@ __device__ __forceinline__ uint32_t project_record(const gsr_gaussians &g, const
     ws.dvals[0][rec] = (uint32_t)rec;
     ws.tinfo[rec] = make_uint4(0u, 0u, 0u, 0u);
     return 0xFFFFFFFFu;
+  }
+  // Only records that enter tile lists receive or give back 2D gradients.
+  if (pc.clear_grad2d) {
+    double2 *gz = reinterpret_cast<double2 *>(ws.grad2d + rec * NGRAD2D);
+#pragma unroll
+    for (int k = 0; k < NGRAD2D / 2; ++k) gz[k] = make_double2(0.0, 0.0);
   }
   const float zf = (float)z;
   const float uh = (float)u, vh = (float)v;

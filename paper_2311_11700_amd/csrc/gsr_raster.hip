@@ -8,10 +8,10 @@
 // coordinates (the record keeps the centre as a float pair, so the offset to
 // a pixel keeps full precision even at x ~ 1000 px), and pre-scales the
 // conic so that alpha = min(alpha_max, o * 2^P) with
-// P = a'' dx^2 + 2 b'' dx dy + c'' dy^2 and (a'', b'', c'') = -log2(e)/2 * conic.
-// The forward and the backward evaluate alpha with the same inlined
-// function and contraction disabled, so both take every threshold decision
-// identically.
+// P = a'' dx^2 + 2 b'' dx dy + c'' dy^2 and (a'', b'', c'') = -log2(e)/2 * conic
+// (the staged record holds 2 b'').  The forward and the backward evaluate
+// alpha with the same inlined function and contraction disabled, so both
+// take every threshold decision identically.
 #pragma clang fp contract(off)
 
 #include "gsr_internal.h"
@@ -549,7 +549,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
 
 __device__ __forceinline__ float sgnf(float x) { return (float)((x > 0.f) - (x < 0.f)); }
 
-// Persistent fused step: pop tiles from the work queue; per tile run the
+// Persistent fused step: blocks take tiles from an atomic counter (in index
+// order, or in the longest-list-first order of `queue`); per tile run the
 // forward blend, the L1 loss gradient of every pixel, and the backward walk
 // without leaving the block (per-pixel state stays in registers).
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_render_fused(RasterArgs a, uint32_t *__restrict__ hdr,
