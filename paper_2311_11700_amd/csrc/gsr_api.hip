@@ -67,6 +67,7 @@ Workspace make_ws(const Plan &p, void *base_v) {
   w.tinfo = reinterpret_cast<uint4 *>(base + p.off_rect);
   w.support = reinterpret_cast<Support *>(base + p.off_support);
   w.count = reinterpret_cast<uint32_t *>(base + p.off_count);
+  w.tile_visible = reinterpret_cast<uint32_t *>(base + p.off_tile_visible);
   for (int k = 0; k < 2; ++k) {
     w.dkeys[k] = reinterpret_cast<uint32_t *>(base + p.off_dkeys[k]);
     w.dvals[k] = reinterpret_cast<uint32_t *>(base + p.off_dvals[k]);
@@ -325,6 +326,7 @@ gsr_status gsr_plan(gsr_ctx *ctx, int64_t n, int n_views, const int32_t *wh_host
   p.off_rect = take(16 * nr);
   p.off_support = take(sizeof(Support) * nr);
   p.off_count = take(4 * nr);
+  p.off_tile_visible = take(4 * (size_t)((nr + (size_t)BLOCK * SORT_ITEMS_DEPTH - 1) / ((size_t)BLOCK * SORT_ITEMS_DEPTH)));
   for (int k = 0; k < 2; ++k) p.off_dkeys[k] = take(4 * nr);
   for (int k = 0; k < 2; ++k) p.off_dvals[k] = take(4 * nr);
   p.off_scan = take(8 * ((size_t)p.n_scan_blocks + 1));

@@ -44,6 +44,7 @@ enum HeaderWord {
   HDR_QUEUE = 5,       // u32: persistent rasteriser work counter
   HDR_FWD_DONE = 6,    // u32: marker that a forward filled this workspace
   HDR_MAGIC = 8,       // u32 x 2 (words 8-9): set once the header has been initialised
+  HDR_NVISIBLE = 10,   // u64 (words 10-11): records that passed the culling (depth-sorted keys)
   HDR_WORDS = 64
 };
 // Header magic: a workspace whose words 8-9 do not hold it has never been
@@ -111,6 +112,7 @@ struct Workspace {
   uint4 *tinfo;            // [n_rec] (view tile offset, view TX | cull << 31, tx0 | tx1 << 16, ty0 | ty1 << 16)
   Support *support;        // [n_rec] alpha-support parameters (records with the cull bit)
   uint32_t *count;         // [n_rec] tiles touched (0 = culled)
+  uint32_t *tile_visible;  // [depth-sort tiles] visible records of each projection block
   uint32_t *dkeys[2];      // [n_rec] depth keys (float32 bits), ping-pong
   uint32_t *dvals[2];      // [n_rec] record ids, ping-pong
   unsigned long long *scan_part;  // [n_scan_blocks + 1]
@@ -155,7 +157,7 @@ struct Plan {
   size_t off_hdr, off_recA, off_recB, off_recC, off_rect, off_count, off_dkeys[2], off_dvals[2],
       off_scan, off_pkeys[2], off_pvals[2], off_hist, off_digit, off_ranges, off_T, off_last, off_zr,
       off_grad2d, off_pose, off_queue, off_loss, off_counts, off_hoff, off_bucket,
-      off_support;
+      off_support, off_tile_visible;
 };
 
 struct Tuning {
@@ -198,6 +200,8 @@ __device__ __forceinline__ void reset_header_words(uint32_t *hdr) {
   }
   hdr[HDR_NPAIRS] = 0u;
   hdr[HDR_NPAIRS + 1] = 0u;
+  hdr[HDR_NVISIBLE] = 0u;
+  hdr[HDR_NVISIBLE + 1] = 0u;
   hdr[HDR_QUEUE] = 0u;
   hdr[HDR_FWD_DONE] = 1u;
 }

@@ -135,8 +135,6 @@ __device__ __forceinline__ uint32_t project_record(const gsr_gaussians &g, const
 
   if (!ok) {
     ws.count[rec] = 0u;
-    ws.dkeys[0][rec] = 0xFFFFFFFFu;
-    ws.dvals[0][rec] = (uint32_t)rec;
     ws.tinfo[rec] = make_uint4(0u, 0u, 0u, 0u);
     return 0xFFFFFFFFu;
   }
@@ -169,38 +167,57 @@ __device__ __forceinline__ uint32_t project_record(const gsr_gaussians &g, const
   ws.tinfo[rec] = make_uint4((uint32_t)vi.tile_off, (uint32_t)vi.TX | (cull ? 0x80000000u : 0u),
                              (uint32_t)tx0 | ((uint32_t)tx1 << 16), (uint32_t)ty0 | ((uint32_t)ty1 << 16));
   ws.count[rec] = (uint32_t)(tx1 - tx0 + 1) * (uint32_t)(ty1 - ty0 + 1);
-  ws.dkeys[0][rec] = __float_as_uint(zf);
-  ws.dvals[0][rec] = (uint32_t)rec;
   return __float_as_uint(zf);
 }
 
-// One block per sort tile of the depth sort: project its records, then
-// count the depth keys' first radix digit (bits 0-7) for the sort, which
-// then needs no counting kernel for its first pass.  Block 0 also resets the
-// per-call header words (and the fused step's loss when it is overwritten).
+// One block per sort tile of the depth sort: project its records, write the
+// depth keys and record ids of the visible ones to the front of the tile's
+// slots in record order (the depth sort reads only those, so culled records
+// never enter the sort), and count the keys' first radix digit (bits 0-7)
+// for the sort's first pass.  Block 0 also resets the per-call header words
+// (and the fused step's loss when it is overwritten).
 constexpr int PRE_BLOCK = BLOCK * SORT_ITEMS_DEPTH;
 __global__ __launch_bounds__(PRE_BLOCK) void k_preprocess(gsr_gaussians g, const gsr_camera *__restrict__ cams,
                                                           const ViewInfo *__restrict__ views, PreConsts pc,
                                                           Workspace ws, int n_views, int max_tiles) {
+  constexpr int NW = PRE_BLOCK / 64;
   __shared__ uint32_t cnt[RADIX];
+  __shared__ uint32_t s_wv[NW];
   const int64_t rec = (int64_t)blockIdx.x * PRE_BLOCK + threadIdx.x;
+  const int wave = threadIdx.x >> 6;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     reset_header_words(ws.hdr);
     if (pc.loss_zero) *pc.loss_zero = 0.f;
   }
   if (threadIdx.x < RADIX) cnt[threadIdx.x] = 0u;
-  __syncthreads();
-  const bool valid = rec < g.n * (int64_t)n_views;
-  uint32_t key = 0u;
-  if (valid) {
+  uint32_t key = 0xFFFFFFFFu;
+  if (rec < g.n * (int64_t)n_views) {
     const int view = (int)(rec / g.n);
     key = project_record(g, cams, views, pc, ws, view, rec - (int64_t)view * g.n, rec);
   }
+  // Culled records have the key 0xFFFFFFFF (a visible depth is a positive
+  // finite float, whose bits are below it).
+  const bool vis = key != 0xFFFFFFFFu;
+  const uint64_t vmask = __ballot(vis);
+  if ((threadIdx.x & 63) == 0) s_wv[wave] = (uint32_t)__popcll(vmask);
+  __syncthreads();
+  uint32_t before = 0u, total = 0u;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    before += w < wave ? s_wv[w] : 0u;
+    total += s_wv[w];
+  }
+  if (vis) {
+    const int64_t pos = (int64_t)blockIdx.x * PRE_BLOCK + before + (uint32_t)__popcll(vmask & lanemask_lt());
+    ws.dkeys[0][pos] = key;
+    ws.dvals[0][pos] = (uint32_t)rec;
+  }
   const uint32_t d = key & (RADIX - 1u);
-  const uint64_t peers = match_digit(d, RADIX_BITS, __ballot(valid));
-  if (valid && (peers & lanemask_lt()) == 0ull) atomicAdd(&cnt[d], (uint32_t)__popcll(peers));
+  const uint64_t peers = match_digit(d, RADIX_BITS, vmask);
+  if (vis && (peers & lanemask_lt()) == 0ull) atomicAdd(&cnt[d], (uint32_t)__popcll(peers));
   __syncthreads();
   if (threadIdx.x < RADIX) ws.hist[(size_t)threadIdx.x * max_tiles + blockIdx.x] = cnt[threadIdx.x];
+  if (threadIdx.x == 0) ws.tile_visible[blockIdx.x] = total;
 }
 
 void launch_preprocess(const gsr_gaussians &g, const gsr_camera *cams, const ViewInfo *views,

@@ -163,13 +163,18 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scan(const uint32_t *__restrict
 // and the digit offsets then place every key in block-local digit order in
 // LDS, and each digit's keys of the tile are written as one contiguous run:
 // consecutive threads store consecutive addresses.
+//
+// With tile_count, sort tile t holds only its first tile_count[t] keys (the
+// rest of its slots are unused) and the output is dense; block 0 then stores
+// the number of keys sorted in *n_out.
 template <int ITEMS, bool VALS>
 __global__ __launch_bounds__(BLOCK) void k_radix_scatter(
     const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in,
     uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out,
     const unsigned long long *n_dev, uint32_t n_static, uint32_t cap, int shift, int nbits,
     const uint32_t *__restrict__ hist, const uint32_t *__restrict__ hoff, int max_tiles,
-    const uint32_t *__restrict__ digit_total) {
+    const uint32_t *__restrict__ digit_total, const uint32_t *__restrict__ tile_count,
+    unsigned long long *__restrict__ n_out) {
   constexpr int STILE = BLOCK * ITEMS;
   constexpr int WKEYS = 64 * ITEMS;
   __shared__ uint32_t s_base[RADIX];   // first output position of each digit
@@ -187,17 +192,19 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(
   {
     uint32_t total;
     s_base[dig] = block_exclusive_scan<uint32_t>(digit_total[dig], s_w, total);
+    if (n_out && blockIdx.x == 0 && threadIdx.x == 0) *n_out = total;
   }
   for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const uint32_t t0 = t * STILE;
-    const uint32_t tn = n - t0 < (uint32_t)STILE ? n - t0 : (uint32_t)STILE;
+    const uint32_t tn = tile_count ? tile_count[t] : (n - t0 < (uint32_t)STILE ? n - t0 : (uint32_t)STILE);
+    const uint32_t tend = t0 + tn;  // keys of this tile: [t0, tend)
     const uint32_t wbase = t0 + wave * WKEYS + lane;
     uint32_t kr[ITEMS], vr[ITEMS], rank[ITEMS];
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
       const uint32_t idx = wbase + r * 64;
-      kr[r] = idx < n ? keys_in[idx] : 0u;
-      if (VALS) vr[r] = idx < n ? vals_in[idx] : 0u;
+      kr[r] = idx < tend ? keys_in[idx] : 0u;
+      if (VALS) vr[r] = idx < tend ? vals_in[idx] : 0u;
     }
     s_wc[0][dig] = s_wc[1][dig] = s_wc[2][dig] = s_wc[3][dig] = 0u;
     {
@@ -209,7 +216,7 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(
     }
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
-      const bool valid = wbase + r * 64 < n;
+      const bool valid = wbase + r * 64 < tend;
       const uint32_t d = (kr[r] >> shift) & mask;
       const uint64_t peers = match_digit(d, nbits, __ballot(valid));
       const uint64_t below = peers & lanemask_lt();
@@ -230,7 +237,7 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
-      if (wbase + r * 64 < n) {
+      if (wbase + r * 64 < tend) {
         const uint32_t lp = s_wc[wave][(kr[r] >> shift) & mask] + rank[r];
         s_k[lp] = kr[r];
         if (VALS) s_v[lp] = vr[r];
@@ -253,15 +260,23 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(
 // the words are sorted alone (packed pairs).  When hist0_ready, the first
 // pass's per-tile digit counts are already in hist (written by the kernel
 // that produced the keys).
+//
+// With tile_count0, the first pass reads tile t's first tile_count0[t] keys
+// only (n_static covering all tiles' slots), stores the number of keys in
+// *n_after0, and the later passes sort that many.
 template <int ITEMS>
 static int radix_sort(uint32_t *keys[2], uint32_t *vals[2], const unsigned long long *n_dev,
                       uint32_t n_static, uint32_t cap, int base, int key_bits, uint32_t *hist, uint32_t *hoff,
-                      int max_tiles, uint32_t *digit_total, int grid, bool hist0_ready, hipStream_t s) {
+                      int max_tiles, uint32_t *digit_total, int grid, bool hist0_ready,
+                      const uint32_t *tile_count0, unsigned long long *n_after0, hipStream_t s) {
   const int per = radix_digit_bits(key_bits);
   int cur = 0;
   for (int sh = 0; sh < key_bits; sh += per) {
     const int nbits = key_bits - sh < per ? key_bits - sh : per;
     const int shift = base + sh;
+    const uint32_t *tile_count = sh == 0 ? tile_count0 : nullptr;
+    unsigned long long *n_out = sh == 0 ? n_after0 : nullptr;
+    if (sh > 0 && tile_count0) n_dev = n_after0;
     if (sh > 0 || !hist0_ready)
       hipLaunchKernelGGL(k_radix_hist<ITEMS>, dim3(grid), dim3(BLOCK), 0, s, keys[cur], n_dev, n_static, cap,
                          shift, nbits, hist, max_tiles);
@@ -270,11 +285,11 @@ static int radix_sort(uint32_t *keys[2], uint32_t *vals[2], const unsigned long 
     if (vals)
       hipLaunchKernelGGL((k_radix_scatter<ITEMS, true>), dim3(grid), dim3(BLOCK), 0, s, keys[cur], vals[cur],
                          keys[cur ^ 1], vals[cur ^ 1], n_dev, n_static, cap, shift, nbits, hist, hoff,
-                         max_tiles, digit_total);
+                         max_tiles, digit_total, tile_count, n_out);
     else
       hipLaunchKernelGGL((k_radix_scatter<ITEMS, false>), dim3(grid), dim3(BLOCK), 0, s, keys[cur],
                          (const uint32_t *)nullptr, keys[cur ^ 1], (uint32_t *)nullptr, n_dev, n_static, cap,
-                         shift, nbits, hist, hoff, max_tiles, digit_total);
+                         shift, nbits, hist, hoff, max_tiles, digit_total, tile_count, n_out);
     cur ^= 1;
   }
   return cur;
@@ -287,9 +302,13 @@ static int sort_grid_for(int64_t n, int items, int cap_grid) {
 }
 
 int launch_depth_sort(const Plan &p, Workspace &ws, hipStream_t s, int sort_grid) {
+  // Only the visible records (compacted per tile by the projection) are
+  // sorted; their number is known after the first pass.
+  unsigned long long *n_vis = reinterpret_cast<unsigned long long *>(ws.hdr + HDR_NVISIBLE);
   ws.dsorted = radix_sort<SORT_ITEMS_DEPTH>(ws.dkeys, ws.dvals, nullptr, (uint32_t)p.n_rec, (uint32_t)p.n_rec, 0, 32,
                                             ws.hist, ws.hoff, p.max_sort_tiles, ws.digit_total,
-                                            sort_grid_for(p.n_rec, SORT_ITEMS_DEPTH, sort_grid), true, s);
+                                            sort_grid_for(p.n_rec, SORT_ITEMS_DEPTH, sort_grid), true,
+                                            ws.tile_visible, n_vis, s);
   return ws.dsorted;
 }
 
@@ -298,17 +317,21 @@ int launch_pair_sort(const Plan &p, Workspace &ws, hipStream_t s, int sort_grid)
   ws.psorted = radix_sort<SORT_ITEMS_PAIR>(ws.pkeys, ws.pack_shift ? nullptr : ws.pvals, n_dev, 0u,
                                            (uint32_t)p.capacity, ws.pack_shift, p.tile_bits,
                                            ws.hist, ws.hoff, p.max_sort_tiles, ws.digit_total,
-                                           sort_grid_for(p.capacity, SORT_ITEMS_PAIR, sort_grid), true, s);
+                                           sort_grid_for(p.capacity, SORT_ITEMS_PAIR, sort_grid), true, nullptr,
+                                           nullptr, s);
   return ws.psorted;
 }
 
 // ----------------------------------------------------------- scan + emit pairs
 
+// The record scan runs over the depth-sorted visible records; their number
+// n_vis comes from the depth sort (blocks past it store zero sums).
 __global__ __launch_bounds__(BLOCK) void k_scan_reduce(const uint32_t *__restrict__ order,
                                                        const uint32_t *__restrict__ count,
-                                                       int64_t n_rec,
+                                                       const unsigned long long *__restrict__ n_vis,
                                                        unsigned long long *__restrict__ part) {
   __shared__ unsigned long long s_w[4];
+  const int64_t n_rec = (int64_t)*n_vis;
   const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK;
   unsigned long long sum = 0ull;
 #pragma unroll
@@ -363,13 +386,15 @@ __global__ __launch_bounds__(BLOCK) void k_scan_top(unsigned long long *__restri
 // scanned array: for few blocks this saves the single-block scan kernel.
 template <bool INLINE>
 __global__ __launch_bounds__(BLOCK) void k_scan_down(const uint32_t *__restrict__ order,
-                                                     const uint32_t *__restrict__ count, int64_t n_rec,
+                                                     const uint32_t *__restrict__ count,
+                                                     const unsigned long long *__restrict__ n_vis,
                                                      const unsigned long long *__restrict__ part, int nblocks,
                                                      uint64_t capacity, uint32_t *__restrict__ hdr,
                                                      uint32_t *__restrict__ off,
                                                      uint32_t *__restrict__ bucket_rec) {
   __shared__ unsigned long long s_w[4];
   __shared__ unsigned long long s_pre, s_tot;
+  const int64_t n_rec = (int64_t)*n_vis;
   unsigned long long block_off, np;
   if (INLINE) {
     unsigned long long pre = 0ull, tot = 0ull;
@@ -442,7 +467,8 @@ __global__ __launch_bounds__(BLOCK) void k_emit_pairs(const uint32_t *__restrict
                                                       const uint4 *__restrict__ tinfo,
                                                       const Support *__restrict__ support,
                                                       const float4 *__restrict__ recB, uint32_t dropped_key,
-                                                      uint32_t n_rec, const unsigned long long *__restrict__ n_dev,
+                                                      const unsigned long long *__restrict__ n_vis,
+                                                      const unsigned long long *__restrict__ n_dev,
                                                       uint32_t cap, const uint32_t *__restrict__ bucket_rec,
                                                       uint32_t *__restrict__ pkeys, uint32_t *__restrict__ pvals,
                                                       int pack_shift, int nbits0, uint32_t *__restrict__ hist,
@@ -456,6 +482,7 @@ __global__ __launch_bounds__(BLOCK) void k_emit_pairs(const uint32_t *__restrict
   __shared__ float4 s_cb[BLOCK];
   __shared__ uint32_t s_cnt[RADIX];
   const uint32_t n = sort_count(n_dev, 0u, cap);
+  const uint32_t n_rec = (uint32_t)*n_vis;  // depth-ordered records
   const uint32_t ntiles = (n + STILE - 1) / STILE;
   const uint32_t mask0 = (1u << nbits0) - 1u;
   const int t = threadIdx.x;
@@ -538,25 +565,26 @@ void launch_emit_pairs(const Plan &p, const Workspace &ws, const ViewInfo *views
   (void)views;
   const uint32_t *order = ws.dvals[ws.dsorted];
   uint32_t *off = ws.dkeys[ws.dsorted ^ 1];  // free after the depth sort
-  hipLaunchKernelGGL(k_scan_reduce, dim3(p.n_scan_blocks), dim3(BLOCK), 0, s, order, ws.count,
-                     p.n_rec, ws.scan_part);
+  const unsigned long long *n_vis = reinterpret_cast<const unsigned long long *>(ws.hdr + HDR_NVISIBLE);
+  hipLaunchKernelGGL(k_scan_reduce, dim3(p.n_scan_blocks), dim3(BLOCK), 0, s, order, ws.count, n_vis,
+                     ws.scan_part);
   const bool inline_top = p.n_rec > 0 && p.n_scan_blocks <= 512;
   if (!inline_top)
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(BLOCK), 0, s, ws.scan_part, p.n_scan_blocks, ws.hdr,
                        (uint64_t)p.capacity);
   if (p.n_rec == 0) return;
   if (inline_top)
-    hipLaunchKernelGGL(k_scan_down<true>, dim3(p.n_scan_blocks), dim3(BLOCK), 0, s, order, ws.count, p.n_rec,
+    hipLaunchKernelGGL(k_scan_down<true>, dim3(p.n_scan_blocks), dim3(BLOCK), 0, s, order, ws.count, n_vis,
                        ws.scan_part, p.n_scan_blocks, (uint64_t)p.capacity, ws.hdr, off, ws.bucket_rec);
   else
-    hipLaunchKernelGGL(k_scan_down<false>, dim3(p.n_scan_blocks), dim3(BLOCK), 0, s, order, ws.count, p.n_rec,
+    hipLaunchKernelGGL(k_scan_down<false>, dim3(p.n_scan_blocks), dim3(BLOCK), 0, s, order, ws.count, n_vis,
                        ws.scan_part, p.n_scan_blocks, (uint64_t)p.capacity, ws.hdr, off, ws.bucket_rec);
   int64_t blocks = (p.capacity + (int64_t)BLOCK * SORT_ITEMS_PAIR - 1) / ((int64_t)BLOCK * SORT_ITEMS_PAIR);
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
   const unsigned long long *n_dev = reinterpret_cast<const unsigned long long *>(ws.hdr + HDR_NPAIRS);
   hipLaunchKernelGGL(k_emit_pairs, dim3((unsigned)blocks), dim3(BLOCK), 0, s, order, off, ws.tinfo, ws.support,
-                     ws.recB, (uint32_t)p.total_tiles, (uint32_t)p.n_rec, n_dev, (uint32_t)p.capacity,
+                     ws.recB, (uint32_t)p.total_tiles, n_vis, n_dev, (uint32_t)p.capacity,
                      ws.bucket_rec, ws.pkeys[0], ws.pack_shift ? nullptr : ws.pvals[0], ws.pack_shift,
                      radix_digit_bits(p.tile_bits), ws.hist,
                      p.max_sort_tiles);
