@@ -135,7 +135,6 @@ __device__ __forceinline__ uint32_t project_record(const gsr_gaussians &g, const
 
   if (!ok) {
     ws.count[rec] = 0u;
-    ws.tinfo[rec] = make_uint4(0u, 0u, 0u, 0u);
     return 0xFFFFFFFFu;
   }
   // Only records that enter tile lists receive or give back 2D gradients.
