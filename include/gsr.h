@@ -229,7 +229,7 @@ int64_t gsr_required_pairs(const gsr_ctx *ctx);
 /* Synchronise `stream` and return the number of (tile, Gaussian) pairs the
  * last forward on `workspace` produced: one per tile of each visible
  * Gaussian's 3-sigma rectangle, including the pairs whose tile lies outside
- * the Gaussian's alpha support (those are sorted past the last tile and not
+ * the Gaussian's alpha support (those are dropped by the pair sort and not
  * rendered). */
 int64_t gsr_pair_count(gsr_ctx *ctx, void *workspace, gsr_stream stream);
 

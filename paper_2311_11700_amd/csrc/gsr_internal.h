@@ -45,6 +45,7 @@ enum HeaderWord {
   HDR_FWD_DONE = 6,    // u32: marker that a forward filled this workspace
   HDR_MAGIC = 8,       // u32 x 2 (words 8-9): set once the header has been initialised
   HDR_NVISIBLE = 10,   // u64 (words 10-11): records that passed the culling (depth-sorted keys)
+  HDR_NLISTED = 12,    // u64 (words 12-13): pairs inside the alpha support (the sorted tile lists)
   HDR_WORDS = 64
 };
 // Header magic: a workspace whose words 8-9 do not hold it has never been
@@ -202,6 +203,8 @@ __device__ __forceinline__ void reset_header_words(uint32_t *hdr) {
   hdr[HDR_NPAIRS + 1] = 0u;
   hdr[HDR_NVISIBLE] = 0u;
   hdr[HDR_NVISIBLE + 1] = 0u;
+  hdr[HDR_NLISTED] = 0u;
+  hdr[HDR_NLISTED + 1] = 0u;
   hdr[HDR_QUEUE] = 0u;
   hdr[HDR_FWD_DONE] = 1u;
 }

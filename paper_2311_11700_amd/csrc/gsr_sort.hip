@@ -165,8 +165,10 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scan(const uint32_t *__restrict
 // consecutive threads store consecutive addresses.
 //
 // With tile_count, sort tile t holds only its first tile_count[t] keys (the
-// rest of its slots are unused) and the output is dense; block 0 then stores
-// the number of keys sorted in *n_out.
+// rest of its slots are unused).  With key_limit != 0, keys >= key_limit are
+// left out (the digit counts in hist must leave them out too).  The output
+// is dense either way; with n_out, block 0 stores the number of keys
+// written there.
 template <int ITEMS, bool VALS>
 __global__ __launch_bounds__(BLOCK) void k_radix_scatter(
     const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in,
@@ -174,7 +176,7 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(
     const unsigned long long *n_dev, uint32_t n_static, uint32_t cap, int shift, int nbits,
     const uint32_t *__restrict__ hist, const uint32_t *__restrict__ hoff, int max_tiles,
     const uint32_t *__restrict__ digit_total, const uint32_t *__restrict__ tile_count,
-    unsigned long long *__restrict__ n_out) {
+    uint32_t key_limit, unsigned long long *__restrict__ n_out) {
   constexpr int STILE = BLOCK * ITEMS;
   constexpr int WKEYS = 64 * ITEMS;
   __shared__ uint32_t s_base[RADIX];   // first output position of each digit
@@ -200,23 +202,27 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(
     const uint32_t tend = t0 + tn;  // keys of this tile: [t0, tend)
     const uint32_t wbase = t0 + wave * WKEYS + lane;
     uint32_t kr[ITEMS], vr[ITEMS], rank[ITEMS];
+    uint32_t live = 0u;  // bit r: item r is a key to sort
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
       const uint32_t idx = wbase + r * 64;
       kr[r] = idx < tend ? keys_in[idx] : 0u;
       if (VALS) vr[r] = idx < tend ? vals_in[idx] : 0u;
     }
+#pragma unroll
+    for (int r = 0; r < ITEMS; ++r)
+      if (wbase + r * 64 < tend && (key_limit == 0u || kr[r] < key_limit)) live |= 1u << r;
     s_wc[0][dig] = s_wc[1][dig] = s_wc[2][dig] = s_wc[3][dig] = 0u;
+    uint32_t tkeys;  // keys of this tile that are sorted (block-uniform)
     {
       const uint32_t cnt = hist[(size_t)dig * max_tiles + t];
-      uint32_t total;
-      const uint32_t lbase = block_exclusive_scan<uint32_t>(cnt, s_w, total);
+      const uint32_t lbase = block_exclusive_scan<uint32_t>(cnt, s_w, tkeys);
       s_lbase[dig] = lbase;
       s_goff[dig] = s_base[dig] + hoff[(size_t)dig * max_tiles + t] - lbase;
     }
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
-      const bool valid = wbase + r * 64 < tend;
+      const bool valid = (live >> r) & 1u;
       const uint32_t d = (kr[r] >> shift) & mask;
       const uint64_t peers = match_digit(d, nbits, __ballot(valid));
       const uint64_t below = peers & lanemask_lt();
@@ -237,14 +243,14 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
-      if (wbase + r * 64 < tend) {
+      if ((live >> r) & 1u) {
         const uint32_t lp = s_wc[wave][(kr[r] >> shift) & mask] + rank[r];
         s_k[lp] = kr[r];
         if (VALS) s_v[lp] = vr[r];
       }
     }
     __syncthreads();
-    for (uint32_t i = threadIdx.x; i < tn; i += BLOCK) {
+    for (uint32_t i = threadIdx.x; i < tkeys; i += BLOCK) {
       const uint32_t key = s_k[i];
       const uint32_t gpos = s_goff[(key >> shift) & mask] + i;
       keys_out[gpos] = key;
@@ -262,21 +268,25 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(
 // that produced the keys).
 //
 // With tile_count0, the first pass reads tile t's first tile_count0[t] keys
-// only (n_static covering all tiles' slots), stores the number of keys in
-// *n_after0, and the later passes sort that many.
+// only (n_static covering all tiles' slots); with key_limit0 != 0 it drops the
+// words >= key_limit0 (the hist0_ready counts leave them out).  With
+// n_after0, the first pass stores the number of words it kept there and the
+// later passes sort that many.
 template <int ITEMS>
 static int radix_sort(uint32_t *keys[2], uint32_t *vals[2], const unsigned long long *n_dev,
                       uint32_t n_static, uint32_t cap, int base, int key_bits, uint32_t *hist, uint32_t *hoff,
                       int max_tiles, uint32_t *digit_total, int grid, bool hist0_ready,
-                      const uint32_t *tile_count0, unsigned long long *n_after0, hipStream_t s) {
+                      const uint32_t *tile_count0, uint32_t key_limit0, unsigned long long *n_after0,
+                      hipStream_t s) {
   const int per = radix_digit_bits(key_bits);
   int cur = 0;
   for (int sh = 0; sh < key_bits; sh += per) {
     const int nbits = key_bits - sh < per ? key_bits - sh : per;
     const int shift = base + sh;
     const uint32_t *tile_count = sh == 0 ? tile_count0 : nullptr;
+    const uint32_t key_limit = sh == 0 ? key_limit0 : 0u;
     unsigned long long *n_out = sh == 0 ? n_after0 : nullptr;
-    if (sh > 0 && tile_count0) n_dev = n_after0;
+    if (sh > 0 && n_after0) n_dev = n_after0;
     if (sh > 0 || !hist0_ready)
       hipLaunchKernelGGL(k_radix_hist<ITEMS>, dim3(grid), dim3(BLOCK), 0, s, keys[cur], n_dev, n_static, cap,
                          shift, nbits, hist, max_tiles);
@@ -285,11 +295,11 @@ static int radix_sort(uint32_t *keys[2], uint32_t *vals[2], const unsigned long 
     if (vals)
       hipLaunchKernelGGL((k_radix_scatter<ITEMS, true>), dim3(grid), dim3(BLOCK), 0, s, keys[cur], vals[cur],
                          keys[cur ^ 1], vals[cur ^ 1], n_dev, n_static, cap, shift, nbits, hist, hoff,
-                         max_tiles, digit_total, tile_count, n_out);
+                         max_tiles, digit_total, tile_count, key_limit, n_out);
     else
       hipLaunchKernelGGL((k_radix_scatter<ITEMS, false>), dim3(grid), dim3(BLOCK), 0, s, keys[cur],
                          (const uint32_t *)nullptr, keys[cur ^ 1], (uint32_t *)nullptr, n_dev, n_static, cap,
-                         shift, nbits, hist, hoff, max_tiles, digit_total, tile_count, n_out);
+                         shift, nbits, hist, hoff, max_tiles, digit_total, tile_count, key_limit, n_out);
     cur ^= 1;
   }
   return cur;
@@ -308,17 +318,23 @@ int launch_depth_sort(const Plan &p, Workspace &ws, hipStream_t s, int sort_grid
   ws.dsorted = radix_sort<SORT_ITEMS_DEPTH>(ws.dkeys, ws.dvals, nullptr, (uint32_t)p.n_rec, (uint32_t)p.n_rec, 0, 32,
                                             ws.hist, ws.hoff, p.max_sort_tiles, ws.digit_total,
                                             sort_grid_for(p.n_rec, SORT_ITEMS_DEPTH, sort_grid), true,
-                                            ws.tile_visible, n_vis, s);
+                                            ws.tile_visible, 0u, n_vis, s);
   return ws.dsorted;
 }
 
+// The first pass drops the pairs outside the alpha support (tile key
+// total_tiles, left out of the emission's digit counts): the later passes,
+// the tile ranges and the lists see only the listed pairs, whose number goes
+// to the header.
 int launch_pair_sort(const Plan &p, Workspace &ws, hipStream_t s, int sort_grid) {
   const unsigned long long *n_dev = reinterpret_cast<const unsigned long long *>(ws.hdr + HDR_NPAIRS);
+  unsigned long long *n_listed = reinterpret_cast<unsigned long long *>(ws.hdr + HDR_NLISTED);
+  const uint32_t key_limit = (uint32_t)p.total_tiles << ws.pack_shift;
   ws.psorted = radix_sort<SORT_ITEMS_PAIR>(ws.pkeys, ws.pack_shift ? nullptr : ws.pvals, n_dev, 0u,
                                            (uint32_t)p.capacity, ws.pack_shift, p.tile_bits,
                                            ws.hist, ws.hoff, p.max_sort_tiles, ws.digit_total,
                                            sort_grid_for(p.capacity, SORT_ITEMS_PAIR, sort_grid), true, nullptr,
-                                           nullptr, s);
+                                           key_limit, n_listed, s);
   return ws.psorted;
 }
 
@@ -536,8 +552,8 @@ __global__ __launch_bounds__(BLOCK) void k_emit_pairs(const uint32_t *__restrict
           tile = ti.x + (uint32_t)(ty * TX + tx);
           if (ti.y & 0x80000000u) {
             // Tiles of the rectangle that the alpha support does not reach
-            // get the key past the last tile: the sort moves them behind
-            // every list.
+            // get the key past the last tile: the pair sort's first pass
+            // drops them.
             const float4 cb = s_cb[a];
             int c0 = 0;
             const int len = support_row(s_sp[a], (double)cb.x, (double)cb.y, (double)cb.z, ty, tx0, tx1, c0);
@@ -551,9 +567,11 @@ __global__ __launch_bounds__(BLOCK) void k_emit_pairs(const uint32_t *__restrict
             pkeys[p] = tile << pack_shift | rec;
           }
         }
+        // The first pass's digit counts leave the dropped pairs out.
+        const bool listed = valid && tile != dropped_key;
         const uint32_t d = tile & mask0;
-        const uint64_t peers = match_digit(d, nbits0, __ballot(valid));
-        if (valid && (peers & lanemask_lt()) == 0ull) atomicAdd(&s_cnt[d], (uint32_t)__popcll(peers));
+        const uint64_t peers = match_digit(d, nbits0, __ballot(listed));
+        if (listed && (peers & lanemask_lt()) == 0ull) atomicAdd(&s_cnt[d], (uint32_t)__popcll(peers));
       }
     }
     __syncthreads();
@@ -596,8 +614,8 @@ void launch_emit_pairs(const Plan &p, const Workspace &ws, const ViewInfo *views
 // change of tile between positions i - 1 and i, the thread of position i
 // closes the earlier tile, writes (i, i) for the empty tiles in between and
 // opens the later one; the last position closes its tile and empties the
-// rest.  Keys past the last tile (pairs outside the alpha support) sort to
-// the end and open nothing.
+// rest.  Keys past the last tile open nothing (the pair sort has already
+// dropped the pairs outside the alpha support).
 __global__ __launch_bounds__(BLOCK) void k_tile_ranges(const uint32_t *__restrict__ keys,
                                                        const unsigned long long *n_dev, uint32_t cap,
                                                        uint32_t total_tiles, int shift,
@@ -632,13 +650,13 @@ __global__ __launch_bounds__(BLOCK) void k_unpack_ids(const uint32_t *__restrict
 }
 
 void launch_unpack_ids(const Plan &p, const Workspace &ws, hipStream_t s) {
-  const unsigned long long *n_dev = reinterpret_cast<const unsigned long long *>(ws.hdr + HDR_NPAIRS);
+  const unsigned long long *n_dev = reinterpret_cast<const unsigned long long *>(ws.hdr + HDR_NLISTED);
   hipLaunchKernelGGL(k_unpack_ids, dim3(1024), dim3(BLOCK), 0, s, ws.pkeys[ws.psorted], n_dev,
                      (uint32_t)p.capacity, ws.id_mask, ws.pvals[ws.psorted]);
 }
 
 void launch_tile_ranges(const Plan &p, const Workspace &ws, hipStream_t s) {
-  const unsigned long long *n_dev = reinterpret_cast<const unsigned long long *>(ws.hdr + HDR_NPAIRS);
+  const unsigned long long *n_dev = reinterpret_cast<const unsigned long long *>(ws.hdr + HDR_NLISTED);
   int64_t blocks = (p.capacity + BLOCK - 1) / BLOCK;
   if (blocks > 8192) blocks = 8192;
   if (blocks < 1) blocks = 1;

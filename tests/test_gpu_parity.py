@@ -33,6 +33,8 @@ def _check_lists(renderer, scene_list, cams, cfg_o):
     rng, sid = renderer.debug_tiles()
     rng = rng.numpy()
     sid = sid.numpy()
+    # The lists tile the sorted pairs without gaps, from position 0.
+    assert rng[0, 0] == 0 and np.array_equal(rng[1:, 0], rng[:-1, 1])
     tile_off = 0
     n = renderer.n
     for v, (sc, cam) in enumerate(zip(scene_list, cams)):
