@@ -34,6 +34,13 @@ class Camera:
     width: int
     height: int
 
+    def __post_init__(self):
+        # The renderer takes the intrinsics as float32: hold exactly those
+        # values, so that the renderer and the oracle see the same camera
+        # (poses from with_pose are float32 too).
+        for k in ("fx", "fy", "cx", "cy"):
+            setattr(self, k, float(np.float32(getattr(self, k))))
+
     def with_pose(self, R, t) -> "Camera":
         return dataclasses.replace(self, R=np.asarray(R, F32).reshape(3, 3).copy(),
                                    t=np.asarray(t, F32).reshape(3).copy())
