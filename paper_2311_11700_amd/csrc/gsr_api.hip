@@ -87,6 +87,7 @@ Workspace make_ws(const Plan &p, void *base_v) {
   w.grad2d = reinterpret_cast<double *>(base + p.off_grad2d);
   w.pose_part = reinterpret_cast<double *>(base + p.off_pose);
   w.queue = reinterpret_cast<uint32_t *>(base + p.off_queue);
+  w.tile_cost = reinterpret_cast<uint32_t *>(base + p.off_tile_cost);
   w.loss_part = reinterpret_cast<float *>(base + p.off_loss);
   w.dsorted = passes_for(32) & 1;
   w.psorted = passes_for(p.tile_bits) & 1;
@@ -344,6 +345,7 @@ gsr_status gsr_plan(gsr_ctx *ctx, int64_t n, int n_views, const int32_t *wh_host
   p.off_grad2d = take(8 * NGRAD2D * nr);
   p.off_pose = take(8 * 6 * (size_t)n_views * p.n_pose_blocks);
   p.off_queue = take(4 * (size_t)p.total_tiles);
+  p.off_tile_cost = take(4 * (size_t)p.total_tiles);
   p.off_loss = take(4);
   p.bytes = off;
 

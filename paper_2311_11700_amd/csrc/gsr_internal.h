@@ -46,6 +46,7 @@ enum HeaderWord {
   HDR_MAGIC = 8,       // u32 x 2 (words 8-9): set once the header has been initialised
   HDR_NVISIBLE = 10,   // u64 (words 10-11): records that passed the culling (depth-sorted keys)
   HDR_NLISTED = 12,    // u64 (words 12-13): pairs inside the alpha support (the sorted tile lists)
+  HDR_COSTS = 14,      // u32: a fused step has recorded every tile's duration (sticky)
   HDR_WORDS = 64
 };
 // Header magic: a workspace whose words 8-9 do not hold it has never been
@@ -131,6 +132,7 @@ struct Workspace {
   double *grad2d;          // [n_rec][NGRAD2D], FP64 sums over tiles
   double *pose_part;       // [n_pose_blocks][n_views][6]
   uint32_t *queue;         // [total_tiles] work order of the persistent rasteriser
+  uint32_t *tile_cost;     // [total_tiles] duration of each tile in the last fused step (10 ns ticks)
   float *loss_part;        // [1] (unused slot kept for alignment)
   int dsorted;             // which depth buffer holds the sorted result
   int psorted;             // which pair buffer holds the sorted result
@@ -158,7 +160,7 @@ struct Plan {
   size_t off_hdr, off_recA, off_recB, off_recC, off_rect, off_count, off_dkeys[2], off_dvals[2],
       off_scan, off_pkeys[2], off_pvals[2], off_hist, off_digit, off_ranges, off_T, off_last, off_zr,
       off_grad2d, off_pose, off_queue, off_loss, off_counts, off_hoff, off_bucket,
-      off_support, off_tile_visible;
+      off_support, off_tile_visible, off_tile_cost;
 };
 
 struct Tuning {
@@ -196,6 +198,7 @@ __device__ __forceinline__ void reset_header_words(uint32_t *hdr) {
     hdr[HDR_REQUIRED] = 0u;
     hdr[HDR_REQUIRED + 1] = 0u;
     hdr[HDR_OVERFLOW] = 0u;
+    hdr[HDR_COSTS] = 0u;
     hdr[HDR_MAGIC] = HDR_MAGIC0;
     hdr[HDR_MAGIC + 1] = HDR_MAGIC1;
   }

@@ -550,9 +550,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
 __device__ __forceinline__ float sgnf(float x) { return (float)((x > 0.f) - (x < 0.f)); }
 
 // Persistent fused step: blocks take tiles from an atomic counter (in index
-// order, or in the longest-list-first order of `queue`); per tile run the
+// order, or in the longest-first order of `queue`); per tile run the
 // forward blend, the L1 loss gradient of every pixel, and the backward walk
-// without leaving the block (per-pixel state stays in registers).
+// without leaving the block (per-pixel state stays in registers).  Each
+// tile's duration goes to tile_cost, the next step's longest-first order.
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_render_fused(RasterArgs a, uint32_t *__restrict__ hdr,
                                                         const uint32_t *__restrict__ queue, int total_tiles,
                                                         int tiles_per_pop, const float *__restrict__ t_rgb,
@@ -560,7 +561,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
                                                         const uint8_t *__restrict__ pmask, float w_rgb,
                                                         float w_depth, const float *__restrict__ loss_cap,
                                                         gsr_images out, float *__restrict__ loss,
-                                                        double *__restrict__ grad2d, PixelState ps) {
+                                                        double *__restrict__ grad2d, PixelState ps,
+                                                        uint32_t *__restrict__ tile_cost) {
   __shared__ Staged s_rec[BATCH];
   __shared__ float s_part[4 * SUB * NMOM];
   __shared__ uint32_t s_id[BATCH];
@@ -578,6 +580,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     for (int q = q0; q < q1; ++q) {
       const int tile = queue ? (int)queue[q] : q;
       const TileInfo ti = tile_info(tile, a.views, a.tile_view, a.ranges);
+      const uint64_t clk0 = wall_clock64();
       FwdState st;
       int staged_lo;
       tile_forward<false>(ti, a.n, a.recA, a.recB, a.recC, a.ids, a.rc, s_rec, st, nullptr, s_id,
@@ -622,6 +625,11 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
       tile_backward(ti, a.n, a.recA, a.recB, a.recC, a.ids, a.rc, in, grad2d, s_rec, s_part, s_id, &s_max,
                     s_mA, staged_lo);
       if (threadIdx.x == 0 && loss) atomicAdd(loss, (s_loss[0] + s_loss[1]) + (s_loss[2] + s_loss[3]));
+      if (threadIdx.x == 0) {
+        const uint64_t d = wall_clock64() - clk0;
+        tile_cost[tile] = d < 0xFFFFFFFFull ? (uint32_t)d : 0xFFFFFFFFu;
+        if (blockIdx.x == 0) hdr[HDR_COSTS] = 1u;
+      }
       // The next tile may have an empty list (no barrier in its forward):
       // keep its shared-memory writes behind this tile's reads.
       __syncthreads();
@@ -713,7 +721,8 @@ void launch_render_fused(const Plan &p, const Workspace &ws, const ViewInfo *vie
   PixelState ps{ws.T_final, ws.last, nullptr};
   const uint32_t *queue = tun.lpt_order ? ws.queue : nullptr;
   hipLaunchKernelGGL(k_render_fused, dim3(grid), dim3(BLOCK), 0, s, a, ws.hdr, queue, p.total_tiles,
-                     tun.tiles_per_pop, t_rgb, t_depth, pmask, w_rgb, w_depth, loss_cap, o, loss, ws.grad2d, ps);
+                     tun.tiles_per_pop, t_rgb, t_depth, pmask, w_rgb, w_depth, loss_cap, o, loss, ws.grad2d, ps,
+                     ws.tile_cost);
 }
 
 // Totals of the per-pixel work counters: counts[0] pairs, [1] entries the

@@ -472,6 +472,45 @@ def test_batched_views_equal_separate_calls(gsr_lib):
         H.assert_close_scaled(gb[k], acc[k], what=k)
 
 
+def test_longest_first_order_equals_index_order(gsr_lib):
+    """The persistent rasteriser's longest-first tile order (list lengths on a
+    fresh workspace, then the durations the previous fused step recorded)
+    gives the index order's images exactly and its loss and gradients up to
+    the order of the FP64 additions, on a graph over many views."""
+    gsr = gsr_lib
+    sc = W.room_scene(20000, seed=5)
+    base = W.camera_tum_coarse()
+    cams = [W.perturb_pose(base, [0.02 * (v % 3), -0.01 * (v % 2), 0.01 * v, 0.004 * v, -0.003 * (v % 4), 0.0])
+            for v in range(12)]
+    sizes = [(c.width, c.height) for c in cams]
+    t_rgb, t_d, mask = W.random_targets(sizes, seed=9)
+    g = H.gpu_scene(gsr, sc)
+    cams_d = gsr.pack_cameras(cams)
+    args = (H.to_dev(t_rgb), H.to_dev(t_d), H.to_dev(mask, torch.uint8))
+    cfg = gsr.Config(flags=gsr.GSR_GAUSS_GRAD | gsr.GSR_POSE_GRAD | gsr.GSR_GRAD_OVERWRITE)
+    r0 = gsr.Renderer()
+    r0.plan(sc.n, sizes)
+    r0.set_tuning(2, 1, 0)
+    out0 = r0.new_images()
+    loss0, grads0 = r0.render_l1_fused(g, cams_d, cfg, *args, out=out0)
+    ref = H.gpu_grads_numpy(grads0)
+    img0 = {k: v.cpu().numpy() for k, v in out0.items() if v is not None}
+    r1 = gsr.Renderer()  # fresh workspace: no recorded durations yet
+    r1.plan(sc.n, sizes)
+    r1.set_tuning(2, 1, 1)
+    out1 = r1.new_images()
+    grads1 = r1.new_grads(sc.n)
+    loss1 = torch.zeros(1, device="cuda")
+    for call in range(3):
+        r1.render_l1_fused(g, cams_d, cfg, *args, out=out1, grads=grads1, loss=loss1)
+        for k, v in img0.items():
+            np.testing.assert_array_equal(out1[k].cpu().numpy(), v, err_msg=f"call {call} {k}")
+        assert abs(loss1.item() - loss0.item()) <= 1e-5 * abs(loss0.item()), call
+        got = H.gpu_grads_numpy(grads1)
+        for k in ref:
+            H.assert_close_scaled(got[k], ref[k], what=(call, k))
+
+
 @pytest.mark.parametrize("n_views", [2, 48])
 def test_overwrite_mode_equals_accumulation_into_zeros(gsr_lib, n_views):
     """GSR_GRAD_OVERWRITE: a fused step into buffers holding garbage gives the
