@@ -172,12 +172,14 @@ void prof_end(gsr_ctx *ctx, hipStream_t s, int first_unmarked) {
 }
 
 // Projection, depth sort, pair emission, tile sort and ranges.  The
-// projection also resets the header, clears grad2d for a fused step and
-// zeroes the fused step's loss when the gradients are overwritten.
+// projection also resets the header, clears grad2d for a fused step, zeroes
+// the fused step's loss when the gradients are overwritten and, with
+// order_queue, writes the rasteriser's longest-first work order.
 void enqueue_lists(gsr_ctx *ctx, const gsr_gaussians &g, const gsr_camera *cams, const gsr_config &cfg,
-                   Workspace &ws, bool clear_grad2d, float *loss_zero, hipStream_t s) {
+                   Workspace &ws, bool clear_grad2d, float *loss_zero, bool order_queue, hipStream_t s) {
   const Plan &p = ctx->plan;
-  launch_preprocess(g, cams, ctx->views_dev, p.n_views, cfg, ws, clear_grad2d, loss_zero, p.max_sort_tiles, s);
+  launch_preprocess(g, cams, ctx->views_dev, p.n_views, cfg, ws, clear_grad2d, loss_zero, p.max_sort_tiles,
+                    order_queue ? p.total_tiles : 0, s);
   prof_mark(ctx, s, GSR_STAGE_PREPROCESS);
   launch_depth_sort(p, ws, s, ctx->sort_grid);
   prof_mark(ctx, s, GSR_STAGE_DEPTH_SORT);
@@ -194,8 +196,8 @@ void enqueue_fused(gsr_ctx *ctx, const gsr_gaussians &g, const gsr_camera *cams,
                    Workspace &ws, const gsr_images *out, const gsr_grads &gr, float *loss, hipStream_t s) {
   const Plan &p = ctx->plan;
   prof_begin(ctx, s);
-  enqueue_lists(ctx, g, cams, cfg, ws, true, (cfg.flags & GSR_GRAD_OVERWRITE) ? loss : nullptr, s);
-  launch_queue_order(p, ws, ctx->tuning.lpt_order, s);
+  enqueue_lists(ctx, g, cams, cfg, ws, true, (cfg.flags & GSR_GRAD_OVERWRITE) ? loss : nullptr,
+                ctx->tuning.lpt_order != 0, s);
   prof_mark(ctx, s, GSR_STAGE_RANGES);
   launch_render_fused(p, ws, ctx->views_dev, ctx->tile_view_dev, g, consts(cfg), t_rgb, t_depth, pmask, w_rgb,
                       w_depth, loss_cap, out, loss, ctx->tuning, ctx->num_cus, s);
@@ -380,7 +382,7 @@ gsr_status gsr_render_forward(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_ca
   hipStream_t s = static_cast<hipStream_t>(stream);
   Workspace ws = make_ws(ctx->plan, workspace);
   prof_begin(ctx, s);
-  enqueue_lists(ctx, *g, cams, *cfg, ws, false, nullptr, s);
+  enqueue_lists(ctx, *g, cams, *cfg, ws, false, nullptr, false, s);
   prof_mark(ctx, s, GSR_STAGE_RANGES);
   launch_render_forward(ctx->plan, ws, ctx->views_dev, ctx->tile_view_dev, *g, consts(*cfg), out, s);
   prof_end(ctx, s, GSR_STAGE_RASTER);
@@ -606,7 +608,7 @@ gsr_status gsr_autotune(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *
   hipStream_t s = static_cast<hipStream_t>(stream);
   Workspace ws = make_ws(ctx->plan, workspace);
   const Plan &p = ctx->plan;
-  enqueue_lists(ctx, *g, cams, *cfg, ws, false, nullptr, s);
+  enqueue_lists(ctx, *g, cams, *cfg, ws, false, nullptr, false, s);
   hipEvent_t e0, e1;
   if ((st = hip_check(ctx, hipEventCreate(&e0), "hipEventCreate")) != GSR_OK) return st;
   if ((st = hip_check(ctx, hipEventCreate(&e1), "hipEventCreate")) != GSR_OK) {
@@ -628,7 +630,7 @@ gsr_status gsr_autotune(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *
         float total = 0.f;
         for (int r = 0; r <= reps && st == GSR_OK; ++r) {
           launch_fill_u32(ws.hdr + HDR_QUEUE, 0u, 1, s);
-          launch_queue_order(p, ws, lpt, s);
+          if (lpt) launch_queue_order(ws, p.total_tiles, s);
           launch_fill_f32(reinterpret_cast<float *>(ws.grad2d), 0.f, 2 * p.n_rec * NGRAD2D, s);
           (void)hipEventRecord(e0, s);
           launch_render_fused(p, ws, ctx->views_dev, ctx->tile_view_dev, *g, consts(*cfg), target_rgb, target_depth,

@@ -228,15 +228,87 @@ __device__ __forceinline__ uint64_t match_digit(uint32_t d, int nbits, uint64_t 
   return m;
 }
 
+// --------------------------------------------------------------- tile order
+
+// Log-scale bucket of a tile length (eight buckets per octave), 0 .. 255.
+__device__ __forceinline__ uint32_t length_bucket(uint32_t x) {
+  if (x == 0u) return 0u;
+  const int b = 31 - __clz(x);  // floor(log2 x)
+  const uint32_t m = b >= 3 ? (x >> (b - 3)) & 7u : (x << (3 - b)) & 7u;
+  const uint32_t k = 1u + 8u * (uint32_t)b + m;
+  return k < (uint32_t)RADIX ? k : (uint32_t)(RADIX - 1);
+}
+
+// Work order of the persistent rasteriser, computed by one block of NT
+// threads: with `timed` (the last fused step on this workspace recorded every
+// tile's duration in tile_cost) the tiles longest first, by a counting sort
+// over length_bucket (order inside a bucket arbitrary; equal buckets inside a
+// wavefront grouped by ballot matching, one LDS atomic per group); otherwise
+// index order.  The queue is a permutation of the tiles whatever the recorded
+// values.  `timed` must be the same in every thread; s_cnt, s_cur hold RADIX
+// words and s_w NT / 64.
+template <int NT>
+__device__ __forceinline__ void order_tiles(const uint32_t *__restrict__ tile_cost, bool timed, int total,
+                                            uint32_t *__restrict__ queue, uint32_t *s_cnt, uint32_t *s_cur,
+                                            uint32_t *s_w) {
+  static_assert(NT >= RADIX && NT % 64 == 0, "one thread per bucket, whole wavefronts");
+  if (!timed) {
+    for (int t = threadIdx.x; t < total; t += NT) queue[t] = (uint32_t)t;
+    return;
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (threadIdx.x < RADIX) s_cnt[threadIdx.x] = 0u;
+  __syncthreads();
+  for (int base = 0; base < total; base += NT) {
+    const int t = base + (int)threadIdx.x;
+    const bool valid = t < total;
+    const uint32_t d = valid ? length_bucket(tile_cost[t]) : 0u;
+    const uint64_t peers = match_digit(d, RADIX_BITS, __ballot(valid));
+    if (valid && (peers & lanemask_lt()) == 0ull) atomicAdd(&s_cnt[d], (uint32_t)__popcll(peers));
+  }
+  __syncthreads();
+  // Start of each bucket: the tiles of all longer buckets (bucket RADIX - 1 - k
+  // is the k-th in the order).
+  {
+    const int k = threadIdx.x;
+    const uint32_t v = k < RADIX ? s_cnt[RADIX - 1 - k] : 0u;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o);
+      if (lane >= o) x += y;
+    }
+    if (lane == 63) s_w[wave] = x;
+    __syncthreads();
+    uint32_t pre = 0u;
+    for (int w = 0; w < wave; ++w) pre += s_w[w];
+    if (k < RADIX) s_cur[RADIX - 1 - k] = pre + x - v;
+  }
+  __syncthreads();
+  for (int base = 0; base < total; base += NT) {
+    const int t = base + (int)threadIdx.x;
+    const bool valid = t < total;
+    const uint32_t d = valid ? length_bucket(tile_cost[t]) : 0u;
+    const uint64_t peers = match_digit(d, RADIX_BITS, __ballot(valid));
+    const int leader = __ffsll((long long)peers) - 1;
+    uint32_t first = 0u;
+    if (valid && lane == leader) first = atomicAdd(&s_cur[d], (uint32_t)__popcll(peers));
+    first = __shfl(first, leader < 0 ? 0 : leader);
+    if (valid) queue[first + (uint32_t)__popcll(peers & lanemask_lt())] = (uint32_t)t;
+  }
+}
+
 // --------------------------------------------------------------- launchers (host)
 
 // Preprocess (projection, binning data, depth keys) for every (view, Gaussian).
 // Also resets the per-call header words, clears grad2d when clear_grad2d,
 // zeroes *loss_zero when it is not null (start of a fused step), and writes
 // the depth sort's first-pass digit counts into hist.
+// With order_total > 0 it also writes the rasteriser's longest-first work
+// order of that many tiles (from the durations the last fused step recorded).
 void launch_preprocess(const gsr_gaussians &g, const gsr_camera *cams, const ViewInfo *views,
                        int n_views, const gsr_config &cfg, const Workspace &ws, bool clear_grad2d,
-                       float *loss_zero, int max_sort_tiles, hipStream_t s);
+                       float *loss_zero, int max_sort_tiles, int order_total, hipStream_t s);
 
 // Reliable-Gaussian selection (fine tracking stage).
 void launch_select_reliable(const gsr_gaussians &g, const gsr_camera *cam, const float *depth, int W, int H,
@@ -252,7 +324,8 @@ void launch_unpack_ids(const Plan &p, const Workspace &ws, hipStream_t s);
 void launch_fill_u32(uint32_t *ptr, uint32_t value, int64_t count, hipStream_t s);
 void launch_fill_f32(float *ptr, float value, int64_t count, hipStream_t s);
 void launch_reset_header(const Workspace &ws, hipStream_t s);
-void launch_queue_order(const Plan &p, const Workspace &ws, int lpt, hipStream_t s);
+// The rasteriser's work order (order_tiles) as a one-block kernel.
+void launch_queue_order(const Workspace &ws, int total_tiles, hipStream_t s);
 
 // Rasterisation.
 void launch_render_forward(const Plan &p, const Workspace &ws, const ViewInfo *views,

@@ -22,6 +22,7 @@ struct PreConsts {
   float alpha_min;
   int clear_grad2d;  // zero each record's grad2d row (start of a fused step)
   float *loss_zero;  // zeroed by one thread when not null
+  int order_total;   // > 0: block 0 writes the rasteriser's work order of this many tiles
 };
 
 // Rotation matrix of a unit quaternion (w, x, y, z) (GS-SLAM supplement,
@@ -182,11 +183,19 @@ __global__ __launch_bounds__(PRE_BLOCK) void k_preprocess(gsr_gaussians g, const
   constexpr int NW = PRE_BLOCK / 64;
   __shared__ uint32_t cnt[RADIX];
   __shared__ uint32_t s_wv[NW];
+  __shared__ uint32_t s_qcnt[RADIX], s_qcur[RADIX], s_qw[NW], s_timed;
   const int64_t rec = (int64_t)blockIdx.x * PRE_BLOCK + threadIdx.x;
   const int wave = threadIdx.x >> 6;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     reset_header_words(ws.hdr);
+    s_timed = ws.hdr[HDR_COSTS];  // read by the thread that reset the header
     if (pc.loss_zero) *pc.loss_zero = 0.f;
+  }
+  if (blockIdx.x == 0 && pc.order_total > 0) {
+    // The rasteriser's work order for this step, from the tile durations
+    // the last fused step recorded (the other blocks cover its time).
+    __syncthreads();
+    order_tiles<PRE_BLOCK>(ws.tile_cost, s_timed != 0u, pc.order_total, ws.queue, s_qcnt, s_qcur, s_qw);
   }
   if (threadIdx.x < RADIX) cnt[threadIdx.x] = 0u;
   uint32_t key = 0xFFFFFFFFu;
@@ -221,9 +230,9 @@ __global__ __launch_bounds__(PRE_BLOCK) void k_preprocess(gsr_gaussians g, const
 
 void launch_preprocess(const gsr_gaussians &g, const gsr_camera *cams, const ViewInfo *views,
                        int n_views, const gsr_config &cfg, const Workspace &ws, bool clear_grad2d,
-                       float *loss_zero, int max_sort_tiles, hipStream_t s) {
+                       float *loss_zero, int max_sort_tiles, int order_total, hipStream_t s) {
   PreConsts pc{cfg.z_near, cfg.lowpass, cfg.cutoff_sigma, cfg.flags, cfg.fov_guard, cfg.alpha_min,
-               clear_grad2d ? 1 : 0, loss_zero};
+               clear_grad2d ? 1 : 0, loss_zero, order_total};
   const int64_t n_rec = g.n * (int64_t)n_views;
   if (g.n > 0) {
     hipLaunchKernelGGL(k_preprocess, dim3((unsigned)((n_rec + PRE_BLOCK - 1) / PRE_BLOCK)), dim3(PRE_BLOCK), 0, s,
@@ -231,6 +240,7 @@ void launch_preprocess(const gsr_gaussians &g, const gsr_camera *cams, const Vie
   } else {
     launch_reset_header(ws, s);
     if (loss_zero) launch_fill_f32(loss_zero, 0.f, 1, s);
+    launch_queue_order(ws, order_total, s);
   }
 }
 

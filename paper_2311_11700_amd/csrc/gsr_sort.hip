@@ -666,84 +666,23 @@ void launch_tile_ranges(const Plan &p, const Workspace &ws, hipStream_t s) {
 
 // ------------------------------------------------------- work order (LPT)
 
-// One block: order the tiles longest first for the persistent rasteriser.
-// The length of a tile is its duration in the last fused step on this
-// workspace when one has recorded them, else its list length; tiles are
-// bucketed on a log scale (eight buckets per octave) and laid out by a
-// counting sort, longest bucket first (order inside a bucket is arbitrary),
-// so the queue is a permutation of the tiles whatever the recorded values.
-// Equal buckets inside a wavefront are grouped by ballot matching, so each
-// group costs one LDS atomic.  (Without the longest-first order the
-// rasteriser takes the tiles in index order and reads no queue.)
+// The rasteriser's work order as a kernel of its own (one block): used where
+// the projection does not write it (no Gaussians; the autotuner's trials).
 constexpr int QUEUE_BLOCK = 1024;
 
-__device__ __forceinline__ uint32_t length_bucket(uint32_t x) {
-  if (x == 0u) return 0u;
-  const int b = 31 - __clz(x);  // floor(log2 x)
-  const uint32_t m = b >= 3 ? (x >> (b - 3)) & 7u : (x << (3 - b)) & 7u;
-  const uint32_t k = 1u + 8u * (uint32_t)b + m;
-  return k < (uint32_t)RADIX ? k : (uint32_t)(RADIX - 1);  // 0 .. 255
-}
-
-__global__ __launch_bounds__(QUEUE_BLOCK) void k_queue_order(const int2 *__restrict__ ranges,
-                                                             const uint32_t *__restrict__ tile_cost,
+__global__ __launch_bounds__(QUEUE_BLOCK) void k_queue_order(const uint32_t *__restrict__ tile_cost,
                                                              const uint32_t *__restrict__ hdr, int total,
                                                              uint32_t *__restrict__ queue) {
   __shared__ uint32_t s_cnt[RADIX];
   __shared__ uint32_t s_cur[RADIX];
   __shared__ uint32_t s_w[QUEUE_BLOCK / 64];
-  const bool timed = hdr[HDR_COSTS] != 0u;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  auto bucket_of = [&](int t) -> uint32_t {
-    if (timed) return length_bucket(tile_cost[t]);
-    const int2 r = ranges[t];
-    return length_bucket((uint32_t)(r.y - r.x));
-  };
-  if (threadIdx.x < RADIX) s_cnt[threadIdx.x] = 0u;
-  __syncthreads();
-  for (int base = 0; base < total; base += QUEUE_BLOCK) {
-    const int t = base + (int)threadIdx.x;
-    const bool valid = t < total;
-    const uint32_t d = valid ? bucket_of(t) : 0u;
-    const uint64_t peers = match_digit(d, 8, __ballot(valid));
-    if (valid && (peers & lanemask_lt()) == 0ull) atomicAdd(&s_cnt[d], (uint32_t)__popcll(peers));
-  }
-  __syncthreads();
-  // Start of each bucket: the tiles of all longer buckets (bucket RADIX - 1 - k
-  // is the k-th in the order).
-  {
-    const int k = threadIdx.x;
-    const uint32_t v = k < RADIX ? s_cnt[RADIX - 1 - k] : 0u;
-    uint32_t x = v;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t y = __shfl_up(x, o);
-      if (lane >= o) x += y;
-    }
-    if (lane == 63) s_w[wave] = x;
-    __syncthreads();
-    uint32_t pre = 0u;
-    for (int w = 0; w < wave; ++w) pre += s_w[w];
-    if (k < RADIX) s_cur[RADIX - 1 - k] = pre + x - v;
-  }
-  __syncthreads();
-  for (int base = 0; base < total; base += QUEUE_BLOCK) {
-    const int t = base + (int)threadIdx.x;
-    const bool valid = t < total;
-    const uint32_t d = valid ? bucket_of(t) : 0u;
-    const uint64_t peers = match_digit(d, 8, __ballot(valid));
-    const int leader = __ffsll((long long)peers) - 1;
-    uint32_t first = 0u;
-    if (valid && lane == leader) first = atomicAdd(&s_cur[d], (uint32_t)__popcll(peers));
-    first = __shfl(first, leader < 0 ? 0 : leader);
-    if (valid) queue[first + (uint32_t)__popcll(peers & lanemask_lt())] = (uint32_t)t;
-  }
+  order_tiles<QUEUE_BLOCK>(tile_cost, hdr[HDR_COSTS] != 0u, total, queue, s_cnt, s_cur, s_w);
 }
 
-void launch_queue_order(const Plan &p, const Workspace &ws, int lpt, hipStream_t s) {
-  if (lpt)
-    hipLaunchKernelGGL(k_queue_order, dim3(1), dim3(QUEUE_BLOCK), 0, s, ws.ranges, ws.tile_cost, ws.hdr,
-                       p.total_tiles, ws.queue);
+void launch_queue_order(const Workspace &ws, int total_tiles, hipStream_t s) {
+  if (total_tiles > 0)
+    hipLaunchKernelGGL(k_queue_order, dim3(1), dim3(QUEUE_BLOCK), 0, s, ws.tile_cost, ws.hdr, total_tiles,
+                       ws.queue);
 }
 
 }  // namespace gsr

@@ -473,10 +473,10 @@ def test_batched_views_equal_separate_calls(gsr_lib):
 
 
 def test_longest_first_order_equals_index_order(gsr_lib):
-    """The persistent rasteriser's longest-first tile order (list lengths on a
-    fresh workspace, then the durations the previous fused step recorded)
+    """The persistent rasteriser's longest-first tile order (index order on a
+    fresh workspace, then by the durations the previous fused step recorded)
     gives the index order's images exactly and its loss and gradients up to
-    the order of the FP64 additions, on a graph over many views."""
+    the order of the FP64 additions, over many views."""
     gsr = gsr_lib
     sc = W.room_scene(20000, seed=5)
     base = W.camera_tum_coarse()
