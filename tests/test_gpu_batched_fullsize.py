@@ -80,6 +80,15 @@ def _check_view(lists, out, scene, cams, sizes, v, n_tiles=12, n_px_tiles=4):
     H.assert_images_close(got, o, done=o["done"], max_ambiguous=0.03)
 
 
+def _loss_rtol(sizes):
+    """The loss is a float32 sum of one partial per tile, added by atomics in
+    whatever order the tiles finish (and per view in the separate calls):
+    two such sums differ by about sqrt(tiles) float32 roundings of the total;
+    six times that bounds them."""
+    tiles = sum(((w + 15) // 16) * ((h + 15) // 16) for w, h in sizes)
+    return 6.0 * np.sqrt(tiles) * 2.0 ** -24
+
+
 def _per_view_calls(gsr, g, cams, sizes, cfg_acc, t_rgb, t_d, grads):
     """One fused call per view, adding into the same gradients and loss (one
     renderer per resolution, reused view after view)."""
@@ -125,7 +134,7 @@ def test_sixteen_keyframes_one_launch(gsr_lib):
     print("CASE 16 per-keyframe fused calls", flush=True)
     ref = {k: torch.zeros_like(t) for k, t in grads.items()}
     loss_ref = _per_view_calls(gsr, g, cams, sizes, gsr.Config(), t_rgb, t_d, ref)
-    assert abs(loss.item() - loss_ref.item()) <= 1e-5 * loss_ref.item(), (loss.item(), loss_ref.item())
+    assert abs(loss.item() - loss_ref.item()) <= _loss_rtol(sizes) * loss_ref.item(), (loss.item(), loss_ref.item())
     for k in ref:
         H.assert_close_scaled(got[k], ref[k].cpu().numpy(), what=k)
 
@@ -166,7 +175,7 @@ def test_pose_hypotheses_one_launch(gsr_lib):
     print("CASE 72 per-pose fused calls", flush=True)
     ref = {"d_pose": torch.zeros(len(cams), 6, device="cuda")}
     loss_ref = _per_view_calls(gsr, g, cams, sizes, gsr.Config(flags=gsr.GSR_POSE_GRAD), t_rgb, t_d, ref)
-    assert abs(loss.item() - loss_ref.item()) <= 1e-5 * loss_ref.item(), (loss.item(), loss_ref.item())
+    assert abs(loss.item() - loss_ref.item()) <= _loss_rtol(sizes) * loss_ref.item(), (loss.item(), loss_ref.item())
     want = ref["d_pose"].cpu().numpy()
     assert np.abs(want).max() > 0
     for v in range(len(cams)):
