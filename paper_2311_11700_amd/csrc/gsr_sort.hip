@@ -56,6 +56,13 @@ void launch_reset_header(const Workspace &ws, hipStream_t s) {
   hipLaunchKernelGGL(k_reset_header, dim3(1), dim3(64), 0, s, ws.hdr);
 }
 
+// LDS writes of this wavefront visible to its other lanes.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ----------------------------------------------------------------- block scan
 
 template <typename T>
@@ -478,6 +485,13 @@ __global__ __launch_bounds__(BLOCK) void k_scan_down(const uint32_t *__restrict_
 // the word(s).  The block also counts the first radix pass's digits of its
 // tile.  Global loads come in two dependent rounds per staged chunk of
 // records instead of per pair.
+//
+// A wavefront takes 64 consecutive pairs [w, w + 64).  Staged records are
+// consecutive and each holds at least one pair, so the record of pair p is
+// the one holding pair w (the number of records starting at or before w,
+// less one: ballots over the staged offsets) plus the number of records that
+// start in (w, p] (flagged in LDS, counted with a ballot): a few LDS round
+// trips per 64 pairs instead of a binary search per pair.
 __global__ __launch_bounds__(BLOCK) void k_emit_pairs(const uint32_t *__restrict__ order,
                                                       const uint32_t *__restrict__ off,
                                                       const uint4 *__restrict__ tinfo,
@@ -497,11 +511,13 @@ __global__ __launch_bounds__(BLOCK) void k_emit_pairs(const uint32_t *__restrict
   __shared__ Support s_sp[BLOCK];
   __shared__ float4 s_cb[BLOCK];
   __shared__ uint32_t s_cnt[RADIX];
+  __shared__ uint32_t s_start[BLOCK / 64][64];  // per wavefront: a staged record starts at pair w + i
   const uint32_t n = sort_count(n_dev, 0u, cap);
   const uint32_t n_rec = (uint32_t)*n_vis;  // depth-ordered records
   const uint32_t ntiles = (n + STILE - 1) / STILE;
   const uint32_t mask0 = (1u << nbits0) - 1u;
   const int t = threadIdx.x;
+  const int lane = t & 63, wv = t >> 6;
   for (uint32_t T = blockIdx.x; T < ntiles; T += gridDim.x) {
     const uint32_t p0 = T * STILE;
     const uint32_t p1 = p0 + STILE < n ? p0 + STILE : n;
@@ -527,16 +543,26 @@ __global__ __launch_bounds__(BLOCK) void k_emit_pairs(const uint32_t *__restrict
       const uint32_t q0 = s_off[0] > p0 ? s_off[0] : p0;
       const uint32_t q1 = s_off[nr] < p1 ? s_off[nr] : p1;
       for (uint32_t base = q0; base < q1; base += BLOCK) {
-        const uint32_t p = base + t;
+        const uint32_t w0 = base + 64u * (uint32_t)wv;  // this wavefront's first pair
+        const uint32_t p = w0 + (uint32_t)lane;
         const bool valid = p < q1;
+        s_start[wv][lane] = 0u;
+        wave_lds_sync();
+        uint32_t upto = 0u;  // staged records starting at or before w0
+        for (uint32_t k = 0; k < nr; k += 64u) {
+          const uint32_t r = k + (uint32_t)lane;
+          const bool in = r < nr;
+          const uint32_t o = in ? s_off[r] : 0xFFFFFFFFu;
+          upto += (uint32_t)__popcll(__ballot(in && o <= w0));
+          if (in && o > w0 && o - w0 < 64u) s_start[wv][o - w0] = 1u;
+        }
+        wave_lds_sync();
+        const bool starts_here = s_start[wv][lane] != 0u;
+        const uint64_t starts = __ballot(starts_here);
+        // (w0 >= q0 >= s_off[0], so upto >= 1.)
+        const uint32_t a = upto - 1u + (uint32_t)__popcll(starts & lanemask_lt()) + (starts_here ? 1u : 0u);
         uint32_t tile = 0u;
         if (valid) {
-          uint32_t a = 0u, z = nr - 1u;  // largest staged record with s_off <= p
-          while (a < z) {
-            const uint32_t mid = a + (z - a + 1u) / 2u;
-            if (s_off[mid] <= p) a = mid;
-            else z = mid - 1u;
-          }
           const uint32_t j = p - s_off[a];
           const uint4 ti = s_ti[a];
           const int TX = (int)(ti.y & 0x7FFFFFFFu);
