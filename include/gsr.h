@@ -140,7 +140,8 @@ typedef struct {
 typedef struct {
   int32_t blocks_per_cu;   /* persistent rasteriser: resident blocks per CU (1..8) */
   int32_t tiles_per_pop;   /* tiles a block takes from the work queue at a time (1..8) */
-  int32_t lpt_order;       /* 1: process tiles longest-list first */
+  int32_t lpt_order;       /* 1: process tiles longest first, by the durations the previous fused step on
+                              the workspace recorded (index order until one has); 0: index order */
   int32_t _reserved;
 } gsr_tuning;
 
