@@ -164,7 +164,7 @@ struct Plan {
 };
 
 struct Tuning {
-  int blocks_per_cu = 2;
+  int blocks_per_cu = 4;  // four blocks fit a CU (LDS): every resident slot busy
   int tiles_per_pop = 1;
   int lpt_order = 1;
 };

@@ -690,7 +690,7 @@ void launch_tile_ranges(const Plan &p, const Workspace &ws, hipStream_t s) {
                      n_dev, (uint32_t)p.capacity, (uint32_t)p.total_tiles, ws.pack_shift, ws.ranges);
 }
 
-// ------------------------------------------------------- work order (LPT)
+// ------------------------------------------------------- work order
 
 // The rasteriser's work order as a kernel of its own (one block): used where
 // the projection does not write it (no Gaussians; the autotuner's trials).

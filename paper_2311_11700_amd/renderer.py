@@ -371,7 +371,7 @@ class Renderer:
         self._check(self.lib.gsr_get_tuning(self.ctx, ctypes.byref(t)))
         return dict(blocks_per_cu=t.blocks_per_cu, tiles_per_pop=t.tiles_per_pop, lpt_order=t.lpt_order)
 
-    def set_tuning(self, blocks_per_cu=2, tiles_per_pop=1, lpt_order=1):
+    def set_tuning(self, blocks_per_cu=4, tiles_per_pop=1, lpt_order=1):
         t = A.gsr_tuning(blocks_per_cu, tiles_per_pop, lpt_order, 0)
         self._check(self.lib.gsr_set_tuning(self.ctx, ctypes.byref(t)))
 
