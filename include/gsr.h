@@ -142,7 +142,8 @@ typedef struct {
   int32_t tiles_per_pop;   /* tiles a block takes from the work queue at a time (1..8) */
   int32_t lpt_order;       /* 1: process tiles longest first, by the durations the previous fused step on
                               the workspace recorded (index order until one has); 0: index order */
-  int32_t _reserved;
+  int32_t batch;           /* records the fused rasteriser stages in LDS per forward round: 64, 128, 192
+                              or 256 (0: 192); fewer leave room for more resident blocks per CU */
 } gsr_tuning;
 
 gsr_config gsr_default_config(void);
@@ -244,10 +245,12 @@ gsr_status gsr_debug_tiles(gsr_ctx *ctx, void *workspace, const int32_t **tile_r
 /* Tuning of the fused rasteriser. */
 gsr_status gsr_get_tuning(const gsr_ctx *ctx, gsr_tuning *out);
 gsr_status gsr_set_tuning(gsr_ctx *ctx, const gsr_tuning *t);
-/* Time every candidate tuning on this workload (same arguments as
+/* Time candidate tunings on this workload (same arguments as
  * gsr_render_l1_fused; gradients and loss are written by the trial runs, so
- * the caller re-zeroes them afterwards), keep the fastest in the context and
- * return it.  `reps` timed launches per candidate. */
+ * the caller re-zeroes them afterwards): every work order, blocks per CU and
+ * tiles per pop at batch 192, then the other batch sizes at the best of
+ * those; keep the fastest in the context and return it.  `reps` timed
+ * launches per candidate. */
 gsr_status gsr_autotune(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams, int n_views,
                         const gsr_config *cfg, const float *target_rgb, const float *target_depth,
                         const uint8_t *pixel_mask, float w_rgb, float w_depth, void *workspace,

@@ -62,7 +62,7 @@ class gsr_grads(ctypes.Structure):
 
 class gsr_tuning(ctypes.Structure):
     _fields_ = [("blocks_per_cu", ctypes.c_int32), ("tiles_per_pop", ctypes.c_int32),
-                ("lpt_order", ctypes.c_int32), ("_reserved", ctypes.c_int32)]
+                ("lpt_order", ctypes.c_int32), ("batch", ctypes.c_int32)]
 
 
 assert ctypes.sizeof(gsr_camera) == 80

@@ -582,17 +582,20 @@ gsr_status gsr_get_tuning(const gsr_ctx *ctx, gsr_tuning *out) {
   out->blocks_per_cu = ctx->tuning.blocks_per_cu;
   out->tiles_per_pop = ctx->tuning.tiles_per_pop;
   out->lpt_order = ctx->tuning.lpt_order;
-  out->_reserved = 0;
+  out->batch = ctx->tuning.batch;
   return GSR_OK;
 }
 
 gsr_status gsr_set_tuning(gsr_ctx *ctx, const gsr_tuning *t) {
   if (!ctx || !t) return GSR_E_INVALID;
-  if (t->blocks_per_cu < 1 || t->blocks_per_cu > 8 || t->tiles_per_pop < 1 || t->tiles_per_pop > 8)
+  const int batch = t->batch == 0 ? 192 : t->batch;
+  if (t->blocks_per_cu < 1 || t->blocks_per_cu > 8 || t->tiles_per_pop < 1 || t->tiles_per_pop > 8 ||
+      (batch != 64 && batch != 128 && batch != 192 && batch != 256))
     return fail(ctx, GSR_E_INVALID, "tuning out of range");
   ctx->tuning.blocks_per_cu = t->blocks_per_cu;
   ctx->tuning.tiles_per_pop = t->tiles_per_pop;
   ctx->tuning.lpt_order = t->lpt_order ? 1 : 0;
+  ctx->tuning.batch = batch;
   return GSR_OK;
 }
 
@@ -618,6 +621,30 @@ gsr_status gsr_autotune(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *
   const Tuning saved = ctx->tuning;
   Tuning best_t = saved;
   float best_ms = 1e30f;
+  // Mean time of `reps` launches of the rasteriser alone (after one warm-up)
+  // on the lists built above; keeps the fastest tuning.
+  auto trial = [&](const Tuning &t) {
+    float total = 0.f;
+    for (int r = 0; r <= reps && st == GSR_OK; ++r) {
+      launch_fill_u32(ws.hdr + HDR_QUEUE, 0u, 1, s);
+      if (t.lpt_order) launch_queue_order(ws, p.total_tiles, s);
+      launch_fill_f32(reinterpret_cast<float *>(ws.grad2d), 0.f, 2 * p.n_rec * NGRAD2D, s);
+      (void)hipEventRecord(e0, s);
+      launch_render_fused(p, ws, ctx->views_dev, ctx->tile_view_dev, *g, consts(*cfg), target_rgb, target_depth,
+                          pixel_mask, w_rgb, w_depth, nullptr, nullptr, loss, t, ctx->num_cus, s);
+      (void)hipEventRecord(e1, s);
+      st = hip_check(ctx, hipEventSynchronize(e1), "hipEventSynchronize");
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      if (r > 0) total += ms;  // first run is a warm-up
+    }
+    if (st == GSR_OK && total / reps < best_ms) {
+      best_ms = total / reps;
+      best_t = t;
+    }
+  };
+  // Work order, blocks per CU and tiles per pop at the default batch, then
+  // the other batch sizes at the best of those.
   const int bpcs[] = {1, 2, 3, 4, 6, 8};
   const int pops[] = {1, 2, 4};
   for (int lpt = 0; lpt <= 1 && st == GSR_OK; ++lpt)
@@ -627,25 +654,15 @@ gsr_status gsr_autotune(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *
         t.blocks_per_cu = bpc;
         t.tiles_per_pop = pop;
         t.lpt_order = lpt;
-        float total = 0.f;
-        for (int r = 0; r <= reps && st == GSR_OK; ++r) {
-          launch_fill_u32(ws.hdr + HDR_QUEUE, 0u, 1, s);
-          if (lpt) launch_queue_order(ws, p.total_tiles, s);
-          launch_fill_f32(reinterpret_cast<float *>(ws.grad2d), 0.f, 2 * p.n_rec * NGRAD2D, s);
-          (void)hipEventRecord(e0, s);
-          launch_render_fused(p, ws, ctx->views_dev, ctx->tile_view_dev, *g, consts(*cfg), target_rgb, target_depth,
-                              pixel_mask, w_rgb, w_depth, nullptr, nullptr, loss, t, ctx->num_cus, s);
-          (void)hipEventRecord(e1, s);
-          st = hip_check(ctx, hipEventSynchronize(e1), "hipEventSynchronize");
-          float ms = 0.f;
-          (void)hipEventElapsedTime(&ms, e0, e1);
-          if (r > 0) total += ms;  // first run is a warm-up
-        }
-        if (st == GSR_OK && total / reps < best_ms) {
-          best_ms = total / reps;
-          best_t = t;
-        }
+        trial(t);
       }
+  const Tuning grid_best = best_t;
+  for (int batch : {64, 128, 256}) {
+    if (st != GSR_OK) break;
+    Tuning t = grid_best;
+    t.batch = batch;
+    trial(t);
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != GSR_OK) return st;

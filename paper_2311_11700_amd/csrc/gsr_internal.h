@@ -167,6 +167,7 @@ struct Tuning {
   int blocks_per_cu = 4;  // four blocks fit a CU (LDS): every resident slot busy
   int tiles_per_pop = 1;
   int lpt_order = 1;
+  int batch = 192;  // records staged per forward round of the fused rasteriser (64, 128, 192, 256)
 };
 
 // Scalar renderer constants passed by value to kernels.

@@ -18,7 +18,7 @@
 
 namespace gsr {
 
-constexpr int BATCH = 192;  // staged records per round (<= BLOCK)
+constexpr int BATCH = 192;  // staged records per forward round (<= BLOCK; the fused kernel's is tunable)
 constexpr float NEG_HALF_LOG2E = -0.72134752044448170368f;  // -log2(e) / 2
 constexpr float LN2 = 0.69314718055994530942f;
 
@@ -102,7 +102,7 @@ struct FwdState {
 // tile): counts[1] += list entries examined by live pixels (including the
 // entry that stopped a pixel), counts[2] += entries blended.  The render
 // kernels do not count; gsr_work_counts re-walks the lists with counting on.
-template <bool COUNT>
+template <bool COUNT, int NB = BATCH>
 __device__ __forceinline__ void tile_forward(const TileInfo &ti, int64_t n, const float4 *__restrict__ recA,
                                              const float4 *__restrict__ recB,
                                              const float4 *__restrict__ recC,
@@ -122,15 +122,16 @@ __device__ __forceinline__ void tile_forward(const TileInfo &ti, int64_t n, cons
   const float ly = (float)(threadIdx.x >> 4);
   // This thread's list word of the next batch, loaded one batch ahead.
   uint32_t next_id = 0u;
-  if ((int)threadIdx.x < BATCH && ti.range.x + (int)threadIdx.x < ti.range.y) next_id = ids[ti.range.x + threadIdx.x];
-  for (int base = ti.range.x; base < ti.range.y; base += BATCH) {
+  static_assert(NB % 64 == 0 && NB <= BLOCK, "whole wavefronts of staging threads");
+  if ((int)threadIdx.x < NB && ti.range.x + (int)threadIdx.x < ti.range.y) next_id = ids[ti.range.x + threadIdx.x];
+  for (int base = ti.range.x; base < ti.range.y; base += NB) {
     if (__syncthreads_and(amin == __builtin_inff())) break;
     const int pos = base + threadIdx.x;
-    if ((int)threadIdx.x < BATCH && pos < ti.range.y) {
+    if ((int)threadIdx.x < NB && pos < ti.range.y) {
       const uint32_t id = next_id & rc.id_mask;
       if (s_id) s_id[threadIdx.x] = id;
       s_rec[threadIdx.x] = stage_record(id, ti.x0, ti.y0, recA, recB, recC);
-      if (pos + BATCH < ti.range.y) next_id = ids[pos + BATCH];
+      if (pos + NB < ti.range.y) next_id = ids[pos + NB];
     }
     if (staged_lo) *staged_lo = base - ti.range.x;
     __syncthreads();
@@ -138,7 +139,7 @@ __device__ __forceinline__ void tile_forward(const TileInfo &ti, int64_t n, cons
     // the result with selects; the wave leaves the batch once all of its
     // pixels have stopped.  `live` (wave-uniform) holds the lanes still
     // blending.
-    const int cnt = min(BATCH, ti.range.y - base);
+    const int cnt = min(NB, ti.range.y - base);
     uint64_t live = __builtin_amdgcn_ballot_w64(amin != __builtin_inff());
     for (int k = 0; k < cnt && live; ++k) {
       if (COUNT) nev_w += (uint32_t)__popcll(live);
@@ -554,6 +555,7 @@ __device__ __forceinline__ float sgnf(float x) { return (float)((x > 0.f) - (x <
 // forward blend, the L1 loss gradient of every pixel, and the backward walk
 // without leaving the block (per-pixel state stays in registers).  Each
 // tile's duration goes to tile_cost, the next step's longest-first order.
+template <int NB>
 __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void k_render_fused(RasterArgs a, uint32_t *__restrict__ hdr,
                                                         const uint32_t *__restrict__ queue, int total_tiles,
                                                         int tiles_per_pop, const float *__restrict__ t_rgb,
@@ -563,9 +565,9 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
                                                         gsr_images out, float *__restrict__ loss,
                                                         double *__restrict__ grad2d, PixelState ps,
                                                         uint32_t *__restrict__ tile_cost) {
-  __shared__ Staged s_rec[BATCH];
+  __shared__ Staged s_rec[NB];
   __shared__ float s_part[4 * SUB * NMOM];
-  __shared__ uint32_t s_id[BATCH];
+  __shared__ uint32_t s_id[NB];
   __shared__ int s_max;
   __shared__ __align__(16) float s_mA[4 * MA_WAVE];
   __shared__ int s_q;
@@ -583,7 +585,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
       const uint64_t clk0 = wall_clock64();
       FwdState st;
       int staged_lo;
-      tile_forward<false>(ti, a.n, a.recA, a.recB, a.recC, a.ids, a.rc, s_rec, st, nullptr, s_id,
+      tile_forward<false, NB>(ti, a.n, a.recA, a.recB, a.recC, a.ids, a.rc, s_rec, st, nullptr, s_id,
                           &staged_lo);
       BwdIn in{st.T, ti.inside ? st.last : 0, st.zr, 0.f, 0.f, 0.f, 0.f, 0.f};
       float lpx = 0.f;
@@ -720,9 +722,17 @@ void launch_render_fused(const Plan &p, const Workspace &ws, const ViewInfo *vie
   if (grid < 1) grid = 1;
   PixelState ps{ws.T_final, ws.last, nullptr};
   const uint32_t *queue = tun.lpt_order ? ws.queue : nullptr;
-  hipLaunchKernelGGL(k_render_fused, dim3(grid), dim3(BLOCK), 0, s, a, ws.hdr, queue, p.total_tiles,
-                     tun.tiles_per_pop, t_rgb, t_depth, pmask, w_rgb, w_depth, loss_cap, o, loss, ws.grad2d, ps,
-                     ws.tile_cost);
+#define GSR_LAUNCH_FUSED(NB_)                                                                                  \
+  hipLaunchKernelGGL(k_render_fused<NB_>, dim3(grid), dim3(BLOCK), 0, s, a, ws.hdr, queue, p.total_tiles,            \
+                     tun.tiles_per_pop, t_rgb, t_depth, pmask, w_rgb, w_depth, loss_cap, o, loss, ws.grad2d, ps,      \
+                     ws.tile_cost)
+  switch (tun.batch) {
+    case 64: GSR_LAUNCH_FUSED(64); break;
+    case 128: GSR_LAUNCH_FUSED(128); break;
+    case 256: GSR_LAUNCH_FUSED(256); break;
+    default: GSR_LAUNCH_FUSED(192); break;
+  }
+#undef GSR_LAUNCH_FUSED
 }
 
 // Totals of the per-pixel work counters: counts[0] pairs, [1] entries the

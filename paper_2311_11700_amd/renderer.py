@@ -369,10 +369,11 @@ class Renderer:
     def get_tuning(self) -> dict:
         t = A.gsr_tuning()
         self._check(self.lib.gsr_get_tuning(self.ctx, ctypes.byref(t)))
-        return dict(blocks_per_cu=t.blocks_per_cu, tiles_per_pop=t.tiles_per_pop, lpt_order=t.lpt_order)
+        return dict(blocks_per_cu=t.blocks_per_cu, tiles_per_pop=t.tiles_per_pop, lpt_order=t.lpt_order,
+                    batch=t.batch)
 
-    def set_tuning(self, blocks_per_cu=4, tiles_per_pop=1, lpt_order=1):
-        t = A.gsr_tuning(blocks_per_cu, tiles_per_pop, lpt_order, 0)
+    def set_tuning(self, blocks_per_cu=4, tiles_per_pop=1, lpt_order=1, batch=192):
+        t = A.gsr_tuning(blocks_per_cu, tiles_per_pop, lpt_order, batch)
         self._check(self.lib.gsr_set_tuning(self.ctx, ctypes.byref(t)))
 
     def autotune(self, g, cams, cfg, target_rgb, target_depth, pixel_mask=None, w_rgb=1.0, w_depth=0.1,
@@ -390,7 +391,8 @@ class Renderer:
                                           ctypes.byref(cc), _ptr(target_rgb), _ptr(target_depth), _ptr(pixel_mask),
                                           float(w_rgb), float(w_depth), ws, wsb, ctypes.byref(gr), _ptr(loss),
                                           int(reps), ctypes.byref(best), _stream_ptr(stream)))
-        return dict(blocks_per_cu=best.blocks_per_cu, tiles_per_pop=best.tiles_per_pop, lpt_order=best.lpt_order)
+        return dict(blocks_per_cu=best.blocks_per_cu, tiles_per_pop=best.tiles_per_pop, lpt_order=best.lpt_order,
+                    batch=best.batch)
 
 
     def select_reliable(self, g: Gaussians, cam: torch.Tensor, depth_obs: torch.Tensor, width: int, height: int,

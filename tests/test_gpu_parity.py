@@ -472,6 +472,45 @@ def test_batched_views_equal_separate_calls(gsr_lib):
         H.assert_close_scaled(gb[k], acc[k], what=k)
 
 
+def test_batch_sizes_equal(gsr_lib):
+    """Every staged batch size of the fused rasteriser gives the default's
+    images exactly and its loss and gradients up to the order of the FP64
+    additions; other sizes are refused."""
+    gsr = gsr_lib
+    sc = W.room_scene(20000, seed=6)
+    base = W.camera_tum_coarse()
+    cams = [W.perturb_pose(base, [0.015 * v, -0.01 * (v % 2), 0.02 * (v % 3), 0.003 * v, 0.0, -0.002 * v])
+            for v in range(6)]
+    sizes = [(c.width, c.height) for c in cams]
+    t_rgb, t_d, mask = W.random_targets(sizes, seed=10)
+    g = H.gpu_scene(gsr, sc)
+    cams_d = gsr.pack_cameras(cams)
+    args = (H.to_dev(t_rgb), H.to_dev(t_d), H.to_dev(mask, torch.uint8))
+    cfg = gsr.Config(flags=gsr.GSR_GAUSS_GRAD | gsr.GSR_POSE_GRAD | gsr.GSR_GRAD_OVERWRITE)
+    r = gsr.Renderer()
+    r.plan(sc.n, sizes)
+    for bad in (32, 100, 320):
+        with pytest.raises(gsr.GsrError) as e:
+            r.set_tuning(4, 1, 1, bad)
+        assert e.value.status == gsr.GSR_E_INVALID
+    results = {}
+    for batch in (192, 64, 128, 256):
+        r.set_tuning(4, 1, 1, batch)
+        assert r.get_tuning()["batch"] == batch
+        out = r.new_images()
+        loss, grads = r.render_l1_fused(g, cams_d, cfg, *args, out=out)
+        results[batch] = ({k: v.cpu().numpy() for k, v in out.items() if v is not None}, loss.item(),
+                          H.gpu_grads_numpy(grads))
+    img0, loss0, ref = results[192]
+    for batch in (64, 128, 256):
+        img, loss, got = results[batch]
+        for k, v in img0.items():
+            np.testing.assert_array_equal(img[k], v, err_msg=f"batch {batch} {k}")
+        assert abs(loss - loss0) <= 1e-5 * abs(loss0), batch
+        for k in ref:
+            H.assert_close_scaled(got[k], ref[k], what=(batch, k))
+
+
 def test_longest_first_order_equals_index_order(gsr_lib):
     """The persistent rasteriser's longest-first tile order (index order on a
     fresh workspace, then by the durations the previous fused step recorded)
