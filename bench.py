@@ -118,8 +118,9 @@ def run_headline(args, gsr, torch, W):
     cfg = gsr.Config(flags=gsr.GSR_GAUSS_GRAD | gsr.GSR_POSE_GRAD | gsr.GSR_GRAD_OVERWRITE)
     tuning = r.get_tuning()
     if args.tuning:
-        b, p, l = (int(x) for x in args.tuning.split(","))
-        r.set_tuning(blocks_per_cu=b, tiles_per_pop=p, lpt_order=l)
+        vals = [int(x) for x in args.tuning.split(",")]
+        b, p, l = vals[:3]
+        r.set_tuning(blocks_per_cu=b, tiles_per_pop=p, lpt_order=l, batch=vals[3] if len(vals) > 3 else 192)
         tuning = r.get_tuning()
         log("tuning:", tuning)
     elif not args.no_autotune:
@@ -461,7 +462,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tuning", type=str, default=None,
-                    help="blocks_per_cu,tiles_per_pop,lpt_order for the headline (skips its autotune)")
+                    help="blocks_per_cu,tiles_per_pop,lpt_order[,batch] for the headline (skips its autotune)")
     ap.add_argument("--no-extra", action="store_true", help="skip the pose-hypothesis and tracking legs")
     ap.add_argument("--hyp-batches", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
