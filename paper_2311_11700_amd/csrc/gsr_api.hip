@@ -408,8 +408,8 @@ gsr_status gsr_render_backward(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_c
   if (!g_rgb || !grads) return fail(ctx, GSR_E_INVALID, "gsr_render_backward: null gradient argument");
   if (ctx->last_forward_ws != workspace)
     return fail(ctx, GSR_E_STATE, "gsr_render_backward: workspace was not filled by the last forward");
-  if ((cfg->flags & GSR_GAUSS_GRAD) && (!grads->d_mean || !grads->d_log_scale || !grads->d_quat ||
-                                        !grads->d_opacity_logit || !grads->d_rgb))
+  if ((cfg->flags & GSR_GAUSS_GRAD) && g->n > 0 &&
+      (!grads->d_mean || !grads->d_log_scale || !grads->d_quat || !grads->d_opacity_logit || !grads->d_rgb))
     return fail(ctx, GSR_E_INVALID, "GSR_GAUSS_GRAD needs every d_* pointer");
   if ((cfg->flags & GSR_POSE_GRAD) && !grads->d_pose) return fail(ctx, GSR_E_INVALID, "GSR_POSE_GRAD needs d_pose");
   if (grads->d_quat && reinterpret_cast<uintptr_t>(grads->d_quat) % 16)
@@ -458,8 +458,8 @@ static gsr_status fused_checks(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_c
   if (st != GSR_OK) return st;
   if (!t_rgb || !t_depth || !grads) return fail(ctx, GSR_E_INVALID, "fused step: null target or gradient argument");
   if (!(w_rgb >= 0.f) || !(w_depth >= 0.f)) return fail(ctx, GSR_E_INVALID, "loss weights must be >= 0");
-  if ((cfg->flags & GSR_GAUSS_GRAD) && (!grads->d_mean || !grads->d_log_scale || !grads->d_quat ||
-                                        !grads->d_opacity_logit || !grads->d_rgb))
+  if ((cfg->flags & GSR_GAUSS_GRAD) && g->n > 0 &&
+      (!grads->d_mean || !grads->d_log_scale || !grads->d_quat || !grads->d_opacity_logit || !grads->d_rgb))
     return fail(ctx, GSR_E_INVALID, "GSR_GAUSS_GRAD needs every d_* pointer");
   if ((cfg->flags & GSR_POSE_GRAD) && !grads->d_pose) return fail(ctx, GSR_E_INVALID, "GSR_POSE_GRAD needs d_pose");
   if (grads->d_quat && reinterpret_cast<uintptr_t>(grads->d_quat) % 16)

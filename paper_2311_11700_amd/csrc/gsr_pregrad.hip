@@ -303,8 +303,12 @@ __global__ __launch_bounds__(BLOCK) void k_pose_reduce(const double *__restrict_
 void launch_preprocess_backward(const Plan &p, const gsr_gaussians &g, const gsr_camera *cams,
                                 const gsr_config &cfg, const Workspace &ws, const gsr_grads &gr,
                                 hipStream_t s) {
-  if (g.n == 0) return;
   const bool want_pose = (cfg.flags & GSR_POSE_GRAD) && gr.d_pose;
+  if (g.n == 0) {
+    // No Gaussian, no gradient: an overwritten pose gradient is zero.
+    if (want_pose && (cfg.flags & GSR_GRAD_OVERWRITE)) launch_fill_f32(gr.d_pose, 0.f, (int64_t)p.n_views * 6, s);
+    return;
+  }
   PreConstsB pc{cfg.z_near, cfg.lowpass, cfg.cutoff_sigma, cfg.flags, cfg.fov_guard};
   const size_t lds = want_pose ? (size_t)4 * p.n_views * 6 * sizeof(double) : 0;
   hipLaunchKernelGGL(k_preprocess_bwd, dim3(p.n_pose_blocks), dim3(BLOCK), lds, s, g, cams,

@@ -124,6 +124,27 @@ def test_edge_cases(gsr_lib):
     empty = W.random_scene(0, seed=0)
     g = H.split_images(r3.render_forward(H.gpu_scene(gsr, empty), gsr.pack_cameras([cam]), cfg), r3.sizes)[0]
     assert np.all(g["T_final"] == 1.0)
+    # The fused step on the empty scene, longest-first order: there is no
+    # projection launch, so the work order comes from its own kernel (index
+    # order first, then by the durations the first call recorded).  Every
+    # pixel is background (0): the loss is the targets' own L1 over the mask.
+    r3.set_tuning(4, 1, 1, 192)
+    t_rgb, t_d, mask = W.random_targets(r3.sizes, seed=11)
+    P = cam.width * cam.height
+    m = mask.astype(bool)
+    want = float(np.abs(t_rgb.astype(np.float64)).reshape(3, P)[:, m].sum()
+                 + 0.1 * np.abs(t_d.astype(np.float64))[m & (t_d > 0)].sum())
+    grads = r3.new_grads(0)
+    for call, flags in enumerate((gsr.GSR_GAUSS_GRAD | gsr.GSR_POSE_GRAD,
+                                  gsr.GSR_GAUSS_GRAD | gsr.GSR_POSE_GRAD | gsr.GSR_GRAD_OVERWRITE)):
+        out = r3.new_images()
+        grads["d_pose"].fill_(7.0 * call)  # the overwriting call must clear it
+        loss, grads = r3.render_l1_fused(H.gpu_scene(gsr, empty), gsr.pack_cameras([cam]), gsr.Config(flags=flags),
+                                         H.to_dev(t_rgb), H.to_dev(t_d), H.to_dev(mask, torch.uint8), out=out,
+                                         grads=grads)
+        assert abs(loss.item() - want) <= 1e-5 * want, (call, loss.item(), want)
+        assert np.all(out["T_final"].cpu().numpy() == 1.0) and np.all(out["rgb"].cpu().numpy() == 0.0), call
+        assert np.all(grads["d_pose"].cpu().numpy() == 0.0), call
 
 
 def test_single_gaussian_closed_form_on_gpu(gsr_lib):
