@@ -190,7 +190,7 @@ def run_batched(args, gsr, torch, W):
     rb.plan(scene.n, sizes, pair_capacity=int(pairs * 1.25) + 4096)
     cfg = gsr.Config(flags=gsr.GSR_GAUSS_GRAD | gsr.GSR_POSE_GRAD | gsr.GSR_GRAD_OVERWRITE)
     if not args.no_autotune:
-        rb.autotune(g, cams_d, cfg, t_rgb, t_d, None, 1.0, 0.1, reps=1)
+        rb.autotune(g, cams_d, cfg, t_rgb, t_d, None, 1.0, 0.1, reps=2)
     grads = rb.new_grads(scene.n)
     loss = torch.zeros(1, device="cuda")
     stream = torch.cuda.Stream()
@@ -277,7 +277,7 @@ def run_hypotheses(args, gsr, torch, W):
     pairs = rb.pair_count()
     rb.plan(scene.n, sizes, pair_capacity=int(pairs * 1.25) + 4096)
     if not args.no_autotune:
-        rb.autotune(g, cams_d, cfg, t_rgb, t_d, None, 1.0, 0.1, reps=1)
+        rb.autotune(g, cams_d, cfg, t_rgb, t_d, None, 1.0, 0.1, reps=2)
     grads = {"d_pose": torch.zeros(len(cams), 6, device="cuda")}
     loss = torch.zeros(1, device="cuda")
     stream = torch.cuda.Stream()
