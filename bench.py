@@ -50,10 +50,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def measured_traffic():
+def measured_traffic(batch):
     """HBM bytes per k_render_fused launch on the headline workload from the
     committed rocprofv3 FETCH_SIZE / WRITE_SIZE passes (scaled by the copy
-    calibration), or None when the kernel sources changed since."""
+    calibration), or None when the kernel sources changed since or the
+    counters were taken on another staged batch size (another instantiation
+    of the kernel) than `batch`."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "k_render_fused_traffic.json")
     try:
@@ -61,7 +63,7 @@ def measured_traffic():
         src = b"".join(open(os.path.join(ROOT, f), "rb").read() for f in rec["sources"])
     except (OSError, ValueError, KeyError):
         return None
-    if hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
+    if hashlib.sha256(src).hexdigest() != rec.get("source_sha256") or rec.get("batch") != batch:
         return None
     return rec
 
@@ -163,7 +165,7 @@ def run_headline(args, gsr, torch, W):
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_FP32_TFLOPS, 1),
             "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
             "kernel": "k_render_fused", "kernel_ms": round(raster_ms, 4), "flop_per_launch": int(flops)}
-    tr = measured_traffic()
+    tr = measured_traffic(tuning.get("batch"))
     if tr is not None:
         # bytes per launch, HBM read + written (rocprofv3 counters, copy-calibrated)
         roof["traffic"] = int(tr["bytes_total"])

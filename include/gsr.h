@@ -249,7 +249,8 @@ gsr_status gsr_set_tuning(gsr_ctx *ctx, const gsr_tuning *t);
  * gsr_render_l1_fused; gradients and loss are written by the trial runs, so
  * the caller re-zeroes them afterwards): every work order, blocks per CU and
  * tiles per pop at batch 192, then the other batch sizes at the best of
- * those; keep the fastest in the context and return it.  `reps` timed
+ * those (one of them only if 2 % faster); keep the fastest in the context
+ * and return it.  `reps` timed
  * launches per candidate. */
 gsr_status gsr_autotune(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams, int n_views,
                         const gsr_config *cfg, const float *target_rgb, const float *target_depth,
