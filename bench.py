@@ -59,9 +59,9 @@ def measured_traffic(batch):
     import hashlib
     path = os.path.join(ROOT, "profiles", "k_render_fused_traffic.json")
     try:
-        rec = json.load(open(path))
+        rec = json.load(open(path))["records"][str(batch)]
         src = b"".join(open(os.path.join(ROOT, f), "rb").read() for f in rec["sources"])
-    except (OSError, ValueError, KeyError):
+    except (OSError, ValueError, KeyError, TypeError):
         return None
     if hashlib.sha256(src).hexdigest() != rec.get("source_sha256") or rec.get("batch") != batch:
         return None
