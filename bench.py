@@ -8,8 +8,11 @@ whole fused step (projection, depth sort, pair emission, tile sort, ranges,
 persistent forward/L1/backward rasteriser, chain to parameters and pose),
 plus zeroing the gradient buffers.  Also reported: per-stage times and the
 roofline of the dominant kernel (from an eager, event-timed loop of the same
-step), the batched 16-keyframe launch against 16 per-frame launches, and the
-CPU oracle timed on a bounded sample of the same workload.
+step), the backward composite's algorithmic bytes against the copy-measured
+achievable HBM bandwidth, the batched 16-keyframe launch against 16
+per-frame launches, 72 pose hypotheses in one launch against 72 calls, the
+coarse-to-fine tracking driver, and the CPU oracle timed on a bounded sample
+of the same workloads (one process and forked worker processes).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -173,8 +176,74 @@ def run_headline(args, gsr, torch, W):
         roof["traffic_written"] = int(tr["bytes_written"])
         roof["traffic_source"] = tr["summary"]
     px = cam.width * cam.height
+    roof["a7_backward_hbm"] = backward_hbm(args, gsr, torch, r, g, cams_d, cam, t_rgb, t_d, raster_ms)
+    if tr is not None and tr.get("valu_busy") is not None:
+        roof["valu_busy"] = tr["valu_busy"]
     return dict(ms=ms, wall=wall, eager_ms=eager_ms, stages=stages, work=work, roof=roof, tuning=tuning,
                 mpx=px / (ms * 1e-3) / 1e6, pairs=pairs)
+
+
+def achievable_hbm_gbs(torch, mib=1024, reps=10):
+    """Achievable HBM bandwidth: a device-to-device copy of `mib` MiB (read +
+    write bytes over its event-timed duration, best of `reps`)."""
+    n = (mib << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * (mib << 20) / (best * 1e-3) / 1e9
+
+
+def visited_pairs(torch, last, width, height):
+    """P_v: the sum over tiles of the tile's longest walked list prefix (the
+    largest `last` of its pixels)."""
+    TX, TY = (width + 15) // 16, (height + 15) // 16
+    img = torch.zeros(TY * 16, TX * 16, dtype=torch.int32, device=last.device)
+    img[:height, :width] = last.view(height, width)
+    return int(img.view(TY, 16, TX, 16).amax(dim=(1, 3)).to(torch.int64).sum().item())
+
+
+def backward_hbm(args, gsr, torch, r, g, cams_d, cam, t_rgb, t_d, fused_ms):
+    """The backward composite (A7) against HBM bandwidth: algorithmic bytes
+    P_v x (4 B list id + 40 B record + 40 B gradient atomics) + pixels x
+    (8 B saved state + 16 B upstream gradient), over the standalone backward
+    kernel's time (forward, L1 gradient and backward as separate calls, the
+    backward stage event-timed) and over the fused kernel's time, as
+    fractions of the copy-measured achievable bandwidth."""
+    px = cam.width * cam.height
+    cfg = gsr.Config()
+    out = r.new_images()
+    r.set_profiling(True)
+    for it in range(3 + args.steps):
+        if it == 3:
+            r.stage_times()
+        r.render_forward(g, cams_d, cfg, out=out, check=False)
+        _, gC, gD = r.l1_loss_grad(out["rgb"], out["depth"], t_rgb, t_d, None, 1.0, 0.1)
+        r.render_backward(g, cams_d, cfg, gC, gD, None)
+    st = r.stage_times()
+    r.set_profiling(False)
+    r.check_overflow()
+    bwd_ms = st["raster_bwd"] / max(1, st["calls"])
+    pv = visited_pairs(torch, out["last"], cam.width, cam.height)
+    bytes_alg = pv * 84 + px * 24
+    ach = achievable_hbm_gbs(torch)
+    gbs_b = bytes_alg / (bwd_ms * 1e-3) / 1e9
+    gbs_f = bytes_alg / (fused_ms * 1e-3) / 1e9
+    return {"kernel": "k_render_bwd", "visited_pairs": pv, "bytes_alg": int(bytes_alg),
+            "kernel_ms": round(bwd_ms, 4), "achieved_gbs": round(gbs_b, 1), "achievable_gbs": round(ach, 1),
+            "frac_of_achievable": round(gbs_b / ach, 4), "frac_of_peak": round(gbs_b / 8000.0, 4),
+            "fused_kernel_gbs": round(gbs_f, 1), "fused_frac_of_achievable": round(gbs_f / ach, 4),
+            "target_frac": 0.5, "met": bool(gbs_b / ach >= 0.5)}
 
 
 def run_batched(args, gsr, torch, W):
@@ -217,7 +286,10 @@ def run_batched(args, gsr, torch, W):
         r.plan(scene.n, [sizes[v]])
         tr = t_rgb[3 * offs[v]:3 * offs[v] + 3 * w * h]
         td = t_d[offs[v]:offs[v] + w * h]
-        per.append((r, gsr.pack_cameras([c]), tr, td))
+        cd = gsr.pack_cameras([c])
+        if not args.no_autotune:  # each per-frame renderer tuned on its own view
+            r.autotune(g, cd, cfg, tr, td, None, 1.0, 0.1, reps=2)
+        per.append((r, cd, tr, td))
     pose = torch.zeros(1, 6, device="cuda")
     gr1 = dict(grads)
     cfg_acc = gsr.Config()  # the frames add into the same buffers
@@ -306,11 +378,16 @@ def run_hypotheses(args, gsr, torch, W):
     for w, hh in sizes:
         offs.append(po)
         po += w * hh
+    per_cams = [gsr.pack_cameras([c]) for c in cams]
     for key, cam in (("half", base_half), ("full", base_full)):
         r = gsr.Renderer(0)
         r.plan(scene.n, [(cam.width, cam.height)])
+        if not args.no_autotune:  # tuned on the first hypothesis of its resolution
+            v = next(k for k, (w, hh) in enumerate(sizes) if (w, hh) == (cam.width, cam.height))
+            w, hh = sizes[v]
+            r.autotune(g, per_cams[v], cfg_acc, t_rgb[3 * offs[v]:3 * (offs[v] + w * hh)],
+                       t_d[offs[v]:offs[v] + w * hh], None, 1.0, 0.1, reps=2)
         rs[(cam.width, cam.height)] = r
-    per_cams = [gsr.pack_cameras([c]) for c in cams]
     gr1 = {"d_pose": None}
 
     def step():
@@ -394,65 +471,122 @@ def run_tracking(args, gsr, torch, W):
             "rot_err_deg": [round(ang(E0[:3, :3]), 3), round(ang(E1[:3, :3]), 3)]}
 
 
-def cpu_baseline(args, W, n_tiles=None):
-    """The FP64 oracle on a bounded sample of the headline workload: projection
-    and binning of all 300k Gaussians (charged pro rata to the sampled tiles)
-    and forward + L1 + backward of a spread of sampled tiles, one thread."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+# State of the CPU-baseline sample, inherited by forked worker processes.
+_CPU = {}
+
+
+def _oracle_tiles(tiles):
+    """Forward + L1 + backward of `tiles` of the prepared workload with the
+    FP64 oracle, one thread; returns the pixels done."""
     import numpy as np
-    try:
-        from threadpoolctl import threadpool_limits
-    except Exception:  # pragma: no cover
-        threadpool_limits = None
+    from threadpoolctl import threadpool_limits
     import oracle as O
-    ctx = threadpool_limits(1) if threadpool_limits else None
-    try:
-        scene, cam = W.room_scene(300_000, seed=0), W.camera_replica()
-        cfg = O.Config().as_f32()
-        t0 = time.perf_counter()
-        proj = O.project(scene, cam, cfg)
-        starts, gauss = O.tile_lists(proj)
-        t_geo = time.perf_counter() - t0
-        TX, TY = proj["TX"], proj["TY"]
-        T = TX * TY
-        rng = np.random.default_rng(0)
-        order = rng.permutation(T)
-        t_rgb, t_d, _ = W.random_targets([(cam.width, cam.height)], seed=1)
-        t_rgb = t_rgb.reshape(3, cam.height, cam.width)
-        t_d = t_d.reshape(cam.height, cam.width)
-        t1 = time.perf_counter()
-        px = 0
-        done_tiles = 0
-        budget = args.cpu_seconds
-        for tile in order[: (n_tiles or T)]:
-            pxs, pys = O.splat._tile_pixels(tile, TX, cam.width, cam.height)
+    st = _CPU
+    proj, (starts, gauss), cfg, cam = st["proj"], st["lists"], st["cfg"], st["cam"]
+    px = 0
+    with threadpool_limits(1):
+        for tile in tiles:
+            pxs, pys = O.splat._tile_pixels(tile, proj["TX"], cam.width, cam.height)
             lst = gauss[starts[tile]:starts[tile + 1]]
             rr = O.splat._blend_tile(proj, lst, pxs, pys, cfg)
-            C = rr["C"].T
-            e = C - t_rgb[:, pys, pxs]
-            ed = rr["D"] - t_d[pys, pxs]
-            gC = np.sign(e).T
-            gD = 0.1 * np.sign(ed) * (t_d[pys, pxs] > 0)
-            O.splat._blend_tile_backward(proj, lst, pxs, pys, cfg, rr, gC, gD, np.zeros_like(gD))
+            if st["backward"]:
+                e = rr["C"].T - st["t_rgb"][:, pys, pxs]
+                ed = rr["D"] - st["t_d"][pys, pxs]
+                gC = np.sign(e).T
+                gD = 0.1 * np.sign(ed) * (st["t_d"][pys, pxs] > 0)
+                O.splat._blend_tile_backward(proj, lst, pxs, pys, cfg, rr, gC, gD, np.zeros_like(gD))
             px += pxs.size
-            done_tiles += 1
-            if time.perf_counter() - t1 > budget:
-                break
-        t_tiles = time.perf_counter() - t1
-        # Per-Gaussian chain for the whole frame, charged pro rata as well.
-        t2 = time.perf_counter()
-        O.backward_params(proj, np.zeros((proj["n"], 10)), cfg)
-        t_chain = time.perf_counter() - t2
-        frac = done_tiles / T
-        total = t_tiles + (t_geo + t_chain) * frac
-        return {"value": round(px / total / 1e6, 6), "unit": "Mpixel/s", "cores": 1, "kind": "oracle",
-                "sample": (f"{done_tiles} of {T} tiles ({px} px) of the 300k-Gaussian 1200x680 workload, "
-                           f"forward + L1 + backward in FP64; projection/binning ({t_geo:.1f} s) and the "
-                           f"per-Gaussian chain ({t_chain:.1f} s) of the full frame charged pro rata"),
-                "cpu": platform.processor() or platform.machine(), "host_cpus": os.cpu_count(),
-                "seconds": round(total, 2)}
-    finally:
-        if ctx is not None:
-            ctx.__exit__(None, None, None)
+    return px
+
+
+def _oracle_frame(W, scene, cam, backward, budget_s, workers, seed=0):
+    """Full-frame oracle time estimated from a sample: projection and tile
+    lists of all Gaussians, then tiles in a seeded random order until
+    `budget_s`, one process (and the same number of tiles per worker across
+    `workers` forked processes), then the per-Gaussian chain of the whole
+    frame (backward only).  Returns per-mode seconds for the whole frame."""
+    import multiprocessing as mp
+
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    import oracle as O
+    cfg = O.Config().as_f32()
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        proj = O.project(scene, cam, cfg)
+        lists = O.tile_lists(proj)
+        t_geo = time.perf_counter() - t0
+    T = proj["TX"] * proj["TY"]
+    t_rgb, t_d, _ = W.random_targets([(cam.width, cam.height)], seed=1)
+    _CPU.update(proj=proj, lists=lists, cfg=cfg, cam=cam, backward=backward,
+                t_rgb=t_rgb.reshape(3, cam.height, cam.width), t_d=t_d.reshape(cam.height, cam.width))
+    order = np.random.default_rng(seed).permutation(T)
+    # one process: tiles in chunks of 8 until the budget
+    t1 = time.perf_counter()
+    done = 0
+    while done < T and time.perf_counter() - t1 < budget_s:
+        _oracle_tiles(order[done:done + 8])
+        done += min(8, T - done)
+    t_one = time.perf_counter() - t1
+    t_chain = 0.0
+    if backward:
+        with threadpool_limits(1):
+            t2 = time.perf_counter()
+            O.backward_params(proj, np.zeros((proj["n"], 10)), cfg)
+            t_chain = time.perf_counter() - t2
+    one = t_geo + t_chain + t_one * T / done
+    # `workers` processes: the next (workers x done) tiles, one chunk each
+    multi, m_done = None, 0
+    if workers > 1:
+        m_tiles = np.concatenate([order[done:], order[:done]])[: min(T, workers * done)]
+        chunks = [c for c in np.array_split(m_tiles, workers * 4) if c.size]
+        with mp.get_context("fork").Pool(workers) as pool:
+            t3 = time.perf_counter()
+            pool.map(_oracle_tiles, chunks, chunksize=1)
+            t_multi = time.perf_counter() - t3
+        m_done = int(m_tiles.size)
+        multi = t_geo + t_chain + t_multi * T / m_done
+    _CPU.clear()
+    return dict(tiles=T, sample_one=done, sample_multi=m_done, t_geo=t_geo, t_chain=t_chain, one=one, multi=multi)
+
+
+def cpu_baseline(args, W):
+    """The FP64 oracle as it stands on the host cores: the 300k-Gaussian
+    1200x680 step (forward + L1 + backward) and the 2 000-Gaussian 160x120
+    forward, each timed in one process and in `workers` forked processes over
+    tile chunks, on a bounded sample of tiles scaled to the whole frame."""
+    workers = max(1, min(16, os.cpu_count() or 1))
+    budget = args.cpu_seconds
+    scene, cam = W.room_scene(300_000, seed=0), W.camera_replica()
+    c2 = _oracle_frame(W, scene, cam, True, 0.35 * budget, workers)
+    px2 = cam.width * cam.height
+    small, cam1 = W.random_scene(2000, seed=0), W.camera_small()
+    c1 = _oracle_frame(W, small, cam1, False, 0.1 * budget, workers)
+    px1 = cam1.width * cam1.height
+    best = c2["multi"] if c2["multi"] else c2["one"]
+    return {"value": round(px2 / best / 1e6, 6), "unit": "Mpixel/s", "cores": workers, "kind": "oracle",
+            "sample": (f"300k-Gaussian 1200x680 step (forward + L1 + backward, FP64): {c2['sample_one']} of "
+                       f"{c2['tiles']} tiles in one process, {c2['sample_multi']} over {workers} processes; "
+                       f"projection and tile lists ({c2['t_geo']:.1f} s) and the per-Gaussian chain "
+                       f"({c2['t_chain']:.1f} s) of the whole frame added once; scaled to the whole frame"),
+            "value_1core": round(px2 / c2["one"] / 1e6, 6),
+            "frame_seconds": {"multi": round(c2["multi"], 2) if c2["multi"] else None, "one": round(c2["one"], 2)},
+            "small_forward": {"workload": "2 000 Gaussians, 160x120, forward only",
+                              "mpx_s_multi": round(px1 / c1["multi"] / 1e6, 6) if c1["multi"] else None,
+                              "mpx_s_1core": round(px1 / c1["one"] / 1e6, 6),
+                              "sample_tiles": [c1["sample_one"], c1["sample_multi"], c1["tiles"]]},
+            "cpu": cpu_model(), "host_cpus": os.cpu_count()}
 
 
 def main():
@@ -466,7 +600,7 @@ def main():
     ap.add_argument("--tuning", type=str, default=None,
                     help="blocks_per_cu,tiles_per_pop,lpt_order[,batch] for the headline (skips its autotune)")
     ap.add_argument("--no-extra", action="store_true", help="skip the pose-hypothesis and tracking legs")
-    ap.add_argument("--hyp-batches", type=int, default=100)
+    ap.add_argument("--hyp-batches", type=int, default=200)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="also run a plain device copy of this many MB (calibrates HBM byte counters)")
@@ -476,10 +610,19 @@ def main():
               "multi-GPU path to time", file=sys.stderr)
         sys.exit(2)
 
+    import workloads as W
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        # The oracle on the host cores, in forked worker processes: before
+        # this process initialises the GPU.
+        log("cpu baseline (oracle sample)")
+        cpu = cpu_baseline(args, W)
+        log("cpu:", cpu)
+
     import torch
 
     import paper_2311_11700_amd as gsr
-    import workloads as W
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -508,11 +651,6 @@ def main():
         log("tracking: 150k Gaussians, 640x480")
         trk = run_tracking(args, gsr, torch, W)
         log("tracking:", trk)
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle sample)")
-        cpu = cpu_baseline(args, W)
-        log("cpu:", cpu)
     line = {
         "metric": METRIC,
         "value": round(h["mpx"], 2),

@@ -166,21 +166,32 @@ gsr_status gsr_plan(gsr_ctx *ctx, int64_t n, int n_views, const int32_t *wh_host
 /* Forward render (Eq. 3-5) of every planned view.  `workspace` (DEVICE,
  * >= workspace_bytes, 256-byte aligned) keeps the projected Gaussians, the
  * sorted tile lists and per-pixel state for gsr_render_backward.
- * Synchronises the stream once at the end to check the pair capacity:
- * on GSR_E_CAPACITY the outputs are undefined and gsr_required_pairs()
- * tells the capacity to plan for. */
+ * Asynchronous: a pair-capacity overflow is recorded on the device and
+ * reported by gsr_check_overflow() (with gsr_required_pairs() telling the
+ * capacity to plan for); after an overflow the outputs are undefined. */
 gsr_status gsr_render_forward(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams,
                               int n_views, const gsr_config *cfg, void *workspace,
                               size_t workspace_bytes, const gsr_images *out, gsr_stream stream);
 
-/* Backward of the last forward on this workspace: upstream gradients g_rgb
+/* Generation of the last successful gsr_render_forward on this context: 1,
+ * 2, ... in call order (0 before the first).  A caller that keeps several
+ * forwards in flight (an autograd graph) records it after each forward and
+ * passes it to gsr_render_backward. */
+int64_t gsr_forward_generation(const gsr_ctx *ctx);
+
+/* Backward of a forward on this workspace: upstream gradients g_rgb
  * [3 * sum HW], g_depth [sum HW], g_T (nullable) [sum HW] w.r.t. the colour,
- * depth and final-transmittance outputs.  Accumulates into `grads`
- * according to cfg->flags.  Asynchronous. */
+ * depth and final-transmittance outputs.  forward_generation must be the
+ * gsr_forward_generation() value of the forward whose state the workspace
+ * holds, i.e. of the last forward on this context, on this workspace, with no
+ * fused step, autotune or plan since; otherwise GSR_E_STATE (the state of an
+ * earlier forward has been overwritten).  Accumulates into `grads` according
+ * to cfg->flags.  Asynchronous. */
 gsr_status gsr_render_backward(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams,
                                int n_views, const gsr_config *cfg, void *workspace,
-                               size_t workspace_bytes, const float *g_rgb, const float *g_depth,
-                               const float *g_T, const gsr_grads *grads, gsr_stream stream);
+                               size_t workspace_bytes, int64_t forward_generation, const float *g_rgb,
+                               const float *g_depth, const float *g_T, const gsr_grads *grads,
+                               gsr_stream stream);
 
 /* Weighted L1 loss (Eq. 6 / Eq. 10) and its gradient w.r.t. the rendered
  * images: loss = w_rgb sum m |C - C*| + w_depth sum m [D* > 0] |D - D*| over
@@ -285,6 +296,40 @@ gsr_status gsr_loss_median(gsr_ctx *ctx, const float *px_loss, const uint8_t *pi
 gsr_status gsr_select_reliable(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cam,
                                const float *depth_obs, int width, int height, float eps, float z_near,
                                uint8_t *mask_out, gsr_stream stream);
+
+/* Camera poses around the renderer.  The renderer's d_pose is the gradient
+ * w.r.t. a left perturbation T <- Exp(xi) T at the rendered pose (the
+ * gradient of Eq. 11, se(3) ordered (rho, phi)).  These calls build the
+ * cameras from two parameterisations and chain that gradient to them; one
+ * thread per view, FP64 inside, asynchronous; no plan needed.  DEVICE arrays;
+ * cams_out may alias cams_in.
+ *
+ * gsr_pose_apply: cams_out[v] = cams_in[v] with the pose Exp(xi_v) T_v, T_v
+ * the pose (R, t) of cams_in[v], xi [n_views][6] = (rho, phi); Exp is the
+ * SE(3) exponential [[R(phi), V(phi) rho], [0, 1]] (Rodrigues' formula).
+ * gsr_pose_xi_grad: d_xi = J_l(xi)^T d_pose (written, [n_views][6]), the
+ * gradient in xi of a loss of Exp(xi) T0 whose left-perturbation gradient at
+ * Exp(xi) T0 is d_pose; J_l is the SE(3) left Jacobian. */
+gsr_status gsr_pose_apply(gsr_ctx *ctx, int n_views, const float *xi, const gsr_camera *cams_in,
+                          gsr_camera *cams_out, gsr_stream stream);
+gsr_status gsr_pose_xi_grad(gsr_ctx *ctx, int n_views, const float *xi, const float *d_pose, float *d_xi,
+                            gsr_stream stream);
+
+/* The paper's pose parameters (supplement Sec. A: a quaternion q and a
+ * translation t per pose, R from eq. q2R).  gsr_pose_from_qt: cams_out[v] =
+ * cams_in[v] (intrinsics and size) with R = R(q_v / |q_v|), t = t_v; q
+ * [n_views][4] = (q_r, q_i, q_j, q_k), nonzero; t [n_views][3].
+ * gsr_pose_qt_grad: the gradient in (q, t) of a loss whose left-perturbation
+ * gradient at [R(q/|q|) | t] is d_pose: d_t = d_pose[0:3] (moving t is the
+ * translation perturbation) and d_q = (I - qh qh^T) / |q| times
+ * (vee(dR/dqh_k R^T) . (g_phi + g_rho x t))_k -- the rotation that a change
+ * of q makes, with the translation held (written; d_q [n_views][4], d_t
+ * [n_views][3]).  With d_pose from GSR_PAPER_POSE_APPROX this is the paper's
+ * own gradient through the projected centres and depths only. */
+gsr_status gsr_pose_from_qt(gsr_ctx *ctx, int n_views, const float *q, const float *t, const gsr_camera *cams_in,
+                            gsr_camera *cams_out, gsr_stream stream);
+gsr_status gsr_pose_qt_grad(gsr_ctx *ctx, int n_views, const float *q, const float *t, const float *d_pose,
+                            float *d_q, float *d_t, gsr_stream stream);
 
 /* Per-stage timing of calls on this context (HIP events recorded on the
  * call's stream around each stage; HIP-graph launches are not split). */

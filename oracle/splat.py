@@ -226,121 +226,59 @@ def project(scene, cam, cfg: Config):
             amb |= ok & (d < AMBIG_BIN * np.maximum(1.0, np.abs(b)))
     valid &= (rect[:, 0] <= rect[:, 1]) & (rect[:, 2] <= rect[:, 3])
     rect[~valid] = (0, -1, 0, -1)
-    runs = None
-    if not cfg.full_rect and cfg.alpha_min > 0:
-        runs, amb_s = _support_runs(u, v, conic, opacity, rect, valid, float(cfg.alpha_min))
-        amb |= amb_s
-
     return dict(
         n=n, TX=TX, TY=TY, valid=valid, rect=rect, bin_ambiguous=amb & valid,
-        Xc=np.stack([x, y, z], axis=1), z=z, zbits=zf.view(np.uint32),
+        Xc=np.stack([x, y, z], axis=1), z=z, zbits=zf.view(np.uint32), mean_w=mean,
         Sigma=Sigma, Sigma_c=Sigma_c, Rq=Rq, s=s, qhat=qhat, qn=qn, J=J, cov2=cov2,
         conic=conic, uv=np.stack([u, v], axis=1), opacity=opacity, rgb=rgb,
-        W=W, fx=fx, fy=fy, rxz=rxz, ryz=ryz, free_x=free_x, free_y=free_y, runs=runs,
+        W=W, fx=fx, fy=fy, rxz=rxz, ryz=ryz, free_x=free_x, free_y=free_y,
     )
-
-
-def _support_runs(u, v, conic, opacity, rect, valid, alpha_min):
-    """Tiles of each rectangle that the Gaussian reaches with alpha >= alpha_min.
-
-    alpha = o exp(-Q/2) reaches alpha_min only where Q <= t = 2 ln(o/alpha_min)
-    (plus a 1e-4 margin on t for float32 rounding of alpha).  Per row of tiles
-    the ellipse {Q <= t} meets the columns whose pixel-centre range
-    [16 tx, 16 tx + 15] overlaps the ellipse's x-range inside the row's
-    pixel-centre band [16 ty, 16 ty + 15]; that x-range is bounded by the
-    ellipse's boundary at the band row nearest to its leftmost / rightmost
-    point.  Inputs are the float32 values the renderer stores (centre as
-    hi + lo, conic, opacity).  Returns ((records, rows, first columns,
-    lengths), ambiguous) with `ambiguous` flagging records with a decision
-    within rounding of a tile edge."""
-    n = u.shape[0]
-    idx = np.nonzero(valid)[0]
-    amb = np.zeros(n, bool)
-
-    def f(x):
-        return np.asarray(x, np.float32).astype(F64)
-
-    uh = f(u[idx])
-    vh = f(v[idx])
-    U = uh + f(u[idx] - uh)
-    V = vh + f(v[idx] - vh)
-    a, b, c = f(conic[idx, 0]), f(conic[idx, 1]), f(conic[idx, 2])
-    o = f(opacity[idx])
-    with np.errstate(all="ignore"):
-        det = a * c - b * b
-        t = 2.0 * np.log(o / alpha_min) + 1e-4
-        ok = (det > 0.0) & (t > 0.0)
-        SA, SB, SC = c / det, -b / det, a / det
-        hy = np.sqrt(t * SC)
-        dys = SB * np.sqrt(t / SA)
-        ra = 1.0 / a
-    tx0, tx1, ty0, ty1 = (rect[idx, k] for k in range(4))
-    out = ([], [], [], [])
-
-    def near(x, scale):
-        return np.abs(x) <= 1e-12 * np.maximum(1.0, np.abs(scale))
-
-    nrows = int((ty1 - ty0).max()) + 1 if idx.size else 0
-    for r in range(nrows):  # one row offset at a time, all records at once
-        ty = ty0 + r
-        m = ok & (ty <= ty1)
-        with np.errstate(all="ignore"):
-            p = (16 * ty).astype(F64) - V
-            q = (16 * ty + 15).astype(F64) - V
-            inband = ~((q < -hy) | (p > hy))
-            dr = np.fmin(np.fmax(dys, p), q)
-            dl = np.fmin(np.fmax(-dys, p), q)
-            br, bl = b * dr, b * dl
-            er = np.fmax(br * br - a * ((c * dr) * dr - t), 0.0)
-            el = np.fmax(bl * bl - a * ((c * dl) * dl - t), 0.0)
-            R = (-br + np.sqrt(er)) * ra
-            L = (-bl - np.sqrt(el)) * ra
-            xlo = ((U + L) - 15.0) * 0.0625
-            xhi = (U + R) * 0.0625
-            clo = np.fmax(np.ceil(xlo), tx0.astype(F64))
-            chi = np.fmin(np.floor(xhi), tx1.astype(F64))
-        keep = m & inband & (clo <= chi)
-        amb[idx[m & (near(q + hy, hy) | near(p - hy, hy))]] = True
-        amb[idx[m & inband & (near(xlo - np.round(xlo), xlo) | near(xhi - np.round(xhi), xhi))]] = True
-        out[0].append(idx[keep])
-        out[1].append(ty[keep])
-        out[2].append(clo[keep].astype(np.int64))
-        out[3].append((chi - clo + 1)[keep].astype(np.int64))
-    runs = tuple(np.concatenate(x) if x else np.zeros(0, np.int64) for x in out)
-    return runs, amb
 
 
 def tile_lists(proj):
     """Per-tile Gaussian lists in blending order.
 
-    Tile id = ty * TX + tx.  Returns (starts [TX*TY + 1], gauss [P]) where the
-    list of tile k is gauss[starts[k]:starts[k+1]], ordered by (float32 depth
-    bits, Gaussian index)."""
+    Every valid Gaussian is listed in every tile of its 3-sigma rectangle
+    (Sec. 3.1: the Gaussians covering a tile, sorted by depth).  Tile id =
+    ty * TX + tx.  Returns (starts [TX*TY + 1], gauss [P]) where the list of
+    tile k is gauss[starts[k]:starts[k+1]], ordered by (float32 depth bits,
+    Gaussian index)."""
     TX, TY = proj["TX"], proj["TY"]
     rect = proj["rect"]
     idx = np.nonzero(proj["valid"])[0]
-    tiles_g, gauss = [], []
-    runs = proj.get("runs")
-    if runs is not None:  # the tiles of each rectangle the alpha support reaches
-        for rec, ty, lo, ln in zip(*runs):
-            tiles_g.append(ty * TX + lo + np.arange(ln))
-            gauss.append(np.full(ln, rec))
-    else:
-        for i in idx:  # plain loop over Gaussians: tiles of the rectangle
-            tx0, tx1, ty0, ty1 = rect[i]
-            ty, tx = np.meshgrid(np.arange(ty0, ty1 + 1), np.arange(tx0, tx1 + 1), indexing="ij")
-            tiles_g.append((ty * TX + tx).ravel())
-            gauss.append(np.full(tiles_g[-1].size, i))
-    if tiles_g:
-        tiles_g = np.concatenate(tiles_g)
-        gauss = np.concatenate(gauss)
-    else:
-        tiles_g = np.zeros(0, np.int64)
-        gauss = np.zeros(0, np.int64)
+    tx0, tx1, ty0, ty1 = (rect[idx, k] for k in range(4))
+    w = tx1 - tx0 + 1
+    cnt = w * (ty1 - ty0 + 1)
+    # One pair per tile of each rectangle, row-major inside the rectangle.
+    gauss = np.repeat(idx, cnt)
+    first = np.repeat(np.cumsum(cnt) - cnt, cnt)
+    j = np.arange(gauss.size) - first
+    ww = np.repeat(w, cnt)
+    tiles_g = (np.repeat(ty0, cnt) + j // ww) * TX + np.repeat(tx0, cnt) + j % ww
     order = np.lexsort((gauss, proj["zbits"][gauss], tiles_g))
     tiles_g, gauss = tiles_g[order], gauss[order]
     starts = np.searchsorted(tiles_g, np.arange(TX * TY + 1), side="left")
     return starts, gauss
+
+
+def tile_alpha_max(proj, tile, lst, width, height, cfg: Config):
+    """For each Gaussian of `lst`, the largest alpha = min(alpha_max,
+    o exp(-Q/2)) it reaches at a pixel centre of tile `tile` inside the
+    image (FP64, every pixel evaluated).  A Gaussian whose value is below
+    alpha_min is skipped by every pixel of the tile (Eq. 4-5 blend only
+    entries with alpha >= alpha_min), so a renderer may leave it out of the
+    tile's list without changing any output."""
+    lst = np.asarray(lst, np.int64)
+    if lst.size == 0:
+        return np.zeros(0)
+    px, py = _tile_pixels(tile, proj["TX"], width, height)
+    u, v = proj["uv"][lst, 0], proj["uv"][lst, 1]
+    a, b, c = (proj["conic"][lst, k] for k in range(3))
+    dx = u[None, :] - px[:, None].astype(F64)
+    dy = v[None, :] - py[:, None].astype(F64)
+    Q = a * dx * dx + 2.0 * b * dx * dy + c * dy * dy
+    alpha = np.minimum(cfg.alpha_max, proj["opacity"][lst][None, :] * np.exp(-0.5 * Q))
+    return alpha.max(axis=0)
 
 
 # --------------------------------------------------------------------------- Eq. 4-5
@@ -512,12 +450,18 @@ def sigma2d_backward(G2, J, Sc):
     return GSc, GJ
 
 
-def backward_params(proj, g2, cfg: Config, approx_pose=False):
+def backward_params(proj, g2, cfg: Config, approx_pose=False, pose_q=None):
     """Chain the 2D gradients to the Gaussian parameters and the camera pose
     (supplement Sec. A).  Pose gradient: left perturbation T_cw <- Exp(xi) T_cw
     with xi = (rho, phi), evaluated at xi = 0.  `approx_pose` drops the Sigma'
     path from the pose gradient only, as the paper does for speed.
-    Returns dict(mean, log_scale, quat, opacity_logit, rgb, pose[6])."""
+    With pose_q (the camera's quaternion, R = R(q / |q|)), also the gradient
+    in the paper's pose parameters: pose_t = sum_i dL/dX_c,i (X_c = R X + t)
+    and pose_q through dX_c/dq = (dR/dq) X (eq. grad_q) and, unless
+    approx_pose, the camera-frame covariance R Sigma R^T; projected onto the
+    tangent of the normalisation.
+    Returns dict(mean, log_scale, quat, opacity_logit, rgb, pose[6]
+    [, pose_q[4], pose_t[3]])."""
     n = proj["n"]
     v = proj["valid"]
     g_u, g_v, g_a, g_b, g_c, g_o = (g2[:, k] for k in range(6))
@@ -581,8 +525,27 @@ def backward_params(proj, g2, cfg: Config, approx_pose=False):
         arr = np.where(v.reshape((-1,) + (1,) * (arr.ndim - 1)), arr, 0.0)
         return arr
 
-    return dict(mean=z0(g_mean), log_scale=z0(g_ls), quat=z0(g_q), opacity_logit=z0(g_op),
-                rgb=z0(g_rgb), pose=np.concatenate([rho, phi]))
+    out = dict(mean=z0(g_mean), log_scale=z0(g_ls), quat=z0(g_q), opacity_logit=z0(g_op),
+               rgb=z0(g_rgb), pose=np.concatenate([rho, phi]))
+    if pose_q is not None:
+        cq = np.asarray(pose_q, np.float64).reshape(1, 4)
+        cqn = float(np.linalg.norm(cq))
+        cqh = cq / cqn
+        Rc = quat_to_rotmat(cqh)[0]
+        dRc = [d[0] for d in quat_to_rotmat_grads(cqh)]
+        g_qh = np.zeros(4)
+        for k in range(4):
+            # centre: dX_c/dq_k = (dR/dq_k) X for the world point X
+            Xw = proj["mean_w"][v]
+            g_qh[k] = np.sum(gXp[v] * (Xw @ dRc[k].T))
+            if not approx_pose:
+                # covariance: d(R Sigma R^T) = dR Sigma R^T + R Sigma dR^T
+                S = proj["Sigma"][v]
+                dSc = np.einsum("ij,njk,lk->nil", dRc[k], S, Rc) + np.einsum("ij,njk,lk->nil", Rc, S, dRc[k])
+                g_qh[k] += np.sum(GSc[v] * dSc)
+        out["pose_q"] = (g_qh - cqh[0] * float(cqh[0] @ g_qh)) / cqn
+        out["pose_t"] = np.sum(gXp[v], axis=0)
+    return out
 
 
 def render_backward(scene, cam, cfg: Config, g_rgb, g_depth, g_T=None, approx_pose=False, fwd=None):

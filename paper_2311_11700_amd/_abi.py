@@ -80,8 +80,9 @@ SIGNATURES = {
                                 _P(ctypes.c_size_t)]),
     "gsr_render_forward": (ctypes.c_int, [c_void_p, _P(gsr_gaussians), c_void_p, ctypes.c_int, _P(gsr_config),
                                           c_void_p, ctypes.c_size_t, _P(gsr_images), c_void_p]),
+    "gsr_forward_generation": (ctypes.c_int64, [c_void_p]),
     "gsr_render_backward": (ctypes.c_int, [c_void_p, _P(gsr_gaussians), c_void_p, ctypes.c_int, _P(gsr_config),
-                                           c_void_p, ctypes.c_size_t, c_void_p, c_void_p, c_void_p,
+                                           c_void_p, ctypes.c_size_t, ctypes.c_int64, c_void_p, c_void_p, c_void_p,
                                            _P(gsr_grads), c_void_p]),
     "gsr_l1_loss_grad": (ctypes.c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                         ctypes.c_float, ctypes.c_float, c_void_p, c_void_p, c_void_p, c_void_p,
@@ -108,6 +109,11 @@ SIGNATURES = {
                                     c_void_p]),
     "gsr_select_reliable": (ctypes.c_int, [c_void_p, _P(gsr_gaussians), c_void_p, c_void_p, ctypes.c_int,
                                            ctypes.c_int, ctypes.c_float, ctypes.c_float, c_void_p, c_void_p]),
+    "gsr_pose_apply": (ctypes.c_int, [c_void_p, ctypes.c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "gsr_pose_xi_grad": (ctypes.c_int, [c_void_p, ctypes.c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "gsr_pose_from_qt": (ctypes.c_int, [c_void_p, ctypes.c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "gsr_pose_qt_grad": (ctypes.c_int, [c_void_p, ctypes.c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                        c_void_p]),
     "gsr_set_profiling": (ctypes.c_int, [c_void_p, ctypes.c_int]),
     "gsr_stage_times": (ctypes.c_int, [c_void_p, _P(ctypes.c_double), _P(ctypes.c_int64)]),
     "gsr_work_counts": (ctypes.c_int, [c_void_p, _P(gsr_gaussians), _P(gsr_config), c_void_p, c_void_p,

@@ -25,6 +25,7 @@ struct gsr_ctx {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
   const void *last_forward_ws = nullptr;
+  int64_t fwd_generation = 0;  // successful gsr_render_forward calls on this context
   int sort_grid = 2048;
   // stage timing
   bool profiling = false;
@@ -387,27 +388,26 @@ gsr_status gsr_render_forward(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_ca
   launch_render_forward(ctx->plan, ws, ctx->views_dev, ctx->tile_view_dev, *g, consts(*cfg), out, s);
   prof_end(ctx, s, GSR_STAGE_RASTER);
   if ((st = last_launch(ctx, "gsr_render_forward launch")) != GSR_OK) return st;
-  st = hip_check(ctx, hipMemcpyAsync(ctx->pinned, ws.hdr + HDR_NPAIRS, 8, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
-  if (st == GSR_OK) st = hip_check(ctx, hipStreamSynchronize(s), "hipStreamSynchronize");
-  if (st != GSR_OK) return st;
   ctx->last_forward_ws = workspace;
-  const int64_t pairs = (int64_t)ctx->pinned[0];
-  if (pairs > ctx->plan.capacity) {
-    ctx->required = pairs;
-    return fail(ctx, GSR_E_CAPACITY, "pair buffer too small: need " + std::to_string(pairs));
-  }
+  ++ctx->fwd_generation;
   return GSR_OK;
 }
 
+int64_t gsr_forward_generation(const gsr_ctx *ctx) { return ctx ? ctx->fwd_generation : 0; }
+
 gsr_status gsr_render_backward(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams, int n_views,
                                const gsr_config *cfg, void *workspace, size_t workspace_bytes,
-                               const float *g_rgb, const float *g_depth, const float *g_T,
-                               const gsr_grads *grads, gsr_stream stream) {
+                               int64_t forward_generation, const float *g_rgb, const float *g_depth,
+                               const float *g_T, const gsr_grads *grads, gsr_stream stream) {
   gsr_status st = validate(ctx, g, cams, n_views, cfg, workspace, workspace_bytes);
   if (st != GSR_OK) return st;
   if (!g_rgb || !grads) return fail(ctx, GSR_E_INVALID, "gsr_render_backward: null gradient argument");
   if (ctx->last_forward_ws != workspace)
     return fail(ctx, GSR_E_STATE, "gsr_render_backward: workspace was not filled by the last forward");
+  if (forward_generation != ctx->fwd_generation)
+    return fail(ctx, GSR_E_STATE, "gsr_render_backward: the workspace holds forward " +
+                                      std::to_string(ctx->fwd_generation) + ", not forward " +
+                                      std::to_string(forward_generation));
   if ((cfg->flags & GSR_GAUSS_GRAD) && g->n > 0 &&
       (!grads->d_mean || !grads->d_log_scale || !grads->d_quat || !grads->d_opacity_logit || !grads->d_rgb))
     return fail(ctx, GSR_E_INVALID, "GSR_GAUSS_GRAD needs every d_* pointer");
@@ -682,6 +682,42 @@ gsr_status gsr_select_reliable(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_c
   if (g->n > 0 && !g->mean) return fail(ctx, GSR_E_INVALID, "gsr_select_reliable: null mean");
   launch_select_reliable(*g, cam, depth_obs, width, height, eps, z_near, mask_out, static_cast<hipStream_t>(stream));
   return last_launch(ctx, "gsr_select_reliable launch");
+}
+
+gsr_status gsr_pose_apply(gsr_ctx *ctx, int n_views, const float *xi, const gsr_camera *cams_in,
+                          gsr_camera *cams_out, gsr_stream stream) {
+  if (!ctx) return GSR_E_INVALID;
+  if (n_views < 0 || (n_views > 0 && (!xi || !cams_in || !cams_out)))
+    return fail(ctx, GSR_E_INVALID, "gsr_pose_apply: invalid argument");
+  launch_pose_apply(n_views, xi, cams_in, cams_out, static_cast<hipStream_t>(stream));
+  return last_launch(ctx, "gsr_pose_apply launch");
+}
+
+gsr_status gsr_pose_xi_grad(gsr_ctx *ctx, int n_views, const float *xi, const float *d_pose, float *d_xi,
+                            gsr_stream stream) {
+  if (!ctx) return GSR_E_INVALID;
+  if (n_views < 0 || (n_views > 0 && (!xi || !d_pose || !d_xi)))
+    return fail(ctx, GSR_E_INVALID, "gsr_pose_xi_grad: invalid argument");
+  launch_pose_xi_grad(n_views, xi, d_pose, d_xi, static_cast<hipStream_t>(stream));
+  return last_launch(ctx, "gsr_pose_xi_grad launch");
+}
+
+gsr_status gsr_pose_from_qt(gsr_ctx *ctx, int n_views, const float *q, const float *t, const gsr_camera *cams_in,
+                            gsr_camera *cams_out, gsr_stream stream) {
+  if (!ctx) return GSR_E_INVALID;
+  if (n_views < 0 || (n_views > 0 && (!q || !t || !cams_in || !cams_out)))
+    return fail(ctx, GSR_E_INVALID, "gsr_pose_from_qt: invalid argument");
+  launch_pose_from_qt(n_views, q, t, cams_in, cams_out, static_cast<hipStream_t>(stream));
+  return last_launch(ctx, "gsr_pose_from_qt launch");
+}
+
+gsr_status gsr_pose_qt_grad(gsr_ctx *ctx, int n_views, const float *q, const float *t, const float *d_pose,
+                            float *d_q, float *d_t, gsr_stream stream) {
+  if (!ctx) return GSR_E_INVALID;
+  if (n_views < 0 || (n_views > 0 && (!q || !t || !d_pose || !d_q || !d_t)))
+    return fail(ctx, GSR_E_INVALID, "gsr_pose_qt_grad: invalid argument");
+  launch_pose_qt_grad(n_views, q, t, d_pose, d_q, d_t, static_cast<hipStream_t>(stream));
+  return last_launch(ctx, "gsr_pose_qt_grad launch");
 }
 
 gsr_status gsr_set_profiling(gsr_ctx *ctx, int enable) {

@@ -352,6 +352,14 @@ void launch_l1(const Plan &p, const ViewInfo *views, const float *rgb, const flo
 void launch_loss_median(const Plan &p, const ViewInfo *views, const float *px_loss, const uint8_t *pmask,
                         float factor, float *cap_out, hipStream_t s);
 
+// Pose parameterisations (one thread per view).
+void launch_pose_apply(int n, const float *xi, const gsr_camera *cin, gsr_camera *cout, hipStream_t s);
+void launch_pose_xi_grad(int n, const float *xi, const float *d_pose, float *d_xi, hipStream_t s);
+void launch_pose_from_qt(int n, const float *q, const float *t, const gsr_camera *cin, gsr_camera *cout,
+                         hipStream_t s);
+void launch_pose_qt_grad(int n, const float *q, const float *t, const float *d_pose, float *d_q, float *d_t,
+                         hipStream_t s);
+
 // Backward preprocess (chain to parameters and pose).
 void launch_preprocess_backward(const Plan &p, const gsr_gaussians &g, const gsr_camera *cams,
                                 const gsr_config &cfg, const Workspace &ws, const gsr_grads &gr,

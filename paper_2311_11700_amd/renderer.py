@@ -144,6 +144,7 @@ class Renderer:
         self.n = -1
         self.sizes: list = []
         self.capacity = 0
+        self.last_generation = 0
 
     def __del__(self):
         try:
@@ -175,9 +176,10 @@ class Renderer:
             acc += w * h
         return offs
 
-    def plan(self, n: int, sizes, pair_capacity: Optional[int] = None) -> int:
+    def plan(self, n: int, sizes, pair_capacity: Optional[int] = None, workspace: bool = True) -> int:
         """Plan n Gaussians over views of (width, height) `sizes`; allocates the
-        workspace.  Default capacity: 64 pairs per pixel (at least 1M)."""
+        workspace (unless `workspace` is False: for the static-scratch step
+        only).  Default capacity: 64 pairs per pixel (at least 1M)."""
         sizes = [(int(w), int(h)) for w, h in sizes]
         if pair_capacity is None:
             pair_capacity = max(1 << 20, 64 * sum(w * h for w, h in sizes))
@@ -185,7 +187,9 @@ class Renderer:
         nbytes = ctypes.c_size_t()
         self._check(self.lib.gsr_plan(self.ctx, int(n), len(sizes), wh, int(pair_capacity), ctypes.byref(nbytes)))
         self.workspace = None
-        self.workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=self.device)
+        if workspace:
+            self.workspace = torch.empty(int(nbytes.value) + 256, dtype=torch.uint8, device=self.device)
+        self.workspace_bytes = int(nbytes.value)
         self.n, self.sizes, self.capacity = int(n), sizes, int(pair_capacity)
         return int(nbytes.value)
 
@@ -238,27 +242,40 @@ class Renderer:
                 _need(out.get(k), m, k, dt)
 
     # --------------------------------------------------------- entry points
-    def render_forward(self, g: Gaussians, cams: torch.Tensor, cfg: Config, out=None, stream=None):
-        """gsr_render_forward; returns the image dict.  Grows the pair buffer
-        and retries once on GSR_E_CAPACITY."""
+    def render_forward(self, g: Gaussians, cams: torch.Tensor, cfg: Config, out=None, stream=None, check=True):
+        """gsr_render_forward; returns the image dict.  The call itself is
+        asynchronous; with `check` the binding then waits for the stream
+        (gsr_check_overflow) and, on GSR_E_CAPACITY, grows the pair buffer and
+        renders again.  Without it, call check_overflow() later: the outputs
+        of an overflowing call are undefined.  The forward's generation goes
+        to self.last_generation (render_backward checks it)."""
         out = out if out is not None else self.new_images()
         self._check_images(out)
         gc, cc = g.c(), cfg.to_c()
         for attempt in range(2):
             ws, wsb = self._ws()
-            st = self.lib.gsr_render_forward(self.ctx, ctypes.byref(gc), _cams_ptr(cams, self.n_views), self.n_views,
-                                             ctypes.byref(cc), ws, wsb, ctypes.byref(self._images_c(out)),
-                                             _stream_ptr(stream))
-            if st == A.GSR_E_CAPACITY and attempt == 0:
+            self._check(self.lib.gsr_render_forward(self.ctx, ctypes.byref(gc), _cams_ptr(cams, self.n_views),
+                                                    self.n_views, ctypes.byref(cc), ws, wsb,
+                                                    ctypes.byref(self._images_c(out)), _stream_ptr(stream)))
+            self.last_generation = int(self.lib.gsr_forward_generation(self.ctx))
+            if not check:
+                break
+            try:
+                self.check_overflow(stream)
+            except GsrError as e:
+                if e.status != A.GSR_E_CAPACITY or attempt > 0:
+                    raise
                 need = int(self.lib.gsr_required_pairs(self.ctx))
                 self.plan(self.n, self.sizes, int(need * 1.25) + 1024)
                 continue
-            self._check(st)
             break
         return out
 
     def render_backward(self, g: Gaussians, cams: torch.Tensor, cfg: Config, g_rgb, g_depth, g_T=None,
-                        grads=None, stream=None):
+                        grads=None, stream=None, generation: Optional[int] = None):
+        """gsr_render_backward of the forward of `generation` (default: this
+        renderer's last forward); GsrError(GSR_E_STATE) when the workspace no
+        longer holds that forward's state."""
         grads = grads if grads is not None else self.new_grads(g.n)
         P = self.total_pixels
         g_rgb = g_rgb.contiguous()
@@ -267,10 +284,11 @@ class Renderer:
         _need(g_rgb, 3 * P, "g_rgb", torch.float32)
         _need(g_depth, P, "g_depth", torch.float32)
         _need(g_T, P, "g_T", torch.float32)
+        gen = self.last_generation if generation is None else int(generation)
         gc, cc = g.c(), cfg.to_c()
         ws, wsb = self._ws()
         self._check(self.lib.gsr_render_backward(
-            self.ctx, ctypes.byref(gc), _cams_ptr(cams, self.n_views), self.n_views, ctypes.byref(cc), ws, wsb,
+            self.ctx, ctypes.byref(gc), _cams_ptr(cams, self.n_views), self.n_views, ctypes.byref(cc), ws, wsb, gen,
             _ptr(g_rgb), _ptr(g_depth), _ptr(g_T), ctypes.byref(self._grads_c(grads, g.n, self.n_views)),
             _stream_ptr(stream)))
         return grads
@@ -305,7 +323,7 @@ class Renderer:
 
     def _fused_args(self, g, cams, cfg, target_rgb, target_depth, pixel_mask, w_rgb, w_depth, out, grads, loss,
                     loss_cap=None):
-        ws, wsb = self._ws()
+        ws, wsb = self._ws() if self.workspace is not None else (None, 0)
         P = self.total_pixels
         for t, m, name in ((target_rgb, 3 * P, "target_rgb"), (target_depth, P, "target_depth"), (loss, 1, "loss"),
                            (loss_cap, self.n_views, "loss_cap")):
@@ -408,6 +426,56 @@ class Renderer:
                                                  _stream_ptr(stream)))
         return out
 
+    # ------------------------------------------------------------ poses
+    def pose_apply(self, xi: torch.Tensor, cams_in: torch.Tensor, cams_out: Optional[torch.Tensor] = None,
+                   stream=None) -> torch.Tensor:
+        """gsr_pose_apply: cameras with the poses Exp(xi_v) T_v ([V, 6] float32 xi)."""
+        V = int(cams_in.shape[0])
+        out = cams_out if cams_out is not None else torch.empty_like(cams_in)
+        _need(xi.contiguous(), 6 * V, "xi", torch.float32)
+        _need(out, 20 * V, "cams_out", torch.float32)
+        xi = xi.contiguous()
+        self._check(self.lib.gsr_pose_apply(self.ctx, V, xi.data_ptr(), _cams_ptr(cams_in, V), out.data_ptr(),
+                                            _stream_ptr(stream)))
+        return out
+
+    def pose_xi_grad(self, xi: torch.Tensor, d_pose: torch.Tensor, stream=None) -> torch.Tensor:
+        """gsr_pose_xi_grad: J_l(xi)^T d_pose per view."""
+        V = int(d_pose.shape[0])
+        xi, d_pose = xi.contiguous(), d_pose.contiguous()
+        _need(xi, 6 * V, "xi", torch.float32)
+        _need(d_pose, 6 * V, "d_pose", torch.float32)
+        out = torch.empty(V, 6, device=self.device)
+        self._check(self.lib.gsr_pose_xi_grad(self.ctx, V, xi.data_ptr(), d_pose.data_ptr(), out.data_ptr(),
+                                              _stream_ptr(stream)))
+        return out
+
+    def pose_from_qt(self, q: torch.Tensor, t: torch.Tensor, cams_in: torch.Tensor,
+                     cams_out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """gsr_pose_from_qt: cameras with R = R(q / |q|) and t ([V, 4], [V, 3])."""
+        V = int(cams_in.shape[0])
+        q, t = q.contiguous(), t.contiguous()
+        _need(q, 4 * V, "q", torch.float32)
+        _need(t, 3 * V, "t", torch.float32)
+        out = cams_out if cams_out is not None else torch.empty_like(cams_in)
+        _need(out, 20 * V, "cams_out", torch.float32)
+        self._check(self.lib.gsr_pose_from_qt(self.ctx, V, q.data_ptr(), t.data_ptr(), _cams_ptr(cams_in, V),
+                                              out.data_ptr(), _stream_ptr(stream)))
+        return out
+
+    def pose_qt_grad(self, q: torch.Tensor, t: torch.Tensor, d_pose: torch.Tensor, stream=None):
+        """gsr_pose_qt_grad: (d_q [V, 4], d_t [V, 3]) from the left-perturbation gradient."""
+        V = int(d_pose.shape[0])
+        q, t, d_pose = q.contiguous(), t.contiguous(), d_pose.contiguous()
+        _need(q, 4 * V, "q", torch.float32)
+        _need(t, 3 * V, "t", torch.float32)
+        _need(d_pose, 6 * V, "d_pose", torch.float32)
+        d_q = torch.empty(V, 4, device=self.device)
+        d_t = torch.empty(V, 3, device=self.device)
+        self._check(self.lib.gsr_pose_qt_grad(self.ctx, V, q.data_ptr(), t.data_ptr(), d_pose.data_ptr(),
+                                              d_q.data_ptr(), d_t.data_ptr(), _stream_ptr(stream)))
+        return d_q, d_t
+
     # ------------------------------------------------------------ profiling
     def set_profiling(self, enable: bool = True):
         self._check(self.lib.gsr_set_profiling(self.ctx, 1 if enable else 0))
@@ -435,11 +503,14 @@ class Renderer:
 
 class _RenderFn(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, mean, log_scale, quat, opacity_logit, rgb, pose_xi, renderer, cams, cfg, mask):
+    def forward(ctx, mean, log_scale, quat, opacity_logit, rgb, pose_xi, renderer, cams0, cfg, mask, check):
         g = Gaussians(mean.contiguous(), log_scale.contiguous(), quat.contiguous(), opacity_logit.contiguous(),
                       rgb.contiguous(), mask)
-        out = renderer.render_forward(g, cams, cfg)
-        ctx.renderer, ctx.cams, ctx.cfg, ctx.g = renderer, cams, cfg, g
+        xi = pose_xi.detach().to(torch.float32).contiguous()
+        cams = renderer.pose_apply(xi, cams0)  # T = Exp(xi) T0 on the device
+        out = renderer.render_forward(g, cams, cfg, check=check)
+        ctx.renderer, ctx.cams, ctx.cfg, ctx.g, ctx.xi = renderer, cams, cfg, g, xi
+        ctx.generation = renderer.last_generation
         ctx.mark_non_differentiable(out["last"])
         return out["rgb"], out["depth"], out["T_final"]
 
@@ -451,21 +522,28 @@ class _RenderFn(torch.autograd.Function):
         g_rgb = torch.zeros(3 * P, device=dev) if g_rgb is None else g_rgb.contiguous()
         g_depth = torch.zeros(P, device=dev) if g_depth is None else g_depth.contiguous()
         g_T = None if g_T is None else g_T.contiguous()
-        grads = r.render_backward(g, ctx.cams, ctx.cfg, g_rgb, g_depth, g_T)
+        grads = r.render_backward(g, ctx.cams, ctx.cfg, g_rgb, g_depth, g_T, generation=ctx.generation)
+        d_xi = r.pose_xi_grad(ctx.xi, grads["d_pose"])
         return (grads["d_mean"], grads["d_log_scale"], grads["d_quat"], grads["d_opacity_logit"], grads["d_rgb"],
-                grads["d_pose"], None, None, None, None)
+                d_xi, None, None, None, None, None)
 
 
 def render(renderer: Renderer, mean, log_scale, quat, opacity_logit, rgb, cams: torch.Tensor,
-           cfg: Optional[Config] = None, pose_xi: Optional[torch.Tensor] = None, mask=None):
-    """Differentiable render of every planned view.  Returns flat (rgb, depth,
-    T_final) over the concatenated views.  `pose_xi` [n_views, 6] is a zero
-    tangent placeholder: its gradient is dL/dxi of a left perturbation
-    T_cw <- Exp(xi) T_cw at xi = 0 (the cameras themselves define the pose)."""
+           cfg: Optional[Config] = None, pose_xi: Optional[torch.Tensor] = None, mask=None, check: bool = True):
+    """Differentiable render of every planned view at the poses
+    T_v = Exp(xi_v) T0_v, T0_v the pose of cams[v] and xi_v = pose_xi[v]
+    (zero when pose_xi is None).  Returns flat (rgb, depth, T_final) over the
+    concatenated views; the gradient of pose_xi is J_l(xi)^T times the
+    renderer's left-perturbation pose gradient (gsr_pose_xi_grad).  The
+    backward of a call must run before the renderer renders again (each
+    forward's state lives in the renderer's one workspace; a later forward
+    makes an earlier call's backward raise GsrError(GSR_E_STATE)).  With
+    check=False the forward does not wait for the stream: call
+    renderer.check_overflow() before trusting the outputs."""
     cfg = cfg or Config()
     if pose_xi is None:
         pose_xi = torch.zeros(renderer.n_views, 6, device=renderer.device)
-    return _RenderFn.apply(mean, log_scale, quat, opacity_logit, rgb, pose_xi, renderer, cams, cfg, mask)
+    return _RenderFn.apply(mean, log_scale, quat, opacity_logit, rgb, pose_xi, renderer, cams, cfg, mask, check)
 
 
 def split_views(flat: torch.Tensor, sizes, channels: int = 1):

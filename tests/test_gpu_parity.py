@@ -21,15 +21,10 @@ def _print_case(**kw):
     print("CASE", kw, flush=True)
 
 
-def _lists_from_gpu(rng, sid, n, tile_off, TXY):
-    out = []
-    for t in range(TXY):
-        a, b = rng[tile_off + t]
-        out.append(list((sid[a:b] - 0).tolist()))
-    return out
-
-
 def _check_lists(renderer, scene_list, cams, cfg_o):
+    """Every tile of every view: the renderer's list against the oracle's
+    rectangle list (in-order subsequence keeping every Gaussian that reaches
+    alpha_min in the tile)."""
     rng, sid = renderer.debug_tiles()
     rng = rng.numpy()
     sid = sid.numpy()
@@ -40,14 +35,16 @@ def _check_lists(renderer, scene_list, cams, cfg_o):
     for v, (sc, cam) in enumerate(zip(scene_list, cams)):
         proj = O.project(sc, cam, cfg_o.as_f32())
         assert not proj["bin_ambiguous"].any()
-        starts, gauss = O.tile_lists(proj)
-        T = proj["TX"] * proj["TY"]
-        for t in range(T):
-            a, b = rng[tile_off + t]
-            got = sid[a:b] - v * n
-            exp = gauss[starts[t]:starts[t + 1]]
-            assert got.shape == exp.shape and np.array_equal(got, exp), (v, t, got[:10], exp[:10])
-        tile_off += T
+        lists = O.tile_lists(proj)
+        n_or, n_gpu, n_amb = H.check_view_lists(rng, sid, tile_off, v * n, proj, lists, cam.width, cam.height, cfg_o)
+        print(f"view {v}: oracle pairs {n_or}, listed {n_gpu}, ambiguous drops {n_amb}", flush=True)
+        tile_off += proj["TX"] * proj["TY"]
+    return rng, sid
+
+
+def _lists_of(renderer):
+    rng, sid = renderer.debug_tiles()
+    return rng.numpy(), sid.numpy(), 0, 0
 
 
 @pytest.mark.parametrize("case", ["small", "ragged77x45", "ragged200x33", "opaque"])
@@ -74,12 +71,14 @@ def test_forward_and_lists_match_oracle(gsr_lib, case):
     torch.cuda.synchronize()
     g = H.split_images(out, r.sizes)[0]
     o = O.render(sc, cam, H.oracle_cfg_of(cfg))
-    H.assert_images_close(g, o)
     assert r.pair_count() == H.rect_pairs(o["proj"])
-    _check_lists(r, [sc], [cam], H.oracle_cfg_of(cfg))
-    # Work totals (the roofline's FLOP count) against the oracle's walk.
+    rng, sid = _check_lists(r, [sc], [cam], H.oracle_cfg_of(cfg))
+    H.assert_images_close(g, o, gpu_lists=(rng, sid, 0, 0))
+    # Work totals (the roofline's FLOP count) against the oracle's walk of
+    # the renderer's lists.
     work = r.work_counts(H.gpu_scene(gsr, sc), cfg)
-    ow = H.oracle_work(o, cam, H.oracle_cfg_of(cfg))
+    T = o["proj"]["TX"] * o["proj"]["TY"]
+    ow = H.oracle_work(o, cam, H.oracle_cfg_of(cfg), H.gpu_view_lists(rng, sid, 0, T, 0))
     assert work["pairs"] == H.rect_pairs(o["proj"])
     assert work["bwd_evals"] == int(g["last"].sum())
     for k in ("fwd_evals", "blended"):
@@ -110,7 +109,7 @@ def test_edge_cases(gsr_lib):
     g = H.split_images(out, r.sizes)[0]
     assert np.isfinite(g["rgb"]).all() and np.isfinite(g["depth"]).all()
     o = O.render(sc, cam, H.oracle_cfg_of(cfg))
-    H.assert_images_close(g, o)
+    H.assert_images_close(g, o, gpu_lists=_lists_of(r))
     # A 1x1 image, a tile-aligned image, and an empty scene.
     for size in [(1, 1), (32, 32), (16, 48)]:
         sc = W.random_scene(200, seed=7)
@@ -118,7 +117,7 @@ def test_edge_cases(gsr_lib):
         r2 = gsr.Renderer()
         r2.plan(sc.n, [size])
         g = H.split_images(r2.render_forward(H.gpu_scene(gsr, sc), gsr.pack_cameras([c2]), cfg), r2.sizes)[0]
-        H.assert_images_close(g, O.render(sc, c2, H.oracle_cfg_of(cfg)))
+        H.assert_images_close(g, O.render(sc, c2, H.oracle_cfg_of(cfg)), gpu_lists=_lists_of(r2))
     r3 = gsr.Renderer()
     r3.plan(0, [(cam.width, cam.height)])
     empty = W.random_scene(0, seed=0)
@@ -177,7 +176,7 @@ def _backward_case(gsr, sc, cams, cfg, seed=1, approx=False):
     sizes = [(c.width, c.height) for c in cams]
     r = gsr.Renderer()
     r.plan(sc.n, sizes)
-    g = H.gpu_scene(gsr, sc)
+    g = H.gpu_scene(gsr, sc, mask=getattr(sc, "mask", None))
     cams_d = gsr.pack_cameras(cams)
     r.render_forward(g, cams_d, cfg)
     ocfg = H.oracle_cfg_of(cfg)
@@ -239,6 +238,34 @@ def test_backward_matches_oracle_room_scene(gsr_lib, posed):
     got2, _ = _backward_case(gsr, sc, [cam], gsr.Config(flags=gsr.GSR_POSE_GRAD))
     assert H.rel_err(got2["pose"][0], ref["pose"][0]) <= 1e-3
     assert not np.any(got2["mean"]) and not np.any(got2["rgb"])
+
+
+def test_masked_gaussians_match_oracle(gsr_lib):
+    """gsr_gaussians.mask (the fine tracking stage's selection, Eq. 12):
+    excluded Gaussians leave the lists, the images and the gradients --
+    forward, lists and backward against the oracle with the same mask."""
+    gsr = gsr_lib
+    _print_case(test="masked")
+    sc = W.room_scene(8000, seed=7)
+    cam = W.perturb_pose(W.camera_tum_coarse(), [0.01, 0.02, -0.01, 0.01, 0.0, 0.02])
+    mask = (np.random.default_rng(4).random(sc.n) > 0.4).astype(np.uint8)
+    r = gsr.Renderer()
+    r.plan(sc.n, [(cam.width, cam.height)])
+    g = H.gpu_scene(gsr, sc, mask=mask)
+    cams_d = gsr.pack_cameras([cam])
+    cfg = gsr.Config()
+    out = r.render_forward(g, cams_d, cfg)
+    sc.mask = mask  # the oracle culls Gaussians with mask 0
+    o = O.render(sc, cam, H.oracle_cfg_of(cfg))
+    assert not o["proj"]["valid"][mask == 0].any()
+    rng, sid = _check_lists(r, [sc], [cam], H.oracle_cfg_of(cfg))
+    assert not np.isin(sid[:int(rng[-1, 1])], np.nonzero(mask == 0)[0]).any()
+    H.assert_images_close(H.split_images(out, r.sizes)[0], o, gpu_lists=(rng, sid, 0, 0))
+    got, ref = _backward_case(gsr, sc, [cam], cfg)
+    H.assert_grads_close(got, ref)
+    assert H.rel_err(got["pose"][0], ref["pose"][0]) <= 1e-3
+    for k in ("mean", "rgb", "opacity_logit"):
+        assert not np.any(got[k][mask == 0]), k
 
 
 def test_paper_approx_pose_gradient(gsr_lib):
@@ -670,14 +697,16 @@ def test_capacity_overflow_reports_required_pairs(gsr_lib):
     g = H.gpu_scene(gsr, sc)
     out = r.new_images()
     ws, wsb = r._ws()
+    stream = torch.cuda.current_stream().cuda_stream
     st = lib.gsr_render_forward(r.ctx, ctypes.byref(g.c()), gsr.pack_cameras([cam]).data_ptr(), 1,
-                                ctypes.byref(gsr.Config().to_c()), ws, wsb, ctypes.byref(r._images_c(out)),
-                                torch.cuda.current_stream().cuda_stream)
-    assert st == gsr.GSR_E_CAPACITY
+                                ctypes.byref(gsr.Config().to_c()), ws, wsb, ctypes.byref(r._images_c(out)), stream)
+    assert st == gsr.GSR_OK  # asynchronous: the overflow is recorded on the device
+    assert lib.gsr_check_overflow(r.ctx, ws, stream) == gsr.GSR_E_CAPACITY
     assert r.required_pairs() == need
+    assert lib.gsr_check_overflow(r.ctx, ws, stream) == gsr.GSR_OK  # reported once
     # The binding grows the buffer and succeeds.
     o = H.split_images(r.render_forward(g, gsr.pack_cameras([cam]), gsr.Config()), r.sizes)[0]
-    H.assert_images_close(o, O.render(sc, cam))
+    H.assert_images_close(o, O.render(sc, cam), gpu_lists=_lists_of(r))
 
 
 def test_invalid_arguments_and_call_order(gsr_lib):
@@ -717,24 +746,88 @@ def test_invalid_arguments_and_call_order(gsr_lib):
         r.render_forward(g, short, gsr.Config())
 
 
-def test_autograd_function(gsr_lib):
+@pytest.mark.parametrize("case", ["one-view", "two-views-xi", "pose-only"])
+def test_autograd_function(gsr_lib, case):
+    """torch.autograd.Function boundary against the oracle at 1e-3: all
+    parameter gradients and the gradient of pose_xi (cameras at
+    Exp(xi) T0, the xi gradient J_l(xi)^T times the oracle's left-perturbation
+    gradient at that pose), ambiguous pixels masked on both sides."""
     gsr = gsr_lib
-    sc, cam = W.random_scene(800, seed=2), W.camera_small()
+    sc = W.random_scene(800, seed=2)
+    cams0 = [W.camera_small()]
+    xi = np.zeros((1, 6))
+    if case == "two-views-xi":
+        cams0.append(W.perturb_pose(W.camera_small().with_size(90.0, 90.0, 44.5, 30.0, 90, 61),
+                                    [0.03, 0.0, -0.02, 0.01, -0.02, 0.0]))
+        xi = np.array([[0.02, -0.01, 0.03, 0.02, 0.01, -0.015], [-0.01, 0.02, 0.0, 0.0, 0.03, 0.01]])
+    _print_case(test="autograd", case=case)
+    sizes = [(c.width, c.height) for c in cams0]
+    xi = xi.astype(np.float32)
+    # The poses the renderer sees: Exp(xi) T0 in FP64, rounded to float32.
+    cams = []
+    for c, x in zip(cams0, xi):
+        R, t = O.apply_xi(x.astype(np.float64), np.asarray(c.R, np.float64), np.asarray(c.t, np.float64))
+        cams.append(dataclasses.replace(c, R=R.astype(np.float32), t=t.astype(np.float32)))
+    cfg = gsr.Config() if case != "pose-only" else gsr.Config(flags=gsr.GSR_POSE_GRAD)
+    r = gsr.Renderer()
+    r.plan(sc.n, sizes)
+    params = [H.to_dev(a).requires_grad_(True) for a in sc.arrays()]
+    xi_d = H.to_dev(xi).requires_grad_(True)
+    rgb, depth, T = gsr.render(r, *params, gsr.pack_cameras(cams0), cfg=cfg, pose_xi=xi_d)
+    fwds = [O.render(sc, c) for c in cams]
+    gr, gd, gT = H.flat_upstream(sizes, seed=6, zero_masks=[f["ambiguous_grad"] for f in fwds])
+    (rgb * H.to_dev(gr)).sum().add((depth * H.to_dev(gd)).sum()).add((T * H.to_dev(gT)).sum()).backward()
+    ref = None
+    for v, (c, f) in enumerate(zip(cams, fwds)):
+        ur, ud, uT = H.view_slices(gr, gd, gT, sizes)[v]
+        assert f["ambiguous_grad"].mean() < 5e-3
+        b = O.render_backward(sc, c, O.Config(), ur, ud, uT, fwd=f)
+        b["xi"] = O.pose_xi_grad(xi[v].astype(np.float64), b["pose"])
+        if ref is None:
+            ref = {k: b[k] for k in ("mean", "log_scale", "quat", "opacity_logit", "rgb")}
+            ref["xi"] = [b["xi"]]
+        else:
+            for k in ("mean", "log_scale", "quat", "opacity_logit", "rgb"):
+                ref[k] = ref[k] + b[k]
+            ref["xi"].append(b["xi"])
+    if case == "pose-only":
+        for p in params:
+            assert p.grad is None or not torch.any(p.grad)
+    else:
+        H.assert_grads_close({k: p.grad.cpu().numpy() for p, k in zip(params, ("mean", "log_scale", "quat",
+                                                                                 "opacity_logit", "rgb"))}, ref)
+    for v in range(len(cams)):
+        assert H.rel_err(xi_d.grad.cpu().numpy()[v], ref["xi"][v]) <= 1e-3, (v, xi_d.grad[v], ref["xi"][v])
+
+
+def test_backward_of_an_overwritten_forward_is_refused(gsr_lib):
+    """Two autograd renders on one renderer before either backward: the
+    first call's state has been overwritten, so its backward raises
+    GSR_E_STATE instead of returning the second call's gradients; the second
+    call's backward is unaffected."""
+    gsr = gsr_lib
+    sc, cam = W.random_scene(500, seed=3), W.camera_small()
     r = gsr.Renderer()
     r.plan(sc.n, [(cam.width, cam.height)])
-    params = [H.to_dev(a).requires_grad_(True) for a in sc.arrays()]
-    xi = torch.zeros(1, 6, device="cuda", requires_grad=True)
-    rgb, depth, T = gsr.render(r, *params, gsr.pack_cameras([cam]), pose_xi=xi)
-    gr, gd, gT = H.flat_upstream([(cam.width, cam.height)], seed=6)
-    (rgb * H.to_dev(gr)).sum().add((depth * H.to_dev(gd)).sum()).add((T * H.to_dev(gT)).sum()).backward()
+    cams = gsr.pack_cameras([cam])
+    p1 = [H.to_dev(a).requires_grad_(True) for a in sc.arrays()]
+    p2 = [H.to_dev(a).requires_grad_(True) for a in sc.arrays()]
+    out1 = gsr.render(r, *p1, cams)
+    out2 = gsr.render(r, *p2, cams)
+    with pytest.raises(gsr.GsrError) as e:
+        out1[0].sum().backward()
+    assert e.value.status == gsr.GSR_E_STATE
+    out2[0].sum().backward()
     f = O.render(sc, cam)
-    assert f["ambiguous_grad"].mean() < 5e-3
-    ref = O.render_backward(sc, cam, O.Config(), gr.reshape(3, cam.height, cam.width), gd.reshape(cam.height, cam.width),
-                            gT.reshape(cam.height, cam.width), fwd=f)
-    # ambiguous pixels are not masked here: compare with a looser bound
-    for p, k in zip(params, ("mean", "log_scale", "quat", "opacity_logit", "rgb")):
-        assert H.rel_err(p.grad.cpu().numpy(), ref[k]) <= 2e-2, k
-    assert H.rel_err(xi.grad.cpu().numpy()[0], ref["pose"]) <= 2e-2
+    gC = np.zeros((3, cam.height, cam.width))
+    gC[:, ~f["ambiguous_grad"]] = 1.0
+    ok = H.to_dev(gC.reshape(-1))
+    for p in p2:
+        p.grad = None
+    out3 = gsr.render(r, *p2, cams)
+    (out3[0] * ok).sum().backward()
+    ref = O.render_backward(sc, cam, O.Config(), gC, np.zeros((cam.height, cam.width)), None, fwd=f)
+    assert H.rel_err(p2[0].grad.cpu().numpy(), ref["mean"]) <= 1e-3
 
 
 def test_reliable_selection_bit_exact(gsr_lib):

@@ -211,48 +211,18 @@ def test_culling_rules():
     assert O.project(sc, cam, cfg)["valid"][0]
 
 
-def _stored(p, i, alpha_min):
-    """The float32 values the renderer keeps for Gaussian i, back in FP64:
-    centre (hi + lo), conic, and the alpha-support level t."""
-    f = lambda x: float(np.float32(x))  # noqa: E731
-    U = f(p["uv"][i, 0]) + f(p["uv"][i, 0] - f(p["uv"][i, 0]))
-    V = f(p["uv"][i, 1]) + f(p["uv"][i, 1] - f(p["uv"][i, 1]))
-    a, b, c = (f(x) for x in p["conic"][i])
-    t = 2.0 * math.log(f(p["opacity"][i]) / alpha_min) + 1e-4
-    return U, V, a, b, c, t
-
-
-def _min_q_over_rect(U, V, a, b, c, x0, x1, y0, y1):
-    """Minimum of the quadratic form over the rectangle of pixel centres,
-    by edges: 0 if the centre is inside, else the least of the four edges'
-    one-dimensional minima."""
-    if x0 <= U <= x1 and y0 <= V <= y1:
-        return 0.0
-    best = math.inf
-    for X in (x0, x1):  # vertical edges: minimise over y
-        dx = X - U
-        dy = min(max(-b * dx / c, y0 - V), y1 - V)
-        best = min(best, a * dx * dx + 2 * b * dx * dy + c * dy * dy)
-    for Y in (y0, y1):  # horizontal edges: minimise over x
-        dy = Y - V
-        dx = min(max(-b * dy / a, x0 - U), x1 - U)
-        best = min(best, a * dx * dx + 2 * b * dx * dy + c * dy * dy)
-    return best
-
-
 @pytest.mark.parametrize("seed,n,size", [(0, 300, (53, 37)), (1, 500, (64, 48)), (2, 200, (17, 80))])
 def test_tile_lists_match_brute_force(seed, n, size):
-    """Brute force: each tile scans all Gaussians with the predicate "in the
-    rectangle and the alpha support {Q <= t} meets the tile's rectangle of
-    pixel centres" (edge minima of Q) and orders them with Python's sorted()
-    on (float32 depth bits, index)."""
+    """Brute force: each tile scans all Gaussians for the ones whose
+    rectangle holds it and orders them with Python's sorted() on (float32
+    depth bits, index)."""
     cam = W.camera_small().with_size(60.0, 60.0, (size[0] - 1) / 2, (size[1] - 1) / 2, *size)
     sc = W.random_scene(n, seed=seed)
     sc.mean[: n // 10, 2] = sc.mean[n // 10: 2 * (n // 10), 2]  # force equal depths (index tie-break)
     cfg = O.Config().as_f32()
     p = O.project(sc, cam, cfg)
     starts, gauss = O.tile_lists(p)
-    dropped = 0
+    ties = 0
     for tile in range(p["TX"] * p["TY"]):
         ty, tx = divmod(tile, p["TX"])
         members = []
@@ -260,46 +230,34 @@ def test_tile_lists_match_brute_force(seed, n, size):
             if not p["valid"][i]:
                 continue
             tx0, tx1, ty0, ty1 = p["rect"][i]
-            if not (tx0 <= tx <= tx1 and ty0 <= ty <= ty1):
-                continue
-            U, V, a, b, c, t = _stored(p, i, cfg.alpha_min)
-            q = _min_q_over_rect(U, V, a, b, c, 16 * tx, 16 * tx + 15, 16 * ty, 16 * ty + 15)
-            assert abs(q - t) > 1e-9 * t, "decision within rounding"
-            if q <= t:
+            if tx0 <= tx <= tx1 and ty0 <= ty <= ty1:
                 members.append((int(np.float32(p["z"][i]).view(np.uint32)), i))
-            else:
-                dropped += 1
+        ties += len(members) - len({m[0] for m in members})
         expect = [i for _, i in sorted(members)]
         assert list(gauss[starts[tile]:starts[tile + 1]]) == expect
-    assert dropped > 0
+    assert ties > 0
     assert not p["bin_ambiguous"].any()
 
 
-def test_dropped_tiles_hold_no_pixel_above_alpha_min():
-    """Tiles of a rectangle outside the alpha support hold only pixels with
-    o exp(-Q/2) < alpha_min, so dropping them leaves the image unchanged; and
-    the rectangle's tiles that are kept contain every pixel at or above it."""
-    cam = W.camera_small()
-    sc = W.random_scene(150, seed=12)
-    sc.opacity_logit[:] = np.linspace(-5.0, 4.0, sc.n)
+def test_tile_alpha_max_closed_forms():
+    """Largest alpha of a Gaussian over a tile's pixel centres: an isotropic
+    Gaussian centred on a pixel centre of the tile reaches min(alpha_max, o)
+    there; centred off the tile, its nearest pixel centre (the centre
+    clamped to the tile's pixel range) gives o exp(-d^2 / (2 s^2)); a tile
+    cut by the image edge only counts its pixels inside the image."""
+    s2 = 9.0
+    p = dict(TX=4, uv=np.array([[21.0, 5.0], [40.5, 7.25], [10.0, 20.0]]),
+             conic=np.array([[1 / s2, 0.0, 1 / s2]] * 3), opacity=np.array([0.995, 0.6, 0.7]))
     cfg = O.Config().as_f32()
-    p = O.project(sc, cam, cfg)
-    starts, gauss = O.tile_lists(p)
-    kept = {(int(g), t) for t in range(p["TX"] * p["TY"]) for g in gauss[starts[t]:starts[t + 1]]}
-    py, px = np.mgrid[0:cam.height, 0:cam.width]
-    n_drop = 0
-    for k in np.nonzero(p["valid"])[0]:
-        a, b, c = p["conic"][k]
-        dx, dy = p["uv"][k, 0] - px, p["uv"][k, 1] - py
-        alpha = p["opacity"][k] * np.exp(-0.5 * (a * dx * dx + 2 * b * dx * dy + c * dy * dy))
-        tx0, tx1, ty0, ty1 = p["rect"][k]
-        for ty in range(ty0, ty1 + 1):
-            for tx in range(tx0, tx1 + 1):
-                sl = (slice(16 * ty, 16 * ty + 16), slice(16 * tx, 16 * tx + 16))
-                if (int(k), ty * p["TX"] + tx) not in kept:
-                    n_drop += 1
-                    assert np.all(alpha[sl] < cfg.alpha_min), (k, tx, ty)
-    assert n_drop > 0
+    got = O.tile_alpha_max(p, 1, [0, 1, 2], 64, 30, cfg)   # tile (tx 1, ty 0): x 16..31, y 0..15
+    want = [min(cfg.alpha_max, 0.995),
+            0.6 * math.exp(-((40.5 - 31) ** 2 + 0.25 ** 2) / (2 * s2)),
+            0.7 * math.exp(-((16 - 10.0) ** 2 + (20 - 15) ** 2) / (2 * s2))]
+    np.testing.assert_allclose(got, want, rtol=1e-12)
+    # tile (tx 0, ty 1) of a 64x18 image holds rows 16 and 17 only
+    got = O.tile_alpha_max(p, 4, [2], 64, 18, cfg)
+    np.testing.assert_allclose(got, [0.7 * math.exp(-(3 ** 2) / (2 * s2))], rtol=1e-12)
+    assert O.tile_alpha_max(p, 4, [], 64, 18, cfg).size == 0
 
 
 def test_rect_contains_every_pixel_inside_the_ellipse():
