@@ -152,7 +152,9 @@ const char *gsr_status_string(gsr_status s);
 const char *gsr_last_error(const gsr_ctx *ctx);
 
 /* Create a context on HIP device `device` (owns a few KB of device memory for
- * the view table and a pinned host word; no other state).  */
+ * the view table and a pinned host word; no other state).  The first call on
+ * a device also resolves the address of that device's static scratch (see
+ * gsr_render_l1_fused_noalloc). */
 gsr_status gsr_create(int device, gsr_ctx **out);
 void gsr_destroy(gsr_ctx *ctx);
 
@@ -222,6 +224,28 @@ gsr_status gsr_render_l1_fused(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_c
                                size_t workspace_bytes, const gsr_images *out, const gsr_grads *grads,
                                float *loss, gsr_stream stream);
 
+/* Size of the static scratch behind gsr_render_l1_fused_noalloc: 64 MiB of
+ * device memory per GPU the library runs on, held until the process ends. */
+#define GSR_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/* gsr_render_l1_fused without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP-graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The workspace is a static device array of
+ * GSR_NOALLOC_SCRATCH_BYTES inside the library (one per GPU, its address
+ * resolved once per device by gsr_create); the call itself allocates nothing
+ * and issues no memset.  Same kernels, arguments, outputs and asynchronous
+ * semantics as gsr_render_l1_fused.  GSR_E_INVALID when the plan's workspace
+ * (gsr_plan's workspace_bytes) exceeds GSR_NOALLOC_SCRATCH_BYTES.
+ * Every call on a GPU shares that GPU's array and leaves its state in it:
+ * calls that overlap on one GPU (two streams, two contexts, two host threads)
+ * race and give undefined results; serialise them.  A pair-capacity
+ * overflow is read with gsr_check_overflow(ctx, NULL, stream). */
+gsr_status gsr_render_l1_fused_noalloc(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams,
+                                       int n_views, const gsr_config *cfg, const float *target_rgb,
+                                       const float *target_depth, const uint8_t *pixel_mask, float w_rgb,
+                                       float w_depth, const float *loss_cap, const gsr_images *out,
+                                       const gsr_grads *grads, float *loss, gsr_stream stream);
+
 /* Capture gsr_render_l1_fused with these exact arguments (pointers and
  * scalar values are baked in; buffer CONTENTS may change between launches)
  * into a HIP graph owned by the context, replacing any earlier capture. */
@@ -235,7 +259,8 @@ gsr_status gsr_graph_capture(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_cam
 gsr_status gsr_graph_launch(gsr_ctx *ctx, gsr_stream stream);
 
 /* Synchronise `stream`, then report GSR_E_CAPACITY if any call since the
- * last check overflowed the pair buffer of this workspace. */
+ * last check overflowed the pair buffer of this workspace (NULL: the static
+ * scratch of gsr_render_l1_fused_noalloc on the context's device). */
 gsr_status gsr_check_overflow(gsr_ctx *ctx, void *workspace, gsr_stream stream);
 /* Pair count of the last overflowing call (0 if none). */
 int64_t gsr_required_pairs(const gsr_ctx *ctx);

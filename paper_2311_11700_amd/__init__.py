@@ -8,7 +8,7 @@ behind the C ABI of include/gsr.h.  This package is the ctypes binding.
 """
 from ._abi import (  # noqa: F401
     GSR_FULL_RECT, GSR_GAUSS_GRAD, GSR_POSE_GRAD, GSR_PAPER_POSE_APPROX, GSR_GRAD_OVERWRITE,
-    GSR_OK, GSR_E_INVALID, GSR_E_CAPACITY, GSR_E_HIP, GSR_E_UNSUPPORTED, GSR_E_STATE,
+    GSR_OK, GSR_E_INVALID, GSR_E_CAPACITY, GSR_E_HIP, GSR_E_UNSUPPORTED, GSR_E_STATE, GSR_NOALLOC_SCRATCH_BYTES,
     load, exported_symbols, LIB_PATH,
 )
 from .renderer import (  # noqa: F401

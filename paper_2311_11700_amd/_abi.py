@@ -32,6 +32,8 @@ GSR_POSE_GRAD = 1 << 2
 GSR_PAPER_POSE_APPROX = 1 << 3
 GSR_GRAD_OVERWRITE = 1 << 4
 
+GSR_NOALLOC_SCRATCH_BYTES = 64 << 20
+
 
 class gsr_camera(ctypes.Structure):
     _fields_ = [("fx", ctypes.c_float), ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
@@ -92,6 +94,10 @@ SIGNATURES = {
                                            c_void_p, c_void_p, c_void_p, ctypes.c_float, ctypes.c_float, c_void_p,
                                            c_void_p, ctypes.c_size_t, _P(gsr_images), _P(gsr_grads), c_void_p,
                                            c_void_p]),
+    "gsr_render_l1_fused_noalloc": (ctypes.c_int, [c_void_p, _P(gsr_gaussians), c_void_p, ctypes.c_int,
+                                                   _P(gsr_config), c_void_p, c_void_p, c_void_p, ctypes.c_float,
+                                                   ctypes.c_float, c_void_p, _P(gsr_images), _P(gsr_grads),
+                                                   c_void_p, c_void_p]),
     "gsr_graph_capture": (ctypes.c_int, [c_void_p, _P(gsr_gaussians), c_void_p, ctypes.c_int, _P(gsr_config),
                                          c_void_p, c_void_p, c_void_p, ctypes.c_float, ctypes.c_float, c_void_p,
                                          c_void_p, ctypes.c_size_t, _P(gsr_images), _P(gsr_grads), c_void_p,

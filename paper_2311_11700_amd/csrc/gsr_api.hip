@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -26,6 +27,7 @@ struct gsr_ctx {
   hipGraphExec_t gexec = nullptr;
   const void *last_forward_ws = nullptr;
   int64_t fwd_generation = 0;  // successful gsr_render_forward calls on this context
+  void *scratch = nullptr;     // device address of this device's static scratch (gsr_render_l1_fused_noalloc)
   int sort_grid = 2048;
   // stage timing
   bool profiling = false;
@@ -36,9 +38,22 @@ struct gsr_ctx {
   hipEvent_t *cur_events = nullptr;  // events of the call being enqueued
 };
 
+// Workspace of the allocation-free fused step (gsr_render_l1_fused_noalloc):
+// a file-scope device array that every GPU the library runs on holds until
+// the process ends.  In host code its name is not a device address; the
+// address is taken once per device with hipGetSymbolAddress (gsr_create) and
+// only that pointer is passed to kernels.
+static __device__ __align__(256) unsigned char scratch[GSR_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 constexpr size_t ALIGN = 256;
+
+// Per-device address of `scratch`, resolved on the first gsr_create on the
+// device (with the device current).
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
 
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
@@ -251,6 +266,15 @@ gsr_status gsr_create(int device, gsr_ctx **out) {
   gsr_status st = hip_check(ctx, hipSetDevice(device), "hipSetDevice");
   if (st == GSR_OK) st = hip_check(ctx, hipDeviceGetAttribute(&ctx->num_cus, hipDeviceAttributeMultiprocessorCount, device), "hipDeviceGetAttribute");
   if (st == GSR_OK) st = hip_check(ctx, hipHostMalloc(reinterpret_cast<void **>(&ctx->pinned), 8 * sizeof(unsigned long long), hipHostMallocDefault), "hipHostMalloc");
+  if (st == GSR_OK && device >= 0 && device < MAX_DEVICES) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+      void *ptr = nullptr;
+      st = hip_check(ctx, hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+      if (st == GSR_OK) g_scratch_ptr[device] = ptr;
+    }
+    ctx->scratch = g_scratch_ptr[device];
+  }
   if (st != GSR_OK) {
     std::fprintf(stderr, "gsr_create: %s\n", ctx->last_error.c_str());
     gsr_destroy(ctx);
@@ -482,6 +506,29 @@ gsr_status gsr_render_l1_fused(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_c
   return last_launch(ctx, "gsr_render_l1_fused launch");
 }
 
+gsr_status gsr_render_l1_fused_noalloc(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams, int n_views,
+                                       const gsr_config *cfg, const float *target_rgb, const float *target_depth,
+                                       const uint8_t *pixel_mask, float w_rgb, float w_depth, const float *loss_cap,
+                                       const gsr_images *out, const gsr_grads *grads, float *loss,
+                                       gsr_stream stream) {
+  if (!ctx) return GSR_E_INVALID;
+  if (!ctx->scratch) return fail(ctx, GSR_E_STATE, "gsr_render_l1_fused_noalloc: no static scratch on this device");
+  if (!ctx->planned) return fail(ctx, GSR_E_STATE, "gsr_plan() has not been called");
+  if (ctx->plan.bytes > GSR_NOALLOC_SCRATCH_BYTES)
+    return fail(ctx, GSR_E_INVALID, "gsr_render_l1_fused_noalloc: the plan needs " + std::to_string(ctx->plan.bytes) +
+                                        " workspace bytes, the static scratch holds " +
+                                        std::to_string((size_t)GSR_NOALLOC_SCRATCH_BYTES) +
+                                        " (use gsr_render_l1_fused with a workspace)");
+  gsr_status st = fused_checks(ctx, g, cams, n_views, cfg, target_rgb, target_depth, w_rgb, w_depth, ctx->scratch,
+                               GSR_NOALLOC_SCRATCH_BYTES, grads);
+  if (st != GSR_OK) return st;
+  Workspace ws = make_ws(ctx->plan, ctx->scratch);
+  enqueue_fused(ctx, *g, cams, *cfg, target_rgb, target_depth, pixel_mask, w_rgb, w_depth, loss_cap, ws, out,
+                *grads, loss, static_cast<hipStream_t>(stream));
+  ctx->last_forward_ws = nullptr;
+  return last_launch(ctx, "gsr_render_l1_fused_noalloc launch");
+}
+
 gsr_status gsr_graph_capture(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams, int n_views,
                              const gsr_config *cfg, const float *target_rgb, const float *target_depth,
                              const uint8_t *pixel_mask, float w_rgb, float w_depth, const float *loss_cap,
@@ -527,7 +574,10 @@ gsr_status gsr_graph_launch(gsr_ctx *ctx, gsr_stream stream) {
 
 gsr_status gsr_check_overflow(gsr_ctx *ctx, void *workspace, gsr_stream stream) {
   if (!ctx) return GSR_E_INVALID;
+  if (!workspace) workspace = ctx->scratch;  // the allocation-free step's static workspace
   if (!ctx->planned || !workspace) return fail(ctx, GSR_E_STATE, "gsr_check_overflow: no plan or workspace");
+  if (workspace == ctx->scratch && ctx->plan.bytes > GSR_NOALLOC_SCRATCH_BYTES)
+    return fail(ctx, GSR_E_STATE, "gsr_check_overflow: the plan does not fit the static scratch");
   hipStream_t s = static_cast<hipStream_t>(stream);
   Workspace ws = make_ws(ctx->plan, workspace);
   gsr_status st = hip_check(ctx, hipMemcpyAsync(ctx->pinned, ws.hdr, 40, hipMemcpyDeviceToHost, s), "hipMemcpyAsync");

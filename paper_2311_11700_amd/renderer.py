@@ -345,6 +345,23 @@ class Renderer:
         self._check(self.lib.gsr_render_l1_fused(*args, _stream_ptr(stream)))
         return loss, grads
 
+    def render_l1_fused_noalloc(self, g: Gaussians, cams, cfg: Config, target_rgb, target_depth, pixel_mask=None,
+                                w_rgb=1.0, w_depth=0.1, out=None, grads=None, loss=None, loss_cap=None, stream=None):
+        """gsr_render_l1_fused_noalloc: the fused step on the library's static
+        scratch (the plan must fit A.GSR_NOALLOC_SCRATCH_BYTES); `grads` and
+        `loss` are caller buffers, as for render_l1_fused."""
+        grads = grads if grads is not None else self.new_grads(g.n)
+        loss = loss if loss is not None else torch.zeros(1, device=self.device)
+        args = self._fused_args(g, cams, cfg, target_rgb, target_depth, pixel_mask, w_rgb, w_depth, out, grads, loss,
+                                loss_cap)
+        args = args[:11] + args[13:]  # no workspace pointer and size
+        self._check(self.lib.gsr_render_l1_fused_noalloc(*args, _stream_ptr(stream)))
+        return loss, grads
+
+    def check_overflow_noalloc(self, stream=None):
+        """gsr_check_overflow on the static scratch (NULL workspace)."""
+        self._check(self.lib.gsr_check_overflow(self.ctx, None, _stream_ptr(stream)))
+
     def graph_capture(self, g, cams, cfg, target_rgb, target_depth, pixel_mask=None, w_rgb=1.0, w_depth=0.1,
                       out=None, grads=None, loss=None, loss_cap=None, stream=None):
         """Capture the fused step into a HIP graph (torch.cuda stream required)."""
