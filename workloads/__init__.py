@@ -27,5 +27,6 @@ from .scenes import (  # noqa: F401
     upstream_grads,
     random_targets,
     loss_images,
+    expansion_images,
     subset,
 )

@@ -415,3 +415,35 @@ def noisy_targets(rgb, depth, seed=1, sigma=0.05, min_alpha=None, alpha=None):
     if min_alpha is not None and alpha is not None:
         t_d[alpha < min_alpha] = 0.0
     return t_rgb, t_d
+
+
+def expansion_images(sizes, seed=4, plant_tau_T=None, plant_tau_D=None, invalid_fraction=0.1,
+                     depth_range=(0.5, 4.0)):
+    """Inputs of the map-expansion adding step for views of the given sizes,
+    concatenated view after view (float32): final transmittance T [sum HW]
+    (uniform in [0, 1], a tenth exactly 1 = empty pixels, a tenth exactly 0),
+    rendered depth [sum HW] (uniform in `depth_range`), observed depth
+    [sum HW] (the rendered depth plus N(0, 0.2^2) noise, `invalid_fraction`
+    zeros, a few NaN) and observed colour [3 * sum HW] (uniform in [0, 1]).
+    With plant_tau_T / plant_tau_D, 2 % of the pixels each are placed exactly
+    on a threshold: T = 1 - plant_tau_T, or rendered depth 1.0 and observed
+    depth 1.0 + plant_tau_D (both exact in float32 for dyadic thresholds)."""
+    rng = np.random.default_rng(seed)
+    npx = sum(int(w) * int(h) for w, h in sizes)
+    T = rng.random(npx)
+    u = rng.random(npx)
+    T[u < 0.1] = 1.0
+    T[(u >= 0.1) & (u < 0.2)] = 0.0
+    dr = rng.uniform(depth_range[0], depth_range[1], size=npx)
+    do = dr + rng.normal(0.0, 0.2, size=npx)
+    do[rng.random(npx) < invalid_fraction] = 0.0
+    do[rng.random(npx) < 0.005] = np.nan
+    rgb = rng.random(3 * npx)
+    if plant_tau_T is not None:
+        sel = rng.random(npx) < 0.02
+        T[sel] = 1.0 - float(plant_tau_T)
+    if plant_tau_D is not None:
+        sel = rng.random(npx) < 0.02
+        dr[sel] = 1.0
+        do[sel] = 1.0 + float(plant_tau_D)
+    return T.astype(F32), dr.astype(F32), do.astype(F32), rgb.astype(F32)
