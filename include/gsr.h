@@ -322,6 +322,64 @@ gsr_status gsr_select_reliable(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_c
                                const float *depth_obs, int width, int height, float eps, float z_near,
                                uint8_t *mask_out, gsr_stream stream);
 
+/* Adaptive expansion of the map (Sec. 3.2).
+ *
+ * Writable Gaussian arrays (DEVICE, same layouts as gsr_gaussians; quat
+ * 16-byte aligned) that the adding step appends to. */
+typedef struct {
+  float *mean, *log_scale, *quat, *opacity_logit, *rgb;
+} gsr_gaussians_out;
+
+/* Adding-step parameters: tau_T (cumulative-opacity threshold) and tau_D
+ * (depth-error threshold, metres) of Eq. 8; the new Gaussians' isotropic
+ * scale is scale_factor * D / sqrt(fx fy) (the spacing of back-projected
+ * neighbouring pixels at depth D) and their opacity logit
+ * opacity_logit_init (the predefined initial opacity of Eq. 7). */
+typedef struct {
+  float tau_T, tau_D, scale_factor, opacity_logit_init;
+} gsr_expand_params;
+
+/* Adding step (Eq. 8) over every planned view: a pixel is unreliable when it
+ * has a depth reading (depth_obs > 0) and its cumulative opacity
+ * 1 - T_final is below tau_T or |depth_obs - depth| exceeds tau_D (FP64
+ * decisions on the float32 inputs).  Each unreliable pixel (x, y) of view v,
+ * in pixel order (views in order, rows top to bottom, left to right),
+ * becomes a new Gaussian (Eq. 7): mean = R^T (X_c - t) with
+ * X_c = D ((x - cx) / fx, (y - cy) / fy, 1) and D = depth_obs, all three
+ * log-scales log(scale_factor D / sqrt(fx fy)), quaternion (1, 0, 0, 0),
+ * opacity logit opacity_logit_init, rgb = rgb_obs at the pixel.  The k-th
+ * new Gaussian is written at index n + k of `out` when n + k < capacity.
+ * Inputs use the concatenated image layouts of the plan's views (T_final and
+ * depth as a forward writes them; depth_obs [sum HW]; rgb_obs [3 * sum HW]);
+ * cams DEVICE [n_views].  Writes *count (DEVICE int64) = the number of
+ * unreliable pixels (new Gaussians wanted: more than capacity - n means the
+ * arrays were too small and only the first capacity - n were written) and,
+ * when pixel_flag (DEVICE uint8 [sum HW]) is not NULL, each pixel's
+ * decision.  Uses only the workspace's adding-step scratch, so a forward's
+ * state in the same workspace is kept.  Asynchronous. */
+gsr_status gsr_expand_add(gsr_ctx *ctx, const gsr_camera *cams, int n_views, const float *T_final, const float *depth,
+                          const float *depth_obs, const float *rgb_obs, const gsr_expand_params *params,
+                          void *workspace, size_t workspace_bytes, int64_t n, int64_t capacity,
+                          const gsr_gaussians_out *out, uint8_t *pixel_flag, int64_t *count, gsr_stream stream);
+
+/* Deleting step (Eq. 9) for one view `cam` (DEVICE, one gsr_camera) with its
+ * observed depth depth_obs (DEVICE [height][width], 0 = no reading).  A
+ * Gaussian is visible when its centre lies beyond z_near and projects to a
+ * pixel of the image (the nearest one, (floor(u + 0.5), floor(v + 0.5)))
+ * with a reading D; the observed surface point of that pixel lies on the
+ * Gaussian's ray at D / z times its camera-frame centre X_c, and when it lies
+ * more than gamma beyond the Gaussian, (D - z) |X_c| / z > gamma (the
+ * Gaussian floats in front of the surface), the opacity is scaled by eta:
+ * sigmoid(Lambda') = eta sigmoid(Lambda), 0 < eta <= 1.  The printed
+ * condition D - dist(X_i, P_uv) > gamma is read as this signed distance.
+ * Writes every Gaussian's logit to opacity_logit_out (DEVICE [n]; may alias
+ * g->opacity_logit) and, when decayed (DEVICE uint8 [n]) is not NULL, 1 for
+ * the decayed ones.  Gaussians excluded by g->mask are left unchanged.
+ * Evaluated in FP64; asynchronous; no plan needed. */
+gsr_status gsr_expand_delete(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cam, const float *depth_obs,
+                             int width, int height, float gamma, float eta, float z_near, float *opacity_logit_out,
+                             uint8_t *decayed, gsr_stream stream);
+
 /* Camera poses around the renderer.  The renderer's d_pose is the gradient
  * w.r.t. a left perturbation T <- Exp(xi) T at the rendered pose (the
  * gradient of Eq. 11, se(3) ordered (rho, phi)).  These calls build the

@@ -67,6 +67,16 @@ class gsr_tuning(ctypes.Structure):
                 ("lpt_order", ctypes.c_int32), ("batch", ctypes.c_int32)]
 
 
+class gsr_gaussians_out(ctypes.Structure):
+    _fields_ = [("mean", c_void_p), ("log_scale", c_void_p), ("quat", c_void_p), ("opacity_logit", c_void_p),
+                ("rgb", c_void_p)]
+
+
+class gsr_expand_params(ctypes.Structure):
+    _fields_ = [("tau_T", ctypes.c_float), ("tau_D", ctypes.c_float), ("scale_factor", ctypes.c_float),
+                ("opacity_logit_init", ctypes.c_float)]
+
+
 assert ctypes.sizeof(gsr_camera) == 80
 assert ctypes.sizeof(gsr_config) == 44
 
@@ -115,6 +125,12 @@ SIGNATURES = {
                                     c_void_p]),
     "gsr_select_reliable": (ctypes.c_int, [c_void_p, _P(gsr_gaussians), c_void_p, c_void_p, ctypes.c_int,
                                            ctypes.c_int, ctypes.c_float, ctypes.c_float, c_void_p, c_void_p]),
+    "gsr_expand_add": (ctypes.c_int, [c_void_p, c_void_p, ctypes.c_int, c_void_p, c_void_p, c_void_p, c_void_p,
+                                      _P(gsr_expand_params), c_void_p, ctypes.c_size_t, ctypes.c_int64,
+                                      ctypes.c_int64, _P(gsr_gaussians_out), c_void_p, c_void_p, c_void_p]),
+    "gsr_expand_delete": (ctypes.c_int, [c_void_p, _P(gsr_gaussians), c_void_p, c_void_p, ctypes.c_int,
+                                         ctypes.c_int, ctypes.c_float, ctypes.c_float, ctypes.c_float, c_void_p,
+                                         c_void_p, c_void_p]),
     "gsr_pose_apply": (ctypes.c_int, [c_void_p, ctypes.c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
     "gsr_pose_xi_grad": (ctypes.c_int, [c_void_p, ctypes.c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
     "gsr_pose_from_qt": (ctypes.c_int, [c_void_p, ctypes.c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),

@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgsr.so")
 SOURCES = ["gsr_preprocess.hip", "gsr_pregrad.hip", "gsr_sort.hip", "gsr_raster.hip", "gsr_median.hip",
-           "gsr_pose.hip", "gsr_api.hip"]
+           "gsr_pose.hip", "gsr_expand.hip", "gsr_api.hip"]
 ARCH = os.environ.get("GSR_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

@@ -104,6 +104,8 @@ Workspace make_ws(const Plan &p, void *base_v) {
   w.pose_part = reinterpret_cast<double *>(base + p.off_pose);
   w.queue = reinterpret_cast<uint32_t *>(base + p.off_queue);
   w.tile_cost = reinterpret_cast<uint32_t *>(base + p.off_tile_cost);
+  w.expand_bits = reinterpret_cast<unsigned long long *>(base + p.off_expand_bits);
+  w.expand_cnt = reinterpret_cast<uint32_t *>(base + p.off_expand_cnt);
   w.loss_part = reinterpret_cast<float *>(base + p.off_loss);
   w.dsorted = passes_for(32) & 1;
   w.psorted = passes_for(p.tile_bits) & 1;
@@ -374,6 +376,11 @@ gsr_status gsr_plan(gsr_ctx *ctx, int64_t n, int n_views, const int32_t *wh_host
   p.off_queue = take(4 * (size_t)p.total_tiles);
   p.off_tile_cost = take(4 * (size_t)p.total_tiles);
   p.off_loss = take(4);
+  {
+    const size_t chunks = (size_t)((pixels + EXPAND_CHUNK - 1) / EXPAND_CHUNK);
+    p.off_expand_bits = take(8 * chunks * (EXPAND_CHUNK / 64));
+    p.off_expand_cnt = take(4 * chunks);
+  }
   p.bytes = off;
 
   gsr_status st = hip_check(ctx, hipSetDevice(ctx->device), "hipSetDevice");
@@ -732,6 +739,46 @@ gsr_status gsr_select_reliable(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_c
   if (g->n > 0 && !g->mean) return fail(ctx, GSR_E_INVALID, "gsr_select_reliable: null mean");
   launch_select_reliable(*g, cam, depth_obs, width, height, eps, z_near, mask_out, static_cast<hipStream_t>(stream));
   return last_launch(ctx, "gsr_select_reliable launch");
+}
+
+gsr_status gsr_expand_add(gsr_ctx *ctx, const gsr_camera *cams, int n_views, const float *T_final, const float *depth,
+                          const float *depth_obs, const float *rgb_obs, const gsr_expand_params *prm,
+                          void *workspace, size_t workspace_bytes, int64_t n, int64_t capacity,
+                          const gsr_gaussians_out *out, uint8_t *pixel_flag, int64_t *count, gsr_stream stream) {
+  if (!ctx) return GSR_E_INVALID;
+  if (!ctx->planned) return fail(ctx, GSR_E_STATE, "gsr_plan() has not been called");
+  if (n_views != ctx->plan.n_views) return fail(ctx, GSR_E_INVALID, "gsr_expand_add: view count differs from the plan");
+  if (!cams || !T_final || !depth || !depth_obs || !rgb_obs || !prm || !workspace || !count)
+    return fail(ctx, GSR_E_INVALID, "gsr_expand_add: null argument");
+  if (workspace_bytes < ctx->plan.bytes) return fail(ctx, GSR_E_INVALID, "workspace smaller than gsr_plan() requires");
+  if (reinterpret_cast<uintptr_t>(workspace) % ALIGN) return fail(ctx, GSR_E_INVALID, "workspace not 256-byte aligned");
+  if (n < 0 || capacity < n) return fail(ctx, GSR_E_INVALID, "gsr_expand_add: need 0 <= n <= capacity");
+  if (capacity > n && (!out || !out->mean || !out->log_scale || !out->quat || !out->opacity_logit || !out->rgb))
+    return fail(ctx, GSR_E_INVALID, "gsr_expand_add: null output array");
+  if (out && reinterpret_cast<uintptr_t>(out->quat) % 16) return fail(ctx, GSR_E_INVALID, "quat must be 16-byte aligned");
+  if (!(prm->tau_T >= 0.f && prm->tau_T < 1e30f) || !(prm->tau_D >= 0.f && prm->tau_D < 1e30f) ||
+      !(prm->scale_factor > 0.f && prm->scale_factor < 1e30f) || !(fabsf(prm->opacity_logit_init) < 1e30f))
+    return fail(ctx, GSR_E_INVALID, "gsr_expand_add: parameters out of range");
+  gsr_gaussians_out o{};
+  if (out) o = *out;
+  launch_expand_add(ctx->plan, ctx->views_dev, cams, T_final, depth, depth_obs, rgb_obs, prm->tau_T, prm->tau_D,
+                    prm->scale_factor, prm->opacity_logit_init, make_ws(ctx->plan, workspace), n, capacity, o,
+                    pixel_flag, count, static_cast<hipStream_t>(stream));
+  return last_launch(ctx, "gsr_expand_add launch");
+}
+
+gsr_status gsr_expand_delete(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cam, const float *depth_obs,
+                             int width, int height, float gamma, float eta, float z_near, float *opacity_logit_out,
+                             uint8_t *decayed, gsr_stream stream) {
+  if (!ctx) return GSR_E_INVALID;
+  if (!g || !cam || !depth_obs || width < 1 || height < 1 || !(gamma >= 0.f && gamma < 1e30f) ||
+      !(eta > 0.f && eta <= 1.f) || !(z_near >= 0.f))
+    return fail(ctx, GSR_E_INVALID, "gsr_expand_delete: invalid argument");
+  if (g->n > 0 && (!g->mean || !g->opacity_logit || !opacity_logit_out))
+    return fail(ctx, GSR_E_INVALID, "gsr_expand_delete: null array");
+  launch_expand_delete(*g, cam, depth_obs, width, height, gamma, eta, z_near, opacity_logit_out, decayed,
+                       static_cast<hipStream_t>(stream));
+  return last_launch(ctx, "gsr_expand_delete launch");
 }
 
 gsr_status gsr_pose_apply(gsr_ctx *ctx, int n_views, const float *xi, const gsr_camera *cams_in,

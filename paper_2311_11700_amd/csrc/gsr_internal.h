@@ -20,6 +20,7 @@ constexpr int RADIX = 1 << RADIX_BITS;
 constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_CHUNK = BLOCK * SCAN_ITEMS;
 constexpr int EMIT_BUCKET = 256;  // pairs per emission bucket (one block-iteration of k_emit_pairs)
+constexpr int EXPAND_CHUNK = 2048;  // pixels per block of the adding step (eight rounds of BLOCK)
 
 // Bits per radix pass for keys of key_bits bits: ceil(key_bits / 8) passes
 // with the bits spread evenly (fewer digit values make longer output runs).
@@ -132,6 +133,8 @@ struct Workspace {
   double *grad2d;          // [n_rec][NGRAD2D], FP64 sums over tiles
   double *pose_part;       // [n_pose_blocks][n_views][6]
   uint32_t *queue;         // [total_tiles] work order of the persistent rasteriser
+  unsigned long long *expand_bits;  // [chunks][8][4] adding step: one bit per pixel (ballot words)
+  uint32_t *expand_cnt;    // [chunks] adding step: unreliable pixels per chunk, then their exclusive scan
   uint32_t *tile_cost;     // [total_tiles] duration of each tile in the last fused step (10 ns ticks)
   float *loss_part;        // [1] (unused slot kept for alignment)
   int dsorted;             // which depth buffer holds the sorted result
@@ -160,7 +163,7 @@ struct Plan {
   size_t off_hdr, off_recA, off_recB, off_recC, off_rect, off_count, off_dkeys[2], off_dvals[2],
       off_scan, off_pkeys[2], off_pvals[2], off_hist, off_digit, off_ranges, off_T, off_last, off_zr,
       off_grad2d, off_pose, off_queue, off_loss, off_counts, off_hoff, off_bucket,
-      off_support, off_tile_visible, off_tile_cost;
+      off_support, off_tile_visible, off_tile_cost, off_expand_bits, off_expand_cnt;
 };
 
 struct Tuning {
@@ -359,6 +362,14 @@ void launch_pose_from_qt(int n, const float *q, const float *t, const gsr_camera
                          hipStream_t s);
 void launch_pose_qt_grad(int n, const float *q, const float *t, const float *d_pose, float *d_q, float *d_t,
                          hipStream_t s);
+
+// Adaptive expansion (adding step over the planned views; deleting step).
+void launch_expand_add(const Plan &p, const ViewInfo *views, const gsr_camera *cams, const float *T_final,
+                       const float *depth, const float *depth_obs, const float *rgb_obs, float tau_T, float tau_D,
+                       float scale_factor, float logit_init, const Workspace &ws, int64_t n, int64_t capacity,
+                       const gsr_gaussians_out &out, uint8_t *pixel_flag, int64_t *count, hipStream_t s);
+void launch_expand_delete(const gsr_gaussians &g, const gsr_camera *cam, const float *depth_obs, int W, int H,
+                          float gamma, float eta, float z_near, float *logit_out, uint8_t *decayed, hipStream_t s);
 
 // Backward preprocess (chain to parameters and pose).
 void launch_preprocess_backward(const Plan &p, const gsr_gaussians &g, const gsr_camera *cams,

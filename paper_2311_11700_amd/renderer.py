@@ -444,6 +444,50 @@ class Renderer:
         return out
 
     # ------------------------------------------------------------ poses
+    def expand_add(self, cams: torch.Tensor, T_final, depth, depth_obs, rgb_obs, out: dict, n: int, capacity: int,
+                   tau_T: float, tau_D: float, scale_factor: float = 1.0, opacity_logit_init: float = -2.1972246,
+                   pixel_flag: Optional[torch.Tensor] = None, count: Optional[torch.Tensor] = None, stream=None):
+        """gsr_expand_add over the planned views (Eq. 8): appends a Gaussian
+        per unreliable pixel to the arrays of `out` (keys mean, log_scale,
+        quat, opacity_logit, rgb; `capacity` rows) from row n on.  Returns the
+        device int64 count of unreliable pixels.  The default initial
+        opacity logit is that of opacity 0.1."""
+        P = self.total_pixels
+        for t, m, name in ((T_final, P, "T_final"), (depth, P, "depth"), (depth_obs, P, "depth_obs"),
+                           (rgb_obs, 3 * P, "rgb_obs")):
+            _need(t, m, name, torch.float32)
+        _need(pixel_flag, P, "pixel_flag", torch.uint8)
+        per = dict(mean=3, log_scale=3, quat=4, opacity_logit=1, rgb=3)
+        o = A.gsr_gaussians_out()
+        for k, c in per.items():
+            _need(out.get(k), c * int(capacity), k, torch.float32)
+            setattr(o, k, _ptr(out.get(k)))
+        count = count if count is not None else torch.zeros(1, dtype=torch.int64, device=self.device)
+        _need(count, 1, "count", torch.int64)
+        prm = A.gsr_expand_params(float(tau_T), float(tau_D), float(scale_factor), float(opacity_logit_init))
+        ws, wsb = self._ws()
+        self._check(self.lib.gsr_expand_add(self.ctx, _cams_ptr(cams, self.n_views), self.n_views, _ptr(T_final),
+                                            _ptr(depth), _ptr(depth_obs), _ptr(rgb_obs), ctypes.byref(prm), ws, wsb,
+                                            int(n), int(capacity), ctypes.byref(o), _ptr(pixel_flag), _ptr(count),
+                                            _stream_ptr(stream)))
+        return count
+
+    def expand_delete(self, g: Gaussians, cam: torch.Tensor, depth_obs: torch.Tensor, width: int, height: int,
+                      gamma: float, eta: float, z_near: float = 0.2, logit_out: Optional[torch.Tensor] = None,
+                      decayed: Optional[torch.Tensor] = None, stream=None):
+        """gsr_expand_delete (Eq. 9) for one view; returns (new logits,
+        decayed mask).  logit_out may be g's own opacity-logit tensor."""
+        logit_out = logit_out if logit_out is not None else torch.empty(g.n, device=self.device)
+        decayed = decayed if decayed is not None else torch.empty(g.n, dtype=torch.uint8, device=self.device)
+        _need(logit_out, g.n, "logit_out", torch.float32)
+        _need(decayed, g.n, "decayed", torch.uint8)
+        _need(depth_obs, int(width) * int(height), "depth_obs", torch.float32)
+        gc = g.c()
+        self._check(self.lib.gsr_expand_delete(self.ctx, ctypes.byref(gc), _cams_ptr(cam, 1), _ptr(depth_obs),
+                                               int(width), int(height), float(gamma), float(eta), float(z_near),
+                                               _ptr(logit_out), _ptr(decayed), _stream_ptr(stream)))
+        return logit_out, decayed
+
     def pose_apply(self, xi: torch.Tensor, cams_in: torch.Tensor, cams_out: Optional[torch.Tensor] = None,
                    stream=None) -> torch.Tensor:
         """gsr_pose_apply: cameras with the poses Exp(xi_v) T_v ([V, 6] float32 xi)."""

@@ -28,5 +28,6 @@ from .scenes import (  # noqa: F401
     random_targets,
     loss_images,
     expansion_images,
+    room_depth,
     subset,
 )

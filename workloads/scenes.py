@@ -447,3 +447,25 @@ def expansion_images(sizes, seed=4, plant_tau_T=None, plant_tau_D=None, invalid_
         dr[sel] = 1.0
         do[sel] = 1.0 + float(plant_tau_D)
     return T.astype(F32), dr.astype(F32), do.astype(F32), rgb.astype(F32)
+
+
+def room_depth(cam: Camera, seed=5, invalid_fraction=0.05):
+    """Observed depth image [H*W] float32 of the empty room box (its floor,
+    ceiling and walls) seen from a camera inside it: per pixel, the
+    camera-frame depth at which the pixel's ray leaves the box, with
+    `invalid_fraction` of the readings removed (0).  A geometric stand-in for
+    a depth sensor; it evaluates nothing of the renderer."""
+    R = np.asarray(cam.R, np.float64).reshape(3, 3)
+    t = np.asarray(cam.t, np.float64).reshape(3)
+    o = -R.T @ t
+    py, px = np.mgrid[0:cam.height, 0:cam.width]
+    d_cam = np.stack([(px - cam.cx) / cam.fx, (py - cam.cy) / cam.fy, np.ones(px.shape)], axis=-1)
+    w = d_cam @ R  # world direction with unit camera-frame depth
+    lo = np.array([-3.0, -1.5, -0.5])
+    hi = np.array([3.0, 1.5, 3.5])
+    with np.errstate(divide="ignore", invalid="ignore"):
+        s = np.where(w > 0, (hi - o) / w, np.where(w < 0, (lo - o) / w, np.inf))
+    depth = s.min(axis=-1).reshape(-1)
+    rng = np.random.default_rng(seed)
+    depth[rng.random(depth.size) < invalid_fraction] = 0.0
+    return depth.astype(F32)
