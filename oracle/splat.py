@@ -12,7 +12,11 @@ What is computed, and where the paper defines it (GS-SLAM, arXiv 2311.11700):
     colour (Sec. 3.1, Eq. 1); covariance factorised as R S S^T R^T with R from
     a real-first quaternion (Eq. 2; quaternion-to-rotation formula, supplement
     Sec. A, eq. q2R).  Colour is view-independent RGB (the tracking colour
-    model of Sec. 3.3 and the paper's light version).
+    model of Sec. 3.3 and the paper's light version) or, when the scene holds
+    them, degree-1 spherical harmonics with 12 coefficients per Gaussian
+    (Sec. 3.1): per channel the coefficients weight the real spherical
+    harmonics of degree <= 1 of the viewing direction from the camera centre
+    to the Gaussian's mean (no offset, no clamp).
   * Projection: Sigma' = J W Sigma W^T J^T (Eq. 3) with J the Jacobian of the
     perspective projection (supplement Sec. A, derivative of m_i w.r.t. the
     camera-frame point; its (0,2) entry carries z^2 in the denominator) and a
@@ -81,6 +85,19 @@ class Config:
         tile in every list: the rendered image is a smooth function of the
         parameters as long as no two depths swap order."""
         return Config(alpha_min=0.0, alpha_max=1.0, T_min=0.0, bg=bg, full_rect=True)
+
+
+# Real spherical harmonics of degree <= 1 (the textbook real basis, without
+# the Condon-Shortley phase) of a unit direction (x, y, z): Y_0 = 1/(2 sqrt(pi))
+# and (Y_1, Y_2, Y_3) = sqrt(3/(4 pi)) (y, z, x).
+SH_C0 = 0.5 / np.sqrt(np.pi)
+SH_C1 = np.sqrt(3.0 / (4.0 * np.pi))
+
+
+def sh_basis(d):
+    """[N, 4] basis values of unit directions d [N, 3]."""
+    d = np.asarray(d, F64)
+    return np.stack([np.full(d.shape[0], SH_C0), SH_C1 * d[:, 1], SH_C1 * d[:, 2], SH_C1 * d[:, 0]], axis=1)
 
 
 # Relative margins inside which a float32 renderer may take a threshold
@@ -163,8 +180,10 @@ def project(scene, cam, cfg: Config):
     TX = (int(cam.width) + TILE - 1) // TILE
     TY = (int(cam.height) + TILE - 1) // TILE
 
+    sh = getattr(scene, "sh", None)
+    sh = None if sh is None else _as64(sh).reshape(n, 4, 3)
     finite = np.ones(n, bool)
-    for a in (mean, log_scale, quat, opl[:, None], rgb):
+    for a in (mean, log_scale, quat, opl[:, None], rgb if sh is None else sh.reshape(n, 12)):
         finite &= np.isfinite(a).all(axis=1)
     with np.errstate(all="ignore"):
         Sigma, Rq, s, qhat, qn = covariance_3d(log_scale, quat)
@@ -202,6 +221,15 @@ def project(scene, cam, cfg: Config):
         rx = cfg.cutoff * np.sqrt(cov2[:, 0, 0])
         ry = cfg.cutoff * np.sqrt(cov2[:, 1, 1])
         opacity = 1.0 / (1.0 + np.exp(-opl))
+        sh_extra = {}
+        if sh is not None:
+            # Viewing direction from the camera centre o = -W^T t to the mean.
+            vdir = mean + (W.T @ t)[None, :]
+            vlen = np.linalg.norm(vdir, axis=1)
+            dirs = vdir / vlen[:, None]
+            Y = sh_basis(dirs)
+            rgb = np.einsum("nk,nkc->nc", Y, sh)
+            sh_extra = dict(sh=sh, sh_Y=Y, sh_dir=dirs, sh_len=vlen, t=t)
 
     valid = finite & (qn > 0) & (z > cfg.z_near) & (det > 0)
     if getattr(scene, "mask", None) is not None:
@@ -231,7 +259,7 @@ def project(scene, cam, cfg: Config):
         Xc=np.stack([x, y, z], axis=1), z=z, zbits=zf.view(np.uint32), mean_w=mean,
         Sigma=Sigma, Sigma_c=Sigma_c, Rq=Rq, s=s, qhat=qhat, qn=qn, J=J, cov2=cov2,
         conic=conic, uv=np.stack([u, v], axis=1), opacity=opacity, rgb=rgb,
-        W=W, fx=fx, fy=fy, rxz=rxz, ryz=ryz, free_x=free_x, free_y=free_y,
+        W=W, fx=fx, fy=fy, rxz=rxz, ryz=ryz, free_x=free_x, free_y=free_y, **sh_extra,
     )
 
 
@@ -515,8 +543,21 @@ def backward_params(proj, g2, cfg: Config, approx_pose=False, pose_q=None):
     else:
         gXp = gX
         A = np.einsum("nij,njk->nik", Sc, GSc) - np.einsum("nij,njk->nik", GSc, Sc)
+    # Degree-1 spherical-harmonic colour: dL/dcoefficients = Y (x) dL/dc, and
+    # through the viewing direction d = vdir / |vdir|, vdir = mean - o:
+    # dL/dvdir = (I - d d^T) dL/dd / |vdir|, which moves with the mean and
+    # against the camera centre (a left perturbation moves o by -W^T rho).
+    g_sh = None
+    g_vdir = np.zeros((n, 3))
+    if "sh" in proj:
+        Y, d, sh = proj["sh_Y"], proj["sh_dir"], proj["sh"]
+        g_sh = Y[:, :, None] * g_rgb[:, None, :]
+        gY = np.einsum("nkc,nc->nk", sh, g_rgb)
+        g_d = SH_C1 * np.stack([gY[:, 3], gY[:, 1], gY[:, 2]], axis=1)
+        g_vdir = (g_d - d * np.sum(d * g_d, axis=1, keepdims=True)) / proj["sh_len"][:, None]
+        g_mean = g_mean + g_vdir
     Xc = proj["Xc"]
-    rho = np.sum(gXp[v], axis=0)
+    rho = np.sum(gXp[v], axis=0) + W @ np.sum(g_vdir[v], axis=0)
     phi_pts = np.cross(Xc[v], gXp[v])
     phi_cov = np.stack([A[v, 1, 2] - A[v, 2, 1], A[v, 2, 0] - A[v, 0, 2], A[v, 0, 1] - A[v, 1, 0]], axis=1)
     phi = np.sum(phi_pts + phi_cov, axis=0)
@@ -527,6 +568,8 @@ def backward_params(proj, g2, cfg: Config, approx_pose=False, pose_q=None):
 
     out = dict(mean=z0(g_mean), log_scale=z0(g_ls), quat=z0(g_q), opacity_logit=z0(g_op),
                rgb=z0(g_rgb), pose=np.concatenate([rho, phi]))
+    if g_sh is not None:
+        out["sh"] = z0(g_sh)
     if pose_q is not None:
         cq = np.asarray(pose_q, np.float64).reshape(1, 4)
         cqn = float(np.linalg.norm(cq))
@@ -543,8 +586,11 @@ def backward_params(proj, g2, cfg: Config, approx_pose=False, pose_q=None):
                 S = proj["Sigma"][v]
                 dSc = np.einsum("ij,njk,lk->nil", dRc[k], S, Rc) + np.einsum("ij,njk,lk->nil", Rc, S, dRc[k])
                 g_qh[k] += np.sum(GSc[v] * dSc)
+            if "sh" in proj:
+                # viewing directions: vdir = mean + R^T t moves by (dR/dq_k)^T t
+                g_qh[k] += float(np.sum(g_vdir[v] @ (dRc[k].T @ proj["t"])))
         out["pose_q"] = (g_qh - cqh[0] * float(cqh[0] @ g_qh)) / cqn
-        out["pose_t"] = np.sum(gXp[v], axis=0)
+        out["pose_t"] = np.sum(gXp[v], axis=0) + Rc @ np.sum(g_vdir[v], axis=0)
     return out
 
 

@@ -29,5 +29,6 @@ from .scenes import (  # noqa: F401
     loss_images,
     expansion_images,
     room_depth,
+    with_sh,
     subset,
 )

@@ -57,6 +57,10 @@ class Scene:
     quat: np.ndarray
     opacity_logit: np.ndarray
     rgb: np.ndarray
+    # Optional degree-1 spherical-harmonic colour coefficients [N, 4, 3]
+    # (coefficient k = 0..3, channel): when present, colour is view-dependent
+    # and `rgb` is not used.
+    sh: np.ndarray | None = None
 
     @property
     def n(self) -> int:
@@ -182,7 +186,7 @@ def tracking_scene(n=60_000, seed=0, outlier_fraction=0.2, offset=(0.2, 0.6)) ->
 
 def subset(scene: Scene, idx) -> Scene:
     idx = np.asarray(idx)
-    return Scene(*(a[idx].copy() for a in scene.arrays()))
+    return Scene(*(a[idx].copy() for a in scene.arrays()), sh=None if scene.sh is None else scene.sh[idx].copy())
 
 
 # --------------------------------------------------------------------------- cameras
@@ -469,3 +473,14 @@ def room_depth(cam: Camera, seed=5, invalid_fraction=0.05):
     rng = np.random.default_rng(seed)
     depth[rng.random(depth.size) < invalid_fraction] = 0.0
     return depth.astype(F32)
+
+
+def with_sh(scene: Scene, seed=6, dc=(0.0, 2.0), sd=0.3) -> Scene:
+    """A copy of `scene` with degree-1 spherical-harmonic colour coefficients
+    [N, 4, 3] float32: the constant coefficient of each channel uniform in
+    `dc`, the three degree-1 coefficients N(0, sd^2) (in that draw order)."""
+    rng = np.random.default_rng(seed)
+    sh = np.empty((scene.n, 4, 3))
+    sh[:, 0, :] = rng.uniform(dc[0], dc[1], size=(scene.n, 3))
+    sh[:, 1:, :] = rng.normal(0.0, sd, size=(scene.n, 3, 3))
+    return dataclasses.replace(scene, sh=sh.astype(F32))
