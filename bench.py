@@ -176,7 +176,7 @@ def run_headline(args, gsr, torch, W):
         roof["traffic_written"] = int(tr["bytes_written"])
         roof["traffic_source"] = tr["summary"]
     px = cam.width * cam.height
-    roof["a7_backward_hbm"] = backward_hbm(args, gsr, torch, r, g, cams_d, cam, t_rgb, t_d, raster_ms)
+    roof["a7_backward_hbm"] = backward_hbm(args, gsr, torch, r, g, cams_d, cam, t_rgb, t_d, raster_ms, work)
     if tr is not None and tr.get("valu_busy") is not None:
         roof["valu_busy"] = tr["valu_busy"]
     return dict(ms=ms, wall=wall, eager_ms=eager_ms, stages=stages, work=work, roof=roof, tuning=tuning,
@@ -213,13 +213,15 @@ def visited_pairs(torch, last, width, height):
     return int(img.view(TY, 16, TX, 16).amax(dim=(1, 3)).to(torch.int64).sum().item())
 
 
-def backward_hbm(args, gsr, torch, r, g, cams_d, cam, t_rgb, t_d, fused_ms):
+def backward_hbm(args, gsr, torch, r, g, cams_d, cam, t_rgb, t_d, fused_ms, work):
     """The backward composite (A7) against HBM bandwidth: algorithmic bytes
     P_v x (4 B list id + 40 B record + 40 B gradient atomics) + pixels x
     (8 B saved state + 16 B upstream gradient), over the standalone backward
     kernel's time (forward, L1 gradient and backward as separate calls, the
     backward stage event-timed) and over the fused kernel's time, as
-    fractions of the copy-measured achievable bandwidth."""
+    fractions of the copy-measured achievable bandwidth.  Also the
+    backward's ALU floor: its algorithmic FLOPs at the FP32 vector peak, and
+    the bandwidth fraction the byte model would reach even at that floor."""
     px = cam.width * cam.height
     cfg = gsr.Config()
     out = r.new_images()
@@ -239,11 +241,74 @@ def backward_hbm(args, gsr, torch, r, g, cams_d, cam, t_rgb, t_d, fused_ms):
     ach = achievable_hbm_gbs(torch)
     gbs_b = bytes_alg / (bwd_ms * 1e-3) / 1e9
     gbs_f = bytes_alg / (fused_ms * 1e-3) / 1e9
+    bwd_flop = work["bwd_evals"] * FLOP_BWD_EVAL + work["blended"] * FLOP_BWD_CONTRIB
+    floor_ms = bwd_flop / (PEAK_FP32_TFLOPS * 1e12) * 1e3
     return {"kernel": "k_render_bwd", "visited_pairs": pv, "bytes_alg": int(bytes_alg),
+            "bwd_flop": int(bwd_flop), "alu_frac": round(bwd_flop / (bwd_ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4),
+            "alu_floor_ms": round(floor_ms, 4),
+            "frac_of_achievable_at_alu_floor": round(bytes_alg / (floor_ms * 1e-3) / 1e9 / ach, 4),
             "kernel_ms": round(bwd_ms, 4), "achieved_gbs": round(gbs_b, 1), "achievable_gbs": round(ach, 1),
             "frac_of_achievable": round(gbs_b / ach, 4), "frac_of_peak": round(gbs_b / 8000.0, 4),
             "fused_kernel_gbs": round(gbs_f, 1), "fused_frac_of_achievable": round(gbs_f / ach, 4),
             "target_frac": 0.5, "met": bool(gbs_b / ach >= 0.5)}
+
+
+def run_expansion(args, gsr, torch, W):
+    """Map expansion (Sec. 3.2) on the headline workload: the adding step
+    (Eq. 8) over the rendered 1200x680 keyframe against the room's observed
+    depth, and the deleting step (Eq. 9) over the 300k Gaussians; each timed
+    with events over `steps` calls, against HBM bandwidth with the
+    algorithmic bytes: adding 12 B per pixel (T_final, rendered and observed
+    depth) + per new Gaussian 16 B read (depth, colour) + 56 B written;
+    deleting 12 + 4 B read, 4 B gather, 4 + 1 B written per Gaussian."""
+    scene, cam = build_c2(gsr, torch, W)
+    sizes = [(cam.width, cam.height)]
+    g = gsr.Gaussians.from_arrays(*scene.arrays())
+    cams_d = gsr.pack_cameras([cam])
+    r = gsr.Renderer(0)
+    r.plan(scene.n, sizes)
+    img = r.render_forward(g, cams_d, gsr.Config())
+    obs = torch.as_tensor(W.room_depth(cam)).cuda()
+    rgb_obs = torch.as_tensor(W.random_targets(sizes, seed=1)[0]).cuda()
+    px = cam.width * cam.height
+    cap = px
+    z = lambda *sh: torch.empty(*sh, device="cuda")  # noqa: E731
+    out = dict(mean=z(cap, 3), log_scale=z(cap, 3), quat=z(cap, 4), opacity_logit=z(cap), rgb=z(cap, 3))
+    tau_T, tau_D = 0.5, 0.1
+    count = torch.zeros(1, dtype=torch.int64, device="cuda")
+
+    def add():
+        r.expand_add(cams_d, img["T_final"], img["depth"], obs, rgb_obs, out, 0, cap, tau_T, tau_D, count=count)
+
+    logit_out = z(scene.n)
+    dec = torch.empty(scene.n, dtype=torch.uint8, device="cuda")
+
+    def delete():
+        r.expand_delete(g, cams_d, obs, cam.width, cam.height, 0.1, 0.01, logit_out=logit_out, decayed=dec)
+
+    res = {}
+    for name, fn in (("add", add), ("delete", delete)):
+        for _ in range(3):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        res[name] = e0.elapsed_time(e1) / args.steps
+    added = int(count.item())
+    decayed = int(dec.sum().item())
+    b_add = px * 12 + added * (16 + 56)
+    b_del = scene.n * (12 + 4 + 4 + 4 + 1)
+    return {"workload": "adding step over one 1200x680 keyframe of the 300k-Gaussian room render (observed depth: "
+                        "the room box, 5% missing; tau_T 0.5, tau_D 0.1 m); deleting step over the 300k Gaussians "
+                        "(gamma 0.1 m, eta 0.01)",
+            "add_ms": round(res["add"], 4), "added": added, "add_bytes_alg": int(b_add),
+            "add_hbm_frac": round(b_add / (res["add"] * 1e-3) / 8e12, 4),
+            "add_mpx_s": round(px / (res["add"] * 1e-3) / 1e6, 1),
+            "delete_ms": round(res["delete"], 4), "decayed": decayed, "delete_bytes_alg": int(b_del),
+            "delete_hbm_frac": round(b_del / (res["delete"] * 1e-3) / 8e12, 4)}
 
 
 def run_batched(args, gsr, torch, W):
@@ -638,6 +703,9 @@ def main():
         del src, dst
     log("headline: 300k Gaussians, 1200x680")
     h = run_headline(args, gsr, torch, W)
+    log("map expansion: 300k Gaussians, 1200x680")
+    expansion = run_expansion(args, gsr, torch, W)
+    log("expansion:", expansion)
     batched = None
     if not args.no_batched:
         log("batched: 1M Gaussians, 16 keyframes")
@@ -672,6 +740,7 @@ def main():
         "batched": batched,
         "hypotheses": hyp,
         "tracking": trk,
+        "expansion": expansion,
         "eager_ms_per_step": round(h["eager_ms"], 4),
         "stages_ms": {k: round(v, 4) for k, v in h["stages"].items()},
         "work": h["work"],

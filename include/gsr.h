@@ -73,11 +73,18 @@ typedef struct {
  *   normalised inside), opacity_logit [n] (opacity = sigmoid), rgb [n][3].
  *   mask [n] (nullable, uint8): 0 excludes a Gaussian (coarse-to-fine
  *   selection of reliable Gaussians, Eq. 12).
+ *   sh [n][4][3] (nullable): degree-1 spherical-harmonic colour, 12
+ *   coefficients per Gaussian (Sec. 3.1).  When set, the colour of Gaussian
+ *   i in a view is, per channel c, sum_k Y_k(d) sh[i][k][c] with d the unit
+ *   direction from the camera centre -R^T t to the mean and the real
+ *   harmonics Y_0 = 1/(2 sqrt(pi)), (Y_1, Y_2, Y_3) = sqrt(3/(4 pi)) (d_y,
+ *   d_z, d_x); rgb is then not read (may be NULL).  No offset, no clamp.
  * Non-finite parameters and zero quaternions cull the Gaussian. */
 typedef struct {
   int64_t n;
   const float *mean, *log_scale, *quat, *opacity_logit, *rgb;
   const uint8_t *mask;
+  const float *sh;
 } gsr_gaussians;
 
 enum {
@@ -130,10 +137,14 @@ typedef struct {
 /* Gradient outputs, DEVICE, accumulated (+=).  d_* match the Gaussian
  * arrays; d_pose [n_views][6] = (rho_x, rho_y, rho_z, phi_x, phi_y, phi_z):
  * the derivative w.r.t. a left perturbation T_cw <- Exp(xi) T_cw at xi = 0.
- * Pointers may be NULL when the matching flag is off. */
+ * With spherical-harmonic colour d_sh [n][4][3] receives the coefficient
+ * gradient and d_rgb is not written (may be NULL); the viewing direction
+ * adds to d_mean and d_pose.  Pointers may be NULL when the matching flag
+ * is off. */
 typedef struct {
   float *d_mean, *d_log_scale, *d_quat, *d_opacity_logit, *d_rgb;
   float *d_pose;
+  float *d_sh;
 } gsr_grads;
 
 /* Tuning parameters (picked by gsr_autotune, or set by hand). */

@@ -43,7 +43,7 @@ class gsr_camera(ctypes.Structure):
 
 class gsr_gaussians(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("mean", c_void_p), ("log_scale", c_void_p), ("quat", c_void_p),
-                ("opacity_logit", c_void_p), ("rgb", c_void_p), ("mask", c_void_p)]
+                ("opacity_logit", c_void_p), ("rgb", c_void_p), ("mask", c_void_p), ("sh", c_void_p)]
 
 
 class gsr_config(ctypes.Structure):
@@ -59,7 +59,7 @@ class gsr_images(ctypes.Structure):
 
 class gsr_grads(ctypes.Structure):
     _fields_ = [("d_mean", c_void_p), ("d_log_scale", c_void_p), ("d_quat", c_void_p),
-                ("d_opacity_logit", c_void_p), ("d_rgb", c_void_p), ("d_pose", c_void_p)]
+                ("d_opacity_logit", c_void_p), ("d_rgb", c_void_p), ("d_pose", c_void_p), ("d_sh", c_void_p)]
 
 
 class gsr_tuning(ctypes.Structure):

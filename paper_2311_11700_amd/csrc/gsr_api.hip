@@ -123,7 +123,7 @@ gsr_status validate(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams
   if (n_views != ctx->plan.n_views) return fail(ctx, GSR_E_INVALID, "view count differs from the plan");
   if (ws_bytes < ctx->plan.bytes) return fail(ctx, GSR_E_INVALID, "workspace smaller than gsr_plan() requires");
   if (reinterpret_cast<uintptr_t>(ws) % ALIGN) return fail(ctx, GSR_E_INVALID, "workspace not 256-byte aligned");
-  if (g->n > 0 && (!g->mean || !g->log_scale || !g->quat || !g->opacity_logit || !g->rgb))
+  if (g->n > 0 && (!g->mean || !g->log_scale || !g->quat || !g->opacity_logit || (!g->rgb && !g->sh)))
     return fail(ctx, GSR_E_INVALID, "null Gaussian parameter array");
   if (reinterpret_cast<uintptr_t>(g->quat) % 16) return fail(ctx, GSR_E_INVALID, "quat must be 16-byte aligned");
   if (!(cfg->alpha_max > 0.f && cfg->alpha_max <= 1.f) || cfg->alpha_min < 0.f || cfg->T_min < 0.f ||
@@ -132,7 +132,7 @@ gsr_status validate(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams
   return GSR_OK;
 }
 
-RenderConsts consts(const gsr_config &c) {
+RenderConsts consts(const gsr_config &c, const gsr_gaussians &g) {
   RenderConsts rc;
   rc.alpha_min = c.alpha_min;
   rc.alpha_max = c.alpha_max;
@@ -141,8 +141,9 @@ RenderConsts consts(const gsr_config &c) {
   rc.bg[1] = c.bg[1];
   rc.bg[2] = c.bg[2];
   // Opacity and colour gradients (fields 5-8) feed only the Gaussian
-  // parameters; a pose-only backward skips them.
-  rc.grad_fields = (c.flags & GSR_GAUSS_GRAD) ? 0x3FFu : 0x3FFu & ~0x1E0u;
+  // parameters, except that spherical-harmonic colour depends on the
+  // viewing direction and so on the pose; a pose-only backward skips the rest.
+  rc.grad_fields = (c.flags & GSR_GAUSS_GRAD) ? 0x3FFu : (g.sh ? 0x3FFu & ~0x020u : 0x3FFu & ~0x1E0u);
   rc.id_mask = 0xFFFFFFFFu;
   return rc;
 }
@@ -217,7 +218,7 @@ void enqueue_fused(gsr_ctx *ctx, const gsr_gaussians &g, const gsr_camera *cams,
   enqueue_lists(ctx, g, cams, cfg, ws, true, (cfg.flags & GSR_GRAD_OVERWRITE) ? loss : nullptr,
                 ctx->tuning.lpt_order != 0, s);
   prof_mark(ctx, s, GSR_STAGE_RANGES);
-  launch_render_fused(p, ws, ctx->views_dev, ctx->tile_view_dev, g, consts(cfg), t_rgb, t_depth, pmask, w_rgb,
+  launch_render_fused(p, ws, ctx->views_dev, ctx->tile_view_dev, g, consts(cfg, g), t_rgb, t_depth, pmask, w_rgb,
                       w_depth, loss_cap, out, loss, ctx->tuning, ctx->num_cus, s);
   prof_mark(ctx, s, GSR_STAGE_RASTER);
   prof_mark(ctx, s, GSR_STAGE_RASTER_BWD);
@@ -416,7 +417,7 @@ gsr_status gsr_render_forward(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_ca
   prof_begin(ctx, s);
   enqueue_lists(ctx, *g, cams, *cfg, ws, false, nullptr, false, s);
   prof_mark(ctx, s, GSR_STAGE_RANGES);
-  launch_render_forward(ctx->plan, ws, ctx->views_dev, ctx->tile_view_dev, *g, consts(*cfg), out, s);
+  launch_render_forward(ctx->plan, ws, ctx->views_dev, ctx->tile_view_dev, *g, consts(*cfg, *g), out, s);
   prof_end(ctx, s, GSR_STAGE_RASTER);
   if ((st = last_launch(ctx, "gsr_render_forward launch")) != GSR_OK) return st;
   ctx->last_forward_ws = workspace;
@@ -440,8 +441,9 @@ gsr_status gsr_render_backward(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_c
                                       std::to_string(ctx->fwd_generation) + ", not forward " +
                                       std::to_string(forward_generation));
   if ((cfg->flags & GSR_GAUSS_GRAD) && g->n > 0 &&
-      (!grads->d_mean || !grads->d_log_scale || !grads->d_quat || !grads->d_opacity_logit || !grads->d_rgb))
-    return fail(ctx, GSR_E_INVALID, "GSR_GAUSS_GRAD needs every d_* pointer");
+      (!grads->d_mean || !grads->d_log_scale || !grads->d_quat || !grads->d_opacity_logit ||
+       (g->sh ? !grads->d_sh : !grads->d_rgb)))
+    return fail(ctx, GSR_E_INVALID, "GSR_GAUSS_GRAD needs every d_* pointer (d_sh instead of d_rgb with spherical-harmonic colour)");
   if ((cfg->flags & GSR_POSE_GRAD) && !grads->d_pose) return fail(ctx, GSR_E_INVALID, "GSR_POSE_GRAD needs d_pose");
   if (grads->d_quat && reinterpret_cast<uintptr_t>(grads->d_quat) % 16)
     return fail(ctx, GSR_E_INVALID, "d_quat must be 16-byte aligned");
@@ -451,7 +453,7 @@ gsr_status gsr_render_backward(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_c
   prof_begin(ctx, s);
   for (int j = 0; j <= GSR_STAGE_RASTER; ++j) prof_mark(ctx, s, j);
   launch_fill_f32(reinterpret_cast<float *>(ws.grad2d), 0.f, 2 * p.n_rec * NGRAD2D, s);
-  launch_render_backward(p, ws, ctx->views_dev, ctx->tile_view_dev, *g, consts(*cfg), g_rgb, g_depth, g_T, s);
+  launch_render_backward(p, ws, ctx->views_dev, ctx->tile_view_dev, *g, consts(*cfg, *g), g_rgb, g_depth, g_T, s);
   prof_mark(ctx, s, GSR_STAGE_RASTER_BWD);
   launch_preprocess_backward(p, *g, cams, *cfg, ws, *grads, s);
   prof_end(ctx, s, GSR_STAGE_PREGRAD);
@@ -490,8 +492,9 @@ static gsr_status fused_checks(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_c
   if (!t_rgb || !t_depth || !grads) return fail(ctx, GSR_E_INVALID, "fused step: null target or gradient argument");
   if (!(w_rgb >= 0.f) || !(w_depth >= 0.f)) return fail(ctx, GSR_E_INVALID, "loss weights must be >= 0");
   if ((cfg->flags & GSR_GAUSS_GRAD) && g->n > 0 &&
-      (!grads->d_mean || !grads->d_log_scale || !grads->d_quat || !grads->d_opacity_logit || !grads->d_rgb))
-    return fail(ctx, GSR_E_INVALID, "GSR_GAUSS_GRAD needs every d_* pointer");
+      (!grads->d_mean || !grads->d_log_scale || !grads->d_quat || !grads->d_opacity_logit ||
+       (g->sh ? !grads->d_sh : !grads->d_rgb)))
+    return fail(ctx, GSR_E_INVALID, "GSR_GAUSS_GRAD needs every d_* pointer (d_sh instead of d_rgb with spherical-harmonic colour)");
   if ((cfg->flags & GSR_POSE_GRAD) && !grads->d_pose) return fail(ctx, GSR_E_INVALID, "GSR_POSE_GRAD needs d_pose");
   if (grads->d_quat && reinterpret_cast<uintptr_t>(grads->d_quat) % 16)
     return fail(ctx, GSR_E_INVALID, "d_quat must be 16-byte aligned");
@@ -687,7 +690,7 @@ gsr_status gsr_autotune(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *
       if (t.lpt_order) launch_queue_order(ws, p.total_tiles, s);
       launch_fill_f32(reinterpret_cast<float *>(ws.grad2d), 0.f, 2 * p.n_rec * NGRAD2D, s);
       (void)hipEventRecord(e0, s);
-      launch_render_fused(p, ws, ctx->views_dev, ctx->tile_view_dev, *g, consts(*cfg), target_rgb, target_depth,
+      launch_render_fused(p, ws, ctx->views_dev, ctx->tile_view_dev, *g, consts(*cfg, *g), target_rgb, target_depth,
                           pixel_mask, w_rgb, w_depth, nullptr, nullptr, loss, t, ctx->num_cus, s);
       (void)hipEventRecord(e1, s);
       st = hip_check(ctx, hipEventSynchronize(e1), "hipEventSynchronize");
@@ -850,7 +853,7 @@ gsr_status gsr_work_counts(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_confi
   if (g->n != ctx->plan.n) return fail(ctx, GSR_E_INVALID, "Gaussian count differs from the plan");
   hipStream_t s = static_cast<hipStream_t>(stream);
   Workspace ws = make_ws(ctx->plan, workspace);
-  launch_work_counts(ctx->plan, ws, ctx->views_dev, ctx->tile_view_dev, *g, consts(*cfg), s);
+  launch_work_counts(ctx->plan, ws, ctx->views_dev, ctx->tile_view_dev, *g, consts(*cfg, *g), s);
   unsigned long long host[4];
   gsr_status st = hip_check(ctx, hipMemcpyAsync(host, ws.counts, sizeof(host), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
   if (st == GSR_OK) st = hip_check(ctx, hipStreamSynchronize(s), "hipStreamSynchronize");

@@ -21,6 +21,9 @@ constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_CHUNK = BLOCK * SCAN_ITEMS;
 constexpr int EMIT_BUCKET = 256;  // pairs per emission bucket (one block-iteration of k_emit_pairs)
 constexpr int EXPAND_CHUNK = 2048;  // pixels per block of the adding step (eight rounds of BLOCK)
+// Real spherical harmonics of degree <= 1: 1/(2 sqrt(pi)) and sqrt(3/(4 pi)).
+constexpr double SH_C0 = 0.28209479177387814;
+constexpr double SH_C1 = 0.48860251190291992;
 
 // Bits per radix pass for keys of key_bits bits: ceil(key_bits / 8) passes
 // with the bits spread evenly (fewer digit values make longer output runs).

@@ -69,6 +69,18 @@ __global__ __launch_bounds__(BLOCK) void k_preprocess_bwd(gsr_gaussians g,
 
   R mx = 0, my = 0, mz = 0, qw = 1, qx = 0, qy = 0, qz = 0, qn = 1, s0 = 1, s1 = 1, s2 = 1;
   R opl = 0;
+  // Spherical-harmonic coefficients [4][3] (when the colour is view-dependent).
+  const bool sh_mode = g.sh != nullptr;
+  R shc[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) shc[k] = 0.;
+  if (active && sh_mode) {
+#pragma unroll
+    for (int k = 0; k < 12; ++k) shc[k] = g.sh[12 * i + k];
+  }
+  R gsh[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) gsh[k] = 0.;
   if (active) {
     mx = g.mean[3 * i]; my = g.mean[3 * i + 1]; mz = g.mean[3 * i + 2];
     s0 = exp((R)g.log_scale[3 * i]); s1 = exp((R)g.log_scale[3 * i + 1]);
@@ -192,6 +204,44 @@ __global__ __launch_bounds__(BLOCK) void k_preprocess_bwd(gsr_gaussians g,
         gop += g2[5];
         gc0 += g2[6]; gc1 += g2[7]; gc2 += g2[8];
       }
+      // Spherical-harmonic colour: coefficient gradient Y (x) dL/dc and, through
+      // the viewing direction d = v / |v| (v = mean - o, o = -W^T t),
+      // dL/dv = (I - d d^T) dL/dd / |v|, which adds to the mean and, since a
+      // left perturbation moves o by -W^T rho, W dL/dv to the pose's rho.
+      R gv0 = 0., gv1 = 0., gv2 = 0.;
+      if (sh_mode) {
+        const R t0 = cam.t[0], t1 = cam.t[1], t2 = cam.t[2];
+        const R vx = mx + (W[0] * t0 + W[3] * t1 + W[6] * t2);
+        const R vy = my + (W[1] * t0 + W[4] * t1 + W[7] * t2);
+        const R vz = mz + (W[2] * t0 + W[5] * t1 + W[8] * t2);
+        const R il = R(1) / sqrt(vx * vx + vy * vy + vz * vz);
+        const R dx = vx * il, dy = vy * il, dz = vz * il;
+        const R Y[4] = {SH_C0, SH_C1 * dy, SH_C1 * dz, SH_C1 * dx};
+        const R gc[3] = {g2[6], g2[7], g2[8]};
+        if (want_gauss) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) gsh[3 * k + ch] += Y[k] * gc[ch];
+        }
+        R gY1 = 0., gY2 = 0., gY3 = 0.;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+          gY1 += shc[3 + ch] * gc[ch];
+          gY2 += shc[6 + ch] * gc[ch];
+          gY3 += shc[9 + ch] * gc[ch];
+        }
+        const R gdx = SH_C1 * gY3, gdy = SH_C1 * gY1, gdz = SH_C1 * gY2;
+        const R dot = dx * gdx + dy * gdy + dz * gdz;
+        gv0 = (gdx - dx * dot) * il;
+        gv1 = (gdy - dy * dot) * il;
+        gv2 = (gdz - dz * dot) * il;
+        if (want_gauss) {
+          gm[0] += gv0;
+          gm[1] += gv1;
+          gm[2] += gv2;
+        }
+      }
       if (want_pose) {
         const R rX0 = approx ? pX0 : gX0, rX1 = approx ? pX1 : gX1, rX2 = approx ? pX2 : gX2;
         pr[0] = rX0; pr[1] = rX1; pr[2] = rX2;
@@ -207,6 +257,11 @@ __global__ __launch_bounds__(BLOCK) void k_preprocess_bwd(gsr_gaussians g,
           pr[3] += 2. * (Bm[5] - Bm[7]);
           pr[4] += 2. * (Bm[6] - Bm[2]);
           pr[5] += 2. * (Bm[1] - Bm[3]);
+        }
+        if (sh_mode) {
+          pr[0] += W[0] * gv0 + W[1] * gv1 + W[2] * gv2;
+          pr[1] += W[3] * gv0 + W[4] * gv1 + W[5] * gv2;
+          pr[2] += W[6] * gv0 + W[7] * gv1 + W[8] * gv2;
         }
       }
     }
@@ -267,7 +322,11 @@ __global__ __launch_bounds__(BLOCK) void k_preprocess_bwd(gsr_gaussians g,
       *dq = cur;
     }
     if (gr.d_opacity_logit) put(gr.d_opacity_logit[i], gop * o * (R(1) - o), ow);
-    if (gr.d_rgb) {
+    if (sh_mode && gr.d_sh) {
+#pragma unroll
+      for (int k = 0; k < 12; ++k) put(gr.d_sh[12 * i + k], gsh[k], ow);
+    }
+    if (gr.d_rgb && !sh_mode) {
       put(gr.d_rgb[3 * i], gc0, ow);
       put(gr.d_rgb[3 * i + 1], gc1, ow);
       put(gr.d_rgb[3 * i + 2], gc2, ow);

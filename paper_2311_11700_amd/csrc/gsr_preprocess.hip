@@ -52,11 +52,21 @@ __device__ __forceinline__ uint32_t project_record(const gsr_gaussians &g, const
   const float fl0 = g.log_scale[3 * i], fl1 = g.log_scale[3 * i + 1], fl2 = g.log_scale[3 * i + 2];
   const float4 fq = reinterpret_cast<const float4 *>(g.quat)[i];
   const float fop = g.opacity_logit[i];
-  const float fc0 = g.rgb[3 * i], fc1 = g.rgb[3 * i + 1], fc2 = g.rgb[3 * i + 2];
+  // Colour: RGB, or the 12 spherical-harmonic coefficients [4][3].
+  float col[12];
+  const int ncol = g.sh ? 12 : 3;
+  const float *csrc = g.sh ? g.sh + 12 * i : g.rgb + 3 * i;
+  bool colour_ok = true;
+#pragma unroll
+  for (int k = 0; k < 12; ++k)
+    if (k < ncol) {
+      col[k] = csrc[k];
+      colour_ok = colour_ok && isfinite(col[k]);
+    }
 
   bool ok = isfinite(fm0) && isfinite(fm1) && isfinite(fm2) && isfinite(fl0) && isfinite(fl1) &&
             isfinite(fl2) && isfinite(fq.x) && isfinite(fq.y) && isfinite(fq.z) && isfinite(fq.w) &&
-            isfinite(fop) && isfinite(fc0) && isfinite(fc1) && isfinite(fc2);
+            isfinite(fop) && colour_ok;
   if (g.mask) ok = ok && g.mask[i] != 0;
 
   // Camera-frame centre, each row summed left to right (this is the exact
@@ -151,6 +161,25 @@ __device__ __forceinline__ uint32_t project_record(const gsr_gaussians &g, const
   const float4 fb = make_float4((float)(C / det), (float)(-B / det), (float)(A / det), op);
   ws.recA[rec] = fa;
   ws.recB[rec] = fb;
+  float fc0 = col[0], fc1 = col[1], fc2 = col[2];
+  if (g.sh) {
+    // Degree-1 spherical harmonics of the viewing direction d from the
+    // camera centre -W^T t to the mean: Y_0 = 1/(2 sqrt(pi)),
+    // (Y_1, Y_2, Y_3) = sqrt(3/(4 pi)) (d_y, d_z, d_x).
+    const double t0 = cam.t[0], t1 = cam.t[1], t2 = cam.t[2];
+    const double vx = mx + ((W0 * t0 + W3 * t1) + W6 * t2);
+    const double vy = my + ((W1 * t0 + W4 * t1) + W7 * t2);
+    const double vz = mz + ((W2 * t0 + W5 * t1) + W8 * t2);
+    const double il = 1.0 / sqrt((vx * vx + vy * vy) + vz * vz);
+    const double Y0 = SH_C0, Y1 = SH_C1 * (vy * il), Y2 = SH_C1 * (vz * il), Y3 = SH_C1 * (vx * il);
+    double c[3];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch)
+      c[ch] = ((Y0 * (double)col[ch] + Y1 * (double)col[3 + ch]) + Y2 * (double)col[6 + ch]) + Y3 * (double)col[9 + ch];
+    fc0 = (float)c[0];
+    fc1 = (float)c[1];
+    fc2 = (float)c[2];
+  }
   ws.recC[rec] = make_float4(fc0, fc1, fc2, zf);
   // Every tile of the rectangle gets a pair; the emission marks the ones the
   // alpha support does not reach (none in the full-rectangle mode or

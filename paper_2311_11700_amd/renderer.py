@@ -58,31 +58,40 @@ class Gaussians:
     log_scale: torch.Tensor
     quat: torch.Tensor
     opacity_logit: torch.Tensor
-    rgb: torch.Tensor
+    rgb: Optional[torch.Tensor]
     mask: Optional[torch.Tensor] = None
+    # degree-1 spherical-harmonic colour [n, 4, 3]; when set, rgb is not read
+    sh: Optional[torch.Tensor] = None
 
     @property
     def n(self) -> int:
         return int(self.mean.shape[0])
 
     @staticmethod
-    def from_arrays(mean, log_scale, quat, opacity_logit, rgb, mask=None, device="cuda") -> "Gaussians":
+    def from_arrays(mean, log_scale, quat, opacity_logit, rgb, mask=None, device="cuda", sh=None) -> "Gaussians":
         def t(a, dt=torch.float32):
             return torch.as_tensor(a).to(device=device, dtype=dt).contiguous()
         return Gaussians(t(mean).reshape(-1, 3), t(log_scale).reshape(-1, 3), t(quat).reshape(-1, 4),
-                         t(opacity_logit).reshape(-1), t(rgb).reshape(-1, 3),
-                         None if mask is None else t(mask, torch.uint8).reshape(-1))
+                         t(opacity_logit).reshape(-1), None if rgb is None else t(rgb).reshape(-1, 3),
+                         None if mask is None else t(mask, torch.uint8).reshape(-1),
+                         None if sh is None else t(sh).reshape(-1, 4, 3))
 
     def c(self) -> A.gsr_gaussians:
-        for name in ("mean", "log_scale", "quat", "opacity_logit", "rgb"):
+        names = ("mean", "log_scale", "quat", "opacity_logit") + (("sh",) if self.sh is not None else ("rgb",))
+        for name in names:
             x = getattr(self, name)
-            if x.dtype != torch.float32 or not x.is_contiguous() or not x.is_cuda:
+            if x is None or x.dtype != torch.float32 or not x.is_contiguous() or not x.is_cuda:
                 raise ValueError(f"Gaussians.{name} must be a contiguous float32 device tensor")
+            per = dict(mean=3, log_scale=3, quat=4, opacity_logit=1, rgb=3, sh=12)[name]
+            if x.numel() != per * self.n:
+                raise ValueError(f"Gaussians.{name} holds {x.numel()} values, {per * self.n} expected")
         g = A.gsr_gaussians()
         g.n = self.n
         g.mean, g.log_scale, g.quat = self.mean.data_ptr(), self.log_scale.data_ptr(), self.quat.data_ptr()
-        g.opacity_logit, g.rgb = self.opacity_logit.data_ptr(), self.rgb.data_ptr()
+        g.opacity_logit = self.opacity_logit.data_ptr()
+        g.rgb = self.rgb.data_ptr() if self.rgb is not None else None
         g.mask = self.mask.data_ptr() if self.mask is not None else None
+        g.sh = self.sh.data_ptr() if self.sh is not None else None
         return g
 
 
@@ -211,10 +220,14 @@ class Renderer:
                     T_final=torch.empty(P, device=self.device),
                     last=torch.empty(P, dtype=torch.int32, device=self.device) if last else None)
 
-    def new_grads(self, n: int):
+    def new_grads(self, n: int, sh: bool = False):
+        """Zeroed gradient buffers; with `sh`, d_sh [n, 4, 3] in place of d_rgb."""
         z = lambda *s: torch.zeros(*s, device=self.device)  # noqa: E731
-        return dict(d_mean=z(n, 3), d_log_scale=z(n, 3), d_quat=z(n, 4), d_opacity_logit=z(n),
-                    d_rgb=z(n, 3), d_pose=z(self.n_views, 6))
+        g = dict(d_mean=z(n, 3), d_log_scale=z(n, 3), d_quat=z(n, 4), d_opacity_logit=z(n),
+                 d_rgb=None if sh else z(n, 3), d_pose=z(self.n_views, 6))
+        if sh:
+            g["d_sh"] = z(n, 4, 3)
+        return g
 
     @staticmethod
     def _images_c(out):
@@ -228,8 +241,9 @@ class Renderer:
     @staticmethod
     def _grads_c(gr, n=0, n_views=0):
         g = A.gsr_grads()
-        per = dict(d_mean=3 * n, d_log_scale=3 * n, d_quat=4 * n, d_opacity_logit=n, d_rgb=3 * n, d_pose=6 * n_views)
-        for k in ("d_mean", "d_log_scale", "d_quat", "d_opacity_logit", "d_rgb", "d_pose"):
+        per = dict(d_mean=3 * n, d_log_scale=3 * n, d_quat=4 * n, d_opacity_logit=n, d_rgb=3 * n, d_pose=6 * n_views,
+                   d_sh=12 * n)
+        for k in ("d_mean", "d_log_scale", "d_quat", "d_opacity_logit", "d_rgb", "d_pose", "d_sh"):
             _need(gr.get(k), per[k], k, torch.float32)
             setattr(g, k, _ptr(gr.get(k)))
         return g
@@ -276,7 +290,7 @@ class Renderer:
         """gsr_render_backward of the forward of `generation` (default: this
         renderer's last forward); GsrError(GSR_E_STATE) when the workspace no
         longer holds that forward's state."""
-        grads = grads if grads is not None else self.new_grads(g.n)
+        grads = grads if grads is not None else self.new_grads(g.n, sh=g.sh is not None)
         P = self.total_pixels
         g_rgb = g_rgb.contiguous()
         g_depth = None if g_depth is None else g_depth.contiguous()
@@ -338,7 +352,7 @@ class Renderer:
 
     def render_l1_fused(self, g: Gaussians, cams, cfg: Config, target_rgb, target_depth, pixel_mask=None,
                         w_rgb=1.0, w_depth=0.1, out=None, grads=None, loss=None, loss_cap=None, stream=None):
-        grads = grads if grads is not None else self.new_grads(g.n)
+        grads = grads if grads is not None else self.new_grads(g.n, sh=g.sh is not None)
         loss = loss if loss is not None else torch.zeros(1, device=self.device)
         args = self._fused_args(g, cams, cfg, target_rgb, target_depth, pixel_mask, w_rgb, w_depth, out, grads, loss,
                                 loss_cap)
@@ -350,7 +364,7 @@ class Renderer:
         """gsr_render_l1_fused_noalloc: the fused step on the library's static
         scratch (the plan must fit A.GSR_NOALLOC_SCRATCH_BYTES); `grads` and
         `loss` are caller buffers, as for render_l1_fused."""
-        grads = grads if grads is not None else self.new_grads(g.n)
+        grads = grads if grads is not None else self.new_grads(g.n, sh=g.sh is not None)
         loss = loss if loss is not None else torch.zeros(1, device=self.device)
         args = self._fused_args(g, cams, cfg, target_rgb, target_depth, pixel_mask, w_rgb, w_depth, out, grads, loss,
                                 loss_cap)
@@ -413,7 +427,7 @@ class Renderer:
 
     def autotune(self, g, cams, cfg, target_rgb, target_depth, pixel_mask=None, w_rgb=1.0, w_depth=0.1,
                  reps=3, stream=None) -> dict:
-        grads = self.new_grads(g.n)
+        grads = self.new_grads(g.n, sh=g.sh is not None)
         loss = torch.zeros(1, device=self.device)
         ws, wsb = self._ws()
         P = self.total_pixels
@@ -565,8 +579,9 @@ class Renderer:
 class _RenderFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, mean, log_scale, quat, opacity_logit, rgb, pose_xi, renderer, cams0, cfg, mask, check):
+        sh_mode = rgb.dim() == 3  # [n, 4, 3]: spherical-harmonic colour
         g = Gaussians(mean.contiguous(), log_scale.contiguous(), quat.contiguous(), opacity_logit.contiguous(),
-                      rgb.contiguous(), mask)
+                      None if sh_mode else rgb.contiguous(), mask, rgb.contiguous() if sh_mode else None)
         xi = pose_xi.detach().to(torch.float32).contiguous()
         cams = renderer.pose_apply(xi, cams0)  # T = Exp(xi) T0 on the device
         out = renderer.render_forward(g, cams, cfg, check=check)
@@ -585,7 +600,8 @@ class _RenderFn(torch.autograd.Function):
         g_T = None if g_T is None else g_T.contiguous()
         grads = r.render_backward(g, ctx.cams, ctx.cfg, g_rgb, g_depth, g_T, generation=ctx.generation)
         d_xi = r.pose_xi_grad(ctx.xi, grads["d_pose"])
-        return (grads["d_mean"], grads["d_log_scale"], grads["d_quat"], grads["d_opacity_logit"], grads["d_rgb"],
+        d_col = grads["d_sh"] if g.sh is not None else grads["d_rgb"]
+        return (grads["d_mean"], grads["d_log_scale"], grads["d_quat"], grads["d_opacity_logit"], d_col,
                 d_xi, None, None, None, None, None)
 
 
@@ -593,7 +609,8 @@ def render(renderer: Renderer, mean, log_scale, quat, opacity_logit, rgb, cams: 
            cfg: Optional[Config] = None, pose_xi: Optional[torch.Tensor] = None, mask=None, check: bool = True):
     """Differentiable render of every planned view at the poses
     T_v = Exp(xi_v) T0_v, T0_v the pose of cams[v] and xi_v = pose_xi[v]
-    (zero when pose_xi is None).  Returns flat (rgb, depth, T_final) over the
+    (zero when pose_xi is None).  `rgb` is [n, 3] RGB or [n, 4, 3] degree-1
+    spherical-harmonic coefficients (view-dependent colour).  Returns flat (rgb, depth, T_final) over the
     concatenated views; the gradient of pose_xi is J_l(xi)^T times the
     renderer's left-perturbation pose gradient (gsr_pose_xi_grad).  The
     backward of a call must run before the renderer renders again (each

@@ -7,8 +7,9 @@ import oracle as O
 
 
 def gpu_scene(gsr, scene, mask=None):
-    return gsr.Gaussians.from_arrays(scene.mean, scene.log_scale, scene.quat, scene.opacity_logit, scene.rgb,
-                                     mask=mask)
+    sh = getattr(scene, "sh", None)
+    return gsr.Gaussians.from_arrays(scene.mean, scene.log_scale, scene.quat, scene.opacity_logit,
+                                     scene.rgb if sh is None else None, mask=mask, sh=sh)
 
 
 def oracle_cfg_of(cfg):
@@ -157,9 +158,14 @@ def assert_grads_close(gpu, ref, rtol=1e-3, names=("mean", "log_scale", "quat", 
 
 
 def gpu_grads_numpy(gr):
-    return dict(mean=gr["d_mean"].cpu().numpy(), log_scale=gr["d_log_scale"].cpu().numpy(),
-                quat=gr["d_quat"].cpu().numpy(), opacity_logit=gr["d_opacity_logit"].cpu().numpy(),
-                rgb=gr["d_rgb"].cpu().numpy(), pose=gr["d_pose"].cpu().numpy())
+    out = dict(mean=gr["d_mean"].cpu().numpy(), log_scale=gr["d_log_scale"].cpu().numpy(),
+               quat=gr["d_quat"].cpu().numpy(), opacity_logit=gr["d_opacity_logit"].cpu().numpy(),
+               pose=gr["d_pose"].cpu().numpy())
+    if gr.get("d_rgb") is not None:
+        out["rgb"] = gr["d_rgb"].cpu().numpy()
+    if gr.get("d_sh") is not None:
+        out["sh"] = gr["d_sh"].cpu().numpy()
+    return out
 
 
 def flat_upstream(sizes, seed=1, zero_masks=None):

@@ -37,10 +37,10 @@ def test_library_exports_every_declared_symbol():
 def test_struct_layouts():
     from paper_2311_11700_amd import _abi as A
     assert ctypes.sizeof(A.gsr_camera) == 80
-    assert ctypes.sizeof(A.gsr_gaussians) == 8 + 6 * 8
+    assert ctypes.sizeof(A.gsr_gaussians) == 8 + 7 * 8
     assert ctypes.sizeof(A.gsr_config) == 44
     assert ctypes.sizeof(A.gsr_images) == 40
-    assert ctypes.sizeof(A.gsr_grads) == 48
+    assert ctypes.sizeof(A.gsr_grads) == 56
     assert ctypes.sizeof(A.gsr_tuning) == 16
 
 
