@@ -49,6 +49,9 @@ __device__ __forceinline__ void quat_rot_r(R w, R x, R y, R z, R M[9]) {
 // derivative rho = sum gX, phi = sum (X_c x gX + 2 vee(G_c Sigma_c - Sigma_c G_c)),
 // reduced per block into fixed slots (deterministic order).
 
+// SH: the colour is degree-1 spherical harmonics (instantiated separately so
+// that the RGB path carries none of their registers).
+template <bool SH>
 __global__ __launch_bounds__(BLOCK) void k_preprocess_bwd(gsr_gaussians g,
                                                           const gsr_camera *__restrict__ cams,
                                                           int n_views, PreConstsB pc, Workspace ws,
@@ -70,7 +73,7 @@ __global__ __launch_bounds__(BLOCK) void k_preprocess_bwd(gsr_gaussians g,
   R mx = 0, my = 0, mz = 0, qw = 1, qx = 0, qy = 0, qz = 0, qn = 1, s0 = 1, s1 = 1, s2 = 1;
   R opl = 0;
   // Spherical-harmonic coefficients [4][3] (when the colour is view-dependent).
-  const bool sh_mode = g.sh != nullptr;
+  constexpr bool sh_mode = SH;
   R shc[12];
 #pragma unroll
   for (int k = 0; k < 12; ++k) shc[k] = 0.;
@@ -370,7 +373,7 @@ void launch_preprocess_backward(const Plan &p, const gsr_gaussians &g, const gsr
   }
   PreConstsB pc{cfg.z_near, cfg.lowpass, cfg.cutoff_sigma, cfg.flags, cfg.fov_guard};
   const size_t lds = want_pose ? (size_t)4 * p.n_views * 6 * sizeof(double) : 0;
-  hipLaunchKernelGGL(k_preprocess_bwd, dim3(p.n_pose_blocks), dim3(BLOCK), lds, s, g, cams,
+  hipLaunchKernelGGL(g.sh ? k_preprocess_bwd<true> : k_preprocess_bwd<false>, dim3(p.n_pose_blocks), dim3(BLOCK), lds, s, g, cams,
                      p.n_views, pc, ws, gr);
   if (want_pose)
     hipLaunchKernelGGL(k_pose_reduce, dim3(p.n_views * 6), dim3(BLOCK), 0, s, ws.pose_part, p.n_pose_blocks,

@@ -41,7 +41,8 @@ __device__ __forceinline__ void quat_rot(T w, T x, T y, T z, T R[9]) {
 }
 
 // Project record rec = view * n + i; returns its depth sort key (float32
-// depth bits, 0xFFFFFFFF when culled).
+// depth bits, 0xFFFFFFFF when culled).  SH: spherical-harmonic colour.
+template <bool SH>
 __device__ __forceinline__ uint32_t project_record(const gsr_gaussians &g, const gsr_camera *__restrict__ cams,
                                                    const ViewInfo *__restrict__ views, const PreConsts &pc,
                                                    const Workspace &ws, int view, int64_t i, int64_t rec) {
@@ -53,16 +54,15 @@ __device__ __forceinline__ uint32_t project_record(const gsr_gaussians &g, const
   const float4 fq = reinterpret_cast<const float4 *>(g.quat)[i];
   const float fop = g.opacity_logit[i];
   // Colour: RGB, or the 12 spherical-harmonic coefficients [4][3].
-  float col[12];
-  const int ncol = g.sh ? 12 : 3;
-  const float *csrc = g.sh ? g.sh + 12 * i : g.rgb + 3 * i;
+  constexpr int ncol = SH ? 12 : 3;
+  float col[ncol];
+  const float *csrc = SH ? g.sh + 12 * i : g.rgb + 3 * i;
   bool colour_ok = true;
 #pragma unroll
-  for (int k = 0; k < 12; ++k)
-    if (k < ncol) {
-      col[k] = csrc[k];
-      colour_ok = colour_ok && isfinite(col[k]);
-    }
+  for (int k = 0; k < ncol; ++k) {
+    col[k] = csrc[k];
+    colour_ok = colour_ok && isfinite(col[k]);
+  }
 
   bool ok = isfinite(fm0) && isfinite(fm1) && isfinite(fm2) && isfinite(fl0) && isfinite(fl1) &&
             isfinite(fl2) && isfinite(fq.x) && isfinite(fq.y) && isfinite(fq.z) && isfinite(fq.w) &&
@@ -162,7 +162,7 @@ __device__ __forceinline__ uint32_t project_record(const gsr_gaussians &g, const
   ws.recA[rec] = fa;
   ws.recB[rec] = fb;
   float fc0 = col[0], fc1 = col[1], fc2 = col[2];
-  if (g.sh) {
+  if constexpr (SH) {
     // Degree-1 spherical harmonics of the viewing direction d from the
     // camera centre -W^T t to the mean: Y_0 = 1/(2 sqrt(pi)),
     // (Y_1, Y_2, Y_3) = sqrt(3/(4 pi)) (d_y, d_z, d_x).
@@ -206,6 +206,7 @@ __device__ __forceinline__ uint32_t project_record(const gsr_gaussians &g, const
 // for the sort's first pass.  Block 0 also resets the per-call header words
 // (and the fused step's loss when it is overwritten).
 constexpr int PRE_BLOCK = BLOCK * SORT_ITEMS_DEPTH;
+template <bool SH>
 __global__ __launch_bounds__(PRE_BLOCK) void k_preprocess(gsr_gaussians g, const gsr_camera *__restrict__ cams,
                                                           const ViewInfo *__restrict__ views, PreConsts pc,
                                                           Workspace ws, int n_views, int max_tiles) {
@@ -230,7 +231,7 @@ __global__ __launch_bounds__(PRE_BLOCK) void k_preprocess(gsr_gaussians g, const
   uint32_t key = 0xFFFFFFFFu;
   if (rec < g.n * (int64_t)n_views) {
     const int view = (int)(rec / g.n);
-    key = project_record(g, cams, views, pc, ws, view, rec - (int64_t)view * g.n, rec);
+    key = project_record<SH>(g, cams, views, pc, ws, view, rec - (int64_t)view * g.n, rec);
   }
   // Culled records have the key 0xFFFFFFFF (a visible depth is a positive
   // finite float, whose bits are below it).
@@ -264,7 +265,7 @@ void launch_preprocess(const gsr_gaussians &g, const gsr_camera *cams, const Vie
                clear_grad2d ? 1 : 0, loss_zero, order_total};
   const int64_t n_rec = g.n * (int64_t)n_views;
   if (g.n > 0) {
-    hipLaunchKernelGGL(k_preprocess, dim3((unsigned)((n_rec + PRE_BLOCK - 1) / PRE_BLOCK)), dim3(PRE_BLOCK), 0, s,
+    hipLaunchKernelGGL(g.sh ? k_preprocess<true> : k_preprocess<false>, dim3((unsigned)((n_rec + PRE_BLOCK - 1) / PRE_BLOCK)), dim3(PRE_BLOCK), 0, s,
                        g, cams, views, pc, ws, n_views, max_sort_tiles);
   } else {
     launch_reset_header(ws, s);
