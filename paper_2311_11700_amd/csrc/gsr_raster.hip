@@ -487,15 +487,17 @@ static RasterArgs raster_args(const Workspace &ws, const ViewInfo *views, const 
   return RasterArgs{ws.recA, ws.recB, ws.recC, ids, ws.ranges, views, tile_view, g.n, rc};
 }
 
+// Per-pixel forward state that a separate backward reads (the unfused
+// forward); all null in the fused step, whose backward keeps it in registers.
 struct PixelState {
   float *T;
   int32_t *last;
-  float *zr;  // null when no separate backward reads it (fused step)
+  float *zr;
 };
 
 __device__ __forceinline__ void save_state(const PixelState &ps, int64_t pix, const FwdState &st) {
-  ps.T[pix] = st.T;
-  ps.last[pix] = st.last;
+  if (ps.T) ps.T[pix] = st.T;
+  if (ps.last) ps.last[pix] = st.last;
   if (ps.zr) ps.zr[pix] = st.zr;
 }
 
@@ -583,6 +585,18 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
       const int tile = queue ? (int)queue[q] : q;
       const TileInfo ti = tile_info(tile, a.views, a.tile_view, a.ranges);
       const uint64_t clk0 = wall_clock64();
+      // The pixel's targets, loaded before the forward walk hides their latency.
+      float tc0 = 0.f, tc1 = 0.f, tc2 = 0.f, td = 0.f, cap = __builtin_inff();
+      bool m = false;
+      if (ti.inside) {
+        const float *tc = t_rgb + 3 * ti.pix_off + (ti.pix - ti.pix_off);
+        tc0 = tc[0];
+        tc1 = tc[ti.HW];
+        tc2 = tc[2 * ti.HW];
+        td = t_depth[ti.pix];
+        m = pmask ? pmask[ti.pix] != 0 : true;
+        if (loss_cap) cap = loss_cap[ti.view];
+      }
       FwdState st;
       int staged_lo;
       tile_forward<false, NB>(ti, a.n, a.recA, a.recB, a.recC, a.ids, a.rc, s_rec, st, nullptr, s_id,
@@ -591,10 +605,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
       float lpx = 0.f;
       if (ti.inside) {
         const int64_t loc = ti.pix - ti.pix_off;
-        const bool m = pmask ? pmask[ti.pix] != 0 : true;
-        const float *tc = t_rgb + 3 * ti.pix_off + loc;
-        const float e0 = st.C0 - tc[0], e1 = st.C1 - tc[ti.HW], e2 = st.C2 - tc[2 * ti.HW];
-        const float td = t_depth[ti.pix];
+        const float e0 = st.C0 - tc0, e1 = st.C1 - tc1, e2 = st.C2 - tc2;
         const bool md = m && td > 0.f;
         const float ed = st.D - td;
         if (m) {
@@ -603,7 +614,7 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
         }
         if (out.loss) out.loss[ti.pix] = lpx;
         // Outlier pixels (own loss above the view's cap) are ignored.
-        const bool keep = m && !(loss_cap && lpx > loss_cap[ti.view]);
+        const bool keep = m && !(lpx > cap);
         lpx = keep ? lpx : 0.f;
         if (keep) {
           in.gC0 = w_rgb * sgnf(e0);
@@ -720,7 +731,7 @@ void launch_render_fused(const Plan &p, const Workspace &ws, const ViewInfo *vie
   const int need = (p.total_tiles + tun.tiles_per_pop - 1) / tun.tiles_per_pop;
   if (grid > need) grid = need;
   if (grid < 1) grid = 1;
-  PixelState ps{ws.T_final, ws.last, nullptr};
+  PixelState ps{nullptr, nullptr, nullptr};  // the fused backward keeps the forward state in registers
   const uint32_t *queue = tun.lpt_order ? ws.queue : nullptr;
 #define GSR_LAUNCH_FUSED(NB_)                                                                                  \
   hipLaunchKernelGGL(k_render_fused<NB_>, dim3(grid), dim3(BLOCK), 0, s, a, ws.hdr, queue, p.total_tiles,            \
@@ -740,22 +751,17 @@ void launch_render_fused(const Plan &p, const Workspace &ws, const ViewInfo *vie
 // Work of the last forward, for the roofline: the forward walk of every
 // tile again, with counting on and no outputs (the workspace still holds the
 // records, lists and ranges of that call).
-__global__ __launch_bounds__(BLOCK) void k_count_walk(RasterArgs a, unsigned long long *__restrict__ counts) {
+// The walk also sums every pixel's `last` (the entries the backward walk
+// examines) into counts[3], and block 0 copies the pair count into counts[0].
+__global__ __launch_bounds__(BLOCK) void k_count_walk(RasterArgs a, const uint32_t *__restrict__ hdr,
+                                                      unsigned long long *__restrict__ counts) {
   __shared__ Staged s_rec[BATCH];
   const TileInfo ti = tile_info(blockIdx.x, a.views, a.tile_view, a.ranges);
   FwdState st;
   tile_forward<true>(ti, a.n, a.recA, a.recB, a.recC, a.ids, a.rc, s_rec, st, counts);
-}
-
-// counts[0] = pairs (from the header), counts[3] = sum of `last`.
-__global__ __launch_bounds__(BLOCK) void k_work_counts(const int32_t *__restrict__ last, int64_t total,
-                                                       const uint32_t *__restrict__ hdr,
-                                                       unsigned long long *__restrict__ counts) {
-  unsigned long long c = 0;
-  for (int64_t p = (int64_t)blockIdx.x * BLOCK + threadIdx.x; p < total; p += (int64_t)gridDim.x * BLOCK)
-    c += (unsigned long long)last[p];
+  unsigned long long c = ti.inside ? (unsigned long long)st.last : 0ull;
   for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
-  if ((threadIdx.x & 63) == 0) atomicAdd(counts + 3, c);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(counts + 3, c);
   if (blockIdx.x == 0 && threadIdx.x == 0)
     counts[0] = *reinterpret_cast<const unsigned long long *>(hdr + HDR_NPAIRS);
 }
@@ -765,8 +771,7 @@ void launch_work_counts(const Plan &p, const Workspace &ws, const ViewInfo *view
   launch_fill_u32(reinterpret_cast<uint32_t *>(ws.counts), 0u, 8, s);
   const RasterArgs a = raster_args(ws, views, tile_view, g, rc);
   if (p.total_tiles > 0)
-    hipLaunchKernelGGL(k_count_walk, dim3(p.total_tiles), dim3(BLOCK), 0, s, a, ws.counts);
-  hipLaunchKernelGGL(k_work_counts, dim3(256), dim3(BLOCK), 0, s, ws.last, p.total_pixels, ws.hdr, ws.counts);
+    hipLaunchKernelGGL(k_count_walk, dim3(p.total_tiles), dim3(BLOCK), 0, s, a, ws.hdr, ws.counts);
 }
 
 }  // namespace gsr
