@@ -90,11 +90,13 @@ Workspace make_ws(const Plan &p, void *base_v) {
     w.pkeys[k] = reinterpret_cast<uint32_t *>(base + p.off_pkeys[k]);
     w.pvals[k] = reinterpret_cast<uint32_t *>(base + p.off_pvals[k]);
   }
-  w.scan_part = reinterpret_cast<unsigned long long *>(base + p.off_scan);
   w.hist = reinterpret_cast<uint32_t *>(base + p.off_hist);
   w.hoff = reinterpret_cast<uint32_t *>(base + p.off_hoff);
   w.bucket_rec = reinterpret_cast<uint32_t *>(base + p.off_bucket);
   w.digit_total = reinterpret_cast<uint32_t *>(base + p.off_digit);
+  w.whist = reinterpret_cast<unsigned long long *>(base + p.off_whist);
+  w.whoff = reinterpret_cast<unsigned long long *>(base + p.off_whoff);
+  w.wdigit = reinterpret_cast<unsigned long long *>(base + p.off_wdigit);
   w.ranges = reinterpret_cast<int2 *>(base + p.off_ranges);
   w.T_final = reinterpret_cast<float *>(base + p.off_T);
   w.last = reinterpret_cast<int32_t *>(base + p.off_last);
@@ -341,7 +343,7 @@ gsr_status gsr_plan(gsr_ctx *ctx, int64_t n, int n_views, const int32_t *wh_host
   p.pack_shift = bits + rbits <= 32 ? rbits : 0;
   const int64_t dtile = (int64_t)BLOCK * SORT_ITEMS_DEPTH, ptile = (int64_t)BLOCK * SORT_ITEMS_PAIR;
   p.max_sort_tiles = (int)std::max<int64_t>((p.n_rec + dtile - 1) / dtile, (p.capacity + ptile - 1) / ptile);
-  p.n_scan_blocks = (int)std::max<int64_t>(1, (p.n_rec + SCAN_CHUNK - 1) / SCAN_CHUNK);
+  p.depth_tiles = (int)std::max<int64_t>(1, (p.n_rec + dtile - 1) / dtile);
   p.n_pose_blocks = (int)std::max<int64_t>(1, (n + BLOCK - 1) / BLOCK);
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -360,13 +362,15 @@ gsr_status gsr_plan(gsr_ctx *ctx, int64_t n, int n_views, const int32_t *wh_host
   p.off_tile_visible = take(4 * (size_t)((nr + (size_t)BLOCK * SORT_ITEMS_DEPTH - 1) / ((size_t)BLOCK * SORT_ITEMS_DEPTH)));
   for (int k = 0; k < 2; ++k) p.off_dkeys[k] = take(4 * nr);
   for (int k = 0; k < 2; ++k) p.off_dvals[k] = take(4 * nr);
-  p.off_scan = take(8 * ((size_t)p.n_scan_blocks + 1));
   for (int k = 0; k < 2; ++k) p.off_pkeys[k] = take(4 * cap);
   for (int k = 0; k < 2; ++k) p.off_pvals[k] = take(4 * cap);
   p.off_hist = take(4 * (size_t)RADIX * p.max_sort_tiles);
   p.off_hoff = take(4 * (size_t)RADIX * p.max_sort_tiles);
   p.off_bucket = take(4 * (cap / EMIT_BUCKET + 2));
   p.off_digit = take(4 * RADIX);
+  p.off_whist = take(8 * (size_t)RADIX * p.depth_tiles);
+  p.off_whoff = take(8 * (size_t)RADIX * p.depth_tiles);
+  p.off_wdigit = take(8 * RADIX);
   p.off_ranges = take(8 * (size_t)p.total_tiles);
   p.off_T = take(4 * (size_t)pixels);
   p.off_last = take(4 * (size_t)pixels);

@@ -18,7 +18,6 @@ constexpr int SORT_ITEMS_PAIR = 8;  // keys per thread per sort tile, tile sort 
 constexpr int RADIX_BITS = 8;
 constexpr int RADIX = 1 << RADIX_BITS;
 constexpr int SCAN_ITEMS = 8;
-constexpr int SCAN_CHUNK = BLOCK * SCAN_ITEMS;
 constexpr int EMIT_BUCKET = 256;  // pairs per emission bucket (one block-iteration of k_emit_pairs)
 constexpr int EXPAND_CHUNK = 2048;  // pixels per block of the adding step (eight rounds of BLOCK)
 // Real spherical harmonics of degree <= 1: 1/(2 sqrt(pi)) and sqrt(3/(4 pi)).
@@ -121,13 +120,15 @@ struct Workspace {
   uint32_t *tile_visible;  // [depth-sort tiles] visible records of each projection block
   uint32_t *dkeys[2];      // [n_rec] depth keys (float32 bits), ping-pong
   uint32_t *dvals[2];      // [n_rec] record ids, ping-pong
-  unsigned long long *scan_part;  // [n_scan_blocks + 1]
   uint32_t *pkeys[2];      // [capacity] global tile ids, ping-pong
   uint32_t *pvals[2];      // [capacity] record ids, ping-pong
   uint32_t *hist;          // [RADIX][max_sort_tiles] digit counts per sort tile
   uint32_t *hoff;          // [RADIX][max_sort_tiles] exclusive scan of hist (digit-major)
   uint32_t *bucket_rec;    // [capacity / EMIT_BUCKET + 2] depth-order record holding pair EMIT_BUCKET * b
   uint32_t *digit_total;   // [RADIX]
+  unsigned long long *whist;   // [RADIX][depth_tiles] pair counts per digit and tile (depth sort's last pass)
+  unsigned long long *whoff;   // [RADIX][depth_tiles] exclusive scan of whist over the tiles
+  unsigned long long *wdigit;  // [RADIX] pair counts per digit
   int2 *ranges;            // [total_tiles]
   float *T_final;          // [total_pixels]
   int32_t *last;           // [total_pixels]
@@ -159,13 +160,13 @@ struct Plan {
   int tile_bits = 0;
   int pack_shift = 0;      // record-id bits below the tile in a packed pair word (0: unpacked)
   int max_sort_tiles = 0;
-  int n_scan_blocks = 0;
+  int depth_tiles = 0;     // sort tiles of the depth sort
   int n_pose_blocks = 0;
   size_t bytes = 0;
   // byte offsets inside the workspace
   size_t off_hdr, off_recA, off_recB, off_recC, off_rect, off_count, off_dkeys[2], off_dvals[2],
-      off_scan, off_pkeys[2], off_pvals[2], off_hist, off_digit, off_ranges, off_T, off_last, off_zr,
-      off_grad2d, off_pose, off_queue, off_loss, off_counts, off_hoff, off_bucket,
+      off_pkeys[2], off_pvals[2], off_hist, off_digit, off_ranges, off_T, off_last, off_zr,
+      off_grad2d, off_pose, off_queue, off_loss, off_counts, off_hoff, off_bucket, off_whist, off_whoff, off_wdigit,
       off_support, off_tile_visible, off_tile_cost, off_expand_bits, off_expand_cnt;
 };
 

@@ -92,49 +92,94 @@ __device__ __forceinline__ uint32_t sort_count(const unsigned long long *n_dev, 
   return n < cap ? (uint32_t)n : cap;
 }
 
-// Digit counts of each sort tile (STILE consecutive keys), digit-major.
-template <int ITEMS>
+// The last pass of the depth sort carries a weight per key (its record's
+// pair count): the histogram also sums the weights per digit and tile, the
+// scan scans them, and the scatter gives every output position the
+// exclusive prefix of the weights in the sorted order (the record's first
+// pair) and fills the emission buckets, so the records need no scan of their
+// own before the emission.
+struct PassWeights {
+  const uint32_t *vals;           // the keys' values (weights are looked up by value)
+  const uint32_t *weight;         // weight of the key with value v: weight[v]
+  unsigned long long *whist;      // [RADIX][wstride] weight sums per digit and tile
+  unsigned long long *whoff;      // [RADIX][wstride] exclusive scan of whist over the tiles
+  unsigned long long *wdigit;     // [RADIX] weight totals per digit
+  int wstride;
+  uint32_t *bucket;               // emission buckets (EMIT_BUCKET pairs each)
+  unsigned long long cap;         // pair capacity: offsets are clamped to it
+  uint32_t *hdr;                  // pair count and overflow flag
+};
+
+// Adds w of every lane in `valid` into acc[d]: one LDS atomic per distinct
+// digit of the wavefront (keys of a tile often share their high digits).
+__device__ __forceinline__ void wave_add_by_digit(unsigned long long *acc, uint32_t d, unsigned long long w,
+                                                  uint64_t valid) {
+  const int lane = __lane_id();
+  uint64_t todo = valid;
+  while (todo) {
+    const int leader = __ffsll((long long)todo) - 1;
+    const uint32_t dl = __shfl(d, leader);
+    const uint64_t grp = __ballot(d == dl) & todo;
+    unsigned long long x = (grp >> lane) & 1ull ? w : 0ull;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+    if (lane == leader) atomicAdd(&acc[dl], x);
+    todo &= ~grp;
+  }
+}
+
+// Digit counts of each sort tile (STILE consecutive keys), digit-major (and,
+// WEIGHTED, the weight sums).
+template <int ITEMS, bool WEIGHTED>
 __global__ __launch_bounds__(BLOCK) void k_radix_hist(const uint32_t *__restrict__ keys,
                                                       const unsigned long long *n_dev,
                                                       uint32_t n_static, uint32_t cap, int shift,
                                                       int nbits, uint32_t *__restrict__ hist,
-                                                      int max_tiles) {
+                                                      int max_tiles, PassWeights pw) {
   __shared__ uint32_t cnt[RADIX];
+  __shared__ unsigned long long wcnt[WEIGHTED ? RADIX : 1];
   const uint32_t n = sort_count(n_dev, n_static, cap);
   constexpr int STILE = BLOCK * ITEMS;
   const uint32_t ntiles = (n + STILE - 1) / STILE;
   const uint32_t mask = (1u << nbits) - 1u;
   for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     cnt[threadIdx.x] = 0u;
-    uint32_t kr[ITEMS];
+    if (WEIGHTED) wcnt[threadIdx.x] = 0ull;
+    uint32_t kr[ITEMS], wr[WEIGHTED ? ITEMS : 1];
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
       const uint32_t idx = t * STILE + r * BLOCK + threadIdx.x;
       kr[r] = idx < n ? keys[idx] : 0u;
+      if (WEIGHTED) wr[r] = idx < n ? pw.weight[pw.vals[idx]] : 0u;
     }
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
       const bool valid = t * STILE + r * BLOCK + threadIdx.x < n;
       const uint32_t d = (kr[r] >> shift) & mask;
-      const uint64_t peers = match_digit(d, nbits, __ballot(valid));
+      const uint64_t vmask = __ballot(valid);
+      const uint64_t peers = match_digit(d, nbits, vmask);
       if (valid && (peers & lanemask_lt()) == 0ull) atomicAdd(&cnt[d], (uint32_t)__popcll(peers));
+      if (WEIGHTED) wave_add_by_digit(wcnt, d, wr[r], vmask);
     }
     __syncthreads();
     hist[(size_t)threadIdx.x * max_tiles + t] = cnt[threadIdx.x];
+    if (WEIGHTED) pw.whist[(size_t)threadIdx.x * pw.wstride + t] = wcnt[threadIdx.x];
     __syncthreads();
   }
 }
 
 // One block per digit: exclusive scan over the tiles of that digit's column
-// (counts stay in hist, offsets go to hoff).
-template <int ITEMS>
+// (counts stay in hist, offsets go to hoff; WEIGHTED, the same for the
+// weight sums).
+template <int ITEMS, bool WEIGHTED>
 __global__ __launch_bounds__(BLOCK) void k_radix_scan(const uint32_t *__restrict__ hist,
                                                       uint32_t *__restrict__ hoff,
                                                       const unsigned long long *n_dev,
                                                       uint32_t n_static, uint32_t cap, int max_tiles,
-                                                      uint32_t *__restrict__ digit_total) {
+                                                      uint32_t *__restrict__ digit_total, PassWeights pw) {
   __shared__ uint32_t s_w[4];
+  __shared__ unsigned long long s_w64[4];
   const uint32_t n = sort_count(n_dev, n_static, cap);
   constexpr int STILE = BLOCK * ITEMS;
   const uint32_t ntiles = (n + STILE - 1) / STILE;
@@ -161,6 +206,31 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scan(const uint32_t *__restrict
     carry += total;
   }
   if (threadIdx.x == 0) digit_total[blockIdx.x] = carry;
+  if (WEIGHTED) {
+    const unsigned long long *wcol = pw.whist + (size_t)blockIdx.x * pw.wstride;
+    unsigned long long *wocol = pw.whoff + (size_t)blockIdx.x * pw.wstride;
+    unsigned long long wcarry = 0ull;
+    for (uint32_t base = 0; base < ntiles; base += BLOCK * SCAN_ITEMS) {
+      unsigned long long v[SCAN_ITEMS];
+      unsigned long long sum = 0ull;
+#pragma unroll
+      for (int k = 0; k < SCAN_ITEMS; ++k) {
+        const uint32_t idx = base + threadIdx.x * SCAN_ITEMS + k;
+        v[k] = idx < ntiles ? wcol[idx] : 0ull;
+        sum += v[k];
+      }
+      unsigned long long total;
+      unsigned long long pre = block_exclusive_scan<unsigned long long>(sum, s_w64, total) + wcarry;
+#pragma unroll
+      for (int k = 0; k < SCAN_ITEMS; ++k) {
+        const uint32_t idx = base + threadIdx.x * SCAN_ITEMS + k;
+        if (idx < ntiles) wocol[idx] = pre;
+        pre += v[k];
+      }
+      wcarry += total;
+    }
+    if (threadIdx.x == 0) pw.wdigit[blockIdx.x] = wcarry;
+  }
 }
 
 // Stable scatter of one digit pass.  Wavefront w ranks the w-th quarter of
@@ -176,16 +246,31 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scan(const uint32_t *__restrict
 // left out (the digit counts in hist must leave them out too).  The output
 // is dense either way; with n_out, block 0 stores the number of keys
 // written there.
-template <int ITEMS, bool VALS>
+//
+// WEIGHTED (the depth sort's last pass): keys_out receives, instead of the
+// keys, each position's exclusive prefix of the weights in the sorted order
+// clamped to the capacity, every emission bucket b gets the position holding
+// weight unit EMIT_BUCKET b (and the one after the last bucket the position
+// holding the last emitted unit), and block 0 stores the weight total as the
+// pair count (with the overflow flag when it exceeds the capacity).
+template <int ITEMS, bool VALS, bool WEIGHTED>
 __global__ __launch_bounds__(BLOCK) void k_radix_scatter(
     const uint32_t *__restrict__ keys_in, const uint32_t *__restrict__ vals_in,
     uint32_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out,
     const unsigned long long *n_dev, uint32_t n_static, uint32_t cap, int shift, int nbits,
     const uint32_t *__restrict__ hist, const uint32_t *__restrict__ hoff, int max_tiles,
     const uint32_t *__restrict__ digit_total, const uint32_t *__restrict__ tile_count,
-    uint32_t key_limit, unsigned long long *__restrict__ n_out) {
+    uint32_t key_limit, unsigned long long *__restrict__ n_out, PassWeights pw) {
+  static_assert(!WEIGHTED || VALS, "weights are looked up by value");
   constexpr int STILE = BLOCK * ITEMS;
   constexpr int WKEYS = 64 * ITEMS;
+  __shared__ unsigned long long s_wbase[WEIGHTED ? RADIX : 1];  // weight before each digit
+  __shared__ unsigned long long s_wgoff[WEIGHTED ? RADIX : 1];  // weight before the tile's run of each digit
+  __shared__ unsigned long long s_lw[WEIGHTED ? RADIX : 1];     // local weight before each digit's run
+  __shared__ unsigned long long s_w64[4];
+  __shared__ uint32_t s_c[WEIGHTED ? STILE : 1];                // weight of each local slot
+  __shared__ unsigned long long s_e[WEIGHTED ? STILE : 1];      // exclusive weight prefix over the local slots
+  __shared__ unsigned long long s_wtotal;
   __shared__ uint32_t s_base[RADIX];   // first output position of each digit
   __shared__ uint32_t s_goff[RADIX];   // output position minus local position, per digit
   __shared__ uint32_t s_lbase[RADIX];  // first local position of each digit
@@ -203,12 +288,24 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(
     s_base[dig] = block_exclusive_scan<uint32_t>(digit_total[dig], s_w, total);
     if (n_out && blockIdx.x == 0 && threadIdx.x == 0) *n_out = total;
   }
+  if (WEIGHTED) {
+    unsigned long long wtotal;
+    s_wbase[dig] = block_exclusive_scan<unsigned long long>(pw.wdigit[dig], s_w64, wtotal);
+    if (threadIdx.x == 0) s_wtotal = wtotal;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      *reinterpret_cast<unsigned long long *>(pw.hdr + HDR_NPAIRS) = wtotal;
+      if (wtotal > pw.cap) {
+        atomicOr(pw.hdr + HDR_OVERFLOW, 1u);
+        atomicMax(reinterpret_cast<unsigned long long *>(pw.hdr + HDR_REQUIRED), wtotal);
+      }
+    }
+  }
   for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const uint32_t t0 = t * STILE;
     const uint32_t tn = tile_count ? tile_count[t] : (n - t0 < (uint32_t)STILE ? n - t0 : (uint32_t)STILE);
     const uint32_t tend = t0 + tn;  // keys of this tile: [t0, tend)
     const uint32_t wbase = t0 + wave * WKEYS + lane;
-    uint32_t kr[ITEMS], vr[ITEMS], rank[ITEMS];
+    uint32_t kr[ITEMS], vr[ITEMS], rank[ITEMS], cr[WEIGHTED ? ITEMS : 1];
     uint32_t live = 0u;  // bit r: item r is a key to sort
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
@@ -219,6 +316,10 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r)
       if (wbase + r * 64 < tend && (key_limit == 0u || kr[r] < key_limit)) live |= 1u << r;
+    if (WEIGHTED) {
+#pragma unroll
+      for (int r = 0; r < ITEMS; ++r) cr[r] = (live >> r) & 1u ? pw.weight[vr[r]] : 0u;
+    }
     s_wc[0][dig] = s_wc[1][dig] = s_wc[2][dig] = s_wc[3][dig] = 0u;
     uint32_t tkeys;  // keys of this tile that are sorted (block-uniform)
     {
@@ -226,6 +327,11 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(
       const uint32_t lbase = block_exclusive_scan<uint32_t>(cnt, s_w, tkeys);
       s_lbase[dig] = lbase;
       s_goff[dig] = s_base[dig] + hoff[(size_t)dig * max_tiles + t] - lbase;
+    }
+    if (WEIGHTED) {
+      unsigned long long ltot;
+      s_lw[dig] = block_exclusive_scan<unsigned long long>(pw.whist[(size_t)dig * pw.wstride + t], s_w64, ltot);
+      s_wgoff[dig] = s_wbase[dig] + pw.whoff[(size_t)dig * pw.wstride + t];
     }
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
@@ -254,13 +360,45 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(
         const uint32_t lp = s_wc[wave][(kr[r] >> shift) & mask] + rank[r];
         s_k[lp] = kr[r];
         if (VALS) s_v[lp] = vr[r];
+        if (WEIGHTED) s_c[lp] = cr[r];
       }
     }
     __syncthreads();
+    if (WEIGHTED) {
+      // Exclusive prefix of the weights over the local slots (thread t:
+      // slots [t ITEMS, (t + 1) ITEMS)).
+      const uint32_t s0 = threadIdx.x * (uint32_t)ITEMS;
+      unsigned long long sum = 0ull;
+#pragma unroll
+      for (int q = 0; q < ITEMS; ++q) sum += s0 + q < tkeys ? s_c[s0 + q] : 0u;
+      unsigned long long ltot;
+      unsigned long long pre = block_exclusive_scan<unsigned long long>(sum, s_w64, ltot);
+#pragma unroll
+      for (int q = 0; q < ITEMS; ++q) {
+        if (s0 + q < tkeys) {
+          s_e[s0 + q] = pre;
+          pre += s_c[s0 + q];
+        }
+      }
+      __syncthreads();
+    }
     for (uint32_t i = threadIdx.x; i < tkeys; i += BLOCK) {
       const uint32_t key = s_k[i];
-      const uint32_t gpos = s_goff[(key >> shift) & mask] + i;
-      keys_out[gpos] = key;
+      const uint32_t d = (key >> shift) & mask;
+      const uint32_t gpos = s_goff[d] + i;
+      if (!WEIGHTED) {
+        keys_out[gpos] = key;
+      } else {
+        // The record's first pair and the emission buckets it holds.
+        const unsigned long long o = s_wgoff[d] + (s_e[i] - s_lw[d]);
+        const unsigned long long oe = o + s_c[i];
+        const unsigned long long e = oe < pw.cap ? oe : pw.cap;
+        const unsigned long long n_emit = s_wtotal < pw.cap ? s_wtotal : pw.cap;
+        keys_out[gpos] = (uint32_t)(o < pw.cap ? o : pw.cap);
+        for (unsigned long long b = (o + EMIT_BUCKET - 1) / EMIT_BUCKET; b * EMIT_BUCKET < e; ++b)
+          pw.bucket[b] = gpos;
+        if (o < n_emit && n_emit <= e) pw.bucket[(n_emit + EMIT_BUCKET - 1) / EMIT_BUCKET] = gpos;
+      }
       if (VALS) vals_out[gpos] = s_v[i];
     }
     __syncthreads();
@@ -278,35 +416,55 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(
 // only (n_static covering all tiles' slots); with key_limit0 != 0 it drops the
 // words >= key_limit0 (the hist0_ready counts leave them out).  With
 // n_after0, the first pass stores the number of words it kept there and the
-// later passes sort that many.
+// later passes sort that many.  With wlast, the last pass is weighted (see
+// PassWeights; wlast->vals is filled in here).
 template <int ITEMS>
 static int radix_sort(uint32_t *keys[2], uint32_t *vals[2], const unsigned long long *n_dev,
                       uint32_t n_static, uint32_t cap, int base, int key_bits, uint32_t *hist, uint32_t *hoff,
                       int max_tiles, uint32_t *digit_total, int grid, bool hist0_ready,
                       const uint32_t *tile_count0, uint32_t key_limit0, unsigned long long *n_after0,
-                      hipStream_t s) {
+                      const PassWeights *wlast, hipStream_t s) {
   const int per = radix_digit_bits(key_bits);
   int cur = 0;
   for (int sh = 0; sh < key_bits; sh += per) {
     const int nbits = key_bits - sh < per ? key_bits - sh : per;
     const int shift = base + sh;
+    const bool weighted = wlast && sh + per >= key_bits;
+    PassWeights pw{};
+    if (weighted) {
+      pw = *wlast;
+      pw.vals = vals[cur];
+    }
     const uint32_t *tile_count = sh == 0 ? tile_count0 : nullptr;
     const uint32_t key_limit = sh == 0 ? key_limit0 : 0u;
     unsigned long long *n_out = sh == 0 ? n_after0 : nullptr;
     if (sh > 0 && n_after0) n_dev = n_after0;
-    if (sh > 0 || !hist0_ready)
-      hipLaunchKernelGGL(k_radix_hist<ITEMS>, dim3(grid), dim3(BLOCK), 0, s, keys[cur], n_dev, n_static, cap,
-                         shift, nbits, hist, max_tiles);
-    hipLaunchKernelGGL(k_radix_scan<ITEMS>, dim3(RADIX), dim3(BLOCK), 0, s, hist, hoff, n_dev, n_static, cap,
-                       max_tiles, digit_total);
-    if (vals)
-      hipLaunchKernelGGL((k_radix_scatter<ITEMS, true>), dim3(grid), dim3(BLOCK), 0, s, keys[cur], vals[cur],
-                         keys[cur ^ 1], vals[cur ^ 1], n_dev, n_static, cap, shift, nbits, hist, hoff,
-                         max_tiles, digit_total, tile_count, key_limit, n_out);
+    if (sh > 0 || !hist0_ready) {
+      if (weighted)
+        hipLaunchKernelGGL((k_radix_hist<ITEMS, true>), dim3(grid), dim3(BLOCK), 0, s, keys[cur], n_dev, n_static,
+                           cap, shift, nbits, hist, max_tiles, pw);
+      else
+        hipLaunchKernelGGL((k_radix_hist<ITEMS, false>), dim3(grid), dim3(BLOCK), 0, s, keys[cur], n_dev,
+                           n_static, cap, shift, nbits, hist, max_tiles, pw);
+    }
+    if (weighted)
+      hipLaunchKernelGGL((k_radix_scan<ITEMS, true>), dim3(RADIX), dim3(BLOCK), 0, s, hist, hoff, n_dev, n_static,
+                         cap, max_tiles, digit_total, pw);
     else
-      hipLaunchKernelGGL((k_radix_scatter<ITEMS, false>), dim3(grid), dim3(BLOCK), 0, s, keys[cur],
+      hipLaunchKernelGGL((k_radix_scan<ITEMS, false>), dim3(RADIX), dim3(BLOCK), 0, s, hist, hoff, n_dev,
+                         n_static, cap, max_tiles, digit_total, pw);
+    if (weighted)
+      hipLaunchKernelGGL((k_radix_scatter<ITEMS, true, true>), dim3(grid), dim3(BLOCK), 0, s, keys[cur],
+                         vals[cur], keys[cur ^ 1], vals[cur ^ 1], n_dev, n_static, cap, shift, nbits, hist, hoff,
+                         max_tiles, digit_total, tile_count, key_limit, n_out, pw);
+    else if (vals)
+      hipLaunchKernelGGL((k_radix_scatter<ITEMS, true, false>), dim3(grid), dim3(BLOCK), 0, s, keys[cur],
+                         vals[cur], keys[cur ^ 1], vals[cur ^ 1], n_dev, n_static, cap, shift, nbits, hist, hoff,
+                         max_tiles, digit_total, tile_count, key_limit, n_out, pw);
+    else
+      hipLaunchKernelGGL((k_radix_scatter<ITEMS, false, false>), dim3(grid), dim3(BLOCK), 0, s, keys[cur],
                          (const uint32_t *)nullptr, keys[cur ^ 1], (uint32_t *)nullptr, n_dev, n_static, cap,
-                         shift, nbits, hist, hoff, max_tiles, digit_total, tile_count, key_limit, n_out);
+                         shift, nbits, hist, hoff, max_tiles, digit_total, tile_count, key_limit, n_out, pw);
     cur ^= 1;
   }
   return cur;
@@ -318,14 +476,26 @@ static int sort_grid_for(int64_t n, int items, int cap_grid) {
   return t < 1 ? 1 : (int)t;
 }
 
+// Only the visible records (compacted per tile by the projection) are
+// sorted; their number is known after the first pass.  The last pass is
+// weighted by the records' pair counts: dvals[dsorted] gets the record
+// order, dkeys[dsorted] each record's first pair (clamped to the capacity),
+// bucket_rec the emission buckets, and the header the pair count.
 int launch_depth_sort(const Plan &p, Workspace &ws, hipStream_t s, int sort_grid) {
-  // Only the visible records (compacted per tile by the projection) are
-  // sorted; their number is known after the first pass.
   unsigned long long *n_vis = reinterpret_cast<unsigned long long *>(ws.hdr + HDR_NVISIBLE);
+  PassWeights w{};
+  w.weight = ws.count;
+  w.whist = ws.whist;
+  w.whoff = ws.whoff;
+  w.wdigit = ws.wdigit;
+  w.wstride = p.depth_tiles;
+  w.bucket = ws.bucket_rec;
+  w.cap = (unsigned long long)p.capacity;
+  w.hdr = ws.hdr;
   ws.dsorted = radix_sort<SORT_ITEMS_DEPTH>(ws.dkeys, ws.dvals, nullptr, (uint32_t)p.n_rec, (uint32_t)p.n_rec, 0, 32,
                                             ws.hist, ws.hoff, p.max_sort_tiles, ws.digit_total,
                                             sort_grid_for(p.n_rec, SORT_ITEMS_DEPTH, sort_grid), true,
-                                            ws.tile_visible, 0u, n_vis, s);
+                                            ws.tile_visible, 0u, n_vis, &w, s);
   return ws.dsorted;
 }
 
@@ -341,140 +511,11 @@ int launch_pair_sort(const Plan &p, Workspace &ws, hipStream_t s, int sort_grid)
                                            (uint32_t)p.capacity, ws.pack_shift, p.tile_bits,
                                            ws.hist, ws.hoff, p.max_sort_tiles, ws.digit_total,
                                            sort_grid_for(p.capacity, SORT_ITEMS_PAIR, sort_grid), true, nullptr,
-                                           key_limit, n_listed, s);
+                                           key_limit, n_listed, nullptr, s);
   return ws.psorted;
 }
 
-// ----------------------------------------------------------- scan + emit pairs
-
-// The record scan runs over the depth-sorted visible records; their number
-// n_vis comes from the depth sort (blocks past it store zero sums).
-__global__ __launch_bounds__(BLOCK) void k_scan_reduce(const uint32_t *__restrict__ order,
-                                                       const uint32_t *__restrict__ count,
-                                                       const unsigned long long *__restrict__ n_vis,
-                                                       unsigned long long *__restrict__ part) {
-  __shared__ unsigned long long s_w[4];
-  const int64_t n_rec = (int64_t)*n_vis;
-  const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK;
-  unsigned long long sum = 0ull;
-#pragma unroll
-  for (int k = 0; k < SCAN_ITEMS; ++k) {
-    const int64_t idx = base + k * BLOCK + threadIdx.x;
-    if (idx < n_rec) sum += count[order[idx]];
-  }
-  unsigned long long total;
-  (void)block_exclusive_scan<unsigned long long>(sum, s_w, total);
-  if (threadIdx.x == 0) part[blockIdx.x] = total;
-}
-
-__global__ __launch_bounds__(BLOCK) void k_scan_top(unsigned long long *__restrict__ part, int nblocks,
-                                                    uint32_t *__restrict__ hdr, uint64_t capacity) {
-  __shared__ unsigned long long s_w[4];
-  unsigned long long carry = 0ull;
-  for (int base = 0; base < nblocks; base += BLOCK * SCAN_ITEMS) {
-    unsigned long long v[SCAN_ITEMS], sum = 0ull;
-#pragma unroll
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-      const int idx = base + threadIdx.x * SCAN_ITEMS + k;
-      v[k] = idx < nblocks ? part[idx] : 0ull;
-      sum += v[k];
-    }
-    unsigned long long total;
-    unsigned long long pre = block_exclusive_scan<unsigned long long>(sum, s_w, total) + carry;
-#pragma unroll
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-      const int idx = base + threadIdx.x * SCAN_ITEMS + k;
-      if (idx < nblocks) part[idx] = pre;
-      pre += v[k];
-    }
-    carry += total;
-  }
-  if (threadIdx.x == 0) {
-    unsigned long long *np = reinterpret_cast<unsigned long long *>(hdr + HDR_NPAIRS);
-    *np = carry;
-    if (carry > capacity) {
-      atomicOr(hdr + HDR_OVERFLOW, 1u);
-      atomicMax(reinterpret_cast<unsigned long long *>(hdr + HDR_REQUIRED), carry);
-    }
-  }
-}
-
-// Per-record pair offsets in depth order, clamped to the capacity (so the
-// array stays non-decreasing and every offset fits 32 bits).  Also records,
-// for every emission bucket b, the record whose pair range holds pair
-// EMIT_BUCKET * b (each such pair lies in exactly one non-empty range), and
-// after the last bucket the record that holds the last pair.  With INLINE
-// the block sums the per-block totals before it itself (and all of them for
-// the pair count, which block 0 stores in the header) instead of reading a
-// scanned array: for few blocks this saves the single-block scan kernel.
-template <bool INLINE>
-__global__ __launch_bounds__(BLOCK) void k_scan_down(const uint32_t *__restrict__ order,
-                                                     const uint32_t *__restrict__ count,
-                                                     const unsigned long long *__restrict__ n_vis,
-                                                     const unsigned long long *__restrict__ part, int nblocks,
-                                                     uint64_t capacity, uint32_t *__restrict__ hdr,
-                                                     uint32_t *__restrict__ off,
-                                                     uint32_t *__restrict__ bucket_rec) {
-  __shared__ unsigned long long s_w[4];
-  __shared__ unsigned long long s_pre, s_tot;
-  const int64_t n_rec = (int64_t)*n_vis;
-  unsigned long long block_off, np;
-  if (INLINE) {
-    unsigned long long pre = 0ull, tot = 0ull;
-    for (int b = threadIdx.x; b < nblocks; b += BLOCK) {
-      const unsigned long long v = part[b];
-      tot += v;
-      if (b < (int)blockIdx.x) pre += v;
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-      pre += __shfl_xor(pre, o);
-      tot += __shfl_xor(tot, o);
-    }
-    if (threadIdx.x == 0) s_pre = s_tot = 0ull;
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) {
-      atomicAdd(&s_pre, pre);
-      atomicAdd(&s_tot, tot);
-    }
-    __syncthreads();
-    block_off = s_pre;
-    np = s_tot;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      *reinterpret_cast<unsigned long long *>(hdr + HDR_NPAIRS) = np;
-      if (np > capacity) {
-        atomicOr(hdr + HDR_OVERFLOW, 1u);
-        atomicMax(reinterpret_cast<unsigned long long *>(hdr + HDR_REQUIRED), np);
-      }
-    }
-  } else {
-    block_off = part[blockIdx.x];
-    np = *reinterpret_cast<const unsigned long long *>(hdr + HDR_NPAIRS);
-  }
-  const int64_t base = (int64_t)blockIdx.x * SCAN_CHUNK + threadIdx.x * SCAN_ITEMS;
-  uint32_t c[SCAN_ITEMS];
-  unsigned long long sum = 0ull;
-#pragma unroll
-  for (int k = 0; k < SCAN_ITEMS; ++k) {
-    const int64_t idx = base + k;
-    c[k] = idx < n_rec ? count[order[idx]] : 0u;
-    sum += c[k];
-  }
-  unsigned long long total;
-  unsigned long long o = block_exclusive_scan<unsigned long long>(sum, s_w, total) + block_off;
-  const unsigned long long n = np < capacity ? np : capacity;  // pairs emitted
-#pragma unroll
-  for (int k = 0; k < SCAN_ITEMS; ++k) {
-    const int64_t idx = base + k;
-    if (idx < n_rec) {
-      off[idx] = (uint32_t)(o < capacity ? o : capacity);
-      const unsigned long long e = o + c[k] < capacity ? o + c[k] : capacity;
-      for (unsigned long long b = (o + EMIT_BUCKET - 1) / EMIT_BUCKET; b * EMIT_BUCKET < e; ++b)
-        bucket_rec[b] = (uint32_t)idx;
-      if (o < n && n <= e) bucket_rec[(n + EMIT_BUCKET - 1) / EMIT_BUCKET] = (uint32_t)idx;
-    }
-    o += c[k];
-  }
-}
+// ------------------------------------------------------------------ emit pairs
 
 // Pair emission.  A block-iteration produces one sort tile of the pair sort
 // (STILE consecutive pairs, in depth order): the records that own those pairs
@@ -608,21 +649,8 @@ __global__ __launch_bounds__(BLOCK) void k_emit_pairs(const uint32_t *__restrict
 void launch_emit_pairs(const Plan &p, const Workspace &ws, const ViewInfo *views, hipStream_t s) {
   (void)views;
   const uint32_t *order = ws.dvals[ws.dsorted];
-  uint32_t *off = ws.dkeys[ws.dsorted ^ 1];  // free after the depth sort
+  const uint32_t *off = ws.dkeys[ws.dsorted];  // first pair of each record (the depth sort's last pass)
   const unsigned long long *n_vis = reinterpret_cast<const unsigned long long *>(ws.hdr + HDR_NVISIBLE);
-  hipLaunchKernelGGL(k_scan_reduce, dim3(p.n_scan_blocks), dim3(BLOCK), 0, s, order, ws.count, n_vis,
-                     ws.scan_part);
-  const bool inline_top = p.n_rec > 0 && p.n_scan_blocks <= 512;
-  if (!inline_top)
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(BLOCK), 0, s, ws.scan_part, p.n_scan_blocks, ws.hdr,
-                       (uint64_t)p.capacity);
-  if (p.n_rec == 0) return;
-  if (inline_top)
-    hipLaunchKernelGGL(k_scan_down<true>, dim3(p.n_scan_blocks), dim3(BLOCK), 0, s, order, ws.count, n_vis,
-                       ws.scan_part, p.n_scan_blocks, (uint64_t)p.capacity, ws.hdr, off, ws.bucket_rec);
-  else
-    hipLaunchKernelGGL(k_scan_down<false>, dim3(p.n_scan_blocks), dim3(BLOCK), 0, s, order, ws.count, n_vis,
-                       ws.scan_part, p.n_scan_blocks, (uint64_t)p.capacity, ws.hdr, off, ws.bucket_rec);
   int64_t blocks = (p.capacity + (int64_t)BLOCK * SORT_ITEMS_PAIR - 1) / ((int64_t)BLOCK * SORT_ITEMS_PAIR);
   if (blocks > 4096) blocks = 4096;
   if (blocks < 1) blocks = 1;
