@@ -163,8 +163,11 @@ __global__ __launch_bounds__(BLOCK) void k_radix_hist(const uint32_t *__restrict
       if (WEIGHTED) wave_add_by_digit(wcnt, d, wr[r], vmask);
     }
     __syncthreads();
-    hist[(size_t)threadIdx.x * max_tiles + t] = cnt[threadIdx.x];
-    if (WEIGHTED) pw.whist[(size_t)threadIdx.x * pw.wstride + t] = wcnt[threadIdx.x];
+    // Only the pass's own digits: one scattered word per row and tile.
+    if (threadIdx.x <= mask) {
+      hist[(size_t)threadIdx.x * max_tiles + t] = cnt[threadIdx.x];
+      if (WEIGHTED) pw.whist[(size_t)threadIdx.x * pw.wstride + t] = wcnt[threadIdx.x];
+    }
     __syncthreads();
   }
 }
@@ -285,12 +288,12 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(
   const int dig = threadIdx.x;
   {
     uint32_t total;
-    s_base[dig] = block_exclusive_scan<uint32_t>(digit_total[dig], s_w, total);
+    s_base[dig] = block_exclusive_scan<uint32_t>(dig <= (int)mask ? digit_total[dig] : 0u, s_w, total);
     if (n_out && blockIdx.x == 0 && threadIdx.x == 0) *n_out = total;
   }
   if (WEIGHTED) {
     unsigned long long wtotal;
-    s_wbase[dig] = block_exclusive_scan<unsigned long long>(pw.wdigit[dig], s_w64, wtotal);
+    s_wbase[dig] = block_exclusive_scan<unsigned long long>(dig <= (int)mask ? pw.wdigit[dig] : 0ull, s_w64, wtotal);
     if (threadIdx.x == 0) s_wtotal = wtotal;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       *reinterpret_cast<unsigned long long *>(pw.hdr + HDR_NPAIRS) = wtotal;
@@ -323,15 +326,18 @@ __global__ __launch_bounds__(BLOCK) void k_radix_scatter(
     s_wc[0][dig] = s_wc[1][dig] = s_wc[2][dig] = s_wc[3][dig] = 0u;
     uint32_t tkeys;  // keys of this tile that are sorted (block-uniform)
     {
-      const uint32_t cnt = hist[(size_t)dig * max_tiles + t];
+      const bool used = dig <= (int)mask;  // rows past the pass's digits are not stored
+      const uint32_t cnt = used ? hist[(size_t)dig * max_tiles + t] : 0u;
       const uint32_t lbase = block_exclusive_scan<uint32_t>(cnt, s_w, tkeys);
       s_lbase[dig] = lbase;
-      s_goff[dig] = s_base[dig] + hoff[(size_t)dig * max_tiles + t] - lbase;
+      s_goff[dig] = s_base[dig] + (used ? hoff[(size_t)dig * max_tiles + t] : 0u) - lbase;
     }
     if (WEIGHTED) {
       unsigned long long ltot;
-      s_lw[dig] = block_exclusive_scan<unsigned long long>(pw.whist[(size_t)dig * pw.wstride + t], s_w64, ltot);
-      s_wgoff[dig] = s_wbase[dig] + pw.whoff[(size_t)dig * pw.wstride + t];
+      const bool used = dig <= (int)mask;
+      s_lw[dig] = block_exclusive_scan<unsigned long long>(used ? pw.whist[(size_t)dig * pw.wstride + t] : 0ull,
+                                                           s_w64, ltot);
+      s_wgoff[dig] = s_wbase[dig] + (used ? pw.whoff[(size_t)dig * pw.wstride + t] : 0ull);
     }
 #pragma unroll
     for (int r = 0; r < ITEMS; ++r) {
@@ -448,10 +454,10 @@ static int radix_sort(uint32_t *keys[2], uint32_t *vals[2], const unsigned long 
                            n_static, cap, shift, nbits, hist, max_tiles, pw);
     }
     if (weighted)
-      hipLaunchKernelGGL((k_radix_scan<ITEMS, true>), dim3(RADIX), dim3(BLOCK), 0, s, hist, hoff, n_dev, n_static,
+      hipLaunchKernelGGL((k_radix_scan<ITEMS, true>), dim3(1u << nbits), dim3(BLOCK), 0, s, hist, hoff, n_dev, n_static,
                          cap, max_tiles, digit_total, pw);
     else
-      hipLaunchKernelGGL((k_radix_scan<ITEMS, false>), dim3(RADIX), dim3(BLOCK), 0, s, hist, hoff, n_dev,
+      hipLaunchKernelGGL((k_radix_scan<ITEMS, false>), dim3(1u << nbits), dim3(BLOCK), 0, s, hist, hoff, n_dev,
                          n_static, cap, max_tiles, digit_total, pw);
     if (weighted)
       hipLaunchKernelGGL((k_radix_scatter<ITEMS, true, true>), dim3(grid), dim3(BLOCK), 0, s, keys[cur],
@@ -642,7 +648,7 @@ __global__ __launch_bounds__(BLOCK) void k_emit_pairs(const uint32_t *__restrict
       }
     }
     __syncthreads();
-    hist[(size_t)t * max_tiles + T] = s_cnt[t];
+    if (t <= (int)mask0) hist[(size_t)t * max_tiles + T] = s_cnt[t];
   }
 }
 
