@@ -539,6 +539,12 @@ int launch_pair_sort(const Plan &p, Workspace &ws, hipStream_t s, int sort_grid)
 // less one: ballots over the staged offsets) plus the number of records that
 // start in (w, p] (flagged in LDS, counted with a ballot): a few LDS round
 // trips per 64 pairs instead of a binary search per pair.
+//
+// The alpha-support test of a record with the cull bit depends only on the
+// row: after staging, the block evaluates the row ranges of all its staged
+// records once (one row per thread, spread evenly over the block; up to
+// EMIT_ROWS rows, the rest per pair) and every pair looks its row up.
+constexpr int EMIT_ROWS = 1024;
 __global__ __launch_bounds__(BLOCK) void k_emit_pairs(const uint32_t *__restrict__ order,
                                                       const uint32_t *__restrict__ off,
                                                       const uint4 *__restrict__ tinfo,
@@ -559,6 +565,9 @@ __global__ __launch_bounds__(BLOCK) void k_emit_pairs(const uint32_t *__restrict
   __shared__ float4 s_cb[BLOCK];
   __shared__ uint32_t s_cnt[RADIX];
   __shared__ uint32_t s_start[BLOCK / 64][64];  // per wavefront: a staged record starts at pair w + i
+  __shared__ uint32_t s_rbase[BLOCK];           // first row slot of each staged record (culled records' rows)
+  __shared__ uint32_t s_row[EMIT_ROWS];         // column range of a row: first | count << 16
+  __shared__ uint32_t s_w[4];
   const uint32_t n = sort_count(n_dev, 0u, cap);
   const uint32_t n_rec = (uint32_t)*n_vis;  // depth-ordered records
   const uint32_t ntiles = (n + STILE - 1) / STILE;
@@ -576,16 +585,40 @@ __global__ __launch_bounds__(BLOCK) void k_emit_pairs(const uint32_t *__restrict
     for (uint32_t rb = r_first; rb <= r_last; rb += BLOCK) {
       const uint32_t nr = r_last - rb + 1u < (uint32_t)BLOCK ? r_last - rb + 1u : (uint32_t)BLOCK;
       __syncthreads();
+      uint32_t rows = 0u;  // rows of this thread's staged record that need the support test
       if ((uint32_t)t < nr) {
         const uint32_t k = rb + t;
         const uint32_t rec = order[k];
         s_off[t] = off[k];
         s_id[t] = rec;
-        s_ti[t] = tinfo[rec];
+        const uint4 ti = tinfo[rec];
+        s_ti[t] = ti;
         s_sp[t] = support[rec];
         s_cb[t] = recB[rec];
+        if (ti.y & 0x80000000u) rows = (ti.w >> 16) - (ti.w & 0xFFFFu) + 1u;
       }
       if (t == 0) s_off[nr] = rb + nr < n_rec ? off[rb + nr] : n;
+      uint32_t rows_total;
+      s_rbase[t] = block_exclusive_scan<uint32_t>(rows, s_w, rows_total);
+      __syncthreads();
+      // Row ranges: slot i belongs to the last staged record whose first slot
+      // is <= i (records without rows share the next one's first slot).
+      const uint32_t rows_cached = rows_total < (uint32_t)EMIT_ROWS ? rows_total : (uint32_t)EMIT_ROWS;
+      for (uint32_t i = (uint32_t)t; i < rows_cached; i += BLOCK) {
+        int lo = 0, hi = (int)nr - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (s_rbase[mid] <= i) lo = mid;
+          else hi = mid - 1;
+        }
+        const uint4 ti = s_ti[lo];
+        const float4 cb = s_cb[lo];
+        const int ty = (int)(ti.w & 0xFFFFu) + (int)(i - s_rbase[lo]);
+        int c0 = 0;
+        const int len = support_row(s_sp[lo], (double)cb.x, (double)cb.y, (double)cb.z, ty, (int)(ti.z & 0xFFFFu),
+                                    (int)(ti.z >> 16), c0);
+        s_row[i] = (uint32_t)c0 | (uint32_t)len << 16;
+      }
       __syncthreads();
       const uint32_t q0 = s_off[0] > p0 ? s_off[0] : p0;
       const uint32_t q1 = s_off[nr] < p1 ? s_off[nr] : p1;
@@ -627,9 +660,16 @@ __global__ __launch_bounds__(BLOCK) void k_emit_pairs(const uint32_t *__restrict
             // Tiles of the rectangle that the alpha support does not reach
             // get the key past the last tile: the pair sort's first pass
             // drops them.
-            const float4 cb = s_cb[a];
-            int c0 = 0;
-            const int len = support_row(s_sp[a], (double)cb.x, (double)cb.y, (double)cb.z, ty, tx0, tx1, c0);
+            const uint32_t slot = s_rbase[a] + q;
+            int c0 = 0, len;
+            if (slot < (uint32_t)EMIT_ROWS) {
+              const uint32_t v = s_row[slot];
+              c0 = (int)(v & 0xFFFFu);
+              len = (int)(v >> 16);
+            } else {
+              const float4 cb = s_cb[a];
+              len = support_row(s_sp[a], (double)cb.x, (double)cb.y, (double)cb.z, ty, tx0, tx1, c0);
+            }
             if (tx < c0 || tx >= c0 + len) tile = dropped_key;
           }
           const uint32_t rec = s_id[a];
@@ -640,11 +680,10 @@ __global__ __launch_bounds__(BLOCK) void k_emit_pairs(const uint32_t *__restrict
             pkeys[p] = tile << pack_shift | rec;
           }
         }
-        // The first pass's digit counts leave the dropped pairs out.
-        const bool listed = valid && tile != dropped_key;
-        const uint32_t d = tile & mask0;
-        const uint64_t peers = match_digit(d, nbits0, __ballot(listed));
-        if (listed && (peers & lanemask_lt()) == 0ull) atomicAdd(&s_cnt[d], (uint32_t)__popcll(peers));
+        // The first pass's digit counts leave the dropped pairs out.  The
+        // pairs of a row of a rectangle have consecutive tiles, so the lanes
+        // of a wavefront rarely share a digit: one LDS atomic per lane.
+        if (valid && tile != dropped_key) atomicAdd(&s_cnt[tile & mask0], 1u);
       }
     }
     __syncthreads();
