@@ -56,13 +56,6 @@ void launch_reset_header(const Workspace &ws, hipStream_t s) {
   hipLaunchKernelGGL(k_reset_header, dim3(1), dim3(64), 0, s, ws.hdr);
 }
 
-// LDS writes of this wavefront visible to its other lanes.
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // ----------------------------------------------------------------- block scan
 
 template <typename T>
@@ -533,12 +526,11 @@ int launch_pair_sort(const Plan &p, Workspace &ws, hipStream_t s, int sort_grid)
 // tile.  Global loads come in two dependent rounds per staged chunk of
 // records instead of per pair.
 //
-// A wavefront takes 64 consecutive pairs [w, w + 64).  Staged records are
-// consecutive and each holds at least one pair, so the record of pair p is
-// the one holding pair w (the number of records starting at or before w,
-// less one: ballots over the staged offsets) plus the number of records that
-// start in (w, p] (flagged in LDS, counted with a ballot): a few LDS round
-// trips per 64 pairs instead of a binary search per pair.
+// Staged records are consecutive and each holds at least one pair, so the
+// staged record of pair p is the last one starting at or before p: every
+// staged record writes its index at its first pair in an LDS map of the
+// chunk's pairs, and a block-wide running maximum over the map fills in the
+// rest (one LDS read per pair afterwards).
 //
 // The alpha-support test of a record with the cull bit depends only on the
 // row: after staging, the block evaluates the row ranges of all its staged
@@ -564,7 +556,7 @@ __global__ __launch_bounds__(BLOCK) void k_emit_pairs(const uint32_t *__restrict
   __shared__ Support s_sp[BLOCK];
   __shared__ float4 s_cb[BLOCK];
   __shared__ uint32_t s_cnt[RADIX];
-  __shared__ uint32_t s_start[BLOCK / 64][64];  // per wavefront: a staged record starts at pair w + i
+  __shared__ uint16_t s_map[STILE];             // staged record of each pair of the chunk (pair - p0)
   __shared__ uint32_t s_rbase[BLOCK];           // first row slot of each staged record (culled records' rows)
   __shared__ uint32_t s_row[EMIT_ROWS];         // column range of a row: first | count << 16
   __shared__ uint32_t s_w[4];
@@ -593,9 +585,11 @@ __global__ __launch_bounds__(BLOCK) void k_emit_pairs(const uint32_t *__restrict
         s_id[t] = rec;
         const uint4 ti = tinfo[rec];
         s_ti[t] = ti;
-        s_sp[t] = support[rec];
-        s_cb[t] = recB[rec];
-        if (ti.y & 0x80000000u) rows = (ti.w >> 16) - (ti.w & 0xFFFFu) + 1u;
+        if (ti.y & 0x80000000u) {  // only the culled records use the support and the conic
+          s_sp[t] = support[rec];
+          s_cb[t] = recB[rec];
+          rows = (ti.w >> 16) - (ti.w & 0xFFFFu) + 1u;
+        }
       }
       if (t == 0) s_off[nr] = rb + nr < n_rec ? off[rb + nr] : n;
       uint32_t rows_total;
@@ -622,27 +616,44 @@ __global__ __launch_bounds__(BLOCK) void k_emit_pairs(const uint32_t *__restrict
       __syncthreads();
       const uint32_t q0 = s_off[0] > p0 ? s_off[0] : p0;
       const uint32_t q1 = s_off[nr] < p1 ? s_off[nr] : p1;
-      for (uint32_t base = q0; base < q1; base += BLOCK) {
-        const uint32_t w0 = base + 64u * (uint32_t)wv;  // this wavefront's first pair
-        const uint32_t p = w0 + (uint32_t)lane;
-        const bool valid = p < q1;
-        s_start[wv][lane] = 0u;
-        wave_lds_sync();
-        uint32_t upto = 0u;  // staged records starting at or before w0
-        for (uint32_t k = 0; k < nr; k += 64u) {
-          const uint32_t r = k + (uint32_t)lane;
-          const bool in = r < nr;
-          const uint32_t o = in ? s_off[r] : 0xFFFFFFFFu;
-          upto += (uint32_t)__popcll(__ballot(in && o <= w0));
-          if (in && o > w0 && o - w0 < 64u) s_start[wv][o - w0] = 1u;
+      // Pair -> staged record over [q0, q1) (map index pair - p0): record
+      // starts, then a running maximum (thread t: SORT_ITEMS_PAIR consecutive
+      // entries of the chunk's STILE).
+      {
+        const uint32_t e0 = (uint32_t)t * SORT_ITEMS_PAIR;
+#pragma unroll
+        for (int k = 0; k < SORT_ITEMS_PAIR; ++k) s_map[e0 + k] = 0;
+        __syncthreads();
+        if ((uint32_t)t < nr && s_off[t] > q0 && s_off[t] < q1) s_map[s_off[t] - p0] = (uint16_t)t;
+        __syncthreads();
+        uint32_t v[SORT_ITEMS_PAIR], run = 0u;
+#pragma unroll
+        for (int k = 0; k < SORT_ITEMS_PAIR; ++k) {
+          run = max(run, (uint32_t)s_map[e0 + k]);
+          v[k] = run;
         }
-        wave_lds_sync();
-        const bool starts_here = s_start[wv][lane] != 0u;
-        const uint64_t starts = __ballot(starts_here);
-        // (w0 >= q0 >= s_off[0], so upto >= 1.)
-        const uint32_t a = upto - 1u + (uint32_t)__popcll(starts & lanemask_lt()) + (starts_here ? 1u : 0u);
+        // Inclusive running maximum of the threads' last values.
+        uint32_t x = run;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+          const uint32_t y = __shfl_up(x, o);
+          if (lane >= o) x = max(x, y);
+        }
+        if (lane == 63) s_w[wv] = x;
+        __syncthreads();
+        uint32_t before = __shfl_up(x, 1);
+        if (lane == 0) before = 0u;
+        for (int w = 0; w < wv; ++w) before = max(before, s_w[w]);
+#pragma unroll
+        for (int k = 0; k < SORT_ITEMS_PAIR; ++k) s_map[e0 + k] = (uint16_t)max(v[k], before);
+        __syncthreads();
+      }
+      for (uint32_t base = q0; base < q1; base += BLOCK) {
+        const uint32_t p = base + (uint32_t)t;
+        const bool valid = p < q1;
         uint32_t tile = 0u;
         if (valid) {
+          const uint32_t a = s_map[p - p0];
           const uint32_t j = p - s_off[a];
           const uint4 ti = s_ti[a];
           const int TX = (int)(ti.y & 0x7FFFFFFFu);
