@@ -6,7 +6,9 @@
  *
  * Method (paper references):
  *   - Scene: Gaussians with mean, covariance R S S^T R^T (Eq. 1-2, rotation
- *     from a real-first quaternion, supplement eq. q2R), opacity, RGB colour.
+ *     from a real-first quaternion, supplement eq. q2R), opacity, and either
+ *     an RGB colour or degree-1 spherical-harmonic coefficients evaluated in
+ *     the viewing direction (Sec. 3.1).
  *   - Projection: Sigma' = J W Sigma W^T J^T (Eq. 3) plus a low-pass term;
  *     centre m = K X_c / z, depth d = z (Sec. 3.1, Sec. 3.3).
  *   - Binning: 16x16 tiles; a Gaussian covers the tiles of the bounding box of
@@ -19,6 +21,8 @@
  *     parameter and to the camera pose (Eq. 11 and supplement Sec. A; the
  *     Sigma' path of the pose gradient is kept unless GSR_PAPER_POSE_APPROX).
  *   - Loss: weighted L1 on colour and depth (Eq. 6, Eq. 10).
+ *   - Map expansion: the adding step (Eq. 8, new Gaussians at unreliable
+ *     pixels) and the deleting step (Eq. 9, opacity decay) of Sec. 3.2.
  *
  * Conventions
  *   - All arrays are caller-owned DEVICE memory unless marked HOST.
