@@ -31,8 +31,14 @@ if ROOT not in sys.path:
 
 METRIC = "fwd+bwd Mpixel/s at 1200×680, 300k Gaussians; batched vs per-frame speedup"
 
-# Algorithmic FP32 operations per unit of rasteriser work (counted from the
-# formulas; an FMA counts 2, exp2 / rcp count 1):
+# Algorithmic FP32 operations of the rasteriser, the per-unit figures of the
+# method's cost model: about 20 per forward evaluation of one list entry at
+# one pixel (Eq. 4-5: the conic quadratic form, opacity, blend) and about 70
+# per backward evaluation (Eq. 11 and the supplement's blend gradient).  These
+# make `roofline.achieved`.
+FLOP_PER_FWD_EVAL, FLOP_PER_BWD_EVAL = 20, 70
+# A finer count of the same work from the formulas (an FMA counts 2, exp2 /
+# rcp count 1), reported beside it as `flop_per_launch_counted`:
 #   forward evaluation of one list entry at one pixel: offset (2), quadratic
 #     form (7), exp2 (1), opacity product (1), clamp (1), alpha test (1)   = 13
 #   blending an accepted entry: 1 - alpha, T update, T test, weight, 4 FMAs = 12
@@ -162,12 +168,15 @@ def run_headline(args, gsr, torch, W):
     # pairs inside the tile lists (the rest lie outside their Gaussian's alpha support)
     work["pairs_listed"] = int((rng[:, 1] - rng[:, 0]).clamp(min=0).sum())
     raster_ms = stages["raster"]
-    flops = (work["fwd_evals"] * FLOP_FWD_EVAL + work["blended"] * FLOP_BLEND +
-             work["bwd_evals"] * FLOP_BWD_EVAL + work["blended"] * FLOP_BWD_CONTRIB)
+    flops = work["fwd_evals"] * FLOP_PER_FWD_EVAL + work["bwd_evals"] * FLOP_PER_BWD_EVAL
+    counted = (work["fwd_evals"] * FLOP_FWD_EVAL + work["blended"] * FLOP_BLEND +
+               work["bwd_evals"] * FLOP_BWD_EVAL + work["blended"] * FLOP_BWD_CONTRIB)
     achieved = flops / (raster_ms * 1e-3) / 1e12
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_FP32_TFLOPS, 1),
             "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None,
-            "kernel": "k_render_fused", "kernel_ms": round(raster_ms, 4), "flop_per_launch": int(flops)}
+            "kernel": "k_render_fused", "kernel_ms": round(raster_ms, 4), "flop_per_launch": int(flops),
+            "flop_per_launch_counted": int(counted),
+            "frac_counted": round(counted / (raster_ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4)}
     tr = measured_traffic(tuning.get("batch"))
     if tr is not None:
         # bytes per launch, HBM read + written (rocprofv3 counters, copy-calibrated)
@@ -235,13 +244,13 @@ def backward_hbm(args, gsr, torch, r, g, cams_d, cam, t_rgb, t_d, fused_ms, work
     st = r.stage_times()
     r.set_profiling(False)
     r.check_overflow()
-    bwd_ms = st["raster_bwd"] / max(1, st["calls"])
+    bwd_ms = st["raster_bwd"] / args.steps  # (the forward calls are timed calls too)
     pv = visited_pairs(torch, out["last"], cam.width, cam.height)
     bytes_alg = pv * 84 + px * 24
     ach = achievable_hbm_gbs(torch)
     gbs_b = bytes_alg / (bwd_ms * 1e-3) / 1e9
     gbs_f = bytes_alg / (fused_ms * 1e-3) / 1e9
-    bwd_flop = work["bwd_evals"] * FLOP_BWD_EVAL + work["blended"] * FLOP_BWD_CONTRIB
+    bwd_flop = work["bwd_evals"] * FLOP_PER_BWD_EVAL
     floor_ms = bwd_flop / (PEAK_FP32_TFLOPS * 1e12) * 1e3
     return {"kernel": "k_render_bwd", "visited_pairs": pv, "bytes_alg": int(bytes_alg),
             "bwd_flop": int(bwd_flop), "alu_frac": round(bwd_flop / (bwd_ms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4),
@@ -250,7 +259,29 @@ def backward_hbm(args, gsr, torch, r, g, cams_d, cam, t_rgb, t_d, fused_ms, work
             "kernel_ms": round(bwd_ms, 4), "achieved_gbs": round(gbs_b, 1), "achievable_gbs": round(ach, 1),
             "frac_of_achievable": round(gbs_b / ach, 4), "frac_of_peak": round(gbs_b / 8000.0, 4),
             "fused_kernel_gbs": round(gbs_f, 1), "fused_frac_of_achievable": round(gbs_f / ach, 4),
-            "target_frac": 0.5, "met": bool(gbs_b / ach >= 0.5)}
+            "target_frac": 0.5, "met": bool(gbs_b / ach >= 0.5), **backward_counters(bytes_alg, bwd_ms, ach)}
+
+
+def backward_counters(bytes_alg, bwd_ms, ach):
+    """The standalone backward kernel's HBM bytes from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE record (copy-calibrated) and its VALU-busy
+    fraction (SQ_INSTS_VALU x 4 cycles over its SIMD-cycles), while its
+    sources are unchanged; the counter bytes are flagged when they exceed
+    1.5x the byte model."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_render_fused_traffic.json")
+    try:
+        rec = json.load(open(path))["k_render_bwd"]
+        src = b"".join(open(os.path.join(ROOT, f), "rb").read() for f in rec["sources"])
+    except (OSError, ValueError, KeyError, TypeError):
+        return {"counter_bytes": None}
+    if hashlib.sha256(src).hexdigest() != rec.get("source_sha256"):
+        return {"counter_bytes": None}
+    cb = int(rec["bytes_total"])
+    gbs = cb / (bwd_ms * 1e-3) / 1e9
+    return {"counter_bytes": cb, "counter_gbs": round(gbs, 1), "counter_frac_of_achievable": round(gbs / ach, 4),
+            "counter_over_alg": round(cb / bytes_alg, 3), "counter_flag": bool(cb > 1.5 * bytes_alg),
+            "valu_busy": rec.get("valu_busy"), "counter_source": rec["summary"]}
 
 
 def run_expansion(args, gsr, torch, W):
@@ -484,24 +515,20 @@ def run_hypotheses(args, gsr, torch, W):
             "pairs": int(pairs)}
 
 
-def run_tracking(args, gsr, torch, W):
-    """Coarse-to-fine tracking of one frame: 150k Gaussians (flat surface
-    Gaussians of the room plus 5% outliers 0.3-0.6 m off the surfaces),
-    640x480 target rendered at the true pose from the surfaces with 10% of
-    the depth readings removed, start perturbed by 2 cm / 1 deg; 5 coarse
-    (160x120) + 95 fine iterations on the Eq. 12 reliable Gaussians."""
+def _track_once(gsr, torch, W, scene, truth, tc, render_mask=None):
+    """One timed coarse-to-fine tracking run (after one warm-up run): targets
+    rendered at `truth` (with `render_mask` selecting the Gaussians that
+    appear in them), 10% of the depth readings removed, start perturbed by
+    2 cm / 1 deg.  Returns the timing, the start and end pose errors and the
+    fine stage's selected Gaussians."""
     import numpy as np
-    from paper_2311_11700_amd.tracking import Tracker, TrackingConfig
-    scene, n_surf = W.tracking_scene(150_000, seed=0, outlier_fraction=0.05, offset=(0.3, 0.6))
-    truth = W.camera_tracking()
+    from paper_2311_11700_amd.tracking import Tracker
     g = gsr.Gaussians.from_arrays(*scene.arrays())
-    tc = TrackingConfig(reliable_eps=0.3)
-    surf = torch.zeros(scene.n, dtype=torch.uint8, device="cuda")
-    surf[:n_surf] = 1
     r = gsr.Renderer(0)
     r.plan(scene.n, [(truth.width, truth.height)])
-    out = r.render_forward(gsr.Gaussians(g.mean, g.log_scale, g.quat, g.opacity_logit, g.rgb, surf),
-                           gsr.pack_cameras([truth]), gsr.Config())
+    gm = g if render_mask is None else gsr.Gaussians(g.mean, g.log_scale, g.quat, g.opacity_logit, g.rgb,
+                                                     render_mask)
+    out = r.render_forward(gm, gsr.pack_cameras([truth]), gsr.Config())
     t_rgb, t_d = out["rgb"].clone(), out["depth"].clone()
     rng = np.random.default_rng(3)
     t_d[torch.as_tensor(rng.random(t_d.numel()) < 0.1, device="cuda")] = 0.0
@@ -527,13 +554,38 @@ def run_tracking(args, gsr, torch, W):
         return float(np.degrees(np.arccos(np.clip((np.trace(R) - 1) / 2, -1, 1))))
 
     iters = tc.coarse_iters + tc.fine_iters
-    return {"workload": "150k Gaussians (flat surface Gaussians + 5% outliers), 640x480 (coarse 160x120), "
-                        "5 + 95 iterations, pose-only, fine stage on Eq. 12 reliable Gaussians (eps 0.3 m)",
-            "reliable": int(tr.reliable.sum().item()),
+    return {"reliable": int(tr.reliable.sum().item()),
             "ms_total": round(ms, 2), "ms_per_iter": round(ms / iters, 3),
             "trans_err_cm": [round(float(np.linalg.norm(E0[:3, 3])) * 100, 3),
                              round(float(np.linalg.norm(E1[:3, 3])) * 100, 3)],
             "rot_err_deg": [round(ang(E0[:3, :3]), 3), round(ang(E1[:3, :3]), 3)]}
+
+
+def run_tracking(args, gsr, torch, W):
+    """Coarse-to-fine tracking of one frame, 640x480 (coarse 160x120), 5 + 95
+    pose-only iterations, start perturbed by 2 cm / 1 deg, 10% of the depth
+    readings removed.  Two maps:
+    - the configured one: the 150k-Gaussian room scene seen from the TUM
+      camera at its identity pose, the fine stage on the Gaussians with
+      sigmoid(opacity) > 0.5;
+    - flat surface Gaussians of the room plus 5% outliers 0.3-0.6 m off the
+      surfaces (the target rendered from the surfaces only), the fine stage on
+      the Eq. 12 reliable Gaussians (eps 0.3 m), which must drop the
+      outliers."""
+    from paper_2311_11700_amd.tracking import TrackingConfig
+    conf = _track_once(gsr, torch, W, W.room_scene(150_000, seed=0), W.camera_tum(),
+                       TrackingConfig(reliable_eps=float("inf"), reliable_opacity=0.5))
+    conf["workload"] = ("150k Gaussians (room scene), 640x480 TUM camera at its identity pose (coarse 160x120), "
+                        "5 + 95 iterations, pose-only, fine stage on sigmoid(opacity) > 0.5")
+    scene, n_surf = W.tracking_scene(150_000, seed=0, outlier_fraction=0.05, offset=(0.3, 0.6))
+    surf = torch.zeros(scene.n, dtype=torch.uint8, device="cuda")
+    surf[:n_surf] = 1
+    res = _track_once(gsr, torch, W, scene, W.camera_tracking(), TrackingConfig(reliable_eps=0.3),
+                      render_mask=surf)
+    res["workload"] = ("150k Gaussians (flat surface Gaussians + 5% outliers), 640x480 (coarse 160x120), "
+                       "5 + 95 iterations, pose-only, fine stage on Eq. 12 reliable Gaussians (eps 0.3 m)")
+    res["configured_scene"] = conf
+    return res
 
 
 def cpu_model():

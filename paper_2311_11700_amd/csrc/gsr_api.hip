@@ -455,8 +455,10 @@ gsr_status gsr_render_backward(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_c
   Workspace ws = make_ws(ctx->plan, workspace);
   const Plan &p = ctx->plan;
   prof_begin(ctx, s);
-  for (int j = 0; j <= GSR_STAGE_RASTER; ++j) prof_mark(ctx, s, j);
+  // The gradient rows are cleared inside the (otherwise empty) stages before
+  // the backward rasteriser, so its stage times the kernel alone.
   launch_fill_f32(reinterpret_cast<float *>(ws.grad2d), 0.f, 2 * p.n_rec * NGRAD2D, s);
+  for (int j = 0; j <= GSR_STAGE_RASTER; ++j) prof_mark(ctx, s, j);
   launch_render_backward(p, ws, ctx->views_dev, ctx->tile_view_dev, *g, consts(*cfg, *g), g_rgb, g_depth, g_T, s);
   prof_mark(ctx, s, GSR_STAGE_RASTER_BWD);
   launch_preprocess_backward(p, *g, cams, *cfg, ws, *grads, s);
