@@ -47,7 +47,28 @@ def _lists_of(renderer):
     return rng.numpy(), sid.numpy(), 0, 0
 
 
-@pytest.mark.parametrize("case", ["small", "ragged77x45", "ragged200x33", "opaque"])
+def _max_rows_per_staged_group(proj, chunk=2048, group=256):
+    """The most alpha-support rows any group of records the pair emission
+    stages together holds (records in depth order; a chunk covers `chunk`
+    consecutive pairs and stages its records `group` at a time; every row of
+    every record needs the row test in the default mode)."""
+    idx = np.nonzero(proj["valid"])[0]
+    order = idx[np.lexsort((idx, proj["zbits"][idx]))]
+    r = proj["rect"][order]
+    cnt = (r[:, 1] - r[:, 0] + 1) * (r[:, 3] - r[:, 2] + 1)
+    rows = r[:, 3] - r[:, 2] + 1
+    off = np.concatenate([[0], np.cumsum(cnt)])
+    best = 0
+    for p0 in range(0, int(off[-1]), chunk):
+        p1 = min(p0 + chunk, int(off[-1]))
+        r_first = int(np.searchsorted(off, p0, side="right")) - 1
+        r_last = int(np.searchsorted(off, p1 - 1, side="right")) - 1
+        for rb in range(r_first, r_last + 1, group):
+            best = max(best, int(rows[rb:min(rb + group, r_last + 1)].sum()))
+    return best
+
+
+@pytest.mark.parametrize("case", ["small", "ragged77x45", "ragged200x33", "opaque", "needles"])
 def test_forward_and_lists_match_oracle(gsr_lib, case):
     gsr = gsr_lib
     if case == "small":
@@ -59,10 +80,16 @@ def test_forward_and_lists_match_oracle(gsr_lib, case):
         sc = W.random_scene(2500, seed=4, xy=1.5)
         cam = W.perturb_pose(W.camera_small().with_size(120.0, 110.0, 99.5, 16.0, 200, 33),
                              [0.05, 0.02, -0.1, 0.03, -0.05, 0.02])
-    else:
+    elif case == "opaque":
         sc = W.random_scene(3000, seed=5, xy=0.8, log_scale_mu=-2.5)
         sc.opacity_logit += 2.0
         cam = W.camera_small()
+    else:
+        # Tall thin Gaussians: the records the emission stages together hold
+        # more alpha-support rows than it caches, so the rest take the
+        # per-pair row test.
+        sc, cam = W.needle_scene(600, seed=0), W.camera_tum()
+        assert _max_rows_per_staged_group(O.project(sc, cam, O.Config().as_f32())) > 1024
     _print_case(test="forward", case=case, n=sc.n, size=(cam.width, cam.height))
     r = gsr.Renderer()
     r.plan(sc.n, [(cam.width, cam.height)])

@@ -9,6 +9,7 @@ from .scenes import (  # noqa: F401
     Camera,
     Scene,
     random_scene,
+    needle_scene,
     room_scene,
     tracking_scene,
     camera_small,

@@ -98,6 +98,26 @@ def random_scene(n=2000, seed=0, xy=1.0, z=(1.0, 5.0), log_scale_mu=-3.0, log_sc
     return Scene(mean, ls, q, op, rgb)
 
 
+def needle_scene(n=600, seed=0, z=(2.5, 3.5), half_width=1.0, sigma_y=(0.2, 0.5), sigma_thin=0.002) -> Scene:
+    """Tall thin Gaussians in front of an identity camera: means uniform in
+    x in [-half_width, half_width], y in [-0.2, 0.2], z in `z`; axis-aligned
+    (identity quaternions) with scales (sigma_thin, U[sigma_y], sigma_thin)
+    metres, so each covers many tile rows but one or two tile columns;
+    opacity logits N(1, 1), RGB uniform in [0, 1]^3."""
+    rng = np.random.default_rng(seed)
+    mx = rng.uniform(-half_width, half_width, size=n)
+    my = rng.uniform(-0.2, 0.2, size=n)
+    mz = rng.uniform(z[0], z[1], size=n)
+    sy = rng.uniform(sigma_y[0], sigma_y[1], size=n)
+    log_scale = np.log(np.stack([np.full(n, sigma_thin), sy, np.full(n, sigma_thin)], axis=1))
+    q = np.zeros((n, 4))
+    q[:, 0] = 1.0
+    opacity_logit = rng.normal(1.0, 1.0, size=n)
+    rgb = rng.random(size=(n, 3))
+    return Scene(np.stack([mx, my, mz], axis=1).astype(F32), log_scale.astype(F32), q.astype(F32),
+                 opacity_logit.astype(F32), rgb.astype(F32))
+
+
 # Room surfaces: (name, fixed axis, fixed value, outward-normal sign, area m^2).
 _ROOM = dict(x=(-3.0, 3.0), y=(-1.5, 1.5), z=(-0.5, 3.5))
 _SURFACES = (
