@@ -18,7 +18,11 @@ covariance set by the point density.  Readings (the paper is silent):
     bottom, pixels left to right);
   * the density-dependent scale is the spacing of back-projected neighbouring
     pixels on a fronto-parallel surface, D / sqrt(fx fy), times a factor; the
-    rotation is the identity quaternion.
+    rotation is the identity quaternion;
+  * in a map with degree-1 spherical-harmonic colour (Sec. 3.1) the new
+    Gaussian's coefficients are the ones whose colour is the observed colour
+    from every direction: the constant term colour / Y_0, the three linear
+    terms zero.
 
 Deleting step (Eq. 9).  Each visible Gaussian's ray from the camera centre
 through its centre X_i meets the image at a pixel with observed depth D; the
@@ -38,6 +42,8 @@ from __future__ import annotations
 import math
 
 import numpy as np
+
+from .splat import SH_C0
 
 F64 = np.float64
 
@@ -69,7 +75,8 @@ def add_gaussians(cams, T_final, depth, depth_obs, rgb_obs, tau_T, tau_D, scale_
     """The adding step over views (lists of per-view arrays: T_final, depth,
     depth_obs [H, W], rgb_obs [3, H, W]).  Returns (mask per view, dict of the
     new Gaussians in pixel order: mean [m, 3], log_scale [m, 3], quat [m, 4],
-    opacity_logit [m], rgb [m, 3], pixel [m, 3] = (view, x, y))."""
+    opacity_logit [m], rgb [m, 3], sh [m, 4, 3] (for a spherical-harmonic
+    map), pixel [m, 3] = (view, x, y))."""
     masks = []
     parts = dict(mean=[], log_scale=[], rgb=[], pixel=[])
     for v, cam in enumerate(cams):
@@ -93,6 +100,9 @@ def add_gaussians(cams, T_final, depth, depth_obs, rgb_obs, tau_T, tau_D, scale_
                opacity_logit=np.full(k, float(np.float32(opacity_logit_init))),
                rgb=np.array(parts["rgb"], F64).reshape(k, 3),
                pixel=np.array(parts["pixel"], np.int64).reshape(k, 3))
+    sh = np.zeros((k, 4, 3), F64)
+    sh[:, 0, :] = out["rgb"] / SH_C0
+    out["sh"] = sh
     return masks, out
 
 

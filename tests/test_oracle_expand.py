@@ -191,3 +191,35 @@ def test_delete_matches_world_space_distance():
         fired += want
         assert bool(dec[i]) == want, i
     assert checked > 500 and 20 < fired < checked - 20
+
+
+def test_new_gaussian_in_a_spherical_harmonic_map_renders_its_observed_colour():
+    """A new Gaussian of a spherical-harmonic map (degree 1) rendered alone,
+    from two cameras seeing it along different directions, gives the image
+    of the same Gaussian in the RGB model with the observed colour: its
+    coefficients carry the colour in the constant term only."""
+    import oracle as O
+    sizes = [(37, 21)]
+    cams = [_posed(W.camera_small().with_size(40.0, 44.0, 18.0, 10.0, 37, 21), 5)]
+    T, dr, do, rgb = W.expansion_images(sizes, seed=7)
+    w, h = sizes[0]
+    masks, new = E.add_gaussians(cams, [T.reshape(h, w)], [dr.reshape(h, w)], [do.reshape(h, w)],
+                                 [rgb.reshape(3, h, w)], 0.3, 0.15, 1.0, 1.5)
+    assert len(new["mean"]) >= 3
+    for j in range(3):
+        mean = new["mean"][j:j + 1].astype(np.float32)
+        ls = np.full((1, 3), math.log(0.05), np.float32)
+        base = dict(mean=mean, log_scale=ls, quat=new["quat"][j:j + 1].astype(np.float32),
+                    opacity_logit=new["opacity_logit"][j:j + 1].astype(np.float32))
+        rgb_scene = W.Scene(rgb=new["rgb"][j:j + 1].astype(np.float32), **base)
+        sh_scene = W.Scene(rgb=np.zeros((1, 3), np.float32), sh=new["sh"][j:j + 1].astype(np.float32), **base)
+        for k, xi in enumerate(([0.0] * 6, [0.08, -0.05, 0.02, 0.1, -0.15, 0.05])):
+            # A camera looking at the Gaussian from 1.5 m, then moved by xi.
+            c = W.camera_small().with_size(60.0, 60.0, 31.5, 23.5, 64, 48)
+            R0 = np.eye(3)
+            t0 = -(R0 @ mean[0].astype(np.float64)) + np.array([0.0, 0.0, 1.5])
+            cam = W.perturb_pose(c.with_pose(R0, t0), xi)
+            a = O.render(rgb_scene, cam, O.Config())
+            b = O.render(sh_scene, cam, O.Config())
+            assert a["rgb"].max() > 0.01, (j, k)
+            np.testing.assert_allclose(b["rgb"], a["rgb"], rtol=0, atol=1e-6)
