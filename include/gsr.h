@@ -339,10 +339,13 @@ gsr_status gsr_select_reliable(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_c
 
 /* Adaptive expansion of the map (Sec. 3.2).
  *
- * Writable Gaussian arrays (DEVICE, same layouts as gsr_gaussians; quat
- * 16-byte aligned) that the adding step appends to. */
+ * Writable Gaussian arrays that the adding step appends to (DEVICE,
+ * `capacity` rows each, same layouts as gsr_gaussians; quat 16-byte
+ * aligned): rgb [capacity][3] and/or, for a map with spherical-harmonic
+ * colour, sh [capacity][4][3] (either may be NULL, not both). */
 typedef struct {
   float *mean, *log_scale, *quat, *opacity_logit, *rgb;
+  float *sh;
 } gsr_gaussians_out;
 
 /* Adding-step parameters: tau_T (cumulative-opacity threshold) and tau_D
@@ -362,7 +365,9 @@ typedef struct {
  * becomes a new Gaussian (Eq. 7): mean = R^T (X_c - t) with
  * X_c = D ((x - cx) / fx, (y - cy) / fy, 1) and D = depth_obs, all three
  * log-scales log(scale_factor D / sqrt(fx fy)), quaternion (1, 0, 0, 0),
- * opacity logit opacity_logit_init, rgb = rgb_obs at the pixel.  The k-th
+ * opacity logit opacity_logit_init, rgb = rgb_obs at the pixel; in a map
+ * with degree-1 SH colour, sh = (rgb_obs / Y_0, 0, 0, 0) per channel (the
+ * observed colour from every direction; Y_0 = 1 / (2 sqrt(pi))).  The k-th
  * new Gaussian is written at index n + k of `out` when n + k < capacity.
  * Inputs use the concatenated image layouts of the plan's views (T_final and
  * depth as a forward writes them; depth_obs [sum HW]; rgb_obs [3 * sum HW]);

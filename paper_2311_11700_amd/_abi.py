@@ -69,7 +69,7 @@ class gsr_tuning(ctypes.Structure):
 
 class gsr_gaussians_out(ctypes.Structure):
     _fields_ = [("mean", c_void_p), ("log_scale", c_void_p), ("quat", c_void_p), ("opacity_logit", c_void_p),
-                ("rgb", c_void_p)]
+                ("rgb", c_void_p), ("sh", c_void_p)]
 
 
 class gsr_expand_params(ctypes.Structure):

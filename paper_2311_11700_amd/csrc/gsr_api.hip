@@ -232,6 +232,7 @@ void enqueue_fused(gsr_ctx *ctx, const gsr_gaussians &g, const gsr_camera *cams,
 
 static_assert(sizeof(gsr_camera) == 80, "gsr_camera layout");
 static_assert(sizeof(gsr_config) == 44, "gsr_config layout");
+static_assert(sizeof(gsr_gaussians_out) == 48, "gsr_gaussians_out layout");
 
 extern "C" {
 
@@ -762,7 +763,8 @@ gsr_status gsr_expand_add(gsr_ctx *ctx, const gsr_camera *cams, int n_views, con
   if (workspace_bytes < ctx->plan.bytes) return fail(ctx, GSR_E_INVALID, "workspace smaller than gsr_plan() requires");
   if (reinterpret_cast<uintptr_t>(workspace) % ALIGN) return fail(ctx, GSR_E_INVALID, "workspace not 256-byte aligned");
   if (n < 0 || capacity < n) return fail(ctx, GSR_E_INVALID, "gsr_expand_add: need 0 <= n <= capacity");
-  if (capacity > n && (!out || !out->mean || !out->log_scale || !out->quat || !out->opacity_logit || !out->rgb))
+  if (capacity > n && (!out || !out->mean || !out->log_scale || !out->quat || !out->opacity_logit ||
+                       (!out->rgb && !out->sh)))
     return fail(ctx, GSR_E_INVALID, "gsr_expand_add: null output array");
   if (out && reinterpret_cast<uintptr_t>(out->quat) % 16) return fail(ctx, GSR_E_INVALID, "quat must be 16-byte aligned");
   if (!(prm->tau_T >= 0.f && prm->tau_T < 1e30f) || !(prm->tau_D >= 0.f && prm->tau_D < 1e30f) ||

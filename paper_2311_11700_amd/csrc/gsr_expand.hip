@@ -91,7 +91,7 @@ __global__ __launch_bounds__(1024) void k_expand_scan(uint32_t *__restrict__ cnt
 }
 
 struct AddOut {
-  float *mean, *log_scale, *quat, *opacity_logit, *rgb;
+  float *mean, *log_scale, *quat, *opacity_logit, *rgb, *sh;
   int64_t n, capacity;
   float scale_factor, logit_init;
 };
@@ -150,9 +150,22 @@ __global__ __launch_bounds__(BLOCK) void k_expand_write(ExpandArgs a, const unsi
     o.opacity_logit[k] = o.logit_init;
     const int64_t HW = (int64_t)vi.W * vi.H;
     const float *c = a.rgb_obs + 3 * vi.pix_off + q;
-    o.rgb[3 * k] = c[0];
-    o.rgb[3 * k + 1] = c[HW];
-    o.rgb[3 * k + 2] = c[2 * HW];
+    const float c0 = c[0], c1 = c[HW], c2 = c[2 * HW];
+    if (o.rgb) {
+      o.rgb[3 * k] = c0;
+      o.rgb[3 * k + 1] = c1;
+      o.rgb[3 * k + 2] = c2;
+    }
+    if (o.sh) {
+      // The observed colour in the constant term (Y_0 = SH_C0), none in the
+      // linear terms.
+      float *sk = o.sh + 12 * k;
+      sk[0] = (float)((double)c0 / SH_C0);
+      sk[1] = (float)((double)c1 / SH_C0);
+      sk[2] = (float)((double)c2 / SH_C0);
+#pragma unroll
+      for (int j = 3; j < 12; ++j) sk[j] = 0.f;
+    }
   }
 }
 
@@ -165,7 +178,8 @@ void launch_expand_add(const Plan &p, const ViewInfo *views, const gsr_camera *c
   hipLaunchKernelGGL(k_expand_flags, dim3(n_chunks), dim3(BLOCK), 0, s, a, ws.expand_bits, ws.expand_cnt,
                      pixel_flag);
   hipLaunchKernelGGL(k_expand_scan, dim3(1), dim3(1024), 0, s, ws.expand_cnt, n_chunks, count);
-  AddOut o{out.mean, out.log_scale, out.quat, out.opacity_logit, out.rgb, n, capacity, scale_factor, logit_init};
+  AddOut o{out.mean, out.log_scale, out.quat, out.opacity_logit, out.rgb, out.sh, n, capacity, scale_factor,
+           logit_init};
   hipLaunchKernelGGL(k_expand_write, dim3(n_chunks), dim3(BLOCK), 0, s, a, ws.expand_bits, ws.expand_cnt, cams,
                      views, p.n_views, o);
 }

@@ -463,17 +463,22 @@ class Renderer:
                    pixel_flag: Optional[torch.Tensor] = None, count: Optional[torch.Tensor] = None, stream=None):
         """gsr_expand_add over the planned views (Eq. 8): appends a Gaussian
         per unreliable pixel to the arrays of `out` (keys mean, log_scale,
-        quat, opacity_logit, rgb; `capacity` rows) from row n on.  Returns the
-        device int64 count of unreliable pixels.  The default initial
-        opacity logit is that of opacity 0.1."""
+        quat, opacity_logit and rgb and/or sh (a spherical-harmonic map,
+        [capacity, 4, 3]); `capacity` rows) from row n on.  Returns the device
+        int64 count of unreliable pixels.  The default initial opacity logit
+        is that of opacity 0.1."""
         P = self.total_pixels
         for t, m, name in ((T_final, P, "T_final"), (depth, P, "depth"), (depth_obs, P, "depth_obs"),
                            (rgb_obs, 3 * P, "rgb_obs")):
             _need(t, m, name, torch.float32)
         _need(pixel_flag, P, "pixel_flag", torch.uint8)
-        per = dict(mean=3, log_scale=3, quat=4, opacity_logit=1, rgb=3)
+        per = dict(mean=3, log_scale=3, quat=4, opacity_logit=1, rgb=3, sh=12)
+        if int(capacity) > int(n) and out.get("rgb") is None and out.get("sh") is None:
+            raise ValueError("expand_add: out needs rgb or sh")
         o = A.gsr_gaussians_out()
         for k, c in per.items():
+            if k in ("rgb", "sh") and out.get(k) is None:
+                continue
             _need(out.get(k), c * int(capacity), k, torch.float32)
             setattr(o, k, _ptr(out.get(k)))
         count = count if count is not None else torch.zeros(1, dtype=torch.int64, device=self.device)

@@ -42,6 +42,7 @@ def test_struct_layouts():
     assert ctypes.sizeof(A.gsr_images) == 40
     assert ctypes.sizeof(A.gsr_grads) == 56
     assert ctypes.sizeof(A.gsr_tuning) == 16
+    assert ctypes.sizeof(A.gsr_gaussians_out) == 6 * 8
 
 
 def test_defaults_match_oracle_constants():

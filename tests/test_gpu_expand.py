@@ -87,6 +87,43 @@ def test_expand_add_matches_oracle_synthetic(gsr_lib):
     _check_new(out, n, new, count_o)
 
 
+def test_expand_add_spherical_harmonic_map(gsr_lib):
+    """A map with degree-1 SH colour: the new Gaussians' coefficients (sh
+    only, then sh beside rgb) equal the oracle's, the constant term rounded
+    once from FP64 on both sides and the linear terms zero; capacity cuts
+    the list in the middle."""
+    gsr = gsr_lib
+    sizes = [(160, 120), (33, 17)]
+    cams = [_posed(W.camera_small().with_size(150.0, 150.0, 79.5, 59.5, 160, 120), 5),
+            _posed(W.camera_small().with_size(30.0, 30.0, 16.0, 8.0, 33, 17), 6)]
+    T, dr, do, rgb = W.expansion_images(sizes, seed=21)
+    r = gsr.Renderer(0)
+    r.plan(10, sizes)
+    _, new = E.add_gaussians(cams, _split(T, sizes), _split(dr, sizes), _split(do, sizes), _split(rgb, sizes, 3),
+                             0.5, 0.25, 1.0, -2.0)
+    count_o = int(new["mean"].shape[0])
+    assert count_o > 500
+    n, cap = 2, 2 + count_o - 37
+    for with_rgb in (False, True):
+        out = _out_arrays(cap)
+        if not with_rgb:
+            del out["rgb"]
+        out["sh"] = torch.full((cap, 4, 3), SENT, device="cuda")
+        cnt = r.expand_add(gsr.pack_cameras(cams), H.to_dev(T), H.to_dev(dr), H.to_dev(do), H.to_dev(rgb), out, n,
+                           cap, 0.5, 0.25, 1.0, -2.0)
+        torch.cuda.synchronize()
+        assert int(cnt.item()) == count_o
+        sh = out.pop("sh").cpu().numpy()
+        np.testing.assert_array_equal(sh[n:], new["sh"][:cap - n].astype(np.float32))
+        assert (sh[:n] == SENT).all()
+        if with_rgb:
+            _check_new(out, n, new, count_o)
+        else:
+            got = out["mean"].cpu().numpy().astype(np.float64)
+            np.testing.assert_allclose(got[n:], new["mean"][:cap - n], rtol=0,
+                                       atol=1e-6 * (1.0 + np.abs(new["mean"]).max()))
+
+
 def test_expand_add_capacity_empty_and_count_only(gsr_lib):
     """Capacity for half the new Gaussians: the first half is written, the
     count still reports all; no unreliable pixel: nothing written; capacity
