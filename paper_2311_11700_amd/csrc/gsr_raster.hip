@@ -204,6 +204,10 @@ struct BwdIn {
   int last;        // list positions [0, last) to walk
   float zr;        // depth of the last contributor (0 if none)
   float gC0, gC1, gC2, gD, gT;
+  // With the split contraction: the upstream colour and depth gradients
+  // divided by their weights (sC = gC / w_rgb, sD = gD / w_depth), values
+  // that bf16 holds exactly (signs of the L1 residuals).
+  float sC0, sC1, sC2, sD;
 };
 
 __device__ __forceinline__ void wave_lds_sync() {
@@ -245,6 +249,41 @@ __device__ __forceinline__ float4v mfma_issue(const float *mA, const float Bm[16
   return D;
 }
 
+// The same contraction on the bf16 matrix cores
+// (v_mfma_f32_16x16x32_bf16): every per-pixel value x of the A rows is held
+// as a pair (h, l) of bf16, h = x with the low 16 bits of its float32 cleared
+// and l = x - h rounded to bf16 (h + l carries 16 significant bits, a
+// relative error below 2^-16), and the pair occupies two consecutive K slots
+// whose B entries both hold the pixel's column value, which bf16 must hold
+// exactly (the moment polynomials of half-integer coordinates have at most
+// 8 significant bits; the upstream columns are residual signs).  K = 128
+// slots (64 pixels x 2) in 4 steps instead of 16; step j covers the wave's
+// pixel row j.  The accumulation stays FP32.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float float2v __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t split_bf16(float x) {
+  const float h = __uint_as_float(__float_as_uint(x) & 0xFFFF0000u);
+  const float2v p = {h, x - h};
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(p, bf16x2));
+}
+
+__device__ __forceinline__ float4v mfma_issue_split(const float *mA, const bf16x8 Bb[4]) {
+  const int lane = __lane_id();
+  const int r = lane & 15, g = lane >> 4;
+  wave_lds_sync();
+  // Lane (g, r): row r, words (pixels) 16 j + 4 g .. + 3 of step j.
+  const uint4 *src = reinterpret_cast<const uint4 *>(mA + r * MA_STRIDE + 4 * g);
+  const uint4 a0 = src[0], a1 = src[4], a2 = src[8], a3 = src[12];
+  float4v D = {0.f, 0.f, 0.f, 0.f};
+  D = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a0), Bb[0], D, 0, 0, 0);
+  D = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a1), Bb[1], D, 0, 0, 0);
+  D = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a2), Bb[2], D, 0, 0, 0);
+  D = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a3), Bb[3], D, 0, 0, 0);
+  return D;
+}
+
 // Store the useful products of a contraction of nq entries into the
 // wavefront's own per-entry sums s_sum[entry][NMOM] (entry q's slot in byte
 // q of slots; a wavefront meets each entry once per sub-batch, so plain
@@ -269,13 +308,19 @@ __device__ __forceinline__ void mfma_consume(const float4v &D, int nq, uint64_t 
 // Gaussian that covers many tiles sums partials of both signs; the FP64 sum
 // keeps the result independent of the order the tiles finish in).  grad2d
 // fields: (u, v, conic a, b, c, opacity, r, g, b, depth).
+//
+// SPLIT: the contraction on the bf16 matrix cores (mfma_issue_split), with
+// the upstream columns taken from in.sC / in.sD and the colour and depth
+// sums scaled by w_rgb and w_depth at the flush.
+template <bool SPLIT>
 __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, const float4 *__restrict__ recA,
                                               const float4 *__restrict__ recB,
                                               const float4 *__restrict__ recC,
                                               const uint32_t *__restrict__ ids, const RenderConsts &rc,
                                               const BwdIn &in, double *__restrict__ grad2d,
                                               Staged *s_rec, float *s_part, uint32_t *s_id, int *s_max,
-                                              float *s_mA, int staged_lo = -1) {
+                                              float *s_mA, int staged_lo = -1, float w_rgb = 1.f,
+                                              float w_depth = 1.f) {
   const float lx = (float)(threadIdx.x & (TILE - 1));
   const float ly = (float)(threadIdx.x >> 4);
   const int lane = __lane_id();
@@ -293,8 +338,39 @@ __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, con
   // of lane (g, col) holds column col of pixel 16 g + s of this wavefront
   // (tile pixel x = s, y = 4 wv + g), coordinates relative to the tile centre.
   // The upstream gradients reach those lanes through the wave's LDS rows.
-  float Bm[16];
-  {
+  float Bm[SPLIT ? 1 : 16];
+  bf16x8 Bb[SPLIT ? 4 : 1];
+  if constexpr (SPLIT) {
+    // Step j, lane (g, col): elements 2 i and 2 i + 1 hold column col of
+    // pixel x = 4 g + i of the wave's row j (y = 4 wv + j).
+    mA[0 * MA_STRIDE + lane] = in.sC0;
+    mA[1 * MA_STRIDE + lane] = in.sC1;
+    mA[2 * MA_STRIDE + lane] = in.sC2;
+    mA[3 * MA_STRIDE + lane] = in.sD;
+    wave_lds_sync();
+    const int col = lane & 15, g = lane >> 4;
+    const bool up = col >= 6 && col < NMOM;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float yc = (float)(4 * wv + j) - 7.5f;
+      // Rebuilt per tile: kept out of the tile loop, these tile-invariant
+      // values would be held in registers (spilled) across the forward walk.
+      __asm__ volatile("" : "+v"(yc));
+      const float4 q = *reinterpret_cast<const float4 *>(mA + (up ? col - 6 : 0) * MA_STRIDE + 16 * j + 4 * g);
+      const float qv[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float xc = (float)(4 * g + i) - 7.5f;
+        // Columns 1, xc, yc, xc^2, xc yc, yc^2, then the upstream values.
+        const float a = col == 1 || col == 3 || col == 4 ? xc : (col == 2 || col == 5 ? yc : 1.f);
+        const float b = col == 3 ? xc : (col == 4 || col == 5 ? yc : 1.f);
+        const __bf16 v = (__bf16)(up ? qv[i] : (col < 6 ? a * b : 0.f));
+        Bb[j][2 * i] = v;
+        Bb[j][2 * i + 1] = v;
+      }
+    }
+    wave_lds_sync();
+  } else {
     mA[0 * MA_STRIDE + lane] = in.gC0;
     mA[1 * MA_STRIDE + lane] = in.gC1;
     mA[2 * MA_STRIDE + lane] = in.gC2;
@@ -396,15 +472,22 @@ __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, con
           // dL/dP with G = 2^P (the ln 2 and the conic pre-scale are applied
           // at the flush); dL/d(opacity) = dLdP / o there.
           const float dLdP = open ? dLda * oG : 0.f;
-          mA[(2 * nq) * MA_STRIDE + lane] = dLdP;
-          mA[(2 * nq + 1) * MA_STRIDE + lane] = w;
+          if constexpr (SPLIT) {
+            uint32_t *mw = reinterpret_cast<uint32_t *>(mA);
+            mw[(2 * nq) * MA_STRIDE + lane] = split_bf16(dLdP);
+            mw[(2 * nq + 1) * MA_STRIDE + lane] = split_bf16(w);
+          } else {
+            mA[(2 * nq) * MA_STRIDE + lane] = dLdP;
+            mA[(2 * nq + 1) * MA_STRIDE + lane] = w;
+          }
           slots |= (uint64_t)j << (8 * nq);
           ++nq;
         }
       }
       if (nq == 8 || (k < lo && nq > 0)) {
         if (p_nq > 0) mfma_consume(pD, p_nq, p_slots, my_part);
-        pD = mfma_issue(mA, Bm);
+        if constexpr (SPLIT) pD = mfma_issue_split(mA, Bb);
+        else pD = mfma_issue(mA, Bm);
         p_nq = nq;
         p_slots = slots;
         nq = 0;
@@ -449,10 +532,10 @@ __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, con
       o[3] = -Sxy;
       o[4] = -0.5 * Syy;
       o[5] = M1 / (double)sr.geo.z;
-      o[6] = m[6];
-      o[7] = m[7];
-      o[8] = m[8];
-      o[9] = m[9];
+      o[6] = SPLIT ? m[6] * (double)w_rgb : m[6];
+      o[7] = SPLIT ? m[7] * (double)w_rgb : m[7];
+      o[8] = SPLIT ? m[8] * (double)w_rgb : m[8];
+      o[9] = SPLIT ? m[9] * (double)w_depth : m[9];
     }
     __syncthreads();
     for (int t = threadIdx.x; t < cnt * NGRAD2D; t += BLOCK) {
@@ -546,8 +629,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     in.gD = g_depth ? g_depth[ti.pix] : 0.f;
     in.gT = g_T ? g_T[ti.pix] : 0.f;
   }
-  tile_backward(ti, a.n, a.recA, a.recB, a.recC, a.ids, a.rc, in, grad2d, s_rec, s_part, s_id, &s_max,
-                s_mA);
+  tile_backward<false>(ti, a.n, a.recA, a.recB, a.recC, a.ids, a.rc, in, grad2d, s_rec, s_part, s_id, &s_max,
+                       s_mA);
 }
 
 __device__ __forceinline__ float sgnf(float x) { return (float)((x > 0.f) - (x < 0.f)); }
@@ -617,10 +700,14 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
         const bool keep = m && !(lpx > cap);
         lpx = keep ? lpx : 0.f;
         if (keep) {
-          in.gC0 = w_rgb * sgnf(e0);
-          in.gC1 = w_rgb * sgnf(e1);
-          in.gC2 = w_rgb * sgnf(e2);
-          if (md) in.gD = w_depth * sgnf(ed);
+          in.sC0 = sgnf(e0);
+          in.sC1 = sgnf(e1);
+          in.sC2 = sgnf(e2);
+          if (md) in.sD = sgnf(ed);
+          in.gC0 = w_rgb * in.sC0;
+          in.gC1 = w_rgb * in.sC1;
+          in.gC2 = w_rgb * in.sC2;
+          in.gD = w_depth * in.sD;
         }
         save_state(ps, ti.pix, st);
         if (out.rgb) {
@@ -635,8 +722,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
       }
       const float ls = wave_sum(lpx);
       if ((threadIdx.x & 63) == 0) s_loss[threadIdx.x >> 6] = ls;
-      tile_backward(ti, a.n, a.recA, a.recB, a.recC, a.ids, a.rc, in, grad2d, s_rec, s_part, s_id, &s_max,
-                    s_mA, staged_lo);
+      tile_backward<true>(ti, a.n, a.recA, a.recB, a.recC, a.ids, a.rc, in, grad2d, s_rec, s_part, s_id, &s_max,
+                          s_mA, staged_lo, w_rgb, w_depth);
       if (threadIdx.x == 0 && loss) atomicAdd(loss, (s_loss[0] + s_loss[1]) + (s_loss[2] + s_loss[3]));
       if (threadIdx.x == 0) {
         const uint64_t d = wall_clock64() - clk0;
