@@ -113,6 +113,8 @@ enum {
  * returns the values of the 3DGS rasteriser the paper extends:
  * alpha_min 1/255, alpha_max 0.99, T_min 1e-4, cutoff_sigma 3, z_near 0.2 m,
  * lowpass 0.3 px^2, bg 0, flags GSR_GAUSS_GRAD | GSR_POSE_GRAD, fov_guard 1.3.
+ * Calls reject alpha_min outside [0, 1], alpha_max outside (0, 1], a
+ * negative T_min, cutoff_sigma <= 0 and a negative or non-finite fov_guard.
  *
  * fov_guard g > 0 limits the Jacobian of Eq. 3 (not the projected centre):
  * x/z and y/z enter J clamped to +-g W/(2 fx) and +-g H/(2 fy), so a

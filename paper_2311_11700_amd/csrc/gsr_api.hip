@@ -128,7 +128,8 @@ gsr_status validate(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams
   if (g->n > 0 && (!g->mean || !g->log_scale || !g->quat || !g->opacity_logit || (!g->rgb && !g->sh)))
     return fail(ctx, GSR_E_INVALID, "null Gaussian parameter array");
   if (reinterpret_cast<uintptr_t>(g->quat) % 16) return fail(ctx, GSR_E_INVALID, "quat must be 16-byte aligned");
-  if (!(cfg->alpha_max > 0.f && cfg->alpha_max <= 1.f) || cfg->alpha_min < 0.f || cfg->T_min < 0.f ||
+  if (!(cfg->alpha_max > 0.f && cfg->alpha_max <= 1.f) || !(cfg->alpha_min >= 0.f && cfg->alpha_min <= 1.f) ||
+      cfg->T_min < 0.f ||
       !(cfg->cutoff_sigma > 0.f) || !(cfg->fov_guard >= 0.f && cfg->fov_guard < 1e30f))
     return fail(ctx, GSR_E_INVALID, "renderer constants out of range");
   return GSR_OK;

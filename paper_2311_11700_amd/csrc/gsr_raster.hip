@@ -21,6 +21,10 @@ namespace gsr {
 constexpr int BATCH = 192;  // staged records per forward round (<= BLOCK; the fused kernel's is tunable)
 constexpr float NEG_HALF_LOG2E = -0.72134752044448170368f;  // -log2(e) / 2
 constexpr float LN2 = 0.69314718055994530942f;
+// Alpha threshold of a pixel that has stopped (or lies outside the image):
+// above any alpha (alpha <= alpha_max <= 1) and an inline constant of the
+// instruction set, so that no register holds it.
+constexpr float A_STOPPED = 2.f;
 
 struct Staged {
   float4 geo;  // (u_rel, v_rel, opacity, depth)
@@ -98,6 +102,15 @@ struct FwdState {
   float zr;  // depth of the last blended entry (0 if none): the backward's reference depth
 };
 
+// Depth of list entry pos of the tile, from the staged batch that starts at
+// entry lo when it holds pos, else from the record.
+__device__ __forceinline__ float entry_depth(int pos, int lo, const Staged *s_rec, const TileInfo &ti,
+                                            const uint32_t *__restrict__ ids, const float4 *__restrict__ recC,
+                                            uint32_t id_mask) {
+  if (pos >= lo) return s_rec[pos - lo].geo.w;
+  return recC[ids[ti.range.x + pos] & id_mask].w;
+}
+
 // With COUNT, the walk also adds its work to counts (wave totals, once per
 // tile): counts[1] += list entries examined by live pixels (including the
 // entry that stopped a pixel), counts[2] += entries blended.  The render
@@ -109,14 +122,14 @@ __device__ __forceinline__ void tile_forward(const TileInfo &ti, int64_t n, cons
                                              const uint32_t *__restrict__ ids, const RenderConsts &rc,
                                              Staged *s_rec, FwdState &st, unsigned long long *counts,
                                              uint32_t *s_id = nullptr, int *staged_lo = nullptr) {
-  if (staged_lo) *staged_lo = -1;
   st.T = 1.f;
   st.C0 = st.C1 = st.C2 = st.D = 0.f;
   st.last = 0;
   st.zr = 0.f;
-  // The pixel's alpha threshold; +inf once it has stopped (or outside the
-  // image), so that no later entry is accepted.
-  float amin = ti.inside ? rc.alpha_min : __builtin_inff();
+  // The pixel's alpha threshold; A_STOPPED once it has stopped (or outside
+  // the image), so that no later entry is accepted.
+  float amin = ti.inside ? rc.alpha_min : A_STOPPED;
+  int lo_last = -1;  // first entry of the staged batch (-1: none staged)
   uint32_t nev_w = 0u, nbl_w = 0u;
   const float lx = (float)(threadIdx.x & (TILE - 1));
   const float ly = (float)(threadIdx.x >> 4);
@@ -125,7 +138,7 @@ __device__ __forceinline__ void tile_forward(const TileInfo &ti, int64_t n, cons
   static_assert(NB % 64 == 0 && NB <= BLOCK, "whole wavefronts of staging threads");
   if ((int)threadIdx.x < NB && ti.range.x + (int)threadIdx.x < ti.range.y) next_id = ids[ti.range.x + threadIdx.x];
   for (int base = ti.range.x; base < ti.range.y; base += NB) {
-    if (__syncthreads_and(amin == __builtin_inff())) break;
+    if (__syncthreads_and(amin == A_STOPPED)) break;
     const int pos = base + threadIdx.x;
     if ((int)threadIdx.x < NB && pos < ti.range.y) {
       const uint32_t id = next_id & rc.id_mask;
@@ -133,14 +146,14 @@ __device__ __forceinline__ void tile_forward(const TileInfo &ti, int64_t n, cons
       s_rec[threadIdx.x] = stage_record(id, ti.x0, ti.y0, recA, recB, recC);
       if (pos + NB < ti.range.y) next_id = ids[pos + NB];
     }
-    if (staged_lo) *staged_lo = base - ti.range.x;
+    lo_last = base - ti.range.x;
     __syncthreads();
     // Branch-free walk: every lane evaluates every entry and keeps or drops
     // the result with selects; the wave leaves the batch once all of its
     // pixels have stopped.  `live` (wave-uniform) holds the lanes still
     // blending.
     const int cnt = min(NB, ti.range.y - base);
-    uint64_t live = __builtin_amdgcn_ballot_w64(amin != __builtin_inff());
+    uint64_t live = __builtin_amdgcn_ballot_w64(amin != A_STOPPED);
     for (int k = 0; k < cnt && live; ++k) {
       if (COUNT) nev_w += (uint32_t)__popcll(live);
       const float4 geo = s_rec[k].geo;
@@ -149,24 +162,29 @@ __device__ __forceinline__ void tile_forward(const TileInfo &ti, int64_t n, cons
       float G, oG;
       const float alpha = splat_alpha(geo, con, dx, dy, rc.alpha_max, G, oG);
       const bool acc = alpha >= amin;
-      const float Tn = st.T * (1.f - alpha);
+      // Blend weight alpha T and the transmittance behind, T - alpha T.
+      const float wa = alpha * st.T;
+      const float Tn = st.T - wa;
       const bool stop = acc && Tn < rc.T_min;
       const bool blend = acc && !stop;
       if (COUNT) nbl_w += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(blend));
-      amin = stop ? __builtin_inff() : amin;
+      amin = stop ? A_STOPPED : amin;
       // Nearly every entry blends in some lane: no branch around the update.
       const float4 col = s_rec[k].col;
-      const float w = blend ? alpha * st.T : 0.f;
+      const float w = blend ? wa : 0.f;
       st.C0 = __fmaf_rn(w, col.x, st.C0);
       st.C1 = __fmaf_rn(w, col.y, st.C1);
       st.C2 = __fmaf_rn(w, col.z, st.C2);
       st.D = __fmaf_rn(w, geo.w, st.D);
       st.T = blend ? Tn : st.T;
       st.last = blend ? base - ti.range.x + k + 1 : st.last;
-      st.zr = blend ? geo.w : st.zr;
-      live = __builtin_amdgcn_ballot_w64(amin != __builtin_inff());
+      live = __builtin_amdgcn_ballot_w64(amin != A_STOPPED);
     }
   }
+  if (staged_lo) *staged_lo = lo_last;
+  // The reference depth: the last blended entry's, read once per pixel (an
+  // entry was blended, so a batch was staged).
+  if (st.last > 0) st.zr = entry_depth(st.last - 1, lo_last, s_rec, ti, ids, recC, rc.id_mask);
   if (COUNT && __lane_id() == 0 && nev_w) {
     atomicAdd(counts + 1, (unsigned long long)nev_w);
     atomicAdd(counts + 2, (unsigned long long)nbl_w);
@@ -460,14 +478,17 @@ __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, con
         // without a contribution are masked with selects (NaN-safe).
         if (__any(has)) {
           const float4 col = s_rec[off + j].col;
-          const float rinv = __builtin_amdgcn_rcpf(1.f - alpha);
+          // Lanes without a contribution take alpha = 0, which leaves T and
+          // S unchanged (1 / (1 - 0) is exactly 1) and gives w = 0.
+          const float ae = has ? alpha : 0.f;
+          const float rinv = __builtin_amdgcn_rcpf(1.f - ae);
           const float Tk = T * rinv;  // transmittance in front of this Gaussian
-          T = has ? Tk : T;
-          const float w = has ? alpha * Tk : 0.f;
+          T = Tk;
+          const float w = ae * Tk;
           const float Q = __fmaf_rn(in.gD, geo.w - zr, __fmaf_rn(in.gC2, col.z, __fmaf_rn(in.gC1, col.y, in.gC0 * col.x)));
           const float QS = Q - S;
           const float dLda = __fmaf_rn(Tk, QS, Kf * rinv);
-          S = has ? __fmaf_rn(alpha, QS, S) : S;
+          S = __fmaf_rn(ae, QS, S);
           const bool open = has && oG <= rc.alpha_max;
           // dL/dP with G = 2^P (the ln 2 and the conic pre-scale are applied
           // at the flush); dL/d(opacity) = dLdP / o there.

@@ -752,9 +752,10 @@ def test_invalid_arguments_and_call_order(gsr_lib):
         r.render_backward(g, gsr.pack_cameras([cam]), gsr.Config(), torch.zeros(3 * P, device="cuda"),
                           torch.zeros(P, device="cuda"))
     assert e.value.status == gsr.GSR_E_STATE
-    with pytest.raises(gsr.GsrError) as e:
-        r.render_forward(g, gsr.pack_cameras([cam]), gsr.Config(alpha_max=1.5))
-    assert e.value.status == gsr.GSR_E_INVALID
+    for bad in (dict(alpha_max=1.5), dict(alpha_min=1.5), dict(alpha_min=float("nan"))):
+        with pytest.raises(gsr.GsrError) as e:
+            r.render_forward(g, gsr.pack_cameras([cam]), gsr.Config(**bad))
+        assert e.value.status == gsr.GSR_E_INVALID, bad
     ws, wsb = r._ws()
     assert r.lib.gsr_render_forward(r.ctx, ctypes.byref(g.c()), gsr.pack_cameras([cam]).data_ptr(), 1,
                                     ctypes.byref(gsr.Config().to_c()), ws, wsb - 4096, None, None) == gsr.GSR_E_INVALID
