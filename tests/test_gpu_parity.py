@@ -446,6 +446,43 @@ def test_fused_l1_step_matches_oracle(gsr_lib):
         assert H.rel_err(got["pose"][v], ref["pose"][v]) <= 1e-3
 
 
+def test_fused_step_equals_separate_calls(gsr_lib):
+    """The fused step's backward sums run on the bf16 matrix cores with each
+    FP32 value split into a high and a low half (16 significant bits); the
+    separate forward, L1 gradient and backward calls run them on the FP32
+    matrix cores.  On the room scene from the TUM camera (two views) the two
+    agree far inside the oracle tolerance: gradients to 1e-4 relative plus
+    5e-5 of each tensor's scale, losses and images exactly."""
+    gsr = gsr_lib
+    sc = W.room_scene(20_000, seed=5)
+    cams = [W.camera_tum(), W.perturb_pose(W.camera_tum(), np.array([0.03, -0.02, 0.01, 0.02, 0.01, -0.03]))]
+    sizes = [(c.width, c.height) for c in cams]
+    t_rgb, t_d, mask = W.random_targets(sizes, seed=8)
+    w_rgb, w_depth = 0.9, 0.2
+    cfg = gsr.Config(flags=gsr.GSR_GAUSS_GRAD | gsr.GSR_POSE_GRAD)
+    g = H.gpu_scene(gsr, sc)
+    cams_d = gsr.pack_cameras(cams)
+    args = (H.to_dev(t_rgb), H.to_dev(t_d), H.to_dev(mask, torch.uint8))
+    rf = gsr.Renderer()
+    rf.plan(sc.n, sizes)
+    imgs_f = rf.new_images()
+    loss_f, grads_f = rf.render_l1_fused(g, cams_d, cfg, *args, w_rgb=w_rgb, w_depth=w_depth, out=imgs_f)
+    rs = gsr.Renderer()
+    rs.plan(sc.n, sizes)
+    imgs_s = rs.render_forward(g, cams_d, cfg)
+    loss_s, gC, gD = rs.l1_loss_grad(imgs_s["rgb"], imgs_s["depth"], *args, w_rgb=w_rgb, w_depth=w_depth)
+    grads_s = rs.render_backward(g, cams_d, cfg, gC, gD)
+    torch.cuda.synchronize()
+    for k in ("rgb", "depth"):
+        assert torch.equal(imgs_f[k], imgs_s[k]), k
+    assert float(loss_f.item()) == pytest.approx(float(loss_s.item()), rel=1e-6)
+    a, b = H.gpu_grads_numpy(grads_f), H.gpu_grads_numpy(grads_s)
+    for k in ("mean", "log_scale", "quat", "opacity_logit", "rgb", "pose"):
+        assert np.abs(b[k]).max() > 0, k
+        assert H.rel_err(a[k], b[k]) <= 1e-4, (k, H.rel_err(a[k], b[k]))
+        H.assert_close_scaled(a[k], b[k], rtol=1e-4, scale_tol=5e-5, what=k)
+
+
 def test_fused_l1_step_with_loss_cap_matches_oracle(gsr_lib):
     """Outlier rejection: with a per-view cap at 1.5x the median pixel loss
     about a quarter of the pixels leave the loss and the backward."""
