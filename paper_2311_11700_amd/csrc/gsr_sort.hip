@@ -518,7 +518,7 @@ int launch_pair_sort(const Plan &p, Workspace &ws, hipStream_t s, int sort_grid)
 
 // Pair emission.  A block-iteration produces one sort tile of the pair sort
 // (STILE consecutive pairs, in depth order): the records that own those pairs
-// (found through the bucket index) are staged in LDS, up to BLOCK at a time,
+// (found through the bucket index) are staged in LDS, up to EMIT_STAGE at a time,
 // with their pair offsets, rectangles, alpha-support parameters and conics;
 // then one thread per pair finds its record among the staged ones, decodes
 // the tile from the rectangle, tests it against the alpha support and writes
@@ -537,6 +537,10 @@ int launch_pair_sort(const Plan &p, Workspace &ws, hipStream_t s, int sort_grid)
 // records once (one row per thread, spread evenly over the block; up to
 // EMIT_ROWS rows, the rest per pair) and every pair looks its row up.
 constexpr int EMIT_ROWS = 1024;
+// Records staged per round: the block's LDS (about 21 KB) lets six blocks
+// share a CU, which hides the staging gathers' latency better than four
+// blocks staging a full BLOCK of records each.
+constexpr int EMIT_STAGE = 160;
 __global__ __launch_bounds__(BLOCK) void k_emit_pairs(const uint32_t *__restrict__ order,
                                                       const uint32_t *__restrict__ off,
                                                       const uint4 *__restrict__ tinfo,
@@ -550,14 +554,14 @@ __global__ __launch_bounds__(BLOCK) void k_emit_pairs(const uint32_t *__restrict
                                                       int max_tiles) {
   static_assert(EMIT_BUCKET == BLOCK, "one emission bucket per BLOCK pairs");
   constexpr int STILE = BLOCK * SORT_ITEMS_PAIR;
-  __shared__ uint32_t s_off[BLOCK + 1];  // first pair of each staged record, then the end
-  __shared__ uint32_t s_id[BLOCK];
-  __shared__ uint4 s_ti[BLOCK];
-  __shared__ Support s_sp[BLOCK];
-  __shared__ float4 s_cb[BLOCK];
+  __shared__ uint32_t s_off[EMIT_STAGE + 1];  // first pair of each staged record, then the end
+  __shared__ uint32_t s_id[EMIT_STAGE];
+  __shared__ uint4 s_ti[EMIT_STAGE];
+  __shared__ Support s_sp[EMIT_STAGE];
+  __shared__ float4 s_cb[EMIT_STAGE];
   __shared__ uint32_t s_cnt[RADIX];
   __shared__ uint16_t s_map[STILE];             // staged record of each pair of the chunk (pair - p0)
-  __shared__ uint32_t s_rbase[BLOCK];           // first row slot of each staged record (culled records' rows)
+  __shared__ uint32_t s_rbase[EMIT_STAGE];      // first row slot of each staged record (culled records' rows)
   __shared__ uint32_t s_row[EMIT_ROWS];         // column range of a row: first | count << 16
   __shared__ uint32_t s_w[4];
   const uint32_t n = sort_count(n_dev, 0u, cap);
@@ -574,8 +578,8 @@ __global__ __launch_bounds__(BLOCK) void k_emit_pairs(const uint32_t *__restrict
     const uint32_t r_first = bucket_rec[p0 / EMIT_BUCKET];
     const uint32_t r_last = bucket_rec[(p1 + EMIT_BUCKET - 1) / EMIT_BUCKET];
     s_cnt[t] = 0u;
-    for (uint32_t rb = r_first; rb <= r_last; rb += BLOCK) {
-      const uint32_t nr = r_last - rb + 1u < (uint32_t)BLOCK ? r_last - rb + 1u : (uint32_t)BLOCK;
+    for (uint32_t rb = r_first; rb <= r_last; rb += EMIT_STAGE) {
+      const uint32_t nr = r_last - rb + 1u < (uint32_t)EMIT_STAGE ? r_last - rb + 1u : (uint32_t)EMIT_STAGE;
       __syncthreads();
       uint32_t rows = 0u;  // rows of this thread's staged record that need the support test
       if ((uint32_t)t < nr) {
@@ -593,7 +597,10 @@ __global__ __launch_bounds__(BLOCK) void k_emit_pairs(const uint32_t *__restrict
       }
       if (t == 0) s_off[nr] = rb + nr < n_rec ? off[rb + nr] : n;
       uint32_t rows_total;
-      s_rbase[t] = block_exclusive_scan<uint32_t>(rows, s_w, rows_total);
+      {
+        const uint32_t rb0 = block_exclusive_scan<uint32_t>(rows, s_w, rows_total);
+        if (t < EMIT_STAGE) s_rbase[t] = rb0;
+      }
       __syncthreads();
       // Row ranges: slot i belongs to the last staged record whose first slot
       // is <= i (records without rows share the next one's first slot).
