@@ -537,11 +537,12 @@ int launch_pair_sort(const Plan &p, Workspace &ws, hipStream_t s, int sort_grid)
 // records once (one row per thread, spread evenly over the block; up to
 // EMIT_ROWS rows, the rest per pair) and every pair looks its row up.
 constexpr int EMIT_ROWS = 1024;
-// Records staged per round: the block's LDS (about 21 KB) lets six blocks
-// share a CU, which hides the staging gathers' latency better than four
-// blocks staging a full BLOCK of records each.
-constexpr int EMIT_STAGE = 160;
-__global__ __launch_bounds__(BLOCK) void k_emit_pairs(const uint32_t *__restrict__ order,
+// Records staged per round: with the block's LDS at 21 KB and its registers
+// held to seven wavefronts per SIMD, seven blocks share a CU, which hides the
+// staging gathers' latency better than four blocks staging a full BLOCK of
+// records each.
+constexpr int EMIT_STAGE = 128;
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(7))) void k_emit_pairs(const uint32_t *__restrict__ order,
                                                       const uint32_t *__restrict__ off,
                                                       const uint4 *__restrict__ tinfo,
                                                       const Support *__restrict__ support,
