@@ -366,14 +366,16 @@ __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, con
     mA[2 * MA_STRIDE + lane] = in.sC2;
     mA[3 * MA_STRIDE + lane] = in.sD;
     wave_lds_sync();
-    const int col = lane & 15, g = lane >> 4;
+    // Rebuilt per tile from an opaque copy of the lane index: kept out of
+    // the tile loop, these tile-invariant values would be held in registers
+    // (or spilled) across the forward walk.
+    int lane_t = lane;
+    __asm__ volatile("" : "+v"(lane_t));
+    const int col = lane_t & 15, g = lane_t >> 4;
     const bool up = col >= 6 && col < NMOM;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      float yc = (float)(4 * wv + j) - 7.5f;
-      // Rebuilt per tile: kept out of the tile loop, these tile-invariant
-      // values would be held in registers (spilled) across the forward walk.
-      __asm__ volatile("" : "+v"(yc));
+      const float yc = (float)(4 * wv + j) - 7.5f;
       const float4 q = *reinterpret_cast<const float4 *>(mA + (up ? col - 6 : 0) * MA_STRIDE + 16 * j + 4 * g);
       const float qv[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
