@@ -236,8 +236,8 @@ gsr_status gsr_l1_loss_grad(gsr_ctx *ctx, const float *rgb, const float *depth,
  * recorded on the device and reported by gsr_check_overflow().  The
  * backward's per-entry sums over a tile's pixels run on the bf16 matrix
  * cores with every FP32 operand split into a high and a low bf16 half
- * (relative error below 2^-16 per product, FP32 accumulation); the separate
- * gsr_render_backward keeps FP32 products. */
+ * (relative error below 2^-16 per operand, FP32 accumulation), as in
+ * gsr_render_backward. */
 gsr_status gsr_render_l1_fused(gsr_ctx *ctx, const gsr_gaussians *g, const gsr_camera *cams,
                                int n_views, const gsr_config *cfg, const float *target_rgb,
                                const float *target_depth, const uint8_t *pixel_mask, float w_rgb,

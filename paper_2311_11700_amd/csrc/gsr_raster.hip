@@ -206,7 +206,8 @@ __device__ __forceinline__ void tile_forward(const TileInfo &ti, int64_t n, cons
 // matrix [1, xc, yc, xc^2, xc yc, yc^2, gC_r, gC_g, gC_b, gD] (pixels x 10),
 // a dense contraction over the pixels.  Each wavefront collects dLdP and w of
 // 8 entries (16 rows) for its 64 pixels in LDS and contracts them on the
-// matrix cores (v_mfma_f32_16x16x4_f32, K = 64 pixels in 16 steps); the four
+// bf16 matrix cores (v_mfma_f32_16x16x32_bf16, each value split into two
+// bf16 halves: K = 128 slots in 4 steps); the four
 // wavefronts add their 16x16 products into the block's per-entry sums.
 
 constexpr int SUB = 64;                   // entries per backward sub-batch
@@ -235,48 +236,19 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // Contract the wave's collected rows (rows 2q = dLdP, 2q+1 = w of entry q)
-// with the per-pixel constants Bm into D.  Operand layout of
-// v_mfma_f32_16x16x4_f32: lane l supplies A[l % 16][k] and B[k][l % 16] for
-// k = l / 16; D[i][l % 16] lands in register i % 4 of lane 16 (i / 4) + l % 16.
-// The 16 steps map K index k of step s to pixel 16 k + s.  The result is
-// consumed (mfma_consume) only at the next group, so the matrix-core chain
-// runs while the wavefront walks on.
-__device__ __forceinline__ float4v mfma_issue(const float *mA, const float Bm[16]) {
-  const int lane = __lane_id();
-  const int r = lane & 15, g = lane >> 4;
-  wave_lds_sync();
-  const float4 *src = reinterpret_cast<const float4 *>(mA + r * MA_STRIDE + 16 * g);
-  const float4 a0 = src[0], a1 = src[1], a2 = src[2], a3 = src[3];
-  float4v D = {0.f, 0.f, 0.f, 0.f};
-  D = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.x, Bm[0], D, 0, 0, 0);
-  D = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.y, Bm[1], D, 0, 0, 0);
-  D = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.z, Bm[2], D, 0, 0, 0);
-  D = __builtin_amdgcn_mfma_f32_16x16x4f32(a0.w, Bm[3], D, 0, 0, 0);
-  D = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.x, Bm[4], D, 0, 0, 0);
-  D = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.y, Bm[5], D, 0, 0, 0);
-  D = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.z, Bm[6], D, 0, 0, 0);
-  D = __builtin_amdgcn_mfma_f32_16x16x4f32(a1.w, Bm[7], D, 0, 0, 0);
-  D = __builtin_amdgcn_mfma_f32_16x16x4f32(a2.x, Bm[8], D, 0, 0, 0);
-  D = __builtin_amdgcn_mfma_f32_16x16x4f32(a2.y, Bm[9], D, 0, 0, 0);
-  D = __builtin_amdgcn_mfma_f32_16x16x4f32(a2.z, Bm[10], D, 0, 0, 0);
-  D = __builtin_amdgcn_mfma_f32_16x16x4f32(a2.w, Bm[11], D, 0, 0, 0);
-  D = __builtin_amdgcn_mfma_f32_16x16x4f32(a3.x, Bm[12], D, 0, 0, 0);
-  D = __builtin_amdgcn_mfma_f32_16x16x4f32(a3.y, Bm[13], D, 0, 0, 0);
-  D = __builtin_amdgcn_mfma_f32_16x16x4f32(a3.z, Bm[14], D, 0, 0, 0);
-  D = __builtin_amdgcn_mfma_f32_16x16x4f32(a3.w, Bm[15], D, 0, 0, 0);
-  return D;
-}
-
-// The same contraction on the bf16 matrix cores
+// with the per-pixel constants on the bf16 matrix cores
 // (v_mfma_f32_16x16x32_bf16): every per-pixel value x of the A rows is held
 // as a pair (h, l) of bf16, h = x with the low 16 bits of its float32 cleared
 // and l = x - h rounded to bf16 (h + l carries 16 significant bits, a
 // relative error below 2^-16), and the pair occupies two consecutive K slots
-// whose B entries both hold the pixel's column value, which bf16 must hold
-// exactly (the moment polynomials of half-integer coordinates have at most
-// 8 significant bits; the upstream columns are residual signs).  K = 128
-// slots (64 pixels x 2) in 4 steps instead of 16; step j covers the wave's
-// pixel row j.  The accumulation stays FP32.
+// whose B entries both hold the pixel's column value (exact in bf16 for the
+// moment polynomials of half-integer coordinates, at most 8 significant
+// bits, and for residual signs).  K = 128 slots (64 pixels x 2) in 4 steps;
+// step j covers the wave's pixel row j.  Lane l supplies A[l % 16][k] and
+// B[k][l % 16] for the 8 slots k of its group l / 16; D[i][l % 16] lands in
+// register i % 4 of lane 16 (i / 4) + l % 16.  The accumulation is FP32.
+// The result is consumed (mfma_consume) only at the next group, so the
+// matrix-core chain runs while the wavefront walks on.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float float2v __attribute__((ext_vector_type(2)));
@@ -287,7 +259,11 @@ __device__ __forceinline__ uint32_t split_bf16(float x) {
   return __builtin_bit_cast(uint32_t, __builtin_convertvector(p, bf16x2));
 }
 
-__device__ __forceinline__ float4v mfma_issue_split(const float *mA, const bf16x8 Bb[4]) {
+// With BLO the B values are not exact in bf16: Bl holds the low halves
+// (B - Bb rounded to bf16) and a second set of steps adds A Bl, so that the
+// products keep about 16 significant bits on both sides.
+template <bool BLO>
+__device__ __forceinline__ float4v mfma_issue_split(const float *mA, const bf16x8 Bb[4], const bf16x8 *Bl) {
   const int lane = __lane_id();
   const int r = lane & 15, g = lane >> 4;
   wave_lds_sync();
@@ -299,6 +275,12 @@ __device__ __forceinline__ float4v mfma_issue_split(const float *mA, const bf16x
   D = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a1), Bb[1], D, 0, 0, 0);
   D = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a2), Bb[2], D, 0, 0, 0);
   D = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a3), Bb[3], D, 0, 0, 0);
+  if constexpr (BLO) {
+    D = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a0), Bl[0], D, 0, 0, 0);
+    D = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a1), Bl[1], D, 0, 0, 0);
+    D = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a2), Bl[2], D, 0, 0, 0);
+    D = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a3), Bl[3], D, 0, 0, 0);
+  }
   return D;
 }
 
@@ -327,10 +309,13 @@ __device__ __forceinline__ void mfma_consume(const float4v &D, int nq, uint64_t 
 // keeps the result independent of the order the tiles finish in).  grad2d
 // fields: (u, v, conic a, b, c, opacity, r, g, b, depth).
 //
-// SPLIT: the contraction on the bf16 matrix cores (mfma_issue_split), with
-// the upstream columns taken from in.sC / in.sD and the colour and depth
-// sums scaled by w_rgb and w_depth at the flush.
-template <bool SPLIT>
+// The per-entry sums run on the bf16 matrix cores (mfma_issue_split).
+// Without BLO (the fused step) the upstream columns are the residual signs
+// in.sC / in.sD and the colour and depth sums are scaled by w_rgb and
+// w_depth at the flush; with BLO (the separate backward, any upstream
+// gradient) they are in.gC / in.gD themselves, split into high and low bf16
+// halves like the A values.
+template <bool BLO>
 __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, const float4 *__restrict__ recA,
                                               const float4 *__restrict__ recB,
                                               const float4 *__restrict__ recC,
@@ -352,19 +337,18 @@ __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, con
   const int maxlast = *s_max;
   if (maxlast == 0) return;
 
-  // Per-pixel constants of the contraction, in the B-operand layout: step s
-  // of lane (g, col) holds column col of pixel 16 g + s of this wavefront
-  // (tile pixel x = s, y = 4 wv + g), coordinates relative to the tile centre.
-  // The upstream gradients reach those lanes through the wave's LDS rows.
-  float Bm[SPLIT ? 1 : 16];
-  bf16x8 Bb[SPLIT ? 4 : 1];
-  if constexpr (SPLIT) {
+  // Per-pixel constants of the contraction, in the B-operand layout,
+  // coordinates relative to the tile centre.  The upstream gradients reach
+  // those lanes through the wave's LDS rows.
+  bf16x8 Bb[4];
+  bf16x8 Bl[BLO ? 4 : 1];
+  {
     // Step j, lane (g, col): elements 2 i and 2 i + 1 hold column col of
     // pixel x = 4 g + i of the wave's row j (y = 4 wv + j).
-    mA[0 * MA_STRIDE + lane] = in.sC0;
-    mA[1 * MA_STRIDE + lane] = in.sC1;
-    mA[2 * MA_STRIDE + lane] = in.sC2;
-    mA[3 * MA_STRIDE + lane] = in.sD;
+    mA[0 * MA_STRIDE + lane] = BLO ? in.gC0 : in.sC0;
+    mA[1 * MA_STRIDE + lane] = BLO ? in.gC1 : in.sC1;
+    mA[2 * MA_STRIDE + lane] = BLO ? in.gC2 : in.sC2;
+    mA[3 * MA_STRIDE + lane] = BLO ? in.gD : in.sD;
     wave_lds_sync();
     // Rebuilt per tile from an opaque copy of the lane index: kept out of
     // the tile loop, these tile-invariant values would be held in registers
@@ -384,33 +368,16 @@ __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, con
         // Columns 1, xc, yc, xc^2, xc yc, yc^2, then the upstream values.
         const float a = col == 1 || col == 3 || col == 4 ? xc : (col == 2 || col == 5 ? yc : 1.f);
         const float b = col == 3 ? xc : (col == 4 || col == 5 ? yc : 1.f);
-        const __bf16 v = (__bf16)(up ? qv[i] : (col < 6 ? a * b : 0.f));
+        const float x = up ? qv[i] : (col < 6 ? a * b : 0.f);
+        const __bf16 v = (__bf16)x;
         Bb[j][2 * i] = v;
         Bb[j][2 * i + 1] = v;
+        if constexpr (BLO) {
+          const __bf16 vl = (__bf16)(x - (float)v);
+          Bl[j][2 * i] = vl;
+          Bl[j][2 * i + 1] = vl;
+        }
       }
-    }
-    wave_lds_sync();
-  } else {
-    mA[0 * MA_STRIDE + lane] = in.gC0;
-    mA[1 * MA_STRIDE + lane] = in.gC1;
-    mA[2 * MA_STRIDE + lane] = in.gC2;
-    mA[3 * MA_STRIDE + lane] = in.gD;
-    wave_lds_sync();
-    const int col = lane & 15, g = lane >> 4;
-    const bool up = col >= 6 && col < NMOM;
-    const float4 *src = reinterpret_cast<const float4 *>(mA + (up ? col - 6 : 0) * MA_STRIDE + 16 * g);
-    const float4 q0 = src[0], q1 = src[1], q2 = src[2], q3 = src[3];
-    const float gv[16] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w,
-                          q2.x, q2.y, q2.z, q2.w, q3.x, q3.y, q3.z, q3.w};
-    // Moment columns as c0 + c1 xc + c2 xc^2.
-    const float yc = (float)(4 * wv + g) - 7.5f;
-    const float c0 = col == 0 ? 1.f : (col == 2 ? yc : (col == 5 ? yc * yc : 0.f));
-    const float c1 = col == 1 ? 1.f : (col == 4 ? yc : 0.f);
-    const float c2 = col == 3 ? 1.f : 0.f;
-#pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      const float xc = (float)s - 7.5f;
-      Bm[s] = up ? gv[s] : __fmaf_rn(__fmaf_rn(c2, xc, c1), xc, c0);
     }
     wave_lds_sync();
   }
@@ -495,22 +462,16 @@ __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, con
           // dL/dP with G = 2^P (the ln 2 and the conic pre-scale are applied
           // at the flush); dL/d(opacity) = dLdP / o there.
           const float dLdP = open ? dLda * oG : 0.f;
-          if constexpr (SPLIT) {
-            uint32_t *mw = reinterpret_cast<uint32_t *>(mA);
-            mw[(2 * nq) * MA_STRIDE + lane] = split_bf16(dLdP);
-            mw[(2 * nq + 1) * MA_STRIDE + lane] = split_bf16(w);
-          } else {
-            mA[(2 * nq) * MA_STRIDE + lane] = dLdP;
-            mA[(2 * nq + 1) * MA_STRIDE + lane] = w;
-          }
+          uint32_t *mw = reinterpret_cast<uint32_t *>(mA);
+          mw[(2 * nq) * MA_STRIDE + lane] = split_bf16(dLdP);
+          mw[(2 * nq + 1) * MA_STRIDE + lane] = split_bf16(w);
           slots |= (uint64_t)j << (8 * nq);
           ++nq;
         }
       }
       if (nq == 8 || (k < lo && nq > 0)) {
         if (p_nq > 0) mfma_consume(pD, p_nq, p_slots, my_part);
-        if constexpr (SPLIT) pD = mfma_issue_split(mA, Bb);
-        else pD = mfma_issue(mA, Bm);
+        pD = mfma_issue_split<BLO>(mA, Bb, Bl);
         p_nq = nq;
         p_slots = slots;
         nq = 0;
@@ -555,10 +516,11 @@ __device__ __forceinline__ void tile_backward(const TileInfo &ti, int64_t n, con
       o[3] = -Sxy;
       o[4] = -0.5 * Syy;
       o[5] = M1 / (double)sr.geo.z;
-      o[6] = SPLIT ? m[6] * (double)w_rgb : m[6];
-      o[7] = SPLIT ? m[7] * (double)w_rgb : m[7];
-      o[8] = SPLIT ? m[8] * (double)w_rgb : m[8];
-      o[9] = SPLIT ? m[9] * (double)w_depth : m[9];
+      constexpr bool SCALED = !BLO;  // the upstream columns were the residual signs
+      o[6] = SCALED ? m[6] * (double)w_rgb : m[6];
+      o[7] = SCALED ? m[7] * (double)w_rgb : m[7];
+      o[8] = SCALED ? m[8] * (double)w_rgb : m[8];
+      o[9] = SCALED ? m[9] * (double)w_depth : m[9];
     }
     __syncthreads();
     for (int t = threadIdx.x; t < cnt * NGRAD2D; t += BLOCK) {
@@ -652,8 +614,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
     in.gD = g_depth ? g_depth[ti.pix] : 0.f;
     in.gT = g_T ? g_T[ti.pix] : 0.f;
   }
-  tile_backward<false>(ti, a.n, a.recA, a.recB, a.recC, a.ids, a.rc, in, grad2d, s_rec, s_part, s_id, &s_max,
-                       s_mA);
+  tile_backward<true>(ti, a.n, a.recA, a.recB, a.recC, a.ids, a.rc, in, grad2d, s_rec, s_part, s_id,
+                            &s_max, s_mA);
 }
 
 __device__ __forceinline__ float sgnf(float x) { return (float)((x > 0.f) - (x < 0.f)); }
@@ -745,8 +707,8 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
       }
       const float ls = wave_sum(lpx);
       if ((threadIdx.x & 63) == 0) s_loss[threadIdx.x >> 6] = ls;
-      tile_backward<true>(ti, a.n, a.recA, a.recB, a.recC, a.ids, a.rc, in, grad2d, s_rec, s_part, s_id, &s_max,
-                          s_mA, staged_lo, w_rgb, w_depth);
+      tile_backward<false>(ti, a.n, a.recA, a.recB, a.recC, a.ids, a.rc, in, grad2d, s_rec, s_part, s_id, &s_max,
+                           s_mA, staged_lo, w_rgb, w_depth);
       if (threadIdx.x == 0 && loss) atomicAdd(loss, (s_loss[0] + s_loss[1]) + (s_loss[2] + s_loss[3]));
       if (threadIdx.x == 0) {
         const uint64_t d = wall_clock64() - clk0;

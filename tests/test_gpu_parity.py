@@ -447,12 +447,13 @@ def test_fused_l1_step_matches_oracle(gsr_lib):
 
 
 def test_fused_step_equals_separate_calls(gsr_lib):
-    """The fused step's backward sums run on the bf16 matrix cores with each
-    FP32 value split into a high and a low half (16 significant bits); the
-    separate forward, L1 gradient and backward calls run them on the FP32
-    matrix cores.  On the room scene from the TUM camera (two views) the two
-    agree far inside the oracle tolerance: gradients to 1e-4 relative plus
-    5e-5 of each tensor's scale, losses and images exactly."""
+    """Both backwards run their per-entry sums on the bf16 matrix cores with
+    each FP32 pixel value split into a high and a low half (16 significant
+    bits); the fused step feeds the upstream columns as exact residual signs
+    and scales at the flush, the separate backward splits the upstream
+    gradients themselves.  On the room scene from the TUM camera (two views)
+    the two agree far inside the oracle tolerance: gradients to 1e-4
+    relative plus 5e-5 of each tensor's scale, losses and images exactly."""
     gsr = gsr_lib
     sc = W.room_scene(20_000, seed=5)
     cams = [W.camera_tum(), W.perturb_pose(W.camera_tum(), np.array([0.03, -0.02, 0.01, 0.02, 0.01, -0.03]))]
