@@ -595,9 +595,10 @@ __global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) void
                                                       const float *__restrict__ g_depth,
                                                       const float *__restrict__ g_T,
                                                       double *__restrict__ grad2d) {
-  __shared__ Staged s_rec[BATCH];
+  // Without a forward in the same kernel the walk stages SUB entries at a time.
+  __shared__ Staged s_rec[SUB];
   __shared__ float s_part[4 * SUB * NMOM];
-  __shared__ uint32_t s_id[BATCH];
+  __shared__ uint32_t s_id[SUB];
   __shared__ int s_max;
   __shared__ __align__(16) float s_mA[4 * MA_WAVE];
   const TileInfo ti = tile_info(blockIdx.x, a.views, a.tile_view, a.ranges);
