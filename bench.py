@@ -284,6 +284,45 @@ def backward_counters(bytes_alg, bwd_ms, ach):
             "valu_busy": rec.get("valu_busy"), "counter_source": rec["summary"]}
 
 
+def run_sh(args, gsr, torch, W, tuning):
+    """The headline step with degree-1 spherical-harmonic colour (12
+    coefficients per Gaussian, Sec. 3.1) in place of RGB: the same scene
+    with seeded coefficients, graph-captured, at the headline's tuning; the
+    projection evaluates the colour per view and the chain carries its
+    gradient to the coefficients, the mean and the pose."""
+    scene, cam = build_c2(gsr, torch, W)
+    sc = W.with_sh(scene)
+    sizes = [(cam.width, cam.height)]
+    g = gsr.Gaussians.from_arrays(sc.mean, sc.log_scale, sc.quat, sc.opacity_logit, None, sh=sc.sh)
+    cams_d = gsr.pack_cameras([cam])
+    r = gsr.Renderer(0)
+    r.plan(sc.n, sizes)
+    (t_rgb, t_d), pairs = make_targets(gsr, torch, W, r, g, cams_d, sizes)
+    r.plan(sc.n, sizes, pair_capacity=int(pairs * 1.25) + 4096)
+    r.set_tuning(**tuning)
+    cfg = gsr.Config(flags=gsr.GSR_GAUSS_GRAD | gsr.GSR_POSE_GRAD | gsr.GSR_GRAD_OVERWRITE)
+    grads = r.new_grads(sc.n, sh=True)
+    loss = torch.zeros(1, device="cuda")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        r.graph_capture(g, cams_d, cfg, t_rgb, t_d, None, 1.0, 0.1, grads=grads, loss=loss, stream=stream)
+    stream.synchronize()
+    ms, _ = time_graph(torch, r, args.steps, args.warmup, stream)
+    r.check_overflow(stream=stream)
+    r.set_profiling(True)
+    for _ in range(3):
+        r.render_l1_fused(g, cams_d, cfg, t_rgb, t_d, None, 1.0, 0.1, grads=grads, loss=loss)
+    r.stage_times()
+    for _ in range(args.steps):
+        r.render_l1_fused(g, cams_d, cfg, t_rgb, t_d, None, 1.0, 0.1, grads=grads, loss=loss)
+    st = r.stage_times()
+    r.set_profiling(False)
+    calls = max(1, st.pop("calls"))
+    return {"workload": "the headline step (300k Gaussians, 1200x680, fwd+L1+bwd) with degree-1 SH colour",
+            "ms_per_step": round(ms, 4), "mpx_s": round(cam.width * cam.height / (ms * 1e-3) / 1e6, 1),
+            "stages_ms": {k: round(v / calls, 4) for k, v in st.items()}}
+
+
 def run_expansion(args, gsr, torch, W):
     """Map expansion (Sec. 3.2) on the headline workload: the adding step
     (Eq. 8) over the rendered 1200x680 keyframe against the room's observed
@@ -758,6 +797,9 @@ def main():
     log("map expansion: 300k Gaussians, 1200x680")
     expansion = run_expansion(args, gsr, torch, W)
     log("expansion:", expansion)
+    log("SH colour: 300k Gaussians, 1200x680")
+    sh_leg = run_sh(args, gsr, torch, W, h["tuning"])
+    log("sh colour:", sh_leg)
     batched = None
     if not args.no_batched:
         log("batched: 1M Gaussians, 16 keyframes")
@@ -793,6 +835,7 @@ def main():
         "hypotheses": hyp,
         "tracking": trk,
         "expansion": expansion,
+        "sh_colour": sh_leg,
         "eager_ms_per_step": round(h["eager_ms"], 4),
         "stages_ms": {k: round(v, 4) for k, v in h["stages"].items()},
         "work": h["work"],
