@@ -755,7 +755,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--tuning", type=str, default=None,
                     help="blocks_per_cu,tiles_per_pop,lpt_order[,batch] for the headline (skips its autotune)")
-    ap.add_argument("--no-extra", action="store_true", help="skip the pose-hypothesis and tracking legs")
+    ap.add_argument("--no-extra", action="store_true", help="skip the pose-hypothesis, tracking and SH-colour legs")
     ap.add_argument("--hyp-batches", type=int, default=200)
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
@@ -797,9 +797,11 @@ def main():
     log("map expansion: 300k Gaussians, 1200x680")
     expansion = run_expansion(args, gsr, torch, W)
     log("expansion:", expansion)
-    log("SH colour: 300k Gaussians, 1200x680")
-    sh_leg = run_sh(args, gsr, torch, W, h["tuning"])
-    log("sh colour:", sh_leg)
+    sh_leg = None
+    if not args.no_extra:
+        log("SH colour: 300k Gaussians, 1200x680")
+        sh_leg = run_sh(args, gsr, torch, W, h["tuning"])
+        log("sh colour:", sh_leg)
     batched = None
     if not args.no_batched:
         log("batched: 1M Gaussians, 16 keyframes")
