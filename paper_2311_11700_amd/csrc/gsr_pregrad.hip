@@ -51,8 +51,10 @@ __device__ __forceinline__ void quat_rot_r(R w, R x, R y, R z, R M[9]) {
 
 // SH: the colour is degree-1 spherical harmonics (instantiated separately so
 // that the RGB path carries none of their registers).
+// Registers held to two wavefronts per SIMD: the SH instance would otherwise
+// take 256 and run one wavefront per SIMD.
 template <bool SH>
-__global__ __launch_bounds__(BLOCK) void k_preprocess_bwd(gsr_gaussians g,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(2))) void k_preprocess_bwd(gsr_gaussians g,
                                                           const gsr_camera *__restrict__ cams,
                                                           int n_views, PreConstsB pc, Workspace ws,
                                                           gsr_grads gr) {
@@ -74,16 +76,20 @@ __global__ __launch_bounds__(BLOCK) void k_preprocess_bwd(gsr_gaussians g,
   R opl = 0;
   // Spherical-harmonic coefficients [4][3] (when the colour is view-dependent).
   constexpr bool sh_mode = SH;
-  R shc[12];
+  // The linear coefficients as stored (float32, widened where used); the
+  // constant term does not enter the direction gradient.
+  float shc[9];
 #pragma unroll
-  for (int k = 0; k < 12; ++k) shc[k] = 0.;
+  for (int k = 0; k < 9; ++k) shc[k] = 0.f;
   if (active && sh_mode) {
 #pragma unroll
-    for (int k = 0; k < 12; ++k) shc[k] = g.sh[12 * i + k];
+    for (int k = 0; k < 9; ++k) shc[k] = g.sh[12 * i + 3 + k];
   }
-  R gsh[12];
+  // Gradients of the linear coefficients; the constant term's is Y_0 times
+  // the colour gradient summed over the views (gc0..gc2).
+  R gsh[9];
 #pragma unroll
-  for (int k = 0; k < 12; ++k) gsh[k] = 0.;
+  for (int k = 0; k < 9; ++k) gsh[k] = 0.;
   if (active) {
     mx = g.mean[3 * i]; my = g.mean[3 * i + 1]; mz = g.mean[3 * i + 2];
     s0 = exp((R)g.log_scale[3 * i]); s1 = exp((R)g.log_scale[3 * i + 1]);
@@ -219,20 +225,20 @@ __global__ __launch_bounds__(BLOCK) void k_preprocess_bwd(gsr_gaussians g,
         const R vz = mz + (W[2] * t0 + W[5] * t1 + W[8] * t2);
         const R il = R(1) / sqrt(vx * vx + vy * vy + vz * vz);
         const R dx = vx * il, dy = vy * il, dz = vz * il;
-        const R Y[4] = {SH_C0, SH_C1 * dy, SH_C1 * dz, SH_C1 * dx};
+        const R Y[3] = {SH_C1 * dy, SH_C1 * dz, SH_C1 * dx};
         const R gc[3] = {g2[6], g2[7], g2[8]};
         if (want_gauss) {
 #pragma unroll
-          for (int k = 0; k < 4; ++k)
+          for (int k = 0; k < 3; ++k)
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) gsh[3 * k + ch] += Y[k] * gc[ch];
         }
         R gY1 = 0., gY2 = 0., gY3 = 0.;
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
-          gY1 += shc[3 + ch] * gc[ch];
-          gY2 += shc[6 + ch] * gc[ch];
-          gY3 += shc[9 + ch] * gc[ch];
+          gY1 += (R)shc[ch] * gc[ch];
+          gY2 += (R)shc[3 + ch] * gc[ch];
+          gY3 += (R)shc[6 + ch] * gc[ch];
         }
         const R gdx = SH_C1 * gY3, gdy = SH_C1 * gY1, gdz = SH_C1 * gY2;
         const R dot = dx * gdx + dy * gdy + dz * gdz;
@@ -326,8 +332,11 @@ __global__ __launch_bounds__(BLOCK) void k_preprocess_bwd(gsr_gaussians g,
     }
     if (gr.d_opacity_logit) put(gr.d_opacity_logit[i], gop * o * (R(1) - o), ow);
     if (sh_mode && gr.d_sh) {
+      put(gr.d_sh[12 * i], SH_C0 * gc0, ow);
+      put(gr.d_sh[12 * i + 1], SH_C0 * gc1, ow);
+      put(gr.d_sh[12 * i + 2], SH_C0 * gc2, ow);
 #pragma unroll
-      for (int k = 0; k < 12; ++k) put(gr.d_sh[12 * i + k], gsh[k], ow);
+      for (int k = 0; k < 9; ++k) put(gr.d_sh[12 * i + 3 + k], gsh[k], ow);
     }
     if (gr.d_rgb && !sh_mode) {
       put(gr.d_rgb[3 * i], gc0, ow);
