@@ -212,7 +212,7 @@ __device__ __forceinline__ void tile_forward(const TileInfo &ti, int64_t n, cons
 
 constexpr int SUB = 64;                   // entries per backward sub-batch
 constexpr int MA_ROWS = 16;               // 8 entries x (dLdP, w)
-constexpr int MA_STRIDE = 64 + 4;         // floats per row (padding spreads LDS banks)
+constexpr int MA_STRIDE = 64 + 4;         // 32-bit words (bf16 pairs) per row (padding spreads LDS banks)
 constexpr int MA_WAVE = MA_ROWS * MA_STRIDE;
 constexpr int NMOM = 10;                  // per-entry sums kept in LDS
 
@@ -223,9 +223,9 @@ struct BwdIn {
   int last;        // list positions [0, last) to walk
   float zr;        // depth of the last contributor (0 if none)
   float gC0, gC1, gC2, gD, gT;
-  // With the split contraction: the upstream colour and depth gradients
-  // divided by their weights (sC = gC / w_rgb, sD = gD / w_depth), values
-  // that bf16 holds exactly (signs of the L1 residuals).
+  // The fused step's upstream colour and depth gradients divided by their
+  // weights (sC = gC / w_rgb, sD = gD / w_depth), values that bf16 holds
+  // exactly (signs of the L1 residuals).
   float sC0, sC1, sC2, sD;
 };
 
