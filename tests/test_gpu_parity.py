@@ -47,7 +47,7 @@ def _lists_of(renderer):
     return rng.numpy(), sid.numpy(), 0, 0
 
 
-def _max_rows_per_staged_group(proj, chunk=2048, group=256):
+def _max_rows_per_staged_group(proj, chunk=2048, group=128):
     """The most alpha-support rows any group of records the pair emission
     stages together holds (records in depth order; a chunk covers `chunk`
     consecutive pairs and stages its records `group` at a time; every row of
