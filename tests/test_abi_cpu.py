@@ -1,10 +1,12 @@
 """Host-side checks of the C ABI (no GPU needed): the library loads, exports
 every entry point include/gsr.h declares, and its defaults match the
-oracle's reading of the renderer constants."""
+oracle's reading of the renderer constants; and the exactness in bf16 of
+the per-pixel columns the backward contraction feeds its matrix cores."""
 import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -84,3 +86,20 @@ def test_product_path_does_not_import_the_oracle():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
+
+
+def test_backward_contraction_operands_fit_bf16():
+    """The fused backward's matrix-core contraction takes its per-pixel
+    columns in bf16 without rounding: the moment polynomials 1, x, y, x^2,
+    x y, y^2 of the tile-centred pixel coordinates (half-integers from -7.5
+    to 7.5) and the L1 residual signs.  bf16 keeps the top 16 bits of a
+    float32, so exactness means the low 16 bits are zero; a value with more
+    than 8 significant bits (e.g. 7.5 * 7.5 + 1/8) would not pass."""
+    c = np.arange(16, dtype=np.float64) - 7.5
+    x, y = np.meshgrid(c, c)
+    cols = [np.ones_like(x), x, y, x * x, x * y, y * y, np.array([-1.0, 0.0, 1.0])]
+    for v in cols:
+        f = np.asarray(v, np.float32)
+        assert np.array_equal(f.astype(np.float64), np.asarray(v, np.float64))
+        assert not (f.view(np.uint32) & 0xFFFF).any()
+    assert np.float32(7.5 * 7.5 + 0.125).view(np.uint32) & 0xFFFF
