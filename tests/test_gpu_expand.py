@@ -245,6 +245,7 @@ def test_expansion_at_full_size(gsr_lib):
                                  0.5, 0.125, 1.0, -2.0)
     count_o = int(new["mean"].shape[0])
     out = _out_arrays(count_o)
+    out["sh"] = torch.full((count_o, 4, 3), SENT, device="cuda")  # an SH map's coefficients beside the RGB
     flag = torch.zeros(r.total_pixels, dtype=torch.uint8, device="cuda")
     print(f"adding step at full size: {count_o} new Gaussians", flush=True)
     cnt = r.expand_add(cams, H.to_dev(T), H.to_dev(dr), H.to_dev(do), H.to_dev(rgb), out, 0, count_o, 0.5, 0.125,
@@ -252,6 +253,7 @@ def test_expansion_at_full_size(gsr_lib):
     torch.cuda.synchronize()
     assert int(cnt.item()) == count_o
     np.testing.assert_array_equal(flag.cpu().numpy(), masks[0].ravel().astype(np.uint8))
+    np.testing.assert_array_equal(out.pop("sh").cpu().numpy(), new["sh"].astype(np.float32))
     _check_new(out, 0, new, count_o)
     obs = W.room_depth(cam)
     lo, dec_o = E.delete_gaussians(sc.mean, sc.opacity_logit, cam, obs, 0.3, 0.01)
